@@ -1,0 +1,176 @@
+/*
+ * csieve.h -- C ABI of the MI355X (gfx950) Combined Sieve library.
+ *
+ * The problem (Section 3 of "Combined Sieve Algorithm for Prime Gaps", S. Troisi,
+ * arXiv 2012.03771): for K = P#/d and many multipliers m, sieve the intervals around
+ * N = m*K with every prime up to the sieve limit.  Concretely, for a job
+ * (P, d, m_start, m_inc, sl, limit):
+ *
+ *   rows     m in [m_start, m_start + m_inc) with gcd(m, d) = 1 (Section 3: only m coprime
+ *            to d are searched; their number is the paper's M_c),
+ *   columns  X in [-sl, sl] with gcd(X, K) = 1 (the interval of size S = 2X + 1 of
+ *            Section 3.2; offsets sharing a factor with K are composite by construction,
+ *            Section 2 "Primorials"),
+ *   bit      1 iff some prime p <= limit divides m*K + X,
+ *   count    per row, the number of pairs (p, X), p <= limit prime, X a column,
+ *            p | m*K + X (every factor the sieve enumerates, Section 3.2).
+ *
+ * Output layout (all rows and columns ascending):
+ *   bitmap   uint32 words; row r, column c at word r*row_words + c/32, bit c%32
+ *            (LSB first), row_words = ceil(n_x/32); padding bits are 0.
+ *   counts   uint32[n_m].
+ *
+ * Conventions for every entry point:
+ *   - Device buffers (d_*) belong to the caller and must stay valid until the work
+ *     enqueued on `stream` has completed.  `stream` is a hipStream_t (NULL = legacy default
+ *     stream).  Calls enqueue work and return without waiting unless stated otherwise.
+ *   - Arguments are validated before anything is enqueued; on any error nothing is enqueued
+ *     and the outputs are untouched.  No entry point prints, throws or aborts.
+ *   - Faults of enqueued work surface as CS_EDEVICE from the next call that synchronises
+ *     (cs_diag_read, cs_server_*); outputs are then undefined.
+ *   - The library allocates device memory only inside batch-graph and server handles.
+ *   - All functions are reentrant; a handle (cs_graph, cs_server) is single-owner.
+ */
+#ifndef CSIEVE_H
+#define CSIEVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cs_status;
+#define CS_OK        0
+#define CS_EINVAL  (-1)  /* a parameter violates the validation rules below */
+#define CS_ERANGE  (-2)  /* a size exceeds a documented limit, or a buffer/workspace is too small */
+#define CS_ENOMEM  (-3)  /* host or device allocation failed (handles only) */
+#define CS_EDEVICE (-4)  /* a HIP runtime error, or the device reported an internal check */
+#define CS_EBUSY   (-5)  /* server: not enough budget or slots now; retry later */
+
+/* One sieve job.  Validation rules (CS_EINVAL unless noted):
+ *   2 <= P < 2^24;  d >= 1 squarefree with every prime factor <= P (d | P#);
+ *   m_start >= 1;  1 <= m_inc < 2^32;  m_start + m_inc < 2^63;
+ *   1 <= sl < 2^17 (a packed row fits an LDS tile) and sl < m_start*K (every N + X > 0);
+ *   2 <= limit and max(limit, P) < 2^40 (CS_ERANGE otherwise).
+ * A job whose range holds no m coprime to d is valid and has no rows. */
+typedef struct cs_job {
+  uint32_t P;
+  uint32_t sl;
+  uint64_t d;
+  uint64_t m_start;
+  uint64_t m_inc;
+  uint64_t limit;
+} cs_job;
+
+/* Large-prime enumeration variants; both give identical outputs. */
+#define CS_LARGE_G         0u  /* one solve of Eq. 3 by the recursion of Eq. 5 per hit (Section 3.3) */
+#define CS_LARGE_THREE_GAP 1u  /* Eq. 5 solves for the first hit and the two return times; then O(1) per hit */
+
+/* Tuning knobs.  Pass NULL for automatic choices.  Outputs never depend on them. */
+typedef struct cs_tune {
+  uint64_t thr;            /* primes p <= thr take the small-prime branch (Section 5: p/S < C_mult);
+                              0 = automatic.  Raised to max(P, 2*sl) (CS_LARGE_G) or 4*sl + 1
+                              (CS_LARGE_THREE_GAP) so that each large prime hits a row at most once. */
+  uint32_t tile_rows;      /* rows per LDS tile of the small branch; 0 = automatic */
+  uint32_t hits_per_item;  /* target expected hits per large-branch work item; 0 = automatic */
+  uint32_t large_mode;     /* CS_LARGE_G or CS_LARGE_THREE_GAP */
+  uint32_t large_blocks;   /* persistent grid of the large branch (workgroups); 0 = automatic */
+  uint32_t small_slices;   /* prime slices per small-branch tile; 0 = automatic */
+  uint32_t branches;       /* cs_sieve_range only: CS_BRANCH_ALL (0), CS_BRANCH_SMALL or
+                              CS_BRANCH_LARGE, to run one branch per call (e.g. to time it) */
+} cs_tune;
+
+#define CS_BRANCH_ALL   0u
+#define CS_BRANCH_SMALL 1u
+#define CS_BRANCH_LARGE 2u
+
+typedef struct cs_layout {
+  uint64_t n_m;            /* rows */
+  uint32_t n_x;            /* columns */
+  uint32_t row_words;      /* ceil(n_x / 32) */
+  uint64_t bitmap_bytes;   /* n_m * row_words * 4 */
+  uint64_t counts_bytes;   /* n_m * 4 */
+  uint64_t ws_bytes;       /* device workspace needed by cs_sieve / cs_prepare / cs_sieve_range */
+  uint64_t prime_cap;      /* capacity of the prime table: an upper bound of pi(max(limit, P)) */
+  uint64_t thr;            /* effective small/large threshold for the given tuning */
+} cs_layout;
+
+/* Counters accumulated by the kernels of the last cs_prepare + cs_sieve_range calls on a
+ * workspace (cs_sieve resets them). */
+typedef struct cs_diag {
+  uint64_t n_primes;        /* primes <= max(limit, P) in the table */
+  uint64_t small_primes;    /* primes handed to the small branch */
+  uint64_t large_primes;    /* primes handed to the large branch */
+  uint64_t small_pairs;     /* (row, prime) residues N mod p computed by the small branch */
+  uint64_t small_marks;     /* column marks (= factors) added by the small branch */
+  uint64_t large_raw_hits;  /* solutions (m, X) of Eq. 3 found, any m in range, any X */
+  uint64_t large_hits;      /* ... with gcd(m, d) = 1 and X a column (= factors added) */
+  uint64_t g_calls;         /* solves of Eq. 3 by the recursion of Eq. 5 */
+  uint64_t g_levels;        /* recursion levels summed over those solves */
+  uint64_t error_flags;     /* nonzero: a device-side consistency check failed */
+} cs_diag;
+
+/* Human-readable name of a status code (static string). */
+const char* cs_strerror(cs_status st);
+
+/* Text of the last HIP runtime failure seen by this thread's calls ("kernel: message"), or ""
+ * if none.  Static thread-local storage; valid until the thread's next failing call. */
+const char* cs_last_error(void);
+
+/* Validates `job` and fills `out` (host only, no device work).  `tune` may be NULL. */
+cs_status cs_plan(const cs_job* job, const cs_tune* tune, cs_layout* out);
+
+/* Host only.  Column c -> X, for c < min(cap, n_x).  Errors: CS_EINVAL (invalid job). */
+cs_status cs_columns(const cs_job* job, int32_t* x_of_col, uint64_t cap);
+
+/* Host only.  Row r -> m, for r < min(cap, n_m). */
+cs_status cs_rows(const cs_job* job, uint64_t* m_of_row, uint64_t cap);
+
+/* The whole sieve (Sections 3.1-3.3): clears d_bitmap and d_counts, builds the prime table
+ * up to max(limit, P), K mod p for every prime (Eq. 1 cache), then runs the small-prime
+ * branch (primes <= thr, marked in LDS tiles of rows) and the large-prime branch (primes
+ * > thr, Eq. 3 solved by Eq. 5, one atomic mark per hit).
+ * d_bitmap: layout.bitmap_bytes; d_counts: layout.counts_bytes; d_ws: layout.ws_bytes
+ * (CS_ERANGE if ws_bytes is smaller).  All three are caller-owned device memory. */
+cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
+                   void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* First half of cs_sieve without touching any output: prime table, K mod p, row and column
+ * tables into d_ws, and the diagnostic counters reset. */
+cs_status cs_prepare(const cs_job* job, const cs_tune* tune, void* d_ws, uint64_t ws_bytes,
+                     void* stream);
+
+/* Sieves with the primes p in [p_lo, p_hi] only (clipped to [2, limit]) and ORs the marks
+ * into d_bitmap and adds the factors into d_counts.  d_ws must hold the tables of the same
+ * job and tuning from cs_prepare, earlier on the same stream.  Splitting [2, limit] into
+ * ranges and calling this once per range gives exactly cs_sieve's result (bitwise OR and
+ * integer sums are order independent), which makes a job splittable and resumable. */
+cs_status cs_sieve_range(const cs_job* job, const cs_tune* tune, uint64_t p_lo, uint64_t p_hi,
+                         uint32_t* d_bitmap, uint32_t* d_counts, void* d_ws, uint64_t ws_bytes,
+                         void* stream);
+
+/* Waits for `stream`, then copies the counters kept in d_ws (see cs_diag).  Returns
+ * CS_EDEVICE if the stream reported an error or error_flags is nonzero. */
+cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream);
+
+/* Prime table alone (the segmented sieve of Eratosthenes behind cs_sieve; the paper counts
+ * it as a one-time cost, Section 5): writes the primes <= limit ascending to d_primes
+ * (capacity `cap`, CS_ERANGE if smaller than cs_primes_ws's *cap_out) and their number to
+ * *d_count (device uint64).  ws: cs_primes_ws bytes. */
+cs_status cs_primes_ws(uint64_t limit, uint64_t* cap_out, uint64_t* ws_bytes_out);
+cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* d_count,
+                    void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* K mod p for n primes (Eq. 1: the cached residue, K = P#/d): d_out[i] = K mod d_primes[i].
+ * Every d_primes[i] must be a prime below 2^40.  d_ws: cs_kmod_ws bytes (it receives the
+ * products of the primes dividing K, grouped below 2^50). */
+cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out);
+cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,
+                  void* d_ws, uint64_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSIEVE_H */

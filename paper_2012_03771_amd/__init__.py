@@ -1,0 +1,10 @@
+"""MI355X Combined Sieve: Python binding of libcsieve.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch only provides device memory and streams.
+Importing this package does not load the library; the first call does, and raises if the
+library was not built (there is no fallback path).
+"""
+from .binding import (  # noqa: F401
+    CsError, Tune, Layout, Diag, LARGE_G, LARGE_THREE_GAP, BRANCH_ALL, BRANCH_SMALL, BRANCH_LARGE, lib, lib_path, plan, columns, rows,
+    sieve, sieve_into, prepare, sieve_range, diag_read, primes, kmod, job_tuple, unpack_bits,
+)

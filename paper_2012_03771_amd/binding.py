@@ -1,0 +1,263 @@
+"""ctypes binding of libcsieve.so.  Mirrors include/csieve.h name for name."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "_lib", "libcsieve.so")
+
+LARGE_G = 0
+LARGE_THREE_GAP = 1
+BRANCH_ALL = 0
+BRANCH_SMALL = 1
+BRANCH_LARGE = 2
+
+_ERRORS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ERANGE", -3: "CS_ENOMEM", -4: "CS_EDEVICE", -5: "CS_EBUSY"}
+
+
+class CsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_ERRORS.get(status, status)}")
+
+
+class cs_job(C.Structure):
+    _fields_ = [("P", C.c_uint32), ("sl", C.c_uint32), ("d", C.c_uint64), ("m_start", C.c_uint64),
+                ("m_inc", C.c_uint64), ("limit", C.c_uint64)]
+
+
+class cs_tune(C.Structure):
+    _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
+                ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
+                ("branches", C.c_uint32)]
+
+
+class cs_layout(C.Structure):
+    _fields_ = [("n_m", C.c_uint64), ("n_x", C.c_uint32), ("row_words", C.c_uint32),
+                ("bitmap_bytes", C.c_uint64), ("counts_bytes", C.c_uint64), ("ws_bytes", C.c_uint64),
+                ("prime_cap", C.c_uint64), ("thr", C.c_uint64)]
+
+
+class cs_diag(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("n_primes", "small_primes", "large_primes", "small_pairs",
+                                          "small_marks", "large_raw_hits", "large_hits", "g_calls",
+                                          "g_levels", "error_flags")]
+
+
+@dataclass
+class Tune:
+    thr: int = 0
+    tile_rows: int = 0
+    hits_per_item: int = 0
+    large_mode: int = LARGE_G
+    large_blocks: int = 0
+    small_slices: int = 0
+    branches: int = 0
+
+    def c(self):
+        return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
+                       self.small_slices, self.branches)
+
+
+@dataclass
+class Layout:
+    n_m: int
+    n_x: int
+    row_words: int
+    bitmap_bytes: int
+    counts_bytes: int
+    ws_bytes: int
+    prime_cap: int
+    thr: int
+
+
+@dataclass
+class Diag:
+    n_primes: int
+    small_primes: int
+    large_primes: int
+    small_pairs: int
+    small_marks: int
+    large_raw_hits: int
+    large_hits: int
+    g_calls: int
+    g_levels: int
+    error_flags: int
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Loads libcsieve.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(_LIB_PATH)
+    P, u64, u32, i32, vp = C.POINTER, C.c_uint64, C.c_uint32, C.c_int32, C.c_void_p
+    sig = {
+        "cs_strerror": ([i32], C.c_char_p),
+        "cs_last_error": ([], C.c_char_p),
+        "cs_plan": ([P(cs_job), P(cs_tune), P(cs_layout)], i32),
+        "cs_columns": ([P(cs_job), vp, u64], i32),
+        "cs_rows": ([P(cs_job), vp, u64], i32),
+        "cs_sieve": ([P(cs_job), P(cs_tune), vp, vp, vp, u64, vp], i32),
+        "cs_prepare": ([P(cs_job), P(cs_tune), vp, u64, vp], i32),
+        "cs_sieve_range": ([P(cs_job), P(cs_tune), u64, u64, vp, vp, vp, u64, vp], i32),
+        "cs_diag_read": ([vp, P(cs_diag), vp], i32),
+        "cs_primes_ws": ([u64, P(u64), P(u64)], i32),
+        "cs_primes": ([u64, vp, u64, vp, vp, u64, vp], i32),
+        "cs_kmod_ws": ([u32, u64, P(u64)], i32),
+        "cs_kmod": ([u32, u64, vp, u64, vp, vp, u64, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        detail = lib().cs_last_error().decode() if st == -4 else ""
+        raise CsError(st, where + (f" [{detail}]" if detail else ""))
+
+
+def job_tuple(job):
+    if hasattr(job, "as_tuple"):
+        return job.as_tuple()
+    return tuple(job)
+
+
+def _cjob(job) -> cs_job:
+    P, d, m_start, m_inc, sl, limit = job_tuple(job)
+    return cs_job(P, sl, d, m_start, m_inc, limit)
+
+
+def _ctune(tune):
+    if tune is None:
+        return None
+    return C.byref(tune.c())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def plan(job, tune: Tune | None = None) -> Layout:
+    out = cs_layout()
+    _check(lib().cs_plan(C.byref(_cjob(job)), _ctune(tune), C.byref(out)), "cs_plan")
+    return Layout(out.n_m, out.n_x, out.row_words, out.bitmap_bytes, out.counts_bytes, out.ws_bytes,
+                  out.prime_cap, out.thr)
+
+
+def columns(job):
+    import numpy as np
+    lay = plan(job)
+    out = np.zeros(max(lay.n_x, 1), dtype=np.int32)
+    _check(lib().cs_columns(C.byref(_cjob(job)), out.ctypes.data_as(C.c_void_p), lay.n_x), "cs_columns")
+    return out[:lay.n_x]
+
+
+def rows(job):
+    import numpy as np
+    lay = plan(job)
+    out = np.zeros(max(lay.n_m, 1), dtype=np.uint64)
+    _check(lib().cs_rows(C.byref(_cjob(job)), out.ctypes.data_as(C.c_void_p), lay.n_m), "cs_rows")
+    return out[:lay.n_m]
+
+
+def alloc_outputs(job, tune=None, device="cuda"):
+    import torch
+    lay = plan(job, tune)
+    bitmap = torch.empty((lay.n_m, lay.row_words), dtype=torch.int32, device=device)
+    counts = torch.empty((lay.n_m,), dtype=torch.int32, device=device)
+    ws = torch.empty((lay.ws_bytes,), dtype=torch.uint8, device=device)
+    return lay, bitmap, counts, ws
+
+
+def sieve_into(job, bitmap, counts, ws, tune: Tune | None = None, stream=None):
+    _check(lib().cs_sieve(C.byref(_cjob(job)), _ctune(tune), _ptr(bitmap), _ptr(counts), _ptr(ws),
+                          ws.numel(), _stream(stream)), "cs_sieve")
+
+
+def sieve(job, tune: Tune | None = None, stream=None):
+    """Runs cs_sieve on freshly allocated device tensors.  Returns (bitmap int32 [n_m, row_words]
+    holding the uint32 words, counts int32 [n_m], workspace)."""
+    lay, bitmap, counts, ws = alloc_outputs(job, tune)
+    sieve_into(job, bitmap, counts, ws, tune, stream)
+    return bitmap, counts, ws
+
+
+def prepare(job, ws, tune: Tune | None = None, stream=None):
+    _check(lib().cs_prepare(C.byref(_cjob(job)), _ctune(tune), _ptr(ws), ws.numel(), _stream(stream)),
+           "cs_prepare")
+
+
+def sieve_range(job, p_lo, p_hi, bitmap, counts, ws, tune: Tune | None = None, stream=None):
+    _check(lib().cs_sieve_range(C.byref(_cjob(job)), _ctune(tune), p_lo, p_hi, _ptr(bitmap), _ptr(counts),
+                                _ptr(ws), ws.numel(), _stream(stream)), "cs_sieve_range")
+
+
+def diag_read(ws, stream=None, check: bool = True) -> Diag:
+    out = cs_diag()
+    st = lib().cs_diag_read(_ptr(ws), C.byref(out), _stream(stream))
+    d = Diag(*[getattr(out, f[0]) for f in cs_diag._fields_])
+    if check:
+        _check(st, f"cs_diag_read (error_flags={d.error_flags})")
+    return d
+
+
+def primes(limit: int, stream=None):
+    """Device prime table (uint64 values in an int64 tensor) and its length."""
+    import torch
+    cap = C.c_uint64()
+    wsb = C.c_uint64()
+    _check(lib().cs_primes_ws(limit, C.byref(cap), C.byref(wsb)), "cs_primes_ws")
+    out = torch.empty((cap.value,), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    ws = torch.empty((wsb.value,), dtype=torch.uint8, device="cuda")
+    _check(lib().cs_primes(limit, _ptr(out), cap.value, _ptr(cnt), _ptr(ws), wsb.value, _stream(stream)),
+           "cs_primes")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    n = int(cnt.item())
+    return out[:n], n
+
+
+def kmod(P: int, d: int, primes_dev, stream=None):
+    """K mod p for each prime of a device int64 tensor (K = P#/d)."""
+    import torch
+    wsb = C.c_uint64()
+    _check(lib().cs_kmod_ws(P, d, C.byref(wsb)), "cs_kmod_ws")
+    ws = torch.empty((max(wsb.value, 8),), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(primes_dev)
+    _check(lib().cs_kmod(P, d, _ptr(primes_dev), primes_dev.numel(), _ptr(out), _ptr(ws), ws.numel(),
+                         _stream(stream)), "cs_kmod")
+    return out
+
+
+def unpack_bits(words, n_x: int):
+    """int32/uint32 words [n, row_words] (numpy) -> uint8 [n, n_x], column c = bit c%32 of word c//32."""
+    import numpy as np
+    w = np.asarray(words).view(np.uint32)
+    n, rw = w.shape
+    out = np.zeros((n, rw * 32), dtype=np.uint8)
+    for b in range(32):
+        out[:, b::32] = ((w >> np.uint32(b)) & np.uint32(1)).astype(np.uint8)
+    return out[:, :n_x]

@@ -1,0 +1,295 @@
+// C ABI of the Combined Sieve library (declared in include/csieve.h).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/csieve.h"
+#include "device.h"
+#include "launch.h"
+#include "plan.h"
+
+using namespace cs;
+
+#define CS_TRY(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return CS_EDEVICE; \
+  } while (0)
+
+extern "C" const char* cs_strerror(cs_status st) {
+  switch (st) {
+    case CS_OK: return "ok";
+    case CS_EINVAL: return "invalid argument";
+    case CS_ERANGE: return "size out of range or buffer too small";
+    case CS_ENOMEM: return "out of memory";
+    case CS_EDEVICE: return "device error";
+    case CS_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* cs_last_error(void) { return last_error_detail(); }
+
+extern "C" cs_status cs_plan(const cs_job* job, const cs_tune* tune, cs_layout* out) {
+  if (!job || !out) return CS_EINVAL;
+  Plan pl;
+  cs_status st = make_plan(job, tune, 256, &pl);
+  if (st) return st;
+  out->n_m = pl.n_m;
+  out->n_x = pl.n_x;
+  out->row_words = pl.row_words;
+  out->bitmap_bytes = pl.n_m * (uint64_t)pl.row_words * 4ull;
+  out->counts_bytes = pl.n_m * 4ull;
+  out->ws_bytes = pl.ws.total;
+  out->prime_cap = pl.cap;
+  out->thr = pl.thr;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_columns(const cs_job* job, int32_t* x_of_col, uint64_t cap) {
+  Plan pl;
+  cs_status st = make_plan(job, nullptr, 256, &pl);
+  if (st) return st;
+  std::vector<int32_t> xs;
+  host_columns(pl.job, pl.kq, &xs);
+  if (x_of_col) {
+    const uint64_t n = std::min<uint64_t>(cap, xs.size());
+    memcpy(x_of_col, xs.data(), n * sizeof(int32_t));
+  }
+  return CS_OK;
+}
+
+extern "C" cs_status cs_rows(const cs_job* job, uint64_t* m_of_row, uint64_t cap) {
+  Plan pl;
+  cs_status st = make_plan(job, nullptr, 256, &pl);
+  if (st) return st;
+  uint64_t r = 0;
+  for (uint64_t o = 0; o < pl.job.m_inc && r < cap; ++o) {
+    const uint64_t m = pl.job.m_start + o;
+    bool ok = true;
+    for (uint32_t q : pl.dq)
+      if (m % q == 0) { ok = false; break; }
+    if (ok) {
+      if (m_of_row) m_of_row[r] = m;
+      ++r;
+    }
+  }
+  return CS_OK;
+}
+
+namespace {
+
+PrimeWs prime_ws_of(const Plan& pl, uint8_t* ws) {
+  PrimeWs pw;
+  const WsLayout& L = pl.ws;
+  pw.base = reinterpret_cast<uint32_t*>(ws + L.base);
+  pw.n_base = reinterpret_cast<uint32_t*>(ws + L.n_base);
+  pw.flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+  pw.seg_count = reinterpret_cast<uint32_t*>(ws + L.seg_count);
+  pw.seg_off = reinterpret_cast<uint64_t*>(ws + L.seg_off);
+  pw.primes = reinterpret_cast<uint64_t*>(ws + L.primes);
+  pw.n_primes = reinterpret_cast<uint64_t*>(ws + L.n_primes);
+  pw.cap = pl.cap;
+  return pw;
+}
+
+cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) {
+  const WsLayout& L = pl.ws;
+  JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
+  JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
+  PrimeWs pw = prime_ws_of(pl, ws);
+  JobDev jd = make_jobdev(pl, ws, pw.primes, pw.n_primes);
+  CS_TRY(launch_zero_ctrl(ctrl, s));
+  CS_TRY(launch_write_job(jd, jdp, s));
+  CS_TRY(launch_primes(pl.Lp, pw, s));
+  CS_TRY(launch_prep_tables(jdp, s));
+  CS_TRY(launch_kmod(jdp, pi_upper(pl.job.limit), n_cu, s));
+  CS_TRY(launch_rows_cols(jdp, pl.job.m_inc, pl.job.sl, n_cu, s));
+  return CS_OK;
+}
+
+cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
+                        uint8_t* ws, hipStream_t s, uint32_t branches) {
+  const WsLayout& L = pl.ws;
+  JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
+  PrimeWs pw = prime_ws_of(pl, ws);
+  JobDev jd = make_jobdev(pl, ws, pw.primes, pw.n_primes);
+  jd.p_lo = p_lo;
+  jd.p_hi = p_hi;
+  jd.bitmap = bitmap;
+  jd.counts = counts;
+  fill_tiers(pl, p_lo, p_hi, &jd);
+  uint64_t* items_base = reinterpret_cast<uint64_t*>(ws + L.items_base);
+  CS_TRY(launch_write_job(jd, jdp, s));
+  CS_TRY(launch_prep_bounds(jdp, s));
+  CS_TRY(launch_items_scan(jdp, 1, items_base, s));
+  if (pl.n_m == 0) return CS_OK;
+  const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
+  if (branches != CS_BRANCH_LARGE)
+    CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s));
+  JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
+  if (branches != CS_BRANCH_SMALL)
+    CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, s));
+  return CS_OK;
+}
+
+}  // namespace
+
+extern "C" cs_status cs_prepare(const cs_job* job, const cs_tune* tune, void* d_ws, uint64_t ws_bytes,
+                                void* stream) {
+  Plan pl;
+  const int n_cu = device_cu_count();
+  cs_status st = make_plan(job, tune, n_cu, &pl);
+  if (st) return st;
+  if (!d_ws) return CS_EINVAL;
+  if (ws_bytes < pl.ws.total) return CS_ERANGE;
+  return prepare_planned(pl, static_cast<uint8_t*>(d_ws), (hipStream_t)stream, n_cu);
+}
+
+extern "C" cs_status cs_sieve_range(const cs_job* job, const cs_tune* tune, uint64_t p_lo, uint64_t p_hi,
+                                    uint32_t* d_bitmap, uint32_t* d_counts, void* d_ws, uint64_t ws_bytes,
+                                    void* stream) {
+  Plan pl;
+  const int n_cu = device_cu_count();
+  cs_status st = make_plan(job, tune, n_cu, &pl);
+  if (st) return st;
+  if (!d_ws || (pl.n_m > 0 && (!d_bitmap || !d_counts))) return CS_EINVAL;
+  if (ws_bytes < pl.ws.total) return CS_ERANGE;
+  const uint32_t branches = tune ? tune->branches : CS_BRANCH_ALL;
+  if (branches > CS_BRANCH_LARGE) return CS_EINVAL;
+  if (p_hi < p_lo) return CS_OK;
+  return range_planned(pl, p_lo, p_hi, d_bitmap, d_counts, static_cast<uint8_t*>(d_ws), (hipStream_t)stream,
+                       branches);
+}
+
+extern "C" cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
+                              void* d_ws, uint64_t ws_bytes, void* stream) {
+  Plan pl;
+  const int n_cu = device_cu_count();
+  cs_status st = make_plan(job, tune, n_cu, &pl);
+  if (st) return st;
+  if (!d_ws || (pl.n_m > 0 && (!d_bitmap || !d_counts))) return CS_EINVAL;
+  if (ws_bytes < pl.ws.total) return CS_ERANGE;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  if (pl.n_m > 0) {
+    CS_TRY(launch_fill_u32(d_bitmap, pl.n_m * (uint64_t)pl.row_words, 0u, s));
+    CS_TRY(launch_fill_u32(d_counts, pl.n_m, 0u, s));
+  }
+  st = prepare_planned(pl, ws, s, n_cu);
+  if (st) return st;
+  return range_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL);
+}
+
+extern "C" cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream) {
+  if (!d_ws || !out) return CS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return CS_EDEVICE;
+  JobCtrl c;
+  if (hipMemcpy(&c, d_ws, sizeof(JobCtrl), hipMemcpyDeviceToHost) != hipSuccess) return CS_EDEVICE;
+  out->n_primes = c.diag[D_NPRIMES];
+  out->small_primes = c.diag[D_SMALL_PRIMES];
+  out->large_primes = c.diag[D_LARGE_PRIMES];
+  out->small_pairs = c.diag[D_SMALL_PAIRS];
+  out->small_marks = c.diag[D_SMALL_MARKS];
+  out->large_raw_hits = c.diag[D_LARGE_RAW];
+  out->large_hits = c.diag[D_LARGE_HITS];
+  out->g_calls = c.diag[D_G_CALLS];
+  out->g_levels = c.diag[D_G_LEVELS];
+  out->error_flags = c.diag[D_ERROR] | c.error;
+  return out->error_flags ? CS_EDEVICE : CS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stand-alone prime table and K mod p.
+// ---------------------------------------------------------------------------------------------
+namespace {
+struct PrimeOnlyLayout {
+  uint64_t n_base, base, flags, seg_count, seg_off, total, n_seg, cap;
+};
+PrimeOnlyLayout prime_only_layout(uint64_t limit) {
+  PrimeOnlyLayout L;
+  uint64_t o = 0;
+  auto take = [&](uint64_t b) { uint64_t at = o; o = (o + std::max<uint64_t>(b, 8) + 255) & ~255ull; return at; };
+  L.n_seg = (limit >> kSegLog) + 1;
+  L.cap = pi_upper(limit);
+  L.n_base = take(8);
+  L.base = take(kBaseCap * 4ull);
+  L.flags = take(L.n_seg * kSegWords * 4ull);
+  L.seg_count = take(L.n_seg * 4ull);
+  L.seg_off = take(L.n_seg * 8ull);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" cs_status cs_primes_ws(uint64_t limit, uint64_t* cap_out, uint64_t* ws_bytes_out) {
+  if (limit < 2) return CS_EINVAL;
+  if (limit >= kMaxLimit) return CS_ERANGE;
+  PrimeOnlyLayout L = prime_only_layout(limit);
+  if (cap_out) *cap_out = L.cap;
+  if (ws_bytes_out) *ws_bytes_out = L.total;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* d_count, void* d_ws,
+                               uint64_t ws_bytes, void* stream) {
+  if (limit < 2 || !d_primes || !d_count || !d_ws) return CS_EINVAL;
+  if (limit >= kMaxLimit) return CS_ERANGE;
+  PrimeOnlyLayout L = prime_only_layout(limit);
+  if (cap < L.cap || ws_bytes < L.total) return CS_ERANGE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  PrimeWs pw;
+  pw.base = reinterpret_cast<uint32_t*>(ws + L.base);
+  pw.n_base = reinterpret_cast<uint32_t*>(ws + L.n_base);
+  pw.flags = reinterpret_cast<uint32_t*>(ws + L.flags);
+  pw.seg_count = reinterpret_cast<uint32_t*>(ws + L.seg_count);
+  pw.seg_off = reinterpret_cast<uint64_t*>(ws + L.seg_off);
+  pw.primes = d_primes;
+  pw.n_primes = d_count;
+  pw.cap = cap;
+  CS_TRY(launch_primes(limit, pw, (hipStream_t)stream));
+  return CS_OK;
+}
+
+extern "C" cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,
+                             void* d_ws, uint64_t ws_bytes, void* stream) {
+  cs_job j;
+  memset(&j, 0, sizeof(j));
+  j.P = P; j.d = d; j.m_start = 1; j.m_inc = 1; j.sl = 1; j.limit = 2;
+  Plan pl;
+  cs_status st = make_plan(&j, nullptr, 256, &pl);
+  if (st == CS_EINVAL) {
+    // sl < m_start*K may fail for K = 1 (d = P#); only P and d matter here
+    j.m_start = 2;
+    st = make_plan(&j, nullptr, 256, &pl);
+  }
+  if (st) return st;
+  if ((n > 0 && (!d_primes || !d_out)) || !d_ws) return CS_EINVAL;
+  std::vector<uint64_t> groups;
+  uint64_t g = 1;
+  for (uint32_t q : pl.kq) {
+    if (g > (kGroupMax - 1) / q) { groups.push_back(g); g = q; }
+    else g *= q;
+  }
+  if (g > 1) groups.push_back(g);
+  if (ws_bytes < std::max<uint64_t>(groups.size(), 1) * 8ull) return CS_ERANGE;
+  if (n == 0) return CS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (!groups.empty()) CS_TRY(launch_upload(d_ws, groups.data(), groups.size() * 8ull, s));
+  CS_TRY(launch_kmod_list(d_primes, n, static_cast<const uint64_t*>(d_ws), (uint32_t)groups.size(), d_out,
+                          device_cu_count(), s));
+  return CS_OK;
+}
+
+extern "C" cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out) {
+  cs_job j;
+  memset(&j, 0, sizeof(j));
+  j.P = P; j.d = d; j.m_start = 2; j.m_inc = 1; j.sl = 1; j.limit = 2;
+  Plan pl;
+  cs_status st = make_plan(&j, nullptr, 256, &pl);
+  if (st) return st;
+  if (ws_bytes_out) *ws_bytes_out = (pl.kq.size() + 1) * 8ull;
+  return CS_OK;
+}

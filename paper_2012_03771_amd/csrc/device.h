@@ -1,0 +1,71 @@
+// Device-side job descriptors shared by the kernels and the host launch code.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace cs {
+
+constexpr int kMaxTiers = 48;     // large-branch prime tiers (chunk count per tier)
+constexpr int kMaxDq = 16;        // prime factors of d (d < 2^64 squarefree has at most 15)
+constexpr int kSegLog = 19;       // prime sieve segment: 2^19 integers, odd-only bits
+constexpr uint32_t kSegBits = 1u << (kSegLog - 1);
+constexpr uint32_t kSegWords = kSegBits / 32;
+constexpr int kWave = 64;
+constexpr uint64_t kGroupMax = 1ull << 50;   // K-prime products stay below 2^50 (mulmod bound)
+
+// Counters in cs_diag order.
+enum DiagSlot {
+  D_NPRIMES = 0, D_SMALL_PRIMES, D_LARGE_PRIMES, D_SMALL_PAIRS, D_SMALL_MARKS,
+  D_LARGE_RAW, D_LARGE_HITS, D_G_CALLS, D_G_LEVELS, D_ERROR, D_COUNT
+};
+
+// Error bits set by device-side checks.
+enum ErrBits : uint32_t {
+  E_ROWS = 1, E_COLS = 2, E_SOLVE = 4, E_TIERS = 8, E_PRIMES = 16
+};
+
+// Written by the device during preparation; read by later kernels of the same job.
+struct JobCtrl {
+  uint64_t n_lim;                    // primes <= limit
+  uint64_t n_pP;                     // primes <= P
+  uint64_t small_lo, small_dense, small_hi;   // prime indices of the small branch
+  uint64_t tier_lo_idx;              // first prime index of tier 0
+  uint64_t tier_idx[kMaxTiers];      // one past the last prime index of tier t
+  uint64_t tier_item_base[kMaxTiers + 1];
+  uint64_t n_items;
+  uint32_t n_kgroups, n_kq, n_dq, error;
+  uint32_t n_base, pad0;
+  uint32_t dq[kMaxDq];
+  uint64_t mq[kMaxDq];               // m_start mod dq[i]
+  unsigned long long diag[D_COUNT];
+};
+
+// Everything a kernel needs about one job.  Lives in device memory (written by a one-thread
+// kernel that receives it as an argument, so no host-to-device copy is ever needed).
+struct JobDev {
+  uint64_t d, m_start, m_inc, limit, thr, p_lo, p_hi, n_m;
+  uint32_t P, sl, w, n_x, row_words, large_mode;
+  uint32_t tile_rows, n_windows, n_slices, hits_per_item;
+  uint64_t small_unit_base;          // first small-branch unit of this job in a fused launch
+  uint64_t dense_max;                // small primes <= dense_max are marked cooperatively
+  uint64_t prime_cap;                // capacity of the prime table
+  uint32_t n_tiers, pad1;
+  uint64_t tier_lo;                  // tier 0 holds primes in (tier_lo, tier_hi[0]]
+  uint64_t tier_hi[kMaxTiers];
+  uint32_t tier_chunks[kMaxTiers];
+  const uint64_t* primes;            // shared ascending prime table
+  const uint64_t* n_primes;          // its length (device scalar)
+  uint64_t* kmod;                    // K mod p per prime index (< n_lim)
+  uint64_t* mk;                      // m_start*K mod p per prime index
+  int32_t* row_of;                   // m - m_start -> row or -1
+  uint32_t* m_off;                   // row -> m - m_start
+  uint32_t* row_blk;                 // scan scratch for the row map
+  uint2* coltab;                     // per 32 offsets j = X + sl: {column mask, columns before}
+  uint64_t* kgroups;                 // products of the primes dividing K, each < 2^50
+  uint32_t* kq;                      // primes dividing K (q <= P, q not dividing d)
+  uint32_t* bitmap;
+  uint32_t* counts;
+  JobCtrl* ctrl;
+};
+
+}  // namespace cs

@@ -1,0 +1,860 @@
+// HIP kernels of the Combined Sieve for gfx950 (wave64, 256 CUs, fp64 at full VALU rate).
+//
+// Pipeline of one job (Sections 3.1-3.3 of the paper):
+//   primes  segmented sieve of Eratosthenes in LDS, compacted to an ascending table
+//   prep    primes dividing K grouped into products < 2^50; prime factors of d
+//   kmod    K mod p (the cached residue of Eq. 1) and m_start*K mod p per prime
+//   rows    m -> row map (gcd(m, d) = 1) and columns X -> column map (gcd(X, K) = 1)
+//   small   primes p <= thr: every (row, p) residue, offsets marked in LDS row tiles
+//   large   primes p >  thr: Eq. 3 solved by Eq. 5 from hit to hit, one atomic mark per hit
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "arith.h"
+#include "device.h"
+#include "launch.h"
+
+namespace cs {
+
+// ------------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// number of table entries <= x (table ascending)
+__device__ uint64_t upper_index(const uint64_t* t, uint64_t n, uint64_t x) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (t[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Block-wide exclusive scan of one uint32 per thread (blockDim.x <= 1024, multiple of 64).
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) sh[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t s = (lane < nw) ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      uint32_t y = __shfl_up(s, o, kWave);
+      if (lane >= o) s += y;
+    }
+    if (lane < nw) sh[lane] = s;           // inclusive per-wave totals
+  }
+  __syncthreads();
+  uint32_t before = (wid > 0 ? sh[wid - 1] : 0) + x - v;
+  if (total) *total = sh[nw - 1];
+  __syncthreads();
+  return before;
+}
+
+// ------------------------------------------------------------------------------------------
+// small kernels
+// ------------------------------------------------------------------------------------------
+__global__ void k_write_job(JobDev jd, JobDev* dst) { *dst = jd; }
+
+struct UploadChunk {
+  uint8_t bytes[2048];
+};
+__global__ void k_upload(UploadChunk c, uint8_t* dst, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.bytes[i];
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t s = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += s) p[i] = v;
+}
+
+__global__ void k_zero_ctrl(JobCtrl* c) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < sizeof(JobCtrl) / 4; i += blockDim.x) w[i] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Prime table: segmented sieve of Eratosthenes, odd numbers only.
+// Segment s covers [s*2^19, (s+1)*2^19); bit i stands for n = s*2^19 + 2i + 1.
+// ------------------------------------------------------------------------------------------
+
+// Odd base primes <= isqrt(lim) (lim < 2^40, so < 2^20), one workgroup, LDS bit sieve.
+// The 64 KB bit array is the whole LDS budget, so the compaction first moves each thread's
+// words to registers and then reuses the array's head as scan scratch.
+__global__ __launch_bounds__(1024) void k_base_primes(uint64_t lim, uint32_t* base, uint32_t* n_base) {
+  constexpr uint32_t kWords = (1u << 19) / 32;              // odd numbers below 2^20
+  constexpr uint32_t kPer = kWords / 1024;                  // 16 words per thread
+  __shared__ uint32_t bits[kWords];
+  uint64_t root = (uint64_t)sqrt((double)lim);
+  while (root * root > lim) --root;
+  while ((root + 1) * (root + 1) <= lim) ++root;
+  const uint32_t nb = (uint32_t)((root + 1) / 2);           // bits for 1, 3, ..., <= root
+  const uint32_t nw = (nb + 31) / 32;
+  for (uint32_t i = threadIdx.x; i < kWords; i += blockDim.x) bits[i] = 0;
+  __syncthreads();
+  for (uint32_t q = 3; (uint64_t)q * q <= root; q += 2) {
+    bool comp = (bits[(q >> 1) >> 5] >> ((q >> 1) & 31)) & 1;   // uniform read after barrier
+    if (!comp) {
+      for (uint64_t n = (uint64_t)q * q + 2ull * q * threadIdx.x; n <= root; n += 2ull * q * blockDim.x) {
+        uint32_t b = (uint32_t)(n >> 1);
+        atomicOr(&bits[b >> 5], 1u << (b & 31));
+      }
+    }
+    __syncthreads();
+  }
+  // bit b unmarked with 3 <= 2b+1 <= root is an odd prime
+  uint32_t mine[kPer];
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < kPer; ++t) {
+    const uint32_t u = threadIdx.x * kPer + t;
+    uint32_t m = 0;
+    if (u < nw) {
+      m = ~bits[u];
+      if (u == 0) m &= ~1u;                                  // n = 1
+      if (u == nw - 1 && (nb & 31)) m &= (1u << (nb & 31)) - 1;
+    }
+    mine[t] = m;
+    c += __popc(m);
+  }
+  __syncthreads();                                           // bits[] is free from here on
+  uint32_t tot;
+  uint32_t off = block_exclusive_scan(c, bits, &tot);
+#pragma unroll
+  for (uint32_t t = 0; t < kPer; ++t) {
+    uint32_t m = mine[t];
+    const uint32_t u = threadIdx.x * kPer + t;
+    while (m) {
+      uint32_t b = __ffs(m) - 1;
+      m &= m - 1;
+      base[off++] = 2 * (u * 32 + b) + 1;
+    }
+  }
+  if (threadIdx.x == 0) *n_base = tot;
+}
+
+// One workgroup per segment: mark odd composites in LDS, write prime flags and the count.
+__global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n_seg,
+                                                        const uint32_t* __restrict__ base,
+                                                        const uint32_t* __restrict__ n_base_p,
+                                                        uint32_t* __restrict__ flags,
+                                                        uint32_t* __restrict__ seg_count) {
+  __shared__ uint32_t bits[kSegWords];
+  __shared__ uint32_t sh[32];
+  const uint32_t n_base = *n_base_p;
+  for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+    const uint64_t lo = s << kSegLog;
+    const uint64_t hi = min(lo + (1ull << kSegLog) - 1, lim);     // inclusive
+    for (uint32_t i = threadIdx.x; i < kSegWords; i += blockDim.x) bits[i] = 0;
+    __syncthreads();
+    const uint32_t nbits = (uint32_t)((hi - lo + 1) / 2);          // bits standing for n <= hi
+    const double dlo = (double)lo;
+    // dense base primes: the whole workgroup strides over the multiples of each
+    uint32_t i = 0;
+    for (; i < n_base; ++i) {
+      const uint64_t q = base[i];
+      if (q * q > hi || q >= 4096) break;
+      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;         // exact: lo < 2^40
+      if (st < q * q) st = q * q;
+      if ((st & 1) == 0) st += q;
+      if (st > hi) continue;
+      const uint32_t b0 = (uint32_t)((st - lo) >> 1);
+      for (uint32_t b = b0 + threadIdx.x * (uint32_t)q; b < nbits; b += blockDim.x * (uint32_t)q)
+        atomicOr(&bits[b >> 5], 1u << (b & 31));
+    }
+    // sparse base primes: one thread per prime
+    for (uint32_t j = i + threadIdx.x; j < n_base; j += blockDim.x) {
+      const uint64_t q = base[j];
+      if (q * q > hi) continue;
+      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;
+      if (st < q * q) st = q * q;
+      if ((st & 1) == 0) st += q;
+      for (uint64_t b = (st - lo) >> 1; b < nbits; b += q)
+        atomicOr(&bits[b >> 5], 1u << (b & 31));
+    }
+    __syncthreads();
+    uint32_t c = 0;
+    for (uint32_t u = threadIdx.x; u < kSegWords; u += blockDim.x) {
+      uint32_t m = ~bits[u];
+      if (s == 0 && u == 0) m &= ~1u;                               // n = 1 is not prime
+      const uint32_t first = u * 32;
+      if (first >= nbits) m = 0;
+      else if (nbits - first < 32) m &= (1u << (nbits - first)) - 1;
+      flags[s * kSegWords + u] = m;
+      c += __popc(m);
+    }
+    uint32_t tot;
+    block_exclusive_scan(c, sh, &tot);
+    if (threadIdx.x == 0) seg_count[s] = tot + ((s == 0 && lim >= 2) ? 1u : 0u);   // the prime 2
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of segment counts (one workgroup, loops over chunks).
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, uint64_t n,
+                                                      uint64_t* __restrict__ off, uint64_t* total) {
+  __shared__ uint32_t sh[32];
+  uint64_t carry = 0;
+  for (uint64_t b = 0; b < n; b += blockDim.x) {
+    uint64_t i = b + threadIdx.x;
+    uint32_t v = i < n ? cnt[i] : 0;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(v, sh, &tot);
+    if (i < n) off[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_compact_primes(uint64_t n_seg, const uint32_t* __restrict__ flags,
+                                                        const uint64_t* __restrict__ off,
+                                                        uint64_t* __restrict__ primes, uint64_t cap) {
+  __shared__ uint32_t sh[32];
+  constexpr uint32_t per = kSegWords / 256;                 // 32 words per thread
+  for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+    const uint32_t* f = flags + s * kSegWords + threadIdx.x * per;
+    uint32_t c = 0;
+    for (uint32_t u = 0; u < per; ++u) c += __popc(f[u]);
+    uint32_t tot;
+    uint64_t pos = off[s] + block_exclusive_scan(c, sh, &tot);
+    if (s == 0) {
+      if (threadIdx.x == 0 && cap > 0) primes[0] = 2;
+      pos += 1;
+    }
+    const uint64_t lo = s << kSegLog;
+    for (uint32_t u = 0; u < per; ++u) {
+      uint32_t m = f[u];
+      const uint32_t word = threadIdx.x * per + u;
+      while (m) {
+        uint32_t b = __ffs(m) - 1;
+        m &= m - 1;
+        if (pos < cap) primes[pos] = lo + 2ull * (word * 32 + b) + 1;
+        ++pos;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Job preparation
+// ------------------------------------------------------------------------------------------
+
+// One thread: primes dividing K grouped into products < 2^50, prime factors of d, and
+// m_start mod each of them.
+__global__ void k_prep_tables(JobDev* jp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  JobDev& j = *jp;
+  JobCtrl& c = *j.ctrl;
+  uint64_t np = *j.n_primes;
+  if (np > j.prime_cap) {
+    atomicOr(&c.error, (uint32_t)E_PRIMES);
+    np = j.prime_cap;
+  }
+  c.n_pP = upper_index(j.primes, np, j.P);
+  c.n_lim = upper_index(j.primes, np, j.limit);
+  uint64_t g = 1;
+  uint32_t ng = 0, nkq = 0, ndq = 0;
+  for (uint64_t i = 0; i < c.n_pP; ++i) {
+    const uint64_t q = j.primes[i];
+    if (j.d % q == 0) {
+      if (ndq < kMaxDq) { c.dq[ndq] = (uint32_t)q; c.mq[ndq] = j.m_start % q; }
+      ++ndq;
+      continue;
+    }
+    j.kq[nkq++] = (uint32_t)q;
+    if (g > (kGroupMax - 1) / q) { j.kgroups[ng++] = g; g = q; }
+    else g *= q;
+  }
+  if (g > 1) j.kgroups[ng++] = g;
+  c.n_kgroups = ng;
+  c.n_kq = nkq;
+  c.n_dq = ndq;
+  c.diag[D_NPRIMES] = np;
+}
+
+// K mod p and m_start*K mod p for every prime index < n_lim (Eq. 1's cached residue).
+__global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jp) {
+  const JobDev& j = *jp;
+  const uint64_t n = j.ctrl->n_lim;
+  const uint32_t ng = j.ctrl->n_kgroups;
+  const uint64_t* __restrict__ G = j.kgroups;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = j.primes[i];
+    const double pinv = 1.0 / (double)p;
+    uint64_t r = 1 % p;
+    for (uint32_t g = 0; g < ng; ++g) r = mulmod(r, G[g], p, pinv);
+    j.kmod[i] = r;
+    j.mk[i] = mulmod(mod64(j.m_start, p, pinv), r, p, pinv);
+  }
+}
+
+// Stand-alone K mod p for the cs_kmod entry point.
+__global__ __launch_bounds__(256) void k_kmod_list(const uint64_t* __restrict__ primes, uint64_t n,
+                                                   const uint64_t* __restrict__ G, uint32_t ng,
+                                                   uint64_t* __restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = primes[i];
+    const double pinv = 1.0 / (double)p;
+    uint64_t r = 1 % p;
+    for (uint32_t g = 0; g < ng; ++g) r = mulmod(r, G[g], p, pinv);
+    out[i] = r;
+  }
+}
+
+__device__ __forceinline__ bool m_coprime(const JobCtrl& c, uint64_t o) {
+  const uint32_t nd = c.n_dq < kMaxDq ? c.n_dq : kMaxDq;
+  for (uint32_t t = 0; t < nd; ++t)
+    if ((c.mq[t] + o) % c.dq[t] == 0) return false;
+  return true;
+}
+
+constexpr uint32_t kRowBlock = 1024;
+
+__global__ __launch_bounds__(256) void k_rows_count(const JobDev* __restrict__ jp) {
+  __shared__ uint32_t sh[32];
+  const JobDev& j = *jp;
+  const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
+  for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    uint32_t c = 0;
+    for (uint32_t t = threadIdx.x; t < kRowBlock; t += blockDim.x) {
+      uint64_t o = b * kRowBlock + t;
+      if (o < j.m_inc && m_coprime(*j.ctrl, o)) ++c;
+    }
+    uint32_t tot;
+    block_exclusive_scan(c, sh, &tot);
+    if (threadIdx.x == 0) j.row_blk[b] = tot;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_rows_scan(const JobDev* __restrict__ jp) {
+  __shared__ uint32_t sh[32];
+  const JobDev& j = *jp;
+  const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
+  uint64_t carry = 0;
+  for (uint64_t b = 0; b < nb; b += blockDim.x) {
+    uint64_t i = b + threadIdx.x;
+    uint32_t v = i < nb ? j.row_blk[i] : 0;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(v, sh, &tot);
+    if (i < nb) j.row_blk[i] = (uint32_t)(carry + ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && carry != j.n_m) atomicOr(&j.ctrl->error, (uint32_t)E_ROWS);
+}
+
+__global__ __launch_bounds__(1024) void k_rows_write(const JobDev* __restrict__ jp) {
+  __shared__ uint32_t sh[32];
+  const JobDev& j = *jp;
+  const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
+  for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint64_t o = b * kRowBlock + threadIdx.x;
+    const bool ok = o < j.m_inc && m_coprime(*j.ctrl, o);
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(ok ? 1u : 0u, sh, &tot);
+    const uint32_t row = j.row_blk[b] + ex;
+    if (o < j.m_inc) j.row_of[o] = ok ? (int32_t)row : -1;
+    if (ok && row < j.n_m) j.m_off[row] = (uint32_t)o;
+  }
+}
+
+// Column table: j = X + sl in [0, 2 sl]; X is a column iff gcd(X, K) = 1.
+__global__ __launch_bounds__(256) void k_cols_mask(const JobDev* __restrict__ jp) {
+  const JobDev& j = *jp;
+  const uint32_t S = 2 * j.sl + 1;
+  const uint32_t nkq = j.ctrl->n_kq;
+  const uint32_t nwords = (S + 31) / 32;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nwords * 32; base += gridDim.x * blockDim.x) {
+    const uint32_t jj = base + threadIdx.x;
+    bool col = false;
+    if (jj < S) {
+      const int64_t X = (int64_t)jj - (int64_t)j.sl;
+      const uint64_t ax = (uint64_t)(X < 0 ? -X : X);
+      if (ax == 0) {
+        col = (nkq == 0);                       // gcd(0, K) = K
+      } else {
+        col = true;
+        for (uint32_t t = 0; t < nkq; ++t) {
+          const uint32_t q = j.kq[t];
+          if (q > ax) break;
+          if (ax % q == 0) { col = false; break; }
+        }
+      }
+    }
+    const uint64_t bal = __ballot(col);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (lane == 0 || lane == 32) {
+      const uint32_t word = jj / 32;
+      if (word < nwords) j.coltab[word].x = (uint32_t)(bal >> lane);
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_cols_prefix(const JobDev* __restrict__ jp) {
+  __shared__ uint32_t sh[32];
+  const JobDev& j = *jp;
+  const uint32_t nwords = (2 * j.sl + 1 + 31) / 32;
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < nwords; b += blockDim.x) {
+    const uint32_t i = b + threadIdx.x;
+    const uint32_t v = i < nwords ? __popc(j.coltab[i].x) : 0;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, sh, &tot);
+    if (i < nwords) j.coltab[i].y = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && carry != j.n_x) atomicOr(&j.ctrl->error, (uint32_t)E_COLS);
+}
+
+// Prime-index bounds of the branches and the large-branch work items of one job.
+__global__ void k_prep_bounds(JobDev* jp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  JobDev& j = *jp;
+  JobCtrl& c = *j.ctrl;
+  const uint64_t n = c.n_lim;
+  const uint64_t* pr = j.primes;
+  const uint64_t lo = j.p_lo > 2 ? j.p_lo : 2;
+  const uint64_t hi = j.p_hi < j.limit ? j.p_hi : j.limit;
+  const uint64_t small_hi_v = hi < j.thr ? hi : j.thr;
+  c.small_lo = upper_index(pr, n, lo - 1);
+  c.small_hi = (small_hi_v >= lo) ? upper_index(pr, n, small_hi_v) : c.small_lo;
+  uint64_t dm = j.dense_max < small_hi_v ? j.dense_max : small_hi_v;
+  c.small_dense = (dm >= lo) ? upper_index(pr, n, dm) : c.small_lo;
+  if (c.small_dense > c.small_hi) c.small_dense = c.small_hi;
+  if (c.small_dense < c.small_lo) c.small_dense = c.small_lo;
+  c.tier_lo_idx = upper_index(pr, n, j.tier_lo);
+  uint64_t prev = c.tier_lo_idx, items = 0;
+  for (uint32_t t = 0; t < j.n_tiers; ++t) {
+    uint64_t e = upper_index(pr, n, j.tier_hi[t]);
+    if (e < prev) e = prev;
+    c.tier_idx[t] = e;
+    c.tier_item_base[t] = items;
+    items += (e - prev) * (uint64_t)j.tier_chunks[t];
+    prev = e;
+  }
+  c.tier_item_base[j.n_tiers] = items;
+  c.n_items = items;
+  c.diag[D_SMALL_PRIMES] += c.small_hi - c.small_lo;
+  c.diag[D_LARGE_PRIMES] += prev - c.tier_lo_idx;
+}
+
+// Prefix of large-branch item counts over the jobs of a launch.
+__global__ void k_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t s = 0;
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    base[i] = s;
+    s += jobs[i].ctrl->n_items;
+  }
+  base[n_jobs] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Small-prime branch (Section 3.1 space-time tradeoff; Section 5: p/S < C_mult).
+// One unit = (job, window of tile_rows consecutive rows, prime slice).  For every row and
+// prime, N mod p = m*K mod p comes from the cached K mod p (Eq. 1), and the offsets
+// X = -N (mod p) of the window are marked in an LDS tile of packed column bits.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool lookup_col(const uint2* ct, uint32_t jj, uint32_t* col) {
+  const uint2 e = ct[jj >> 5];
+  const uint32_t b = jj & 31;
+  if (!((e.x >> b) & 1u)) return false;
+  *col = e.y + __popc(e.x & ((1u << b) - 1u));
+  return true;
+}
+
+__device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t p) {
+  return a >= b ? a - b : a + p - b;
+}
+
+__global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, uint32_t n_jobs,
+                                               uint64_t total_units, uint32_t lds_ct_words) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const uint32_t nwaves = blockDim.x / kWave;
+  unsigned long long n_pairs = 0, n_marks = 0;
+  for (uint64_t unit = blockIdx.x; unit < total_units; unit += gridDim.x) {
+    uint32_t ji = 0;
+    while (ji + 1 < n_jobs && jobs[ji + 1].small_unit_base <= unit) ++ji;
+    const JobDev& j = jobs[ji];
+    const JobCtrl& c = *j.ctrl;
+    const uint64_t local = unit - j.small_unit_base;
+    const uint64_t window = local / j.n_slices;
+    const uint32_t slice = (uint32_t)(local % j.n_slices);
+    const uint64_t row_lo = window * j.tile_rows;
+    const uint64_t row_hi = min(row_lo + j.tile_rows, j.n_m);
+    const uint32_t R = (uint32_t)(row_hi - row_lo);
+    const uint32_t rw = j.row_words;
+    const uint32_t w = j.w;
+    // prime slice
+    const uint64_t span = c.small_hi - c.small_lo;
+    const uint64_t s_lo = c.small_lo + span * slice / j.n_slices;
+    const uint64_t s_hi = c.small_lo + span * (slice + 1) / j.n_slices;
+    // LDS: [column table][tile R x rw][counts R]
+    const uint32_t nct = (2 * j.sl + 1 + 31) / 32;
+    const bool ct_in_lds = nct <= lds_ct_words;
+    uint2* ct_l = reinterpret_cast<uint2*>(lds);
+    uint32_t* tile = lds + 2 * lds_ct_words;
+    uint32_t* cnt = tile + (uint32_t)j.tile_rows * rw;
+    if (ct_in_lds)
+      for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = j.coltab[i];
+    for (uint32_t i = threadIdx.x; i < R * rw; i += blockDim.x) tile[i] = 0;
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const uint2* ct = ct_in_lds ? ct_l : j.coltab;
+
+    // dense primes: one wave per prime, lanes stride over its multiples in each row
+    const uint64_t d_hi = min(s_hi, max(c.small_dense, s_lo));
+    for (uint64_t i = s_lo + wid; i < d_hi; i += nwaves) {
+      const uint64_t p = j.primes[i];
+      const uint64_t k = j.kmod[i];
+      if (k == 0) continue;                         // p | K: never divides a column's N + X
+      const double pinv = 1.0 / (double)p;
+      const uint64_t mk = j.mk[i];
+      const uint64_t slp = mod64(j.sl, p, pinv);
+      for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t o = j.m_off[row_lo + r];
+        uint64_t rn = mk + mulmod(o, k, p, pinv);
+        rn = rn >= p ? rn - p : rn;                 // N mod p
+        const uint64_t s0 = sub_mod(slp, rn, p);    // first offset j = X + sl with p | N + X
+        uint32_t cc = 0;
+        for (uint64_t jj = s0 + (uint64_t)lane * p; jj <= w; jj += (uint64_t)kWave * p) {
+          uint32_t col;
+          if (lookup_col(ct, (uint32_t)jj, &col)) {
+            atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+            ++cc;
+          }
+        }
+        cc = wave_sum_u32(cc);
+        if (lane == 0) {
+          if (cc) atomicAdd(&cnt[r], cc);
+          n_pairs += 1;
+          n_marks += cc;
+        }
+      }
+    }
+    // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
+    const uint64_t sp_lo = max(s_lo, min(c.small_dense, s_hi));
+    for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
+      const uint64_t i = ib + threadIdx.x;
+      bool act = i < s_hi;
+      uint64_t p = 3, k = 0, mk = 0;
+      if (act) { p = j.primes[i]; k = j.kmod[i]; mk = j.mk[i]; }
+      act = act && k != 0;
+      const double pinv = 1.0 / (double)p;
+      uint64_t s = 0;
+      uint32_t o_prev = 0;
+      if (R > 0) {
+        o_prev = j.m_off[row_lo];
+        uint64_t rn = mk + mulmod(o_prev, k, p, pinv);
+        rn = rn >= p ? rn - p : rn;
+        s = sub_mod(mod64(j.sl, p, pinv), rn, p);
+      }
+      for (uint32_t r = 0; r < R; ++r) {
+        if (r > 0) {
+          const uint32_t o = j.m_off[row_lo + r];
+          const uint32_t dm = o - o_prev;           // same for every lane
+          o_prev = o;
+          if (dm <= 12) {
+            for (uint32_t t = 0; t < dm; ++t) s = sub_mod(s, k, p);
+          } else {
+            s = sub_mod(s, mulmod(dm, k, p, pinv), p);
+          }
+        }
+        uint32_t cc = 0;
+        if (act) {
+          for (uint64_t jj = s; jj <= w; jj += p) {
+            uint32_t col;
+            if (lookup_col(ct, (uint32_t)jj, &col)) {
+              atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+              ++cc;
+            }
+          }
+        }
+        const uint32_t na = (uint32_t)__popcll(__ballot(act));
+        cc = wave_sum_u32(cc);
+        if (lane == 0) {
+          if (cc) atomicAdd(&cnt[r], cc);
+          n_pairs += na;
+          n_marks += cc;
+        }
+      }
+    }
+    __syncthreads();
+    // write the tile: rows of this unit belong to it alone unless the primes are sliced
+    for (uint32_t r = 0; r < R; ++r) {
+      uint32_t* dst = j.bitmap + (row_lo + r) * (uint64_t)rw;
+      for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) {
+        const uint32_t v = tile[r * rw + u];
+        if (!v) continue;
+        if (j.n_slices == 1) dst[u] |= v;
+        else atomicOr(&dst[u], v);
+      }
+    }
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
+      const uint32_t v = cnt[r];
+      if (!v) continue;
+      if (j.n_slices == 1) j.counts[row_lo + r] += v;
+      else atomicAdd(&j.counts[row_lo + r], v);
+    }
+    __syncthreads();
+  }
+  if (lane == 0 && n_jobs > 0) {
+    atomicAdd(&jobs[0].ctrl->diag[D_SMALL_PAIRS], n_pairs);
+    atomicAdd(&jobs[0].ctrl->diag[D_SMALL_MARKS], n_marks);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Large-prime branch (Section 3.2-3.3).  One item = (job, prime, chunk of the m range).
+// From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
+// G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void record_hit(const JobDev& j, uint64_t o, uint32_t jj,
+                                           unsigned long long& useful) {
+  const int32_t row = j.row_of[o];
+  if (row < 0) return;                             // m shares a factor with d (Section 3.2)
+  uint32_t col;
+  if (!lookup_col(j.coltab, jj, &col)) return;     // X shares a factor with K
+  atomicOr(&j.bitmap[(uint64_t)row * j.row_words + (col >> 5)], 1u << (col & 31));
+  atomicAdd(&j.counts[row], 1u);
+  ++useful;
+}
+
+__global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
+                                               const uint64_t* __restrict__ job_item_base,
+                                               unsigned long long* __restrict__ diag) {
+  const uint64_t total = job_item_base[n_jobs];
+  unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
+  uint32_t err = 0;
+  for (uint64_t item = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; item < total;
+       item += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t ji = 0;
+    while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
+    const JobDev& j = jobs[ji];
+    const JobCtrl& c = *j.ctrl;
+    const uint64_t local = item - job_item_base[ji];
+    uint32_t t = 0;
+    while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
+    const uint64_t li = local - c.tier_item_base[t];
+    const uint32_t C = j.tier_chunks[t];
+    const uint64_t pi = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]) + li / C;
+    const uint32_t chunk = (uint32_t)(li % C);
+    const uint64_t L = (j.m_inc + C - 1) / C;
+    const uint64_t o_lo = (uint64_t)chunk * L;
+    const uint64_t o_hi = min(o_lo + L, j.m_inc);
+    if (o_lo >= o_hi) continue;
+
+    const uint64_t p = j.primes[pi];
+    const uint64_t k = j.kmod[pi];
+    const double pinv = 1.0 / (double)p;
+    const uint64_t w = j.w;
+    const uint64_t kinv = modinv(k, p);
+    // residue of m*K + SL at m = m_start + o_lo
+    uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
+    r = r >= p ? r - p : r;
+    r += mod64(j.sl, p, pinv);
+    r = r >= p ? r - p : r;
+    uint64_t o = o_lo;
+
+    if (j.large_mode == 0) {
+      // one solve of Eq. 3 per hit
+      while (true) {
+        if (r > w) {
+          int lv = 0;
+          uint64_t rn;
+          const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+          ++calls;
+          levels += (unsigned)lv;
+          if (tstep == 0) { err |= E_SOLVE; break; }
+          o += tstep;
+          if (o >= o_hi) break;
+          r = rn;
+        }
+        ++raw;
+        record_hit(j, o, (uint32_t)(w - r), useful);
+        if (++o >= o_hi) break;
+        r += k;
+        r = r >= p ? r - p : r;
+      }
+    } else {
+      // three-gap stepping: solve for the first hit and the two return times only
+      gaps3 g;
+      int lv = 0;
+      if (!three_gap_setup(p, k, kinv, pinv, w, &g, &lv)) { err |= E_SOLVE; continue; }
+      calls += 2;
+      levels += (unsigned)lv;
+      if (r > w) {
+        uint64_t rn;
+        lv = 0;
+        const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+        ++calls;
+        levels += (unsigned)lv;
+        if (tstep == 0) { err |= E_SOLVE; continue; }
+        o += tstep;
+        r = rn;
+      }
+      const bool a_first = g.ta < g.tb;
+      while (o < o_hi) {
+        ++raw;
+        record_hit(j, o, (uint32_t)(w - r), useful);
+        const bool fa = r + g.a <= w, fb = r >= g.b;
+        if (fa && (a_first || !fb)) { o += g.ta; r += g.a; }
+        else if (fb) { o += g.tb; r -= g.b; }
+        else { o += g.ta + g.tb; r = r + g.a - g.b; }
+      }
+    }
+  }
+  raw = wave_sum_u64(raw);
+  useful = wave_sum_u64(useful);
+  calls = wave_sum_u64(calls);
+  levels = wave_sum_u64(levels);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicAdd(&diag[D_LARGE_RAW], raw);
+    atomicAdd(&diag[D_LARGE_HITS], useful);
+    atomicAdd(&diag[D_G_CALLS], calls);
+    atomicAdd(&diag[D_G_LEVELS], levels);
+  }
+  if (err) atomicOr(reinterpret_cast<unsigned long long*>(&diag[D_ERROR]), (unsigned long long)err);
+}
+
+// ------------------------------------------------------------------------------------------
+// launch wrappers (host)
+// ------------------------------------------------------------------------------------------
+static thread_local char g_last_error[256];
+
+// Records the failing kernel's name with the runtime's message; returns the error.
+static hipError_t note(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+  return e;
+}
+
+const char* last_error_detail() { return g_last_error; }
+
+hipError_t launch_write_job(const JobDev& jd, JobDev* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_job, dim3(1), dim3(1), 0, s, jd, dst); { hipError_t e_ = note("k_write_job"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
+  const uint8_t* in = static_cast<const uint8_t*>(src);
+  uint8_t* out = static_cast<uint8_t*>(dst);
+  for (uint64_t at = 0; at < bytes; at += sizeof(UploadChunk)) {
+    UploadChunk c;
+    const uint32_t n = (uint32_t)((bytes - at) < sizeof(c) ? (bytes - at) : sizeof(c));
+    memcpy(c.bytes, in + at, n);
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, c, out + at, n); { hipError_t e_ = note("k_upload"); if (e_ != hipSuccess) return e_; }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v); { hipError_t e_ = note("k_fill_u32"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ctrl(JobCtrl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, s, c); { hipError_t e_ = note("k_zero_ctrl"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s) {
+  hipLaunchKernelGGL(k_base_primes, dim3(1), dim3(1024), 0, s, lim, pw.base, pw.n_base); { hipError_t e_ = note("k_base_primes"); if (e_ != hipSuccess) return e_; }
+  const uint64_t n_seg = (lim >> kSegLog) + 1;
+  uint32_t blocks = (uint32_t)(n_seg < 8192 ? n_seg : 8192);
+  hipLaunchKernelGGL(k_sieve_segments, dim3(blocks), dim3(512), 0, s, lim, n_seg, pw.base, pw.n_base,
+                     pw.flags, pw.seg_count); { hipError_t e_ = note("k_sieve_segments"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pw.seg_count, n_seg, pw.seg_off, pw.n_primes); { hipError_t e_ = note("k_scan_counts"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_compact_primes, dim3(blocks), dim3(256), 0, s, n_seg, pw.flags, pw.seg_off,
+                     pw.primes, pw.cap); { hipError_t e_ = note("k_compact_primes"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_tables(JobDev* jd, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_tables, dim3(1), dim3(64), 0, s, jd); { hipError_t e_ = note("k_prep_tables"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_kmod(const JobDev* jd, uint64_t cap, int n_cu, hipStream_t s) {
+  uint64_t blocks = (cap + 255) / 256;
+  uint64_t maxb = (uint64_t)n_cu * 32;
+  if (blocks > maxb) blocks = maxb;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_kmod, dim3((uint32_t)blocks), dim3(256), 0, s, jd); { hipError_t e_ = note("k_kmod"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_kmod_list(const uint64_t* primes, uint64_t n, const uint64_t* groups, uint32_t ng,
+                            uint64_t* out, int n_cu, hipStream_t s) {
+  uint64_t blocks = (n + 255) / 256;
+  uint64_t maxb = (uint64_t)n_cu * 32;
+  if (blocks > maxb) blocks = maxb;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_kmod_list, dim3((uint32_t)blocks), dim3(256), 0, s, primes, n, groups, ng, out); { hipError_t e_ = note("k_kmod_list"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_cols(const JobDev* jd, uint64_t m_inc, uint32_t sl, int n_cu, hipStream_t s) {
+  const uint64_t nb = (m_inc + kRowBlock - 1) / kRowBlock;
+  uint32_t blocks = (uint32_t)(nb < (uint64_t)n_cu * 16 ? nb : (uint64_t)n_cu * 16);
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_rows_count, dim3(blocks), dim3(256), 0, s, jd); { hipError_t e_ = note("k_rows_count"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_rows_scan"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_rows_write, dim3(blocks), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_rows_write"); if (e_ != hipSuccess) return e_; }
+  const uint32_t nwords = (2 * sl + 1 + 31) / 32;
+  uint32_t cb = (nwords * 32 + 255) / 256;
+  if (cb > 4096) cb = 4096;
+  hipLaunchKernelGGL(k_cols_mask, dim3(cb), dim3(256), 0, s, jd); { hipError_t e_ = note("k_cols_mask"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_cols_prefix, dim3(1), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_cols_prefix"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_bounds(JobDev* jd, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_bounds, dim3(1), dim3(64), 0, s, jd); { hipError_t e_ = note("k_prep_bounds"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s) {
+  hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(64), 0, s, jobs, n_jobs, base); { hipError_t e_ = note("k_items_scan"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
+                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s) {
+  if (total_units == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_small, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, total_units, lds_ct_words); { hipError_t e_ = note("k_small"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
+                        unsigned long long* diag, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_large, dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag); { hipError_t e_ = note("k_large"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+}  // namespace cs

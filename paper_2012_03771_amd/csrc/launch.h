@@ -1,0 +1,44 @@
+// Host-side launch wrappers of the kernels (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace cs {
+
+// Scratch of the segmented prime sieve.
+struct PrimeWs {
+  uint32_t* base;       // odd primes <= 2^20
+  uint32_t* n_base;     // device scalar
+  uint32_t* flags;      // n_seg * kSegWords prime flags
+  uint32_t* seg_count;  // n_seg
+  uint64_t* seg_off;    // n_seg
+  uint64_t* primes;     // output table
+  uint64_t* n_primes;   // device scalar
+  uint64_t cap;
+};
+
+// Name and message of the last failed launch in this thread (empty if none).
+const char* last_error_detail();
+
+hipError_t launch_write_job(const JobDev& jd, JobDev* dst, hipStream_t s);
+// Copies a small host table to device memory through kernel arguments (2 KB per launch):
+// no pinned staging buffer and nothing that a graph capture would reject.
+hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_zero_ctrl(JobCtrl* c, hipStream_t s);
+hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s);
+hipError_t launch_prep_tables(JobDev* jd, hipStream_t s);
+hipError_t launch_kmod(const JobDev* jd, uint64_t cap, int n_cu, hipStream_t s);
+hipError_t launch_kmod_list(const uint64_t* primes, uint64_t n, const uint64_t* groups, uint32_t ng,
+                            uint64_t* out, int n_cu, hipStream_t s);
+hipError_t launch_rows_cols(const JobDev* jd, uint64_t m_inc, uint32_t sl, int n_cu, hipStream_t s);
+hipError_t launch_prep_bounds(JobDev* jd, hipStream_t s);
+hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s);
+hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
+                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
+hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
+                        unsigned long long* diag, uint32_t blocks, hipStream_t s);
+
+}  // namespace cs

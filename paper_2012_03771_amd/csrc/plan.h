@@ -1,0 +1,64 @@
+// Host-side job planning: validation, row/column counts, workspace layout, work decomposition.
+#pragma once
+#include <stdint.h>
+#include <vector>
+
+#include "../../include/csieve.h"
+#include "device.h"
+
+namespace cs {
+
+constexpr uint32_t kMaxSl = (1u << 17) - 1;     // a packed row (<= 2^18 bits) fits an LDS tile
+constexpr uint64_t kMaxLimit = 1ull << 40;
+constexpr uint32_t kMaxP = 1u << 24;
+constexpr uint64_t kMaxMInc = 1ull << 32;
+constexpr uint32_t kSmallBlock = 512;
+constexpr uint32_t kLargeBlock = 256;
+constexpr uint32_t kLdsBudget = 64 * 1024;
+constexpr uint32_t kLdsCtMax = 32 * 1024;
+constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024) plus slack
+
+struct WsLayout {
+  uint64_t ctrl, jobdev, items_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
+      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, total;
+};
+
+struct Plan {
+  cs_job job;
+  uint64_t Lp;              // max(limit, P): extent of the prime table
+  uint64_t n_seg;
+  uint64_t cap;             // prime table capacity
+  uint64_t n_m;
+  uint32_t n_x, row_words, S, ct_words;
+  uint32_t w;
+  uint64_t thr;
+  uint32_t large_mode;
+  uint32_t tile_rows, n_windows, n_slices;
+  uint32_t hits_per_item;
+  uint32_t large_blocks, small_blocks;
+  uint32_t lds_bytes, lds_ct_words;
+  uint64_t dense_max;
+  std::vector<uint32_t> kq;         // primes dividing K
+  std::vector<uint32_t> dq;         // primes dividing d
+  WsLayout ws;
+};
+
+// Upper bound of pi(x).
+uint64_t pi_upper(uint64_t x);
+
+// Validates the job and fills everything except the range-dependent tiers.
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out);
+
+// Host count of rows and columns (also used by cs_rows / cs_columns).
+void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs);
+uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq);
+
+// Fills the range-dependent part of a job descriptor (tiers for primes in (max(thr, p_lo-1), p_hi]).
+void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd);
+
+// Job descriptor with pointers into a workspace at `ws` (outputs left null).
+JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const uint64_t* n_primes);
+
+int device_cu_count();
+
+}  // namespace cs

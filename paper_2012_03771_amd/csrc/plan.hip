@@ -1,0 +1,268 @@
+// Host-side planning for the Combined Sieve library.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "plan.h"
+
+namespace cs {
+
+typedef unsigned __int128 u128;
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+uint64_t pi_upper(uint64_t x) {
+  if (x < 17) return 7;
+  const double lx = log((double)x);
+  double b;
+  if (x >= 355991) b = (double)x / lx * (1.0 + 1.0 / lx + 2.51 / (lx * lx));   // Dusart 2010
+  else b = 1.25506 * (double)x / lx;                                            // Rosser-Schoenfeld
+  return (uint64_t)b + 64;
+}
+
+static std::vector<uint32_t> host_primes_upto(uint32_t n) {
+  std::vector<uint8_t> comp(n + 1, 0);
+  std::vector<uint32_t> out;
+  for (uint64_t i = 2; i <= n; ++i) {
+    if (comp[i]) continue;
+    out.push_back((uint32_t)i);
+    for (uint64_t j = i * i; j <= n; j += i) comp[j] = 1;
+  }
+  return out;
+}
+
+void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs) {
+  const uint32_t sl = job.sl;
+  std::vector<uint8_t> bad(2 * (size_t)sl + 1, 0);
+  for (uint32_t q : kq) {
+    if (q > sl) break;
+    for (uint64_t x = q; x <= sl; x += q) {
+      bad[sl + x] = 1;
+      bad[sl - x] = 1;
+    }
+  }
+  if (!kq.empty()) bad[sl] = 1;    // gcd(0, K) = K > 1
+  xs->clear();
+  for (uint64_t i = 0; i < bad.size(); ++i)
+    if (!bad[i]) xs->push_back((int32_t)((int64_t)i - (int64_t)sl));
+}
+
+// #{m in [0, x) : gcd(m, d) = 1} by inclusion-exclusion over the prime factors of d.
+static u128 coprime_below(u128 x, const std::vector<uint32_t>& dq) {
+  const size_t k = dq.size();
+  u128 acc_pos = 0, acc_neg = 0;
+  for (uint64_t mask = 0; mask < (1ull << k); ++mask) {
+    u128 e = 1;
+    int bits = 0;
+    for (size_t t = 0; t < k; ++t)
+      if (mask >> t & 1) { e *= dq[t]; ++bits; }
+    const u128 c = (x + e - 1) / e;
+    if (bits & 1) acc_neg += c; else acc_pos += c;
+  }
+  return acc_pos - acc_neg;
+}
+
+uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq) {
+  return (uint64_t)(coprime_below((u128)job.m_start + job.m_inc, dq) - coprime_below(job.m_start, dq));
+}
+
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out) {
+  if (!job || !out) return CS_EINVAL;
+  const cs_job j = *job;
+  if (j.P < 2 || j.P >= kMaxP) return CS_EINVAL;
+  if (j.d == 0 || j.m_start == 0 || j.m_inc == 0) return CS_EINVAL;
+  if (j.m_inc >= kMaxMInc) return CS_EINVAL;
+  if (j.m_start >= (1ull << 63) || j.m_inc >= (1ull << 63) - j.m_start) return CS_EINVAL;
+  if (j.sl == 0 || j.sl > kMaxSl) return CS_EINVAL;
+  if (j.limit < 2) return CS_EINVAL;
+  if (j.limit >= kMaxLimit) return CS_ERANGE;
+  const uint32_t mode = tune ? tune->large_mode : CS_LARGE_G;
+  if (mode > CS_LARGE_THREE_GAP) return CS_EINVAL;
+
+  Plan& pl = *out;
+  pl.job = j;
+  pl.kq.clear();
+  pl.dq.clear();
+  std::vector<uint32_t> ps = host_primes_upto(j.P);
+  uint64_t rest = j.d;
+  for (uint32_t q : ps) {
+    if (rest % q == 0) {
+      rest /= q;
+      if (rest % q == 0) return CS_EINVAL;    // not squarefree
+      pl.dq.push_back(q);
+    } else {
+      pl.kq.push_back(q);
+    }
+  }
+  if (rest != 1) return CS_EINVAL;            // d does not divide P#
+  if (pl.dq.size() > (size_t)kMaxDq) return CS_EINVAL;
+  // every N + X must be positive: sl < m_start * K
+  {
+    u128 K = 1;
+    bool big = false;
+    for (uint32_t q : pl.kq) {
+      K *= q;
+      if (K >> 64) { big = true; break; }
+    }
+    if (!big && (u128)j.sl >= K * (u128)j.m_start) return CS_EINVAL;
+  }
+
+  pl.Lp = std::max<uint64_t>(j.limit, j.P);
+  pl.n_seg = (pl.Lp >> kSegLog) + 1;
+  pl.cap = pi_upper(pl.Lp);
+  pl.n_m = host_row_count(j, pl.dq);
+  std::vector<int32_t> xs;
+  host_columns(j, pl.kq, &xs);
+  pl.n_x = (uint32_t)xs.size();
+  pl.row_words = (pl.n_x + 31) / 32;
+  pl.S = 2 * j.sl + 1;
+  pl.ct_words = (pl.S + 31) / 32;
+  pl.w = 2 * j.sl;
+  pl.large_mode = mode;
+
+  // small/large threshold: C_mult * S with C_mult = 10 M / M_c (Section 5), clamped so that a
+  // large prime divides at most one number of an interval (p > 2 sl), or (three-gap) p > 4 sl.
+  uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
+  if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
+  uint64_t thr = tune && tune->thr ? tune->thr : 0;
+  if (!thr) {
+    double cm = pl.n_m ? 10.0 * (double)j.m_inc / (double)pl.n_m : 10.0;
+    thr = (uint64_t)(cm * (double)pl.S);
+  }
+  pl.thr = std::max(thr, thr_min);
+
+  // small branch tiles
+  const bool ct_lds = pl.ct_words * 8u <= kLdsCtMax;
+  const uint32_t ct_bytes = ct_lds ? pl.ct_words * 8u : 0u;
+  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
+  rows = std::max(1u, std::min(rows, 64u));
+  if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
+  pl.tile_rows = rows;
+  pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
+  pl.lds_ct_words = ct_lds ? pl.ct_words : 0;
+  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 4u * rows;
+  const double est_small = (double)pl.thr / std::max(1.0, log((double)pl.thr));
+  uint32_t max_slices = (uint32_t)std::max(1.0, std::min(64.0, est_small / 512.0));
+  uint32_t slices = pl.n_windows ? (uint32_t)((4u * (uint32_t)n_cu + pl.n_windows - 1) / pl.n_windows) : 1;
+  slices = std::max(1u, std::min(slices, max_slices));
+  if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
+  pl.n_slices = slices;
+  const uint64_t units = (uint64_t)pl.n_windows * slices;
+  pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, (uint64_t)n_cu * 2);
+  pl.dense_max = std::max<uint64_t>(1, pl.w / 32);
+
+  pl.hits_per_item = tune && tune->hits_per_item ? tune->hits_per_item
+                                                 : (mode == CS_LARGE_G ? 128u : 1024u);
+  pl.large_blocks = tune && tune->large_blocks ? tune->large_blocks : (uint32_t)n_cu * 8u;
+
+  // workspace layout
+  WsLayout& L = pl.ws;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { uint64_t at = o; o = align256(o + std::max<uint64_t>(bytes, 8)); return at; };
+  const uint64_t cap_lim = pi_upper(j.limit);
+  L.ctrl = take(sizeof(JobCtrl));
+  L.jobdev = take(sizeof(JobDev));
+  L.items_base = take(2 * sizeof(uint64_t));
+  L.n_base = take(8);
+  L.n_primes = take(8);
+  L.base = take(kBaseCap * 4ull);
+  L.flags = take(pl.n_seg * kSegWords * 4ull);
+  L.seg_count = take(pl.n_seg * 4ull);
+  L.seg_off = take(pl.n_seg * 8ull);
+  L.primes = take(pl.cap * 8ull);
+  L.kmod = take(cap_lim * 8ull);
+  L.mk = take(cap_lim * 8ull);
+  L.row_of = take(j.m_inc * 4ull);
+  L.m_off = take(std::max<uint64_t>(pl.n_m, 1) * 4ull);
+  L.row_blk = take(((j.m_inc + 1023) / 1024) * 4ull);
+  L.coltab = take(pl.ct_words * 8ull);
+  L.kgroups = take((pl.kq.size() + 1) * 8ull);
+  L.kq = take((pl.kq.size() + 1) * 4ull);
+  L.total = o;
+  return CS_OK;
+}
+
+void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
+  const uint64_t lo = std::max<uint64_t>(pl.thr, p_lo > 0 ? p_lo - 1 : 0);
+  const uint64_t hi = std::min<uint64_t>(p_hi, pl.job.limit);
+  jd->tier_lo = lo;
+  jd->n_tiers = 0;
+  if (hi <= lo) return;
+  const double mw = (double)pl.job.m_inc * (double)(pl.w + 1);
+  const double H = (double)pl.hits_per_item;
+  uint64_t b = lo;
+  uint32_t nt = 0;
+  while (b < hi) {
+    uint64_t nb = std::min<uint64_t>(hi, std::max<uint64_t>(2 * b, b + 1));
+    double expect = mw / (double)(b + 1);
+    uint64_t C = (uint64_t)ceil(expect / H);
+    C = std::max<uint64_t>(1, std::min<uint64_t>(C, pl.job.m_inc));
+    C = std::min<uint64_t>(C, 1u << 30);
+    if (nt > 0 && jd->tier_chunks[nt - 1] == (uint32_t)C) {
+      jd->tier_hi[nt - 1] = nb;
+    } else if (nt < (uint32_t)kMaxTiers) {
+      jd->tier_hi[nt] = nb;
+      jd->tier_chunks[nt] = (uint32_t)C;
+      ++nt;
+    } else {
+      jd->tier_hi[nt - 1] = nb;      // more chunks than needed is still exact
+      jd->tier_chunks[nt - 1] = std::max<uint32_t>(jd->tier_chunks[nt - 1], (uint32_t)C);
+    }
+    b = nb;
+  }
+  jd->n_tiers = nt;
+}
+
+JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const uint64_t* n_primes) {
+  JobDev jd;
+  memset(&jd, 0, sizeof(jd));
+  const cs_job& j = pl.job;
+  jd.d = j.d;
+  jd.m_start = j.m_start;
+  jd.m_inc = j.m_inc;
+  jd.limit = j.limit;
+  jd.thr = pl.thr;
+  jd.p_lo = 2;
+  jd.p_hi = j.limit;
+  jd.n_m = pl.n_m;
+  jd.P = j.P;
+  jd.sl = j.sl;
+  jd.w = pl.w;
+  jd.n_x = pl.n_x;
+  jd.row_words = pl.row_words;
+  jd.large_mode = pl.large_mode;
+  jd.tile_rows = pl.tile_rows;
+  jd.n_windows = pl.n_windows;
+  jd.n_slices = pl.n_slices;
+  jd.hits_per_item = pl.hits_per_item;
+  jd.small_unit_base = 0;
+  jd.dense_max = pl.dense_max;
+  jd.prime_cap = pl.cap;
+  jd.primes = primes;
+  jd.n_primes = n_primes;
+  const WsLayout& L = pl.ws;
+  jd.kmod = reinterpret_cast<uint64_t*>(ws + L.kmod);
+  jd.mk = reinterpret_cast<uint64_t*>(ws + L.mk);
+  jd.row_of = reinterpret_cast<int32_t*>(ws + L.row_of);
+  jd.m_off = reinterpret_cast<uint32_t*>(ws + L.m_off);
+  jd.row_blk = reinterpret_cast<uint32_t*>(ws + L.row_blk);
+  jd.coltab = reinterpret_cast<uint2*>(ws + L.coltab);
+  jd.kgroups = reinterpret_cast<uint64_t*>(ws + L.kgroups);
+  jd.kq = reinterpret_cast<uint32_t*>(ws + L.kq);
+  jd.ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
+  fill_tiers(pl, 2, j.limit, &jd);
+  return jd;
+}
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+}  // namespace cs

@@ -1,0 +1,131 @@
+// Host-side check of the kernels' arithmetic header against brute force.
+// Built and run by tests/test_arith_host.py with g++ (the header's functions are plain inline
+// C++ outside hipcc).  Exit status 0 means every case agreed.
+#include <cstdio>
+#include <cstdint>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "../paper_2012_03771_amd/csrc/arith.h"
+
+typedef unsigned __int128 u128;
+
+static bool is_prime(uint64_t n) {
+  if (n < 2) return false;
+  for (uint64_t q = 2; q * q <= n; ++q)
+    if (n % q == 0) return false;
+  return true;
+}
+
+static uint64_t brute_G(uint64_t p, uint64_t K, uint64_t L, uint64_t R) {
+  for (uint64_t m = 0; m < p; ++m) {
+    uint64_t v = (uint64_t)((u128)m * K % p);
+    if (L <= v && v <= R) return m;
+  }
+  return ~0ull;
+}
+
+static int fail(const char* what, uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
+  std::printf("FAIL %s %llu %llu %llu %llu\n", what, (unsigned long long)a, (unsigned long long)b,
+              (unsigned long long)c, (unsigned long long)d);
+  return 1;
+}
+
+int main(int argc, char** argv) {
+  unsigned seed = argc > 1 ? (unsigned)std::atoi(argv[1]) : 1;
+  std::mt19937_64 rng(seed);
+  int bad = 0;
+
+  // mulmod / mod64 / modinv against 128-bit integer arithmetic, p up to 2^40
+  for (int i = 0; i < 200000 && !bad; ++i) {
+    uint64_t p = (rng() >> (24 + rng() % 38)) | 3;
+    if (p >= (1ull << 40)) p &= (1ull << 40) - 1;
+    if (p < 3) p = 3;
+    double pinv = 1.0 / (double)p;
+    uint64_t a = rng() % p, b = rng() % p;
+    if (cs::mulmod(a, b, p, pinv) != (uint64_t)((u128)a * b % p)) bad = fail("mulmod", a, b, p, 0);
+    uint64_t x = rng();
+    if (cs::mod64(x, p, pinv) != x % p) bad = fail("mod64", x, p, 0, 0);
+    uint64_t o = rng() & 0xffffffffull;
+    if (cs::mulmod(o, a, p, pinv) != (uint64_t)((u128)o * a % p)) bad = fail("mulmod_o", o, a, p, 0);
+  }
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t p;
+    do { p = (rng() >> (24 + rng() % 30)) | 1; } while (!is_prime(p));
+    uint64_t k = 1 + rng() % (p - 1);
+    uint64_t inv = cs::modinv(k, p);
+    if ((uint64_t)((u128)inv * k % p) != 1) bad = fail("modinv", k, p, inv, 0);
+  }
+
+  // G of Eq. 4 (via the offset form) against brute force on small primes
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t p;
+    do { p = 3 + rng() % 20000; } while (!is_prime(p));
+    uint64_t K = 1 + rng() % (p - 1);
+    uint64_t L = rng() % p;
+    uint64_t R = L + rng() % (p - L);
+    if (rng() % 4 == 0) R = L + rng() % 4 < p ? L + rng() % 4 : L;
+    if (R >= p) R = p - 1;
+    uint64_t want = brute_G(p, K, L, R);
+    int lv = 0;
+    double off = cs::g_offset((double)p, (double)K, (double)L, (double)(R - L), &lv);
+    if (off < 0) { bad = fail("g_offset_neg", p, K, L, R); break; }
+    uint64_t v = L + (uint64_t)off;
+    uint64_t got = (uint64_t)((u128)v * cs::modinv(K, p) % p);
+    if (L == 0) got = 0;
+    if (got != want) bad = fail("G", p, K, L, R);
+  }
+
+  // The driver: every m with (m*k + SL) mod p <= w, enumerated by next_hit and by the
+  // three-gap rule, against a direct scan.
+  for (int i = 0; i < 3000 && !bad; ++i) {
+    uint64_t w = 2 * (1 + rng() % 60);
+    uint64_t p;
+    do { p = 2 * w + 1 + rng() % 50000; } while (!is_prime(p));
+    uint64_t k = 1 + rng() % (p - 1);
+    uint64_t kinv = cs::modinv(k, p);
+    double pinv = 1.0 / (double)p;
+    uint64_t m_inc = 1 + rng() % (4 * p);
+    uint64_t r0 = rng() % p;
+    std::vector<uint64_t> want, got, got3;
+    uint64_t r = r0;
+    for (uint64_t o = 0; o < m_inc; ++o) {
+      if (r <= w) want.push_back(o);
+      r += k; if (r >= p) r -= p;
+    }
+    // G per hit
+    uint64_t o = 0; r = r0;
+    while (o < m_inc) {
+      if (r > w) {
+        uint64_t rn; int lv;
+        uint64_t t = cs::next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+        if (t == 0) { bad = fail("next_hit0", p, k, r, w); break; }
+        o += t; if (o >= m_inc) break;
+        r = rn;
+      }
+      got.push_back(o);
+      o += 1; r += k; if (r >= p) r -= p;
+    }
+    if (!bad && got != want) bad = fail("driver", p, k, w, m_inc);
+    // three-gap
+    cs::gaps3 g; int lv3;
+    if (!cs::three_gap_setup(p, k, kinv, pinv, w, &g, &lv3)) { bad = fail("3gap_setup", p, k, w, 0); break; }
+    o = 0; r = r0;
+    if (r > w) {
+      uint64_t rn; int lv;
+      uint64_t t = cs::next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+      o = t; r = rn;
+    }
+    while (o < m_inc) {
+      got3.push_back(o);
+      bool a_first = g.ta < g.tb;
+      if (a_first ? (r + g.a <= w) : !(r >= g.b) && (r + g.a <= w)) { o += g.ta; r += g.a; }
+      else if (r >= g.b) { o += g.tb; r -= g.b; }
+      else { o += g.ta + g.tb; r = r + g.a - g.b; }
+    }
+    if (!bad && got3 != want) bad = fail("three_gap", p, k, w, m_inc);
+  }
+  if (!bad) std::printf("OK\n");
+  return bad;
+}

@@ -1,0 +1,103 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the headers declare, and its
+host-only planning (rows, columns, layout, validation) agrees with the oracle.  No GPU work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coracle
+import paper_2012_03771_amd as cs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(cs_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = cs.lib()
+    names = _declared_functions()
+    assert "cs_sieve" in names and "cs_plan" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror():
+    L = cs.lib()
+    assert L.cs_strerror(0) == b"ok"
+    assert L.cs_strerror(-1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("job", [W.SMALL, W.MEDIUM, W.PAPER_SCALE] + W.tiny_jobs(11, 20),
+                         ids=lambda j: "P%d_d%d_m%d+%d_sl%d_L%d" % j.as_tuple())
+def test_rows_and_columns_match_oracle(job):
+    lay = cs.plan(job)
+    xs = coracle.columns(job.P, job.d, job.sl)
+    assert lay.n_x == len(xs)
+    assert lay.row_words == (len(xs) + 31) // 32
+    assert np.array_equal(cs.columns(job), xs)
+    if job.m_inc <= 10**5:
+        ms = coracle.rows(job.d, job.m_start, job.m_inc)
+        assert lay.n_m == len(ms)
+        assert np.array_equal(cs.rows(job), ms)
+    assert lay.bitmap_bytes == lay.n_m * lay.row_words * 4
+    assert lay.counts_bytes == lay.n_m * 4
+
+
+def test_paper_scale_layout():
+    """953#/210 over m in [1e8, 1e8 + 1e6): 228,573 rows, 13,102 columns, a 375 MB bitmap."""
+    lay = cs.plan(W.PAPER_SCALE)
+    assert lay.n_m == len(coracle.rows(210, 10**8, 10**6)) == 228573
+    assert lay.n_x == 13102
+    assert lay.bitmap_bytes == 228573 * 410 * 4
+    assert lay.prime_cap >= 455052511
+
+
+def test_coprime_m_count_13_primorial(paper_values):
+    c = paper_values["coprime_m_count"]
+    lay = cs.plan(W.Job(8887, c["d"], 1, c["M"], 1000, 10**6))
+    assert lay.n_m == c["M_c"]
+
+
+@pytest.mark.parametrize("bad,code", [
+    (W.Job(1, 1, 1, 10, 10, 100), -1),               # P < 2
+    (W.Job(11, 4, 1, 10, 10, 100), -1),              # d not squarefree
+    (W.Job(11, 13, 1, 10, 10, 100), -1),             # d has a factor above P
+    (W.Job(11, 0, 1, 10, 10, 100), -1),              # d = 0
+    (W.Job(11, 1, 0, 10, 10, 100), -1),              # m_start = 0
+    (W.Job(11, 1, 1, 0, 10, 100), -1),               # m_inc = 0
+    (W.Job(11, 1, 1, 2**32, 10, 100), -1),           # m_inc too large
+    (W.Job(11, 1, 1, 10, 0, 100), -1),               # sl = 0
+    (W.Job(11, 1, 1, 10, 2**17, 100), -1),           # sl too large
+    (W.Job(11, 1, 1, 10, 10, 1), -1),                # limit < 2
+    (W.Job(11, 1, 1, 10, 10, 2**40), -2),            # limit too large
+    (W.Job(5, 30, 1, 10, 1, 100), -1),               # K = 1, sl >= m_start*K
+    (W.Job(7, 6, 1, 10, 35, 100), -1),               # K = 35, sl = 35 >= 1*35
+])
+def test_validation(bad, code):
+    with pytest.raises(cs.CsError) as e:
+        cs.plan(bad)
+    assert e.value.status == code
+
+
+def test_three_gap_threshold_floor():
+    lay = cs.plan(W.SMALL, cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP))
+    assert lay.thr >= 4 * W.SMALL.sl
+    lay = cs.plan(W.SMALL, cs.Tune(thr=1))
+    assert lay.thr == max(W.SMALL.P, 2 * W.SMALL.sl)
+
+
+def test_zero_row_job_is_valid():
+    lay = cs.plan(W.Job(11, 2, 4, 1, 5, 100))     # m = 4 only, even, d = 2
+    assert lay.n_m == 0 and lay.bitmap_bytes == 0
