@@ -35,6 +35,9 @@ def _args():
     ap.add_argument("--cpu-pmax", type=int, default=2**30)
     ap.add_argument("--workload", default="paper_953")
     ap.add_argument("--phase-only", action="store_true", help="time the phases once, no steps")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of this many MiB (a known-size reference for "
+                         "HBM byte counters)")
     return ap.parse_args()
 
 
@@ -83,6 +86,12 @@ def main():
     tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe * 2**20 // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
     print(f"# workload {args.workload} rows={lay.n_m} cols={lay.n_x} ws={lay.ws_bytes/2**30:.2f} GiB "
           f"thr={lay.thr}", file=sys.stderr, flush=True)

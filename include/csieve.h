@@ -169,6 +169,38 @@ cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out);
 cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,
                   void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batches: many jobs (different P, d, m ranges, sl, limits) sieved by one sequence of fused
+ * launches.  The prime table is built once up to the largest limit and shared; the per-job
+ * preparation kernels and the two sieve kernels each cover every job in a single launch
+ * (persistent grids over all jobs' tiles and items).  The sequence is captured once in a
+ * hipGraph and replayed.  Outputs are bit-identical to one cs_sieve call per job.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct cs_batch cs_batch;
+
+/* Validates and plans every job, allocates the batch's device memory (prime table, per-job
+ * tables; see cs_batch_layout's ws_bytes) on the current device.  tunes: n entries or NULL.
+ * Errors: those of cs_plan for any job; CS_ENOMEM; CS_EDEVICE. */
+cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tune* tunes, cs_batch** out);
+
+/* Layout of job i (n_m, n_x, row_words, bitmap and counts bytes); ws_bytes is the batch's
+ * total device memory. */
+cs_status cs_batch_layout(const cs_batch* b, uint32_t i, cs_layout* out);
+
+/* Sieves every job into its caller-owned outputs d_bitmaps[i] / d_counts[i] (sizes from
+ * cs_batch_layout), on `stream`.  use_graph != 0: the launch sequence is captured into a
+ * hipGraph on the first call (and again whenever the output pointers change) and replayed;
+ * use_graph = 0: the same launches are enqueued directly.  Calls on one handle must not
+ * overlap on the device (they share the handle's tables). */
+cs_status cs_batch_run(cs_batch* b, uint32_t* const* d_bitmaps, uint32_t* const* d_counts,
+                       int use_graph, void* stream);
+
+/* Waits for `stream` and reads the batch's counters (summed over jobs). */
+cs_status cs_batch_diag(cs_batch* b, cs_diag* out, void* stream);
+
+/* Frees the handle (waits for the device first).  NULL is a no-op. */
+cs_status cs_batch_destroy(cs_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

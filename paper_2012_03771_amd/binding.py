@@ -117,6 +117,11 @@ def lib():
         "cs_primes": ([u64, vp, u64, vp, vp, u64, vp], i32),
         "cs_kmod_ws": ([u32, u64, P(u64)], i32),
         "cs_kmod": ([u32, u64, vp, u64, vp, vp, u64, vp], i32),
+        "cs_batch_create": ([P(cs_job), u32, P(cs_tune), P(vp)], i32),
+        "cs_batch_layout": ([vp, u32, P(cs_layout)], i32),
+        "cs_batch_run": ([vp, P(vp), P(vp), i32, vp], i32),
+        "cs_batch_diag": ([vp, P(cs_diag), vp], i32),
+        "cs_batch_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -261,3 +266,53 @@ def unpack_bits(words, n_x: int):
     for b in range(32):
         out[:, b::32] = ((w >> np.uint32(b)) & np.uint32(1)).astype(np.uint8)
     return out[:, :n_x]
+
+
+class Batch:
+    """Many jobs sieved by one fused launch sequence (replayed from a hipGraph)."""
+
+    def __init__(self, jobs, tunes=None):
+        jobs = list(jobs)
+        self.n = len(jobs)
+        arr = (cs_job * self.n)(*[_cjob(j) for j in jobs])
+        tarr = None
+        if tunes is not None:
+            tarr = (cs_tune * self.n)(*[t.c() if t is not None else Tune().c() for t in tunes])
+        h = C.c_void_p()
+        _check(lib().cs_batch_create(arr, self.n, tarr, C.byref(h)), "cs_batch_create")
+        self.h = h
+        self.layouts = []
+        for i in range(self.n):
+            out = cs_layout()
+            _check(lib().cs_batch_layout(self.h, i, C.byref(out)), "cs_batch_layout")
+            self.layouts.append(Layout(out.n_m, out.n_x, out.row_words, out.bitmap_bytes, out.counts_bytes,
+                                       out.ws_bytes, out.prime_cap, out.thr))
+
+    def alloc_outputs(self):
+        import torch
+        bm = [torch.empty((L.n_m, L.row_words), dtype=torch.int32, device="cuda") for L in self.layouts]
+        ct = [torch.empty((L.n_m,), dtype=torch.int32, device="cuda") for L in self.layouts]
+        return bm, ct
+
+    def run(self, bitmaps, counts, use_graph=True, stream=None):
+        bp = (C.c_void_p * self.n)(*[t.data_ptr() if t.numel() else None for t in bitmaps])
+        cp = (C.c_void_p * self.n)(*[t.data_ptr() if t.numel() else None for t in counts])
+        _check(lib().cs_batch_run(self.h, bp, cp, 1 if use_graph else 0, _stream(stream)), "cs_batch_run")
+
+    def diag(self, stream=None) -> Diag:
+        out = cs_diag()
+        st = lib().cs_batch_diag(self.h, C.byref(out), _stream(stream))
+        d = Diag(*[getattr(out, f[0]) for f in cs_diag._fields_])
+        _check(st, f"cs_batch_diag (error_flags={d.error_flags})")
+        return d
+
+    def close(self):
+        if self.h:
+            lib().cs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

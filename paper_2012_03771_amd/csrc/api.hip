@@ -103,9 +103,10 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
   CS_TRY(launch_zero_ctrl(ctrl, s));
   CS_TRY(launch_write_job(jd, jdp, s));
   CS_TRY(launch_primes(pl.Lp, pw, s));
-  CS_TRY(launch_prep_tables(jdp, s));
-  CS_TRY(launch_kmod(jdp, pi_upper(pl.job.limit), n_cu, s));
-  CS_TRY(launch_rows_cols(jdp, pl.job.m_inc, pl.job.sl, n_cu, s));
+  CS_TRY(launch_prep_tables(jdp, 1, s));
+  CS_TRY(launch_kmod(jdp, 1, reinterpret_cast<uint64_t*>(ws + L.lim_base), pi_upper(pl.job.limit), n_cu, s));
+  CS_TRY(launch_rows_cols(jdp, 1, pl.job.m_inc, pl.job.sl, n_cu, s));
+  if (!pl.dpre.empty()) CS_TRY(launch_upload(ws + L.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
   return CS_OK;
 }
 
@@ -122,7 +123,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   fill_tiers(pl, p_lo, p_hi, &jd);
   uint64_t* items_base = reinterpret_cast<uint64_t*>(ws + L.items_base);
   CS_TRY(launch_write_job(jd, jdp, s));
-  CS_TRY(launch_prep_bounds(jdp, s));
+  CS_TRY(launch_prep_bounds(jdp, 1, s));
   CS_TRY(launch_items_scan(jdp, 1, items_base, s));
   if (pl.n_m == 0) return CS_OK;
   const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
@@ -130,7 +131,8 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s));
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
   if (branches != CS_BRANCH_SMALL)
-    CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, s));
+    CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, pl.large_lds_bytes,
+                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), s));
   return CS_OK;
 }
 

@@ -1,0 +1,300 @@
+// Batched sieving: many jobs with different P, d, m ranges, intervals and limits in one
+// sequence of fused launches, captured once in a hipGraph and replayed.
+//
+// The prime table is built once up to the largest limit and shared; every other table is per
+// job.  Each kernel of the sequence covers all jobs: the per-job preparation kernels take the
+// job from blockIdx.y, K mod p runs over the flattened prime index space of all jobs, and the
+// two sieve kernels are persistent grids over the small-branch tiles and large-branch items of
+// all jobs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/csieve.h"
+#include "batch_internal.h"
+#include "device.h"
+#include "launch.h"
+#include "plan.h"
+
+using namespace cs;
+
+#define CS_TRY(expr)                                 \
+  do {                                               \
+    if ((expr) != hipSuccess) return CS_EDEVICE;     \
+  } while (0)
+
+namespace cs {
+
+static uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Re-derives the small-branch tiles of a plan for a shared LDS column-table size.
+void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune) {
+  const uint32_t ct_bytes = lds_ct_words * 8u;
+  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
+  rows = std::max(1u, std::min(rows, 64u));
+  if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
+  pl.tile_rows = rows;
+  pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
+  pl.lds_ct_words = lds_ct_words;
+  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 4u * rows;
+  const double est_small = (double)pl.thr / std::max(1.0, log((double)pl.thr));
+  uint32_t max_slices = (uint32_t)std::max(1.0, std::min(64.0, est_small / 512.0));
+  uint32_t slices = pl.n_windows ? (uint32_t)((4u * (uint32_t)n_cu + pl.n_windows - 1) / pl.n_windows) : 1;
+  slices = std::max(1u, std::min(slices, max_slices));
+  if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
+  pl.n_slices = slices;
+}
+
+cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uint32_t n, int n_cu,
+                      uint64_t prime_extent) {
+  b.n = n;
+  b.n_cu = n_cu;
+  b.plans.assign(n, Plan());
+  uint64_t Lp = std::max<uint64_t>(prime_extent, 2);
+  uint32_t max_ct = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    cs_status st = make_plan(&jobs[i], tunes ? &tunes[i] : nullptr, n_cu, &b.plans[i], false);
+    if (st) return st;
+    Lp = std::max(Lp, b.plans[i].Lp);
+    max_ct = std::max(max_ct, b.plans[i].ct_words);
+  }
+  if (Lp >= kMaxLimit) return CS_ERANGE;
+  b.Lp = Lp;
+  b.lds_ct_words = max_ct * 8u <= kLdsCtMax ? max_ct : 0u;
+  b.units = 0;
+  b.lds_bytes = 0;
+  b.max_words = 0;
+  b.max_m_inc = 0;
+  b.max_sl = 0;
+  b.kmod_cap = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    Plan& pl = b.plans[i];
+    retile_small(pl, b.lds_ct_words, n_cu, tunes ? &tunes[i] : nullptr);
+    b.lds_bytes = std::max(b.lds_bytes, pl.lds_bytes);
+    b.max_words = std::max<uint64_t>(b.max_words, pl.n_m * (uint64_t)pl.row_words);
+    b.max_m_inc = std::max<uint64_t>(b.max_m_inc, pl.job.m_inc);
+    b.max_sl = std::max(b.max_sl, pl.job.sl);
+    b.kmod_cap += pi_upper(pl.job.limit);
+  }
+  // device memory: shared prime table, job descriptors, prefix arrays, per-job tables
+  b.n_seg = (Lp >> kSegLog) + 1;
+  b.cap = pi_upper(Lp);
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { uint64_t at = o; o = a256(o + std::max<uint64_t>(bytes, 8)); return at; };
+  b.o_nbase = take(8);
+  b.o_np = take(8);
+  b.o_base = take(kBaseCap * 4ull);
+  b.o_flags = take(b.n_seg * kSegWords * 4ull);
+  b.o_cnt = take(b.n_seg * 4ull);
+  b.o_off = take(b.n_seg * 8ull);
+  b.o_primes = take(b.cap * 8ull);
+  b.o_jobs = take(sizeof(JobDev) * (uint64_t)n);
+  b.o_lim = take(8ull * (n + 1));
+  b.o_items = take(8ull * (n + 1));
+  b.job_off.resize(n);
+  for (uint32_t i = 0; i < n; ++i) b.job_off[i] = take(b.plans[i].ws.total);
+  b.mem_bytes = o;
+  return CS_OK;
+}
+
+cs_status multi_alloc(MultiJob& b, hipStream_t s) {
+  if (hipMalloc(&b.mem, b.mem_bytes) != hipSuccess) {
+    b.mem = nullptr;
+    return CS_ENOMEM;
+  }
+  uint8_t* m = b.mem;
+  b.pw.n_base = reinterpret_cast<uint32_t*>(m + b.o_nbase);
+  b.pw.n_primes = reinterpret_cast<uint64_t*>(m + b.o_np);
+  b.pw.base = reinterpret_cast<uint32_t*>(m + b.o_base);
+  b.pw.flags = reinterpret_cast<uint32_t*>(m + b.o_flags);
+  b.pw.seg_count = reinterpret_cast<uint32_t*>(m + b.o_cnt);
+  b.pw.seg_off = reinterpret_cast<uint64_t*>(m + b.o_off);
+  b.pw.primes = reinterpret_cast<uint64_t*>(m + b.o_primes);
+  b.pw.cap = b.cap;
+  b.jobs_dev = reinterpret_cast<JobDev*>(m + b.o_jobs);
+  b.lim_base = reinterpret_cast<uint64_t*>(m + b.o_lim);
+  b.items_base = reinterpret_cast<uint64_t*>(m + b.o_items);
+  b.jds.resize(b.n);
+  uint64_t unit_base = 0;
+  for (uint32_t i = 0; i < b.n; ++i) {
+    const Plan& pl = b.plans[i];
+    uint8_t* ws = m + b.job_off[i];
+    b.jds[i] = make_jobdev(pl, ws, b.pw.primes, b.pw.n_primes);
+    b.jds[i].small_unit_base = unit_base;
+    b.jds[i].prime_cap = b.cap;
+    unit_base += (uint64_t)pl.n_windows * pl.n_slices;
+    if (!pl.dpre.empty())
+      CS_TRY(launch_upload(ws + pl.ws.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
+  }
+  b.units = unit_base;
+  b.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b.units, 1), (uint64_t)b.n_cu * 2);
+  b.large_blocks = (uint32_t)b.n_cu * 8u;
+  return CS_OK;
+}
+
+cs_status multi_bind(MultiJob& b, uint32_t* const* bitmaps, uint32_t* const* counts, hipStream_t s) {
+  for (uint32_t i = 0; i < b.n; ++i) {
+    if (b.plans[i].n_m > 0 && (!bitmaps[i] || !counts[i])) return CS_EINVAL;
+    b.jds[i].bitmap = bitmaps[i];
+    b.jds[i].counts = counts[i];
+    CS_TRY(launch_write_job(b.jds[i], b.jobs_dev + i, s));
+  }
+  return CS_OK;
+}
+
+// The whole sieve of every job: outputs cleared, shared prime table, per-job tables, both
+// branches over all primes <= each job's limit.
+cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
+  const uint32_t n = b.n;
+  CS_TRY(launch_fill_jobs(b.jobs_dev, n, b.max_words, s));
+  CS_TRY(launch_zero_ctrls(b.jobs_dev, n, s));
+  CS_TRY(launch_primes(b.Lp, b.pw, s));
+  CS_TRY(launch_prep_tables(b.jobs_dev, n, s));
+  CS_TRY(launch_kmod(b.jobs_dev, n, b.lim_base, b.kmod_cap, b.n_cu, s));
+  CS_TRY(launch_rows_cols(b.jobs_dev, n, b.max_m_inc, b.max_sl, b.n_cu, s));
+  CS_TRY(launch_prep_bounds(b.jobs_dev, n, s));
+  CS_TRY(launch_items_scan(b.jobs_dev, n, b.items_base, s));
+  CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));
+  JobCtrl* c0 = b.jds[0].ctrl;
+  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, s));
+  return CS_OK;
+}
+
+cs_status multi_diag(const MultiJob& b, cs_diag* out) {
+  memset(out, 0, sizeof(*out));
+  uint64_t err = 0;
+  for (uint32_t i = 0; i < b.n; ++i) {
+    JobCtrl c;
+    if (hipMemcpy(&c, b.jds[i].ctrl, sizeof(JobCtrl), hipMemcpyDeviceToHost) != hipSuccess) return CS_EDEVICE;
+    if (i == 0) {
+      out->n_primes = c.diag[D_NPRIMES];
+      out->small_pairs = c.diag[D_SMALL_PAIRS];
+      out->small_marks = c.diag[D_SMALL_MARKS];
+      out->large_raw_hits = c.diag[D_LARGE_RAW];
+      out->large_hits = c.diag[D_LARGE_HITS];
+      out->g_calls = c.diag[D_G_CALLS];
+      out->g_levels = c.diag[D_G_LEVELS];
+      err |= c.diag[D_ERROR];
+    }
+    out->small_primes += c.diag[D_SMALL_PRIMES];
+    out->large_primes += c.diag[D_LARGE_PRIMES];
+    err |= c.error;
+  }
+  out->error_flags = err;
+  return err ? CS_EDEVICE : CS_OK;
+}
+
+}  // namespace cs
+
+struct cs_batch {
+  MultiJob mj;
+  int device = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint32_t*> bound_b, bound_c;
+  bool bound = false;
+};
+
+static void drop_graph(cs_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tune* tunes, cs_batch** out) {
+  if (!jobs || !out || n == 0) return CS_EINVAL;
+  *out = nullptr;
+  cs_batch* b = new (std::nothrow) cs_batch();
+  if (!b) return CS_ENOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) { delete b; return CS_EDEVICE; }
+  cs_status st = multi_build(b->mj, jobs, tunes, n, device_cu_count(), 2);
+  if (st) { delete b; return st; }
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return CS_EDEVICE; }
+  st = multi_alloc(b->mj, b->cap_stream);
+  if (st == CS_OK && hipStreamSynchronize(b->cap_stream) != hipSuccess) st = CS_EDEVICE;
+  if (st) {
+    if (b->mj.mem) (void)hipFree(b->mj.mem);
+    (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_batch_layout(const cs_batch* b, uint32_t i, cs_layout* out) {
+  if (!b || !out || i >= b->mj.n) return CS_EINVAL;
+  const Plan& pl = b->mj.plans[i];
+  out->n_m = pl.n_m;
+  out->n_x = pl.n_x;
+  out->row_words = pl.row_words;
+  out->bitmap_bytes = pl.n_m * (uint64_t)pl.row_words * 4ull;
+  out->counts_bytes = pl.n_m * 4ull;
+  out->ws_bytes = b->mj.mem_bytes;
+  out->prime_cap = b->mj.cap;
+  out->thr = pl.thr;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_batch_run(cs_batch* b, uint32_t* const* d_bitmaps, uint32_t* const* d_counts,
+                                  int use_graph, void* stream) {
+  if (!b || !d_bitmaps || !d_counts) return CS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t n = b->mj.n;
+  bool same = b->bound;
+  for (uint32_t i = 0; same && i < n; ++i) same = b->bound_b[i] == d_bitmaps[i] && b->bound_c[i] == d_counts[i];
+  if (!same) {
+    drop_graph(b);
+    cs_status st = multi_bind(b->mj, d_bitmaps, d_counts, b->cap_stream);
+    if (st) return st;
+    if (hipStreamSynchronize(b->cap_stream) != hipSuccess) return CS_EDEVICE;
+    b->bound_b.assign(d_bitmaps, d_bitmaps + n);
+    b->bound_c.assign(d_counts, d_counts + n);
+    b->bound = true;
+  }
+  if (!use_graph) return multi_enqueue(b->mj, s);
+  if (!b->exec) {
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return CS_EDEVICE;
+    cs_status st = multi_enqueue(b->mj, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st ? st : CS_EDEVICE;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(b);
+      return CS_EDEVICE;
+    }
+  }
+  CS_TRY(hipGraphLaunch(b->exec, s));
+  return CS_OK;
+}
+
+extern "C" cs_status cs_batch_diag(cs_batch* b, cs_diag* out, void* stream) {
+  if (!b || !out) return CS_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CS_EDEVICE;
+  return multi_diag(b->mj, out);
+}
+
+extern "C" cs_status cs_batch_destroy(cs_batch* b) {
+  if (!b) return CS_OK;
+  drop_graph(b);
+  if (b->cap_stream) {
+    (void)hipStreamSynchronize(b->cap_stream);
+    (void)hipStreamDestroy(b->cap_stream);
+  }
+  if (b->mj.mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b->mj.mem);
+  }
+  delete b;
+  return CS_OK;
+}

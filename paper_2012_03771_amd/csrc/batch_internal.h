@@ -1,0 +1,49 @@
+// Fused multi-job launches shared by the batch graph and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "device.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace cs {
+
+struct MultiJob {
+  uint32_t n = 0;
+  int n_cu = 256;
+  std::vector<Plan> plans;
+  uint64_t Lp = 0, n_seg = 0, cap = 0;
+  // device memory (one allocation) and offsets inside it
+  uint8_t* mem = nullptr;
+  uint64_t mem_bytes = 0;
+  uint64_t o_nbase = 0, o_np = 0, o_base = 0, o_flags = 0, o_cnt = 0, o_off = 0, o_primes = 0;
+  uint64_t o_jobs = 0, o_lim = 0, o_items = 0;
+  std::vector<uint64_t> job_off;
+  PrimeWs pw{};
+  JobDev* jobs_dev = nullptr;
+  uint64_t* lim_base = nullptr;
+  uint64_t* items_base = nullptr;
+  std::vector<JobDev> jds;
+  // launch shapes
+  uint64_t units = 0, max_words = 0, max_m_inc = 0, kmod_cap = 0;
+  uint32_t small_blocks = 1, large_blocks = 1, lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
+};
+
+void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune);
+// Plans every job (tables without a prime table) and lays out one device allocation whose
+// shared prime table reaches at least prime_extent.
+cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uint32_t n, int n_cu,
+                      uint64_t prime_extent);
+// Allocates the device memory (hipMalloc) and uploads the per-job residue tables on s.
+cs_status multi_alloc(MultiJob& b, hipStream_t s);
+// Points every job's descriptor at its outputs and writes the descriptors on s.
+cs_status multi_bind(MultiJob& b, uint32_t* const* bitmaps, uint32_t* const* counts, hipStream_t s);
+// Enqueues the whole sieve of all jobs on s.
+cs_status multi_enqueue(MultiJob& b, hipStream_t s);
+// Reads the counters of all jobs (the caller has synchronised).
+cs_status multi_diag(const MultiJob& b, cs_diag* out);
+
+}  // namespace cs

@@ -12,6 +12,7 @@ constexpr uint32_t kSegBits = 1u << (kSegLog - 1);
 constexpr uint32_t kSegWords = kSegBits / 32;
 constexpr int kWave = 64;
 constexpr uint64_t kGroupMax = 1ull << 50;   // K-prime products stay below 2^50 (mulmod bound)
+constexpr uint32_t kDSmall = 4096;            // d <= kDSmall: m -> row from a residue table of d entries
 
 // Counters in cs_diag order.
 enum DiagSlot {
@@ -50,6 +51,12 @@ struct JobDev {
   uint64_t dense_max;                // small primes <= dense_max are marked cooperatively
   uint64_t prime_cap;                // capacity of the prime table
   uint32_t n_tiers, pad1;
+  uint32_t d_small;                  // 1 if d <= kDSmall (rows from dpre, no per-m table lookups)
+  uint32_t phi_d;                    // residues mod d coprime to d
+  uint32_t r0_d;                     // m_start mod d
+  uint32_t pre_r0;                   // coprime residues below r0_d
+  double inv_d;                      // 1/d, correctly rounded
+  const uint16_t* dpre;              // d entries: bit 15 = coprime to d, bits 0-14 = coprime residues below
   uint64_t tier_lo;                  // tier 0 holds primes in (tier_lo, tier_hi[0]]
   uint64_t tier_hi[kMaxTiers];
   uint32_t tier_chunks[kMaxTiers];

@@ -261,9 +261,9 @@ __global__ __launch_bounds__(256) void k_compact_primes(uint64_t n_seg, const ui
 
 // One thread: primes dividing K grouped into products < 2^50, prime factors of d, and
 // m_start mod each of them.
-__global__ void k_prep_tables(JobDev* jp) {
+__global__ void k_prep_tables(JobDev* jobs) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  JobDev& j = *jp;
+  JobDev& j = jobs[blockIdx.y];
   JobCtrl& c = *j.ctrl;
   uint64_t np = *j.n_primes;
   if (np > j.prime_cap) {
@@ -292,21 +292,55 @@ __global__ void k_prep_tables(JobDev* jp) {
   c.diag[D_NPRIMES] = np;
 }
 
-// K mod p and m_start*K mod p for every prime index < n_lim (Eq. 1's cached residue).
-__global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jp) {
-  const JobDev& j = *jp;
-  const uint64_t n = j.ctrl->n_lim;
-  const uint32_t ng = j.ctrl->n_kgroups;
-  const uint64_t* __restrict__ G = j.kgroups;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+// Prefix of the per-job prime counts (primes <= limit) over the jobs of a launch.
+__global__ void k_lim_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t s = 0;
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    base[i] = s;
+    s += jobs[i].ctrl->n_lim;
+  }
+  base[n_jobs] = s;
+}
+
+// K mod p and m_start*K mod p for every prime index < n_lim of every job (Eq. 1's cached
+// residue); the index space of all jobs is flattened so one launch covers a whole batch.
+__global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, uint32_t n_jobs,
+                                              const uint64_t* __restrict__ lim_base) {
+  const uint64_t total = lim_base[n_jobs];
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = n_jobs;                   // job: last base <= g
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (lim_base[mid] <= g) lo = mid; else hi = mid;
+    }
+    const JobDev& j = jobs[lo];
+    const uint64_t i = g - lim_base[lo];
+    const uint32_t ng = j.ctrl->n_kgroups;
+    const uint64_t* __restrict__ G = j.kgroups;
     const uint64_t p = j.primes[i];
     const double pinv = 1.0 / (double)p;
     uint64_t r = 1 % p;
-    for (uint32_t g = 0; g < ng; ++g) r = mulmod(r, G[g], p, pinv);
+    for (uint32_t t = 0; t < ng; ++t) r = mulmod(r, G[t], p, pinv);
     j.kmod[i] = r;
     j.mk[i] = mulmod(mod64(j.m_start, p, pinv), r, p, pinv);
   }
+}
+
+// Clears the outputs of every job (blockIdx.y = job).
+__global__ void k_fill_jobs(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  const uint64_t nb = j.n_m * (uint64_t)j.row_words;
+  const uint64_t s = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nb; i += s) j.bitmap[i] = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < j.n_m; i += s) j.counts[i] = 0;
+}
+
+// Clears the control block of every job (blockIdx.y = job).
+__global__ void k_zero_ctrls(const JobDev* __restrict__ jobs) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(jobs[blockIdx.y].ctrl);
+  for (uint32_t i = threadIdx.x; i < sizeof(JobCtrl) / 4; i += blockDim.x) w[i] = 0;
 }
 
 // Stand-alone K mod p for the cs_kmod entry point.
@@ -332,9 +366,9 @@ __device__ __forceinline__ bool m_coprime(const JobCtrl& c, uint64_t o) {
 
 constexpr uint32_t kRowBlock = 1024;
 
-__global__ __launch_bounds__(256) void k_rows_count(const JobDev* __restrict__ jp) {
+__global__ __launch_bounds__(256) void k_rows_count(const JobDev* __restrict__ jobs) {
   __shared__ uint32_t sh[32];
-  const JobDev& j = *jp;
+  const JobDev& j = jobs[blockIdx.y];
   const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     uint32_t c = 0;
@@ -348,9 +382,9 @@ __global__ __launch_bounds__(256) void k_rows_count(const JobDev* __restrict__ j
   }
 }
 
-__global__ __launch_bounds__(1024) void k_rows_scan(const JobDev* __restrict__ jp) {
+__global__ __launch_bounds__(1024) void k_rows_scan(const JobDev* __restrict__ jobs) {
   __shared__ uint32_t sh[32];
-  const JobDev& j = *jp;
+  const JobDev& j = jobs[blockIdx.y];
   const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
   uint64_t carry = 0;
   for (uint64_t b = 0; b < nb; b += blockDim.x) {
@@ -364,9 +398,9 @@ __global__ __launch_bounds__(1024) void k_rows_scan(const JobDev* __restrict__ j
   if (threadIdx.x == 0 && carry != j.n_m) atomicOr(&j.ctrl->error, (uint32_t)E_ROWS);
 }
 
-__global__ __launch_bounds__(1024) void k_rows_write(const JobDev* __restrict__ jp) {
+__global__ __launch_bounds__(1024) void k_rows_write(const JobDev* __restrict__ jobs) {
   __shared__ uint32_t sh[32];
-  const JobDev& j = *jp;
+  const JobDev& j = jobs[blockIdx.y];
   const uint64_t nb = (j.m_inc + kRowBlock - 1) / kRowBlock;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const uint64_t o = b * kRowBlock + threadIdx.x;
@@ -380,8 +414,8 @@ __global__ __launch_bounds__(1024) void k_rows_write(const JobDev* __restrict__ 
 }
 
 // Column table: j = X + sl in [0, 2 sl]; X is a column iff gcd(X, K) = 1.
-__global__ __launch_bounds__(256) void k_cols_mask(const JobDev* __restrict__ jp) {
-  const JobDev& j = *jp;
+__global__ __launch_bounds__(256) void k_cols_mask(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[blockIdx.y];
   const uint32_t S = 2 * j.sl + 1;
   const uint32_t nkq = j.ctrl->n_kq;
   const uint32_t nwords = (S + 31) / 32;
@@ -411,9 +445,9 @@ __global__ __launch_bounds__(256) void k_cols_mask(const JobDev* __restrict__ jp
   }
 }
 
-__global__ __launch_bounds__(1024) void k_cols_prefix(const JobDev* __restrict__ jp) {
+__global__ __launch_bounds__(1024) void k_cols_prefix(const JobDev* __restrict__ jobs) {
   __shared__ uint32_t sh[32];
-  const JobDev& j = *jp;
+  const JobDev& j = jobs[blockIdx.y];
   const uint32_t nwords = (2 * j.sl + 1 + 31) / 32;
   uint32_t carry = 0;
   for (uint32_t b = 0; b < nwords; b += blockDim.x) {
@@ -428,9 +462,9 @@ __global__ __launch_bounds__(1024) void k_cols_prefix(const JobDev* __restrict__
 }
 
 // Prime-index bounds of the branches and the large-branch work items of one job.
-__global__ void k_prep_bounds(JobDev* jp) {
+__global__ void k_prep_bounds(JobDev* jobs) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  JobDev& j = *jp;
+  JobDev& j = jobs[blockIdx.y];
   JobCtrl& c = *j.ctrl;
   const uint64_t n = c.n_lim;
   const uint64_t* pr = j.primes;
@@ -631,20 +665,78 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
 // From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
 // G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void record_hit(const JobDev& j, uint64_t o, uint32_t jj,
-                                           unsigned long long& useful) {
-  const int32_t row = j.row_of[o];
-  if (row < 0) return;                             // m shares a factor with d (Section 3.2)
+// Position of m = m_start + o relative to d: m_start mod d + o = dq * d + rd.  With the residue
+// table of d this gives gcd(m, d) = 1 and the row of m with no per-m memory lookup.
+struct MPos {
+  uint32_t rd;
+  uint32_t dq;
+};
+
+__device__ __forceinline__ void mpos_divmod(uint64_t x, uint32_t d, double inv_d, uint32_t* q, uint32_t* r) {
+  const double xd = (double)x, dd = (double)d;
+  double qq = floor(xd * inv_d);
+  double rr = fma(-qq, dd, xd);
+  if (rr < 0.0) { rr += dd; qq -= 1.0; }
+  if (rr >= dd) { rr -= dd; qq += 1.0; }
+  *q = (uint32_t)qq;
+  *r = (uint32_t)rr;
+}
+
+__device__ __forceinline__ void mpos_add(MPos& s, uint32_t tq, uint32_t tr, uint32_t d) {
+  s.rd += tr;
+  s.dq += tq;
+  if (s.rd >= d) { s.rd -= d; s.dq += 1; }
+}
+
+// Table accessors: LDS copies for a single-job launch, global memory otherwise.
+template <bool kLds>
+struct LargeTables {
+  const uint2* ct;
+  const uint16_t* dp;
+};
+
+template <bool kLds>
+__device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
+                                           uint32_t jj, unsigned long long& useful) {
+  uint64_t row;
+  if (j.d_small) {
+    const uint32_t e = T.dp[mp.rd];
+    if (!(e >> 15)) return;                         // m shares a factor with d (Section 3.2)
+    row = (uint64_t)j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
+  } else {
+    const int32_t r = j.row_of[o];
+    if (r < 0) return;
+    row = (uint64_t)r;
+  }
   uint32_t col;
-  if (!lookup_col(j.coltab, jj, &col)) return;     // X shares a factor with K
-  atomicOr(&j.bitmap[(uint64_t)row * j.row_words + (col >> 5)], 1u << (col & 31));
+  if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
+  atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
   atomicAdd(&j.counts[row], 1u);
   ++useful;
 }
 
+// ------------------------------------------------------------------------------------------
+// Large-prime branch (Section 3.2-3.3).  One item = (job, prime, chunk of the m range).
+// From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
+// G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
+// ------------------------------------------------------------------------------------------
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
-                                               unsigned long long* __restrict__ diag) {
+                                               unsigned long long* __restrict__ diag, uint32_t lds_ct_words,
+                                               uint32_t dpre_n) {
+  extern __shared__ uint32_t lds[];
+  LargeTables<kLds> T;
+  if constexpr (kLds) {
+    const JobDev& j0 = jobs[0];
+    uint2* ctl = reinterpret_cast<uint2*>(lds);
+    uint16_t* dpl = reinterpret_cast<uint16_t*>(lds + 2 * lds_ct_words);
+    for (uint32_t i = threadIdx.x; i < lds_ct_words; i += blockDim.x) ctl[i] = j0.coltab[i];
+    for (uint32_t i = threadIdx.x; i < dpre_n; i += blockDim.x) dpl[i] = j0.dpre[i];
+    __syncthreads();
+    T.ct = lds_ct_words ? ctl : j0.coltab;
+    T.dp = dpl;
+  }
   const uint64_t total = job_item_base[n_jobs];
   unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
   uint32_t err = 0;
@@ -653,6 +745,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     uint32_t ji = 0;
     while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
     const JobDev& j = jobs[ji];
+    if constexpr (!kLds) {
+      T.ct = j.coltab;
+      T.dp = j.dpre;
+    }
     const JobCtrl& c = *j.ctrl;
     const uint64_t local = item - job_item_base[ji];
     uint32_t t = 0;
@@ -670,6 +766,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const uint64_t k = j.kmod[pi];
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
+    const uint32_t d32 = (uint32_t)j.d;
     const uint64_t kinv = modinv(k, p);
     // residue of m*K + SL at m = m_start + o_lo
     uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
@@ -677,6 +774,8 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     r += mod64(j.sl, p, pinv);
     r = r >= p ? r - p : r;
     uint64_t o = o_lo;
+    MPos mp = {0, 0};
+    if (j.d_small) mpos_divmod(j.r0_d + o_lo, d32, j.inv_d, &mp.dq, &mp.rd);
 
     if (j.large_mode == 0) {
       // one solve of Eq. 3 per hit
@@ -691,10 +790,16 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
           o += tstep;
           if (o >= o_hi) break;
           r = rn;
+          if (j.d_small) {
+            uint32_t tq, tr;
+            mpos_divmod(tstep, d32, j.inv_d, &tq, &tr);
+            mpos_add(mp, tq, tr, d32);
+          }
         }
         ++raw;
-        record_hit(j, o, (uint32_t)(w - r), useful);
+        record_hit<kLds>(j, T, o, mp, (uint32_t)(w - r), useful);
         if (++o >= o_hi) break;
+        if (j.d_small) mpos_add(mp, 0, 1, d32);
         r += k;
         r = r >= p ? r - p : r;
       }
@@ -714,15 +819,26 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         if (tstep == 0) { err |= E_SOLVE; continue; }
         o += tstep;
         r = rn;
+        if (j.d_small && o < o_hi) {
+          uint32_t tq, tr;
+          mpos_divmod(tstep, d32, j.inv_d, &tq, &tr);
+          mpos_add(mp, tq, tr, d32);
+        }
+      }
+      uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
+      if (j.d_small) {
+        mpos_divmod(g.ta, d32, j.inv_d, &aq, &ar);
+        mpos_divmod(g.tb, d32, j.inv_d, &bq, &br);
+        mpos_divmod(g.ta + g.tb, d32, j.inv_d, &abq, &abr);
       }
       const bool a_first = g.ta < g.tb;
       while (o < o_hi) {
         ++raw;
-        record_hit(j, o, (uint32_t)(w - r), useful);
+        record_hit<kLds>(j, T, o, mp, (uint32_t)(w - r), useful);
         const bool fa = r + g.a <= w, fb = r >= g.b;
-        if (fa && (a_first || !fb)) { o += g.ta; r += g.a; }
-        else if (fb) { o += g.tb; r -= g.b; }
-        else { o += g.ta + g.tb; r = r + g.a - g.b; }
+        if (fa && (a_first || !fb)) { o += g.ta; r += g.a; mpos_add(mp, aq, ar, d32); }
+        else if (fb) { o += g.tb; r -= g.b; mpos_add(mp, bq, br, d32); }
+        else { o += g.ta + g.tb; r = r + g.a - g.b; mpos_add(mp, abq, abr, d32); }
       }
     }
   }
@@ -795,17 +911,32 @@ hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep_tables(JobDev* jd, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_tables, dim3(1), dim3(64), 0, s, jd); { hipError_t e_ = note("k_prep_tables"); if (e_ != hipSuccess) return e_; }
+hipError_t launch_prep_tables(JobDev* jobs, uint32_t n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_tables, dim3(1, n_jobs), dim3(64), 0, s, jobs); { hipError_t e_ = note("k_prep_tables"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 
-hipError_t launch_kmod(const JobDev* jd, uint64_t cap, int n_cu, hipStream_t s) {
-  uint64_t blocks = (cap + 255) / 256;
+hipError_t launch_kmod(const JobDev* jobs, uint32_t n_jobs, uint64_t* lim_base, uint64_t total_cap, int n_cu,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_lim_scan, dim3(1), dim3(64), 0, s, jobs, n_jobs, lim_base); { hipError_t e_ = note("k_lim_scan"); if (e_ != hipSuccess) return e_; }
+  uint64_t blocks = (total_cap + 255) / 256;
   uint64_t maxb = (uint64_t)n_cu * 32;
   if (blocks > maxb) blocks = maxb;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_kmod, dim3((uint32_t)blocks), dim3(256), 0, s, jd); { hipError_t e_ = note("k_kmod"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_kmod, dim3((uint32_t)blocks), dim3(256), 0, s, jobs, n_jobs, (const uint64_t*)lim_base); { hipError_t e_ = note("k_kmod"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_jobs(const JobDev* jobs, uint32_t n_jobs, uint64_t max_words, hipStream_t s) {
+  uint64_t blocks = (max_words + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fill_jobs, dim3((uint32_t)blocks, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_fill_jobs"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ctrls(const JobDev* jobs, uint32_t n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ctrls, dim3(1, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_zero_ctrls"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 
@@ -819,23 +950,24 @@ hipError_t launch_kmod_list(const uint64_t* primes, uint64_t n, const uint64_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_rows_cols(const JobDev* jd, uint64_t m_inc, uint32_t sl, int n_cu, hipStream_t s) {
-  const uint64_t nb = (m_inc + kRowBlock - 1) / kRowBlock;
+hipError_t launch_rows_cols(const JobDev* jobs, uint32_t n_jobs, uint64_t max_m_inc, uint32_t max_sl, int n_cu,
+                            hipStream_t s) {
+  const uint64_t nb = (max_m_inc + kRowBlock - 1) / kRowBlock;
   uint32_t blocks = (uint32_t)(nb < (uint64_t)n_cu * 16 ? nb : (uint64_t)n_cu * 16);
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_rows_count, dim3(blocks), dim3(256), 0, s, jd); { hipError_t e_ = note("k_rows_count"); if (e_ != hipSuccess) return e_; }
-  hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_rows_scan"); if (e_ != hipSuccess) return e_; }
-  hipLaunchKernelGGL(k_rows_write, dim3(blocks), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_rows_write"); if (e_ != hipSuccess) return e_; }
-  const uint32_t nwords = (2 * sl + 1 + 31) / 32;
+  hipLaunchKernelGGL(k_rows_count, dim3(blocks, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_rows_count"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_rows_scan, dim3(1, n_jobs), dim3(1024), 0, s, jobs); { hipError_t e_ = note("k_rows_scan"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_rows_write, dim3(blocks, n_jobs), dim3(1024), 0, s, jobs); { hipError_t e_ = note("k_rows_write"); if (e_ != hipSuccess) return e_; }
+  const uint32_t nwords = (2 * max_sl + 1 + 31) / 32;
   uint32_t cb = (nwords * 32 + 255) / 256;
   if (cb > 4096) cb = 4096;
-  hipLaunchKernelGGL(k_cols_mask, dim3(cb), dim3(256), 0, s, jd); { hipError_t e_ = note("k_cols_mask"); if (e_ != hipSuccess) return e_; }
-  hipLaunchKernelGGL(k_cols_prefix, dim3(1), dim3(1024), 0, s, jd); { hipError_t e_ = note("k_cols_prefix"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_cols_mask, dim3(cb, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_cols_mask"); if (e_ != hipSuccess) return e_; }
+  hipLaunchKernelGGL(k_cols_prefix, dim3(1, n_jobs), dim3(1024), 0, s, jobs); { hipError_t e_ = note("k_cols_prefix"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 
-hipError_t launch_prep_bounds(JobDev* jd, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_bounds, dim3(1), dim3(64), 0, s, jd); { hipError_t e_ = note("k_prep_bounds"); if (e_ != hipSuccess) return e_; }
+hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_bounds, dim3(1, n_jobs), dim3(64), 0, s, jobs); { hipError_t e_ = note("k_prep_bounds"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 
@@ -852,9 +984,17 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 }
 
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
-                        unsigned long long* diag, uint32_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_large, dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag); { hipError_t e_ = note("k_large"); if (e_ != hipSuccess) return e_; }
-  return hipGetLastError();
+                        unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
+                        uint32_t dpre_n, hipStream_t s) {
+  if (lds_bytes && n_jobs == 1) {
+    hipLaunchKernelGGL(k_large<true>, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base, diag,
+                       lds_ct_words, dpre_n);
+    { hipError_t e_ = note("k_large<lds>"); if (e_ != hipSuccess) return e_; }
+  } else {
+    hipLaunchKernelGGL(k_large<false>, dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag, 0u, 0u);
+    { hipError_t e_ = note("k_large"); if (e_ != hipSuccess) return e_; }
+  }
+  return hipSuccess;
 }
 
 }  // namespace cs

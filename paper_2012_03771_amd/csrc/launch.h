@@ -29,16 +29,26 @@ hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_zero_ctrl(JobCtrl* c, hipStream_t s);
 hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s);
-hipError_t launch_prep_tables(JobDev* jd, hipStream_t s);
-hipError_t launch_kmod(const JobDev* jd, uint64_t cap, int n_cu, hipStream_t s);
+// Kernels over a job array take the job from blockIdx.y (grid.y = n_jobs).
+hipError_t launch_prep_tables(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
+// lim_base: n_jobs + 1 device words; total_cap: an upper bound of all jobs' primes <= limit.
+hipError_t launch_kmod(const JobDev* jobs, uint32_t n_jobs, uint64_t* lim_base, uint64_t total_cap, int n_cu,
+                       hipStream_t s);
+hipError_t launch_fill_jobs(const JobDev* jobs, uint32_t n_jobs, uint64_t max_words, hipStream_t s);
+hipError_t launch_zero_ctrls(const JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_kmod_list(const uint64_t* primes, uint64_t n, const uint64_t* groups, uint32_t ng,
                             uint64_t* out, int n_cu, hipStream_t s);
-hipError_t launch_rows_cols(const JobDev* jd, uint64_t m_inc, uint32_t sl, int n_cu, hipStream_t s);
-hipError_t launch_prep_bounds(JobDev* jd, hipStream_t s);
+hipError_t launch_rows_cols(const JobDev* jobs, uint32_t n_jobs, uint64_t max_m_inc, uint32_t max_sl, int n_cu,
+                            hipStream_t s);
+hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s);
 hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
                         uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
+// lds_bytes = 0: tables read from global memory (any number of jobs); otherwise n_jobs must be 1
+// and the column table (lds_ct_words uint2, 0 = global) and residue table (dpre_n entries) of
+// that job are staged in LDS.
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
-                        unsigned long long* diag, uint32_t blocks, hipStream_t s);
+                        unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
+                        uint32_t dpre_n, hipStream_t s);
 
 }  // namespace cs

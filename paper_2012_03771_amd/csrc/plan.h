@@ -19,8 +19,8 @@ constexpr uint32_t kLdsCtMax = 32 * 1024;
 constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024) plus slack
 
 struct WsLayout {
-  uint64_t ctrl, jobdev, items_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
-      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, total;
+  uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
+      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, total;
 };
 
 struct Plan {
@@ -37,7 +37,10 @@ struct Plan {
   uint32_t hits_per_item;
   uint32_t large_blocks, small_blocks;
   uint32_t lds_bytes, lds_ct_words;
+  uint32_t large_lds_bytes, large_lds_ct_words;   // LDS tables of the large branch (0: global)
   uint64_t dense_max;
+  uint32_t phi_d, r0_d;
+  std::vector<uint16_t> dpre;       // residue table when d <= kDSmall
   std::vector<uint32_t> kq;         // primes dividing K
   std::vector<uint32_t> dq;         // primes dividing d
   WsLayout ws;
@@ -46,8 +49,9 @@ struct Plan {
 // Upper bound of pi(x).
 uint64_t pi_upper(uint64_t x);
 
-// Validates the job and fills everything except the range-dependent tiers.
-cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out);
+// Validates the job and fills everything except the range-dependent tiers.  With own_primes
+// false the workspace layout leaves out the prime table (a batch or server shares one).
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes = true);
 
 // Host count of rows and columns (also used by cs_rows / cs_columns).
 void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs);

@@ -69,7 +69,7 @@ uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq) {
   return (uint64_t)(coprime_below((u128)job.m_start + job.m_inc, dq) - coprime_below(job.m_start, dq));
 }
 
-cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out) {
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes) {
   if (!job || !out) return CS_EINVAL;
   const cs_job j = *job;
   if (j.P < 2 || j.P >= kMaxP) return CS_EINVAL;
@@ -123,13 +123,16 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out)
   pl.w = 2 * j.sl;
   pl.large_mode = mode;
 
-  // small/large threshold: C_mult * S with C_mult = 10 M / M_c (Section 5), clamped so that a
-  // large prime divides at most one number of an interval (p > 2 sl), or (three-gap) p > 4 sl.
+  // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
+  // 5 M / M_c (half the paper's 10 M / M_c, measured faster on gfx950); with three-gap stepping
+  // a hit costs a few operations, so the paper's naive 10 S is used.  Clamped so that a large
+  // prime divides at most one number of an interval (p > 2 sl), or (three-gap) p > 4 sl.
   uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
   uint64_t thr = tune && tune->thr ? tune->thr : 0;
   if (!thr) {
-    double cm = pl.n_m ? 10.0 * (double)j.m_inc / (double)pl.n_m : 10.0;
+    double cm = mode == CS_LARGE_THREE_GAP ? 10.0
+                                           : (pl.n_m ? 5.0 * (double)j.m_inc / (double)pl.n_m : 5.0);
     thr = (uint64_t)(cm * (double)pl.S);
   }
   pl.thr = std::max(thr, thr_min);
@@ -154,6 +157,32 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out)
   pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, (uint64_t)n_cu * 2);
   pl.dense_max = std::max<uint64_t>(1, pl.w / 32);
 
+  // residue table of d: m -> row without a per-m lookup
+  pl.dpre.clear();
+  pl.phi_d = 0;
+  pl.r0_d = 0;
+  if (j.d <= kDSmall) {
+    const uint32_t d32 = (uint32_t)j.d;
+    pl.dpre.resize(d32);
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < d32; ++r) {
+      bool cop = true;
+      for (uint32_t q : pl.dq)
+        if (r % q == 0) { cop = false; break; }
+      if (d32 == 1) cop = true;
+      pl.dpre[r] = (uint16_t)(c | (cop ? 0x8000u : 0u));
+      c += cop ? 1 : 0;
+    }
+    pl.phi_d = c;
+    pl.r0_d = (uint32_t)(j.m_start % j.d);
+  }
+  {
+    const uint32_t ct_b = pl.ct_words * 8u;
+    const uint32_t dp_b = (uint32_t)pl.dpre.size() * 2u;
+    pl.large_lds_ct_words = ct_b <= 16384u ? pl.ct_words : 0u;
+    pl.large_lds_bytes = (pl.large_lds_ct_words ? ct_b : 0u) + ((dp_b + 3u) & ~3u);
+  }
+
   pl.hits_per_item = tune && tune->hits_per_item ? tune->hits_per_item
                                                  : (mode == CS_LARGE_G ? 128u : 1024u);
   pl.large_blocks = tune && tune->large_blocks ? tune->large_blocks : (uint32_t)n_cu * 8u;
@@ -166,13 +195,15 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out)
   L.ctrl = take(sizeof(JobCtrl));
   L.jobdev = take(sizeof(JobDev));
   L.items_base = take(2 * sizeof(uint64_t));
+  L.lim_base = take(2 * sizeof(uint64_t));
   L.n_base = take(8);
   L.n_primes = take(8);
-  L.base = take(kBaseCap * 4ull);
-  L.flags = take(pl.n_seg * kSegWords * 4ull);
-  L.seg_count = take(pl.n_seg * 4ull);
-  L.seg_off = take(pl.n_seg * 8ull);
-  L.primes = take(pl.cap * 8ull);
+  const uint64_t ns = own_primes ? pl.n_seg : 0;
+  L.base = take(own_primes ? kBaseCap * 4ull : 0);
+  L.flags = take(ns * kSegWords * 4ull);
+  L.seg_count = take(ns * 4ull);
+  L.seg_off = take(ns * 8ull);
+  L.primes = take(own_primes ? pl.cap * 8ull : 0);
   L.kmod = take(cap_lim * 8ull);
   L.mk = take(cap_lim * 8ull);
   L.row_of = take(j.m_inc * 4ull);
@@ -181,6 +212,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out)
   L.coltab = take(pl.ct_words * 8ull);
   L.kgroups = take((pl.kq.size() + 1) * 8ull);
   L.kq = take((pl.kq.size() + 1) * 4ull);
+  L.dpre = take(std::max<uint64_t>(pl.dpre.size(), 1) * 2ull);
   L.total = o;
   return CS_OK;
 }
@@ -190,7 +222,7 @@ void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
   const uint64_t hi = std::min<uint64_t>(p_hi, pl.job.limit);
   jd->tier_lo = lo;
   jd->n_tiers = 0;
-  if (hi <= lo) return;
+  if (hi <= lo || pl.n_m == 0) return;
   const double mw = (double)pl.job.m_inc * (double)(pl.w + 1);
   const double H = (double)pl.hits_per_item;
   uint64_t b = lo;
@@ -253,6 +285,12 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.kgroups = reinterpret_cast<uint64_t*>(ws + L.kgroups);
   jd.kq = reinterpret_cast<uint32_t*>(ws + L.kq);
   jd.ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
+  jd.d_small = pl.dpre.empty() ? 0u : 1u;
+  jd.phi_d = pl.phi_d;
+  jd.r0_d = pl.r0_d;
+  jd.pre_r0 = pl.dpre.empty() ? 0u : (uint32_t)(pl.dpre[pl.r0_d] & 0x7fffu);
+  jd.inv_d = 1.0 / (double)j.d;
+  jd.dpre = reinterpret_cast<const uint16_t*>(ws + L.dpre);
   fill_tiers(pl, 2, j.limit, &jd);
   return jd;
 }

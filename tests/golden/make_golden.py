@@ -1,0 +1,79 @@
+"""Writes the stored oracle results used by the GPU parity tests at full job sizes.
+
+Every value written here comes from oracle/ (the plain CPU sieve) on jobs from workloads/;
+nothing comes from the HIP path.  Run from the repository root:
+
+    python tests/golden/make_golden.py [medium] [paper] [batch]
+
+medium_503_rows.npz   per-row digests of the whole 503#/210 job (2,287 rows), plus 64 full rows
+paper_953_rows.npz    16 rows of the 953#/210 paper-scale job, primes up to 1e10: the first, the
+                      last, the row of m = 100054841 (the merit-38.048 record gap) and 13 seeded
+batch_rows.npz        4 rows of each of the 64 seeded mixed-batch jobs
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, HERE)
+
+import workloads as W  # noqa: E402
+from oracle import coracle  # noqa: E402
+from goldens import row_digests  # noqa: E402
+
+
+def medium():
+    job = W.MEDIUM
+    t = time.time()
+    ms = coracle.rows(job.d, job.m_start, job.m_inc)
+    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms, 2, job.limit, mode=coracle.CACHED)
+    full = W.sample_rows(len(ms), 64, seed=21)
+    np.savez_compressed(os.path.join(HERE, "medium_503_rows.npz"), job=np.array(job.as_tuple(), dtype=np.uint64),
+                        digests=row_digests(bits, counts), rows=np.array(full), bits=bits[full],
+                        counts=counts[full], total_factors=np.uint64(counts.sum()))
+    print(f"medium: {len(ms)} rows in {time.time() - t:.1f} s, {int(counts.sum())} factors")
+
+
+def paper():
+    job = W.PAPER_SCALE
+    t = time.time()
+    ms = coracle.rows(job.d, job.m_start, job.m_inc)
+    rec = W.RECORD_GAPS[0][2]
+    r_rec = int(np.searchsorted(ms, rec))
+    assert ms[r_rec] == rec
+    rows = W.sample_rows(len(ms), 16, seed=31, must=[r_rec])
+    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.CACHED)
+    np.savez_compressed(os.path.join(HERE, "paper_953_rows.npz"), job=np.array(job.as_tuple(), dtype=np.uint64),
+                        rows=np.array(rows), m=ms[rows], bits=bits, counts=counts, record_row=np.int64(r_rec))
+    print(f"paper: {len(rows)} rows in {time.time() - t:.1f} s")
+
+
+def batch():
+    jobs = W.batch_jobs(64, seed=0)
+    t = time.time()
+    out = {}
+    for i, job in enumerate(jobs):
+        ms = coracle.rows(job.d, job.m_start, job.m_inc)
+        if len(ms) == 0:
+            continue
+        rows = W.sample_rows(len(ms), 4, seed=100 + i)
+        bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.CACHED)
+        out[f"job{i}_rows"] = np.array(rows)
+        out[f"job{i}_bits"] = bits
+        out[f"job{i}_counts"] = counts
+        out[f"job{i}_tuple"] = np.array(job.as_tuple(), dtype=np.uint64)
+        print(f"  batch job {i}: {job} rows={len(ms)} ({time.time() - t:.0f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "batch_rows.npz"), **out)
+    print(f"batch: 64 jobs in {time.time() - t:.1f} s")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["medium", "paper", "batch"]
+    for w in which:
+        {"medium": medium, "paper": paper, "batch": batch}[w]()

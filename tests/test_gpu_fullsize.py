@@ -1,0 +1,89 @@
+"""GPU parity at full job sizes, in the launch configuration the benchmark times.
+
+Expected values are stored oracle results (tests/golden/make_golden.py, which calls only
+oracle/): every row of the 503#/210 job by digest, and sampled rows of the paper-scale 953#/210
+job with primes up to 1e10.  Rows the oracle cannot reach are checked by properties that hold
+at any size."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2012_03771_amd as cs  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from goldens import load, row_digests  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run(job, tune):
+    bitmap, counts, ws = cs.sieve(job, tune)
+    torch.cuda.synchronize()
+    diag = cs.diag_read(ws)
+    b = bitmap.cpu().numpy().view(np.uint32)
+    c = counts.cpu().numpy().view(np.uint32)
+    del bitmap, counts, ws
+    torch.cuda.empty_cache()
+    return b, c, diag
+
+
+MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP)]
+
+
+@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap"])
+def test_medium_503_every_row(tune):
+    g = load("medium_503_rows.npz")
+    job = W.Job(*[int(x) for x in g["job"]])
+    assert job == W.MEDIUM
+    _say("medium", tune)
+    b, c, diag = _run(job, tune)
+    dig = row_digests(b, c)
+    bad = np.nonzero(dig != g["digests"])[0]
+    assert len(bad) == 0, f"{len(bad)} of {len(dig)} rows differ from the oracle, first {bad[:5]}"
+    rows = g["rows"]
+    assert np.array_equal(b[rows], g["bits"]) and np.array_equal(c[rows], g["counts"])
+    assert int(c.sum()) == int(g["total_factors"])
+    assert diag.small_marks + diag.large_hits == int(g["total_factors"])
+    assert diag.n_primes == 5761455
+
+
+@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap"])
+def test_paper_953_sampled_rows_and_invariants(tune):
+    g = load("paper_953_rows.npz")
+    job = W.Job(*[int(x) for x in g["job"]])
+    assert job == W.PAPER_SCALE
+    _say("paper", tune)
+    b, c, diag = _run(job, tune)
+    lay = cs.plan(job)
+    rows = g["rows"]
+    assert np.array_equal(cs.rows(job)[rows], g["m"])
+    got_b, got_c = b[rows], c[rows]
+    diff = np.nonzero((got_b != g["bits"]).any(axis=1) | (got_c != g["counts"]))[0]
+    assert len(diff) == 0, f"sampled rows {rows[diff]} differ from the oracle"
+    # the merit-38.048 record: 100054841*953#/210 - 9670 is prime, so its bit is clear
+    xs = cs.columns(job)
+    col = int(np.searchsorted(xs, -9670))
+    assert xs[col] == -9670
+    r = int(g["record_row"])
+    assert (b[r, col // 32] >> np.uint32(col % 32)) & 1 == 0
+    # every row: padding bits clear, counts at least the number of marked columns
+    pad = lay.row_words * 32 - lay.n_x
+    if pad:
+        assert not np.any(b[:, -1] >> np.uint32(32 - pad))
+    lut = np.array([bin(i).count("1") for i in range(256)], dtype=np.uint16)
+    b8 = b.view(np.uint8)
+    for lo in range(0, len(c), 16384):
+        pop = lut[b8[lo:lo + 16384]].sum(axis=1, dtype=np.int64)
+        assert np.all(c[lo:lo + 16384] >= pop)
+    assert int(c.astype(np.int64).sum()) == diag.small_marks + diag.large_hits
+    assert diag.n_primes == 455052511
+    assert diag.error_flags == 0
