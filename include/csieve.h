@@ -201,6 +201,70 @@ cs_status cs_batch_diag(cs_batch* b, cs_diag* out, void* stream);
 /* Frees the handle (waits for the device first).  NULL is a no-op. */
 cs_status cs_batch_destroy(cs_batch* b);
 
+/* ------------------------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  The server keeps the prime table (up to
+ * max_limit) and K mod p tables (per (P, d), reused by any later job whose limit they cover)
+ * resident, admits queued jobs in arrival order as slots and budget allow, and runs
+ * iterations on its own stream: one iteration is one fused launch sequence that advances every
+ * active job by one prime-range chunk (small primes first, then `chunks` ranges of large
+ * primes).  Jobs that arrive while others run join the next iteration.  Each job's result is
+ * bit-identical to cs_sieve of that job alone.  Outputs live in the server's memory until
+ * released.  A server handle may be used from several host threads.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct cs_server cs_server;
+
+typedef struct cs_server_config {
+  uint64_t budget_bytes;   /* device bytes for per-job tables, K mod p tables and outputs */
+  uint64_t max_limit;      /* largest max(limit, P) accepted; the resident prime table reaches it */
+  uint32_t max_active;     /* jobs in flight at once (slots) */
+  uint32_t chunks;         /* large-prime chunks per job (0 = 4) */
+  cs_tune tune;            /* applied to every job */
+} cs_server_config;
+
+typedef struct cs_ticket_info {
+  int32_t state;           /* 0 queued, 1 running, 2 done, -1 failed */
+  uint32_t n_x;
+  uint32_t row_words;
+  uint32_t pad;
+  uint64_t n_m;
+  double queued_s;         /* submit -> admission (or now) */
+  double latency_s;        /* submit -> completion (or now) */
+} cs_ticket_info;
+
+typedef struct cs_server_stats {
+  uint64_t submitted, admitted, completed, failed, iterations;
+  uint64_t kmod_builds, kmod_hits, kmod_evictions;
+  uint64_t bytes_in_use, active, queued;
+} cs_server_counters;
+
+/* Allocates budget_bytes plus the prime table on the current device, builds the prime table
+ * and starts the server thread.  Errors: CS_EINVAL, CS_ERANGE (max_limit), CS_ENOMEM,
+ * CS_EDEVICE. */
+cs_status cs_server_create(const cs_server_config* cfg, cs_server** out);
+
+/* Queues a job and returns its ticket; never blocks on the device.  CS_ERANGE if the job can
+ * never fit the budget or its limit exceeds max_limit; validation errors as cs_plan. */
+cs_status cs_server_submit(cs_server* s, const cs_job* job, uint64_t* ticket);
+
+/* State and timing of a ticket (CS_EDEVICE if it failed). */
+cs_status cs_server_poll(cs_server* s, uint64_t ticket, cs_ticket_info* out);
+
+/* Waits until the ticket is done or failed, at most timeout_s seconds (CS_EBUSY on timeout). */
+cs_status cs_server_wait(cs_server* s, uint64_t ticket, double timeout_s, cs_ticket_info* out);
+
+/* Copies a done ticket's outputs (layout as cs_sieve) to caller-owned device buffers on
+ * `stream`.  CS_EBUSY if not done yet. */
+cs_status cs_server_copy_outputs(cs_server* s, uint64_t ticket, uint32_t* d_bitmap, uint32_t* d_counts,
+                                 void* stream);
+
+/* Frees a finished ticket's outputs (synchronise any copy first).  CS_EBUSY if still running. */
+cs_status cs_server_release(cs_server* s, uint64_t ticket);
+
+cs_status cs_server_stats(cs_server* s, cs_server_counters* out);
+
+/* Stops the thread after the current iteration and frees everything.  NULL is a no-op. */
+cs_status cs_server_destroy(cs_server* s);
+
 #ifdef __cplusplus
 }
 #endif

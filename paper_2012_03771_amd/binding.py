@@ -46,6 +46,22 @@ class cs_diag(C.Structure):
                                           "g_levels", "error_flags")]
 
 
+class cs_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_limit", C.c_uint64), ("max_active", C.c_uint32),
+                ("chunks", C.c_uint32), ("tune", cs_tune)]
+
+
+class cs_ticket_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("n_x", C.c_uint32), ("row_words", C.c_uint32), ("pad", C.c_uint32),
+                ("n_m", C.c_uint64), ("queued_s", C.c_double), ("latency_s", C.c_double)]
+
+
+class cs_server_counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "iterations",
+                                          "kmod_builds", "kmod_hits", "kmod_evictions", "bytes_in_use",
+                                          "active", "queued")]
+
+
 @dataclass
 class Tune:
     thr: int = 0
@@ -122,6 +138,14 @@ def lib():
         "cs_batch_run": ([vp, P(vp), P(vp), i32, vp], i32),
         "cs_batch_diag": ([vp, P(cs_diag), vp], i32),
         "cs_batch_destroy": ([vp], i32),
+        "cs_server_create": ([P(cs_server_config), P(vp)], i32),
+        "cs_server_submit": ([vp, P(cs_job), P(u64)], i32),
+        "cs_server_poll": ([vp, u64, P(cs_ticket_info)], i32),
+        "cs_server_wait": ([vp, u64, C.c_double, P(cs_ticket_info)], i32),
+        "cs_server_copy_outputs": ([vp, u64, vp, vp, vp], i32),
+        "cs_server_release": ([vp, u64], i32),
+        "cs_server_stats": ([vp, P(cs_server_counters)], i32),
+        "cs_server_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -309,6 +333,64 @@ class Batch:
     def close(self):
         if self.h:
             lib().cs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching sieve server (native loop in libcsieve; this class only marshals)."""
+
+    def __init__(self, budget_bytes: int, max_limit: int, max_active: int = 16, chunks: int = 4,
+                 tune: Tune | None = None):
+        cfg = cs_server_config(budget_bytes, max_limit, max_active, chunks, (tune or Tune()).c())
+        h = C.c_void_p()
+        _check(lib().cs_server_create(C.byref(cfg), C.byref(h)), "cs_server_create")
+        self.h = h
+
+    def submit(self, job) -> int:
+        t = C.c_uint64()
+        _check(lib().cs_server_submit(self.h, C.byref(_cjob(job)), C.byref(t)), "cs_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        info = cs_ticket_info()
+        st = lib().cs_server_poll(self.h, ticket, C.byref(info))
+        _check(st, "cs_server_poll")
+        return info
+
+    def wait(self, ticket: int, timeout_s: float = 120.0):
+        info = cs_ticket_info()
+        st = lib().cs_server_wait(self.h, ticket, timeout_s, C.byref(info))
+        _check(st, "cs_server_wait")
+        return info
+
+    def fetch(self, ticket: int, stream=None):
+        """Copies a finished ticket's outputs into new device tensors."""
+        import torch
+        info = self.poll(ticket)
+        bm = torch.empty((info.n_m, info.row_words), dtype=torch.int32, device="cuda")
+        ct = torch.empty((info.n_m,), dtype=torch.int32, device="cuda")
+        _check(lib().cs_server_copy_outputs(self.h, ticket, _ptr(bm) if bm.numel() else None,
+                                            _ptr(ct) if ct.numel() else None, _stream(stream)),
+               "cs_server_copy_outputs")
+        return bm, ct
+
+    def release(self, ticket: int):
+        _check(lib().cs_server_release(self.h, ticket), "cs_server_release")
+
+    def stats(self) -> dict:
+        out = cs_server_counters()
+        _check(lib().cs_server_stats(self.h, C.byref(out)), "cs_server_stats")
+        return {f[0]: getattr(out, f[0]) for f in cs_server_counters._fields_}
+
+    def close(self):
+        if self.h:
+            lib().cs_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

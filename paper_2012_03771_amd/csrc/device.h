@@ -56,6 +56,7 @@ struct JobDev {
   uint32_t r0_d;                     // m_start mod d
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
+  uint32_t kmod_cached, pad2;        // 1: kmod already holds K mod p (a shared table); only mk is built
   const uint16_t* dpre;              // d entries: bit 15 = coprime to d, bits 0-14 = coprime residues below
   uint64_t tier_lo;                  // tier 0 holds primes in (tier_lo, tier_hi[0]]
   uint64_t tier_hi[kMaxTiers];

@@ -317,13 +317,18 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
     }
     const JobDev& j = jobs[lo];
     const uint64_t i = g - lim_base[lo];
-    const uint32_t ng = j.ctrl->n_kgroups;
-    const uint64_t* __restrict__ G = j.kgroups;
     const uint64_t p = j.primes[i];
     const double pinv = 1.0 / (double)p;
-    uint64_t r = 1 % p;
-    for (uint32_t t = 0; t < ng; ++t) r = mulmod(r, G[t], p, pinv);
-    j.kmod[i] = r;
+    uint64_t r;
+    if (j.kmod_cached) {
+      r = j.kmod[i];
+    } else {
+      const uint32_t ng = j.ctrl->n_kgroups;
+      const uint64_t* __restrict__ G = j.kgroups;
+      r = 1 % p;
+      for (uint32_t t = 0; t < ng; ++t) r = mulmod(r, G[t], p, pinv);
+      j.kmod[i] = r;
+    }
     j.mk[i] = mulmod(mod64(j.m_start, p, pinv), r, p, pinv);
   }
 }

@@ -50,8 +50,10 @@ struct Plan {
 uint64_t pi_upper(uint64_t x);
 
 // Validates the job and fills everything except the range-dependent tiers.  With own_primes
-// false the workspace layout leaves out the prime table (a batch or server shares one).
-cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes = true);
+// false the workspace layout leaves out the prime table (a batch or server shares one); with
+// own_kmod false it leaves out the K mod p table (a server shares one per (P, d)).
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes = true,
+                    bool own_kmod = true);
 
 // Host count of rows and columns (also used by cs_rows / cs_columns).
 void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs);

@@ -69,7 +69,7 @@ uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq) {
   return (uint64_t)(coprime_below((u128)job.m_start + job.m_inc, dq) - coprime_below(job.m_start, dq));
 }
 
-cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes) {
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes, bool own_kmod) {
   if (!job || !out) return CS_EINVAL;
   const cs_job j = *job;
   if (j.P < 2 || j.P >= kMaxP) return CS_EINVAL;
@@ -204,7 +204,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.seg_count = take(ns * 4ull);
   L.seg_off = take(ns * 8ull);
   L.primes = take(own_primes ? pl.cap * 8ull : 0);
-  L.kmod = take(cap_lim * 8ull);
+  L.kmod = take(own_kmod ? cap_lim * 8ull : 0);
   L.mk = take(cap_lim * 8ull);
   L.row_of = take(j.m_inc * 4ull);
   L.m_off = take(std::max<uint64_t>(pl.n_m, 1) * 4ull);
