@@ -29,12 +29,21 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["g", "three_gap"], default="g")
+    ap.add_argument("--mode", choices=["g", "three_gap"], default="three_gap")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--cpu-pmax", type=int, default=2**30)
     ap.add_argument("--workload", default="paper_953")
     ap.add_argument("--phase-only", action="store_true", help="time the phases once, no steps")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-job batched leg")
+    ap.add_argument("--traffic-gb", type=float, default=None,
+                    help="HBM traffic of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile "
+                         "of the same kernel (GB), reported as roofline.traffic")
+    ap.add_argument("--also-g", action="store_true",
+                    help="also time the phases once with one Eq. 5 solve per hit (the paper's enumeration)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (Poisson) leg")
+    ap.add_argument("--serve-jobs", type=int, default=512)
+    ap.add_argument("--serve-warmup", type=int, default=32)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (a known-size reference for "
                          "HBM byte counters)")
@@ -70,6 +79,86 @@ def _cpu_baseline(job, n_rows, p_max):
             "sample": f"{len(ms)} rows of {lay.n_m} (first, last, record-gap row, seeded), primes <= "
                       f"{min(p_max, job.limit)}, plain per-interval sieve with bignum N mod p "
                       f"(direct mode), {dt:.1f} s wall"}
+
+
+def _batch_leg(cs, torch, W, mode, reps=3):
+    """64 seeded mixed jobs: one fused launch sequence replayed from a hipGraph, against 64
+    sequential cs_sieve calls on the same GPU."""
+    jobs = W.batch_jobs(64, seed=0)
+    tunes = [cs.Tune(large_mode=mode) for _ in jobs]
+    batch = cs.Batch(jobs, tunes)
+    bm, ct = batch.alloc_outputs()
+    batch.run(bm, ct, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.run(bm, ct, use_graph=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    factors = sum(int(c.to(torch.int64).sum().item()) for c in ct)
+    diag = batch.diag()
+    # the same jobs, one plain launch sequence each, one after the other
+    lays = [cs.plan(j, t) for j, t in zip(jobs, tunes)]
+    ws = torch.empty((max(L.ws_bytes for L in lays),), dtype=torch.uint8, device="cuda")
+    sb = [torch.empty((L.n_m, L.row_words), dtype=torch.int32, device="cuda") for L in lays]
+    sc = [torch.empty((L.n_m,), dtype=torch.int32, device="cuda") for L in lays]
+    for i, j in enumerate(jobs):
+        cs.sieve_into(j, sb[i], sc[i], ws, tunes[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i, j in enumerate(jobs):
+            cs.sieve_into(j, sb[i], sc[i], ws, tunes[i])
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    same = all(torch.equal(a, b) for a, b in zip(bm, sb)) and all(torch.equal(a, b) for a, b in zip(ct, sc))
+    batch.close()
+    del bm, ct, sb, sc, ws
+    torch.cuda.empty_cache()
+    return {"workload": "64 seeded mixed jobs (P in primes [307,1019], d in {1,2,6,30,210}, m_inc 1e3-1e5, "
+                        "limit 1e7-1e9, sl = round(40 ln N))",
+            "ms_batched": t_batch * 1e3, "ms_sequential": t_seq * 1e3, "speedup": t_seq / t_batch,
+            "jobs_per_s": 64 / t_batch, "factors_per_s": factors / t_batch,
+            "seq_jobs_per_s": 64 / t_seq, "factors": factors, "identical_to_sequential": bool(same),
+            "primes_in_shared_table": diag.n_primes}
+
+
+def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm):
+    """Poisson arrivals of jobs from the mixed-batch distribution into the continuous-batching
+    server (64 GB budget); latency = completion - arrival."""
+    import numpy as np
+    times, jobs = W.poisson_arrivals(n_warm + n_jobs, rate, seed=1)
+    srv = cs.Server(budget_bytes=64 << 30, max_limit=max(j.limit for j in jobs), max_active=32, chunks=4,
+                    tune=cs.Tune(large_mode=mode))
+    tickets = []
+    t0 = time.perf_counter()
+    for t_arr, job in zip(times, jobs):
+        delay = t_arr - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(job))
+    lat, factors = [], 0
+    t_first = None
+    for i, t in enumerate(tickets):
+        info = srv.wait(t, 600.0)
+        if i >= n_warm:
+            lat.append(info.latency_s)
+            if t_first is None:
+                t_first = times[i]
+            _, c = srv.fetch(t)
+            factors += int(c.to(torch.int64).sum().item())
+        srv.release(t)
+    t_end = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    span = t_end - t_first
+    lat = np.array(lat)
+    return {"workload": f"{n_jobs} jobs (+{n_warm} warm-up) from the mixed-batch distribution, Poisson arrivals, "
+                        "64 GB admission budget, 32 slots, 4 large-prime chunks per job",
+            "arrival_rate_per_s": rate, "jobs_per_s": n_jobs / span, "factors_per_s": factors / span,
+            "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_latency_ms": float(lat.mean() * 1e3), "iterations": st["iterations"],
+            "kmod_table_hits": st["kmod_hits"], "kmod_table_builds": st["kmod_builds"]}
 
 
 def main():
@@ -144,13 +233,13 @@ def main():
     value = factors / T
     primes_per_s = diag.n_primes / T
 
-    # roofline of the large branch (one k_large launch per step): algorithmic VALU operations =
-    # recursion levels x operations per level + solves x per-solve operations
+    # roofline of the large branch (one k_large launch per step): algorithmic VALU operations
+    # = units counted by the kernel x their operation prices (paper_2012_03771_amd/roofline.py)
     from paper_2012_03771_amd import roofline as RL
     t_large = phases["large"] / 1e3
-    ops = RL.large_branch_ops(diag_ph)
+    ops = RL.large_branch_ops(diag_ph, args.mode == "three_gap")
     roof = {"bound": "alu", "kernel": "k_large", "achieved": ops / t_large / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS, "traffic": None,
+            "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS, "traffic": args.traffic_gb,
             "ops_per_launch": ops, "launch_ms": phases["large"]}
 
     out = {
@@ -166,6 +255,46 @@ def main():
                                                   "g_calls", "g_levels")},
         "roofline": roof,
     }
+    if args.also_g and args.mode != "g":
+        tg = cs.Tune(large_mode=cs.LARGE_G)
+        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        bitmap.zero_()
+        counts.zero_()
+        ev2[0].record(stream)
+        cs.prepare(job, ws, tg, stream)
+        ev2[1].record(stream)
+        cs.sieve_range(job, 2, job.limit, bitmap, counts, ws, cs.Tune(large_mode=cs.LARGE_G, branches=cs.BRANCH_SMALL), stream)
+        ev2[2].record(stream)
+        cs.sieve_range(job, 2, job.limit, bitmap, counts, ws, cs.Tune(large_mode=cs.LARGE_G, branches=cs.BRANCH_LARGE), stream)
+        ev2[3].record(stream)
+        torch.cuda.synchronize()
+        dg = cs.diag_read(ws, stream)
+        ph = {"prepare": ev2[0].elapsed_time(ev2[1]), "small": ev2[1].elapsed_time(ev2[2]),
+              "large": ev2[2].elapsed_time(ev2[3])}
+        og = RL.large_branch_ops(dg, False)
+        tlg = ph["large"] / 1e3
+        out["g_mode"] = {"phases_ms": ph, "ms_per_step": sum(ph.values()), "thr": cs.plan(job, tg).thr,
+                         "factors_per_s": factors / (sum(ph.values()) / 1e3),
+                         "identical": bool(torch.equal(bitmap, ref_bitmap) and torch.equal(counts, ref_counts)),
+                         "g_calls": dg.g_calls, "g_levels": dg.g_levels,
+                         "roofline": {"bound": "alu", "kernel": "k_large", "achieved": og / tlg / 1e12,
+                                      "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
+                                      "frac": og / tlg / ALU_PEAK_OPS, "ops_per_launch": og,
+                                      "launch_ms": ph["large"]}}
+    mode_b = cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP
+    del bitmap, counts, ws, ref_bitmap, ref_counts
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        print("# batch leg ...", file=sys.stderr, flush=True)
+        out["batch"] = _batch_leg(cs, torch, W, mode_b)
+        print(f"# batch {out['batch']['ms_batched']:.1f} ms vs sequential {out['batch']['ms_sequential']:.1f} ms",
+              file=sys.stderr, flush=True)
+    if not args.no_serve:
+        rate = 0.8 * out["batch"]["jobs_per_s"] if "batch" in out else 20.0
+        print(f"# serve leg at {rate:.1f} jobs/s ...", file=sys.stderr, flush=True)
+        out["serve"] = _serve_leg(cs, torch, W, mode_b, rate, args.serve_jobs, args.serve_warmup)
+        print(f"# serve p50 {out['serve']['p50_latency_ms']:.1f} ms p99 {out['serve']['p99_latency_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = _cpu_baseline(job, args.cpu_rows, args.cpu_pmax)
