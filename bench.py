@@ -36,6 +36,7 @@ def _args():
     ap.add_argument("--workload", default="paper_953")
     ap.add_argument("--phase-only", action="store_true", help="time the phases once, no steps")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-job batched leg")
+    ap.add_argument("--no-autotune", action="store_true", help="batch leg with default tunings")
     ap.add_argument("--traffic-gb", type=float, default=None,
                     help="HBM traffic of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile "
                          "of the same kernel (GB), reported as roofline.traffic")
@@ -81,11 +82,21 @@ def _cpu_baseline(job, n_rows, p_max):
                       f"(direct mode), {dt:.1f} s wall"}
 
 
-def _batch_leg(cs, torch, W, mode, reps=3):
+def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
     """64 seeded mixed jobs: one fused launch sequence replayed from a hipGraph, against 64
-    sequential cs_sieve calls on the same GPU."""
+    sequential cs_sieve calls on the same GPU (both with the same tunings)."""
     jobs = W.batch_jobs(64, seed=0)
-    tunes = [cs.Tune(large_mode=mode) for _ in jobs]
+    t_tune = 0.0
+    n_buckets = 0
+    if autotune:
+        from paper_2012_03771_amd.autotune import Autotuner
+        t0 = time.perf_counter()
+        tuner = Autotuner()
+        tunes = tuner.tune_all(jobs)
+        t_tune = time.perf_counter() - t0
+        n_buckets = len(tuner.cache)
+    else:
+        tunes = [cs.Tune(large_mode=mode) for _ in jobs]
     batch = cs.Batch(jobs, tunes)
     bm, ct = batch.alloc_outputs()
     batch.run(bm, ct, use_graph=True)
@@ -120,7 +131,8 @@ def _batch_leg(cs, torch, W, mode, reps=3):
             "ms_batched": t_batch * 1e3, "ms_sequential": t_seq * 1e3, "speedup": t_seq / t_batch,
             "jobs_per_s": 64 / t_batch, "factors_per_s": factors / t_batch,
             "seq_jobs_per_s": 64 / t_seq, "factors": factors, "identical_to_sequential": bool(same),
-            "primes_in_shared_table": diag.n_primes}
+            "primes_in_shared_table": diag.n_primes, "autotuned": autotune, "autotune_buckets": n_buckets,
+            "autotune_s": t_tune}
 
 
 def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm):
@@ -286,7 +298,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batch:
         print("# batch leg ...", file=sys.stderr, flush=True)
-        out["batch"] = _batch_leg(cs, torch, W, mode_b)
+        out["batch"] = _batch_leg(cs, torch, W, mode_b, autotune=not args.no_autotune)
         print(f"# batch {out['batch']['ms_batched']:.1f} ms vs sequential {out['batch']['ms_sequential']:.1f} ms",
               file=sys.stderr, flush=True)
     if not args.no_serve:

@@ -1,0 +1,81 @@
+"""Autotuner for the sieve's launch knobs, per job-shape bucket.
+
+A bucket is (log2 rows, log2 columns, half-decade of the sieve limit, d).  For the first job of
+a bucket every candidate tuning is timed with cs_sieve (one warm-up, then the fastest of two
+timed runs, HIP events on the launch stream) and the fastest is kept for the whole bucket.
+Candidates vary the small/large threshold (a multiple of S = 2 sl + 1, Section 5's C_mult) and
+the expected hits per large-branch work item; all give identical outputs, so the choice only
+affects speed.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import binding as B
+
+DEFAULT_CANDIDATES = [
+    {"thr_mult": m, "hits_per_item": h, "large_mode": B.LARGE_THREE_GAP}
+    for m in (4, 10, 25) for h in (512, 2048)
+]
+
+
+class Autotuner:
+    def __init__(self, candidates=None, cache_path: str | None = None):
+        self.candidates = candidates or DEFAULT_CANDIDATES
+        self.cache_path = cache_path
+        self.cache: dict[str, dict] = {}
+        self.timings: dict[str, list] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    @staticmethod
+    def bucket(job) -> str:
+        lay = B.plan(job)
+        P, d, m_start, m_inc, sl, limit = B.job_tuple(job)
+        return "%d/%d/%.1f/%d" % (round(math.log2(max(lay.n_m, 1))), round(math.log2(max(lay.n_x, 1))),
+                                  round(2 * math.log10(limit)) / 2, d)
+
+    @staticmethod
+    def _tune_of(job, cand) -> B.Tune:
+        sl = B.job_tuple(job)[4]
+        return B.Tune(thr=int(cand["thr_mult"] * (2 * sl + 1)), hits_per_item=cand["hits_per_item"],
+                      large_mode=cand["large_mode"])
+
+    def _time(self, job, tune, bitmap, counts, ws) -> float:
+        import torch
+        s = torch.cuda.current_stream()
+        B.sieve_into(job, bitmap, counts, ws, tune, s)
+        best = float("inf")
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            B.sieve_into(job, bitmap, counts, ws, tune, s)
+            e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    def tune(self, job) -> B.Tune:
+        key = self.bucket(job)
+        if key not in self.cache:
+            import torch
+            lays = [B.plan(job, self._tune_of(job, c)) for c in self.candidates]
+            lay0 = lays[0]
+            bitmap = torch.empty((lay0.n_m, lay0.row_words), dtype=torch.int32, device="cuda")
+            counts = torch.empty((lay0.n_m,), dtype=torch.int32, device="cuda")
+            ws = torch.empty((max(L.ws_bytes for L in lays),), dtype=torch.uint8, device="cuda")
+            times = [self._time(job, self._tune_of(job, c), bitmap, counts, ws) for c in self.candidates]
+            best = min(range(len(times)), key=times.__getitem__)
+            self.cache[key] = dict(self.candidates[best])
+            self.timings[key] = times
+            del bitmap, counts, ws
+            if self.cache_path:
+                with open(self.cache_path, "w") as f:
+                    json.dump(self.cache, f, indent=1)
+        return self._tune_of(job, self.cache[key])
+
+    def tune_all(self, jobs):
+        return [self.tune(j) for j in jobs]

@@ -106,7 +106,11 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
   CS_TRY(launch_prep_tables(jdp, 1, s));
   CS_TRY(launch_kmod(jdp, 1, reinterpret_cast<uint64_t*>(ws + L.lim_base), pi_upper(pl.job.limit), n_cu, s));
   CS_TRY(launch_rows_cols(jdp, 1, pl.job.m_inc, pl.job.sl, n_cu, s));
-  if (!pl.dpre.empty()) CS_TRY(launch_upload(ws + L.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
+  if (!pl.dpre.empty()) {
+    CS_TRY(launch_upload(ws + L.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
+    CS_TRY(launch_upload(ws + L.dres, pl.dres.data(), pl.dres.size() * 2ull, s));
+  }
+  if (pl.dpat_on) CS_TRY(launch_dpattern(jdp, 1, pl.phi_d, pl.row_words, s));
   return CS_OK;
 }
 

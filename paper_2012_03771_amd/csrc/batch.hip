@@ -127,8 +127,14 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
     b.jds[i].small_unit_base = unit_base;
     b.jds[i].prime_cap = b.cap;
     unit_base += (uint64_t)pl.n_windows * pl.n_slices;
-    if (!pl.dpre.empty())
+    if (!pl.dpre.empty()) {
       CS_TRY(launch_upload(ws + pl.ws.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
+      CS_TRY(launch_upload(ws + pl.ws.dres, pl.dres.data(), pl.dres.size() * 2ull, s));
+    }
+    if (pl.dpat_on) {
+      b.max_phi = std::max(b.max_phi, pl.phi_d);
+      b.max_rw = std::max(b.max_rw, pl.row_words);
+    }
   }
   b.units = unit_base;
   b.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b.units, 1), (uint64_t)b.n_cu * 2);
@@ -156,6 +162,7 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   CS_TRY(launch_prep_tables(b.jobs_dev, n, s));
   CS_TRY(launch_kmod(b.jobs_dev, n, b.lim_base, b.kmod_cap, b.n_cu, s));
   CS_TRY(launch_rows_cols(b.jobs_dev, n, b.max_m_inc, b.max_sl, b.n_cu, s));
+  CS_TRY(launch_dpattern(b.jobs_dev, n, b.max_phi, b.max_rw, s));
   CS_TRY(launch_prep_bounds(b.jobs_dev, n, s));
   CS_TRY(launch_items_scan(b.jobs_dev, n, b.items_base, s));
   CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));

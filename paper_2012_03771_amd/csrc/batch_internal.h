@@ -30,6 +30,7 @@ struct MultiJob {
   // launch shapes
   uint64_t units = 0, max_words = 0, max_m_inc = 0, kmod_cap = 0;
   uint32_t small_blocks = 1, large_blocks = 1, lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
+  uint32_t max_phi = 0, max_rw = 0;   // class-pattern launch shape
 };
 
 void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune);

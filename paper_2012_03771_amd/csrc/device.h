@@ -57,6 +57,13 @@ struct JobDev {
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
   uint32_t kmod_cached, pad2;        // 1: kmod already holds K mod p (a shared table); only mk is built
+  // Marks of the primes dividing d depend only on m mod d: one packed row (and its factor
+  // count) per residue class coprime to d, built once per job and OR-ed into each row's tile.
+  uint32_t dpat_on;                  // pattern table built for this job
+  uint32_t dpat_apply;               // this call's prime range covers every prime dividing d
+  uint32_t* dpat;                    // phi(d) x row_words words
+  uint32_t* dpat_cnt;                // phi(d) counts
+  const uint16_t* dres;              // the phi(d) residues coprime to d, ascending
   const uint16_t* dpre;              // d entries: bit 15 = coprime to d, bits 0-14 = coprime residues below
   uint64_t tier_lo;                  // tier 0 holds primes in (tier_lo, tier_hi[0]]
   uint64_t tier_hi[kMaxTiers];

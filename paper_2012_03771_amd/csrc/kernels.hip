@@ -42,6 +42,16 @@ __device__ uint64_t upper_index(const uint64_t* t, uint64_t n, uint64_t x) {
   return lo;
 }
 
+// Column of offset j = X + sl from the table {mask, columns before} per 32 offsets, or false
+// if X is not a column (gcd(X, K) > 1).
+__device__ __forceinline__ bool lookup_col(const uint2* ct, uint32_t jj, uint32_t* col) {
+  const uint2 e = ct[jj >> 5];
+  const uint32_t b = jj & 31;
+  if (!((e.x >> b) & 1u)) return false;
+  *col = e.y + __popc(e.x & ((1u << b) - 1u));
+  return true;
+}
+
 // Block-wide exclusive scan of one uint32 per thread (blockDim.x <= 1024, multiple of 64).
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -509,19 +519,58 @@ __global__ void k_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base
   base[n_jobs] = s;
 }
 
+// Per residue class c of m mod d (c coprime to d): the packed column marks and factor count
+// of the primes q dividing d.  For those primes N mod q = (m mod q)(K mod q) mod q depends
+// only on m mod d, so one row per class replaces their per-row marking (Eq. 1).
+__global__ __launch_bounds__(256) void k_dpattern(const JobDev* __restrict__ jobs) {
+  extern __shared__ uint32_t row[];
+  __shared__ uint32_t kmq[kMaxDq];
+  __shared__ uint32_t cnt_sh;
+  const JobDev& j = jobs[blockIdx.y];
+  if (!j.dpat_on) return;
+  const JobCtrl& c = *j.ctrl;
+  const uint32_t nd = c.n_dq < kMaxDq ? c.n_dq : kMaxDq;
+  if (threadIdx.x < nd) {
+    const uint32_t q = c.dq[threadIdx.x];
+    uint32_t r = 1 % q;
+    for (uint32_t i = 0; i < c.n_kq; ++i) r = (uint32_t)(((uint64_t)r * (j.kq[i] % q)) % q);
+    kmq[threadIdx.x] = r;                           // K mod q
+  }
+  __syncthreads();
+  const uint32_t rw = j.row_words, w = j.w;
+  for (uint32_t cls = blockIdx.x; cls < j.phi_d; cls += gridDim.x) {
+    for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) row[u] = 0;
+    if (threadIdx.x == 0) cnt_sh = 0;
+    __syncthreads();
+    const uint32_t res = j.dres[cls];
+    uint32_t cc = 0;
+    for (uint32_t t = 0; t < nd; ++t) {
+      const uint32_t q = c.dq[t];
+      const uint32_t nq = (uint32_t)(((uint64_t)(res % q) * kmq[t]) % q);     // N mod q
+      const uint32_t s0 = (j.sl % q + q - nq) % q;                            // j = X + sl
+      for (uint64_t jj = s0 + (uint64_t)threadIdx.x * q; jj <= w; jj += (uint64_t)blockDim.x * q) {
+        uint32_t col;
+        if (lookup_col(j.coltab, (uint32_t)jj, &col)) {
+          atomicOr(&row[col >> 5], 1u << (col & 31));
+          ++cc;
+        }
+      }
+    }
+    cc = wave_sum_u32(cc);
+    if ((threadIdx.x & (kWave - 1)) == 0 && cc) atomicAdd(&cnt_sh, cc);
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) j.dpat[(uint64_t)cls * rw + u] = row[u];
+    if (threadIdx.x == 0) j.dpat_cnt[cls] = cnt_sh;
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Small-prime branch (Section 3.1 space-time tradeoff; Section 5: p/S < C_mult).
 // One unit = (job, window of tile_rows consecutive rows, prime slice).  For every row and
 // prime, N mod p = m*K mod p comes from the cached K mod p (Eq. 1), and the offsets
 // X = -N (mod p) of the window are marked in an LDS tile of packed column bits.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ bool lookup_col(const uint2* ct, uint32_t jj, uint32_t* col) {
-  const uint2 e = ct[jj >> 5];
-  const uint32_t b = jj & 31;
-  if (!((e.x >> b) & 1u)) return false;
-  *col = e.y + __popc(e.x & ((1u << b) - 1u));
-  return true;
-}
 
 __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t p) {
   return a >= b ? a - b : a + p - b;
@@ -562,6 +611,25 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
     for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     const uint2* ct = ct_in_lds ? ct_l : j.coltab;
+    const bool dpat = j.dpat_apply != 0;
+    if (dpat && slice == 0) {
+      // primes dividing d: the row of this m's residue class (tile rows start cleared)
+      const double dd = (double)j.d;
+      for (uint32_t r = 0; r < R; ++r) {
+        const double x = (double)j.r0_d + (double)j.m_off[row_lo + r];
+        double rr = fma(-floor(x * j.inv_d), dd, x);
+        rr = rr < 0.0 ? rr + dd : (rr >= dd ? rr - dd : rr);
+        const uint32_t cls = j.dpre[(uint32_t)rr] & 0x7fffu;
+        const uint32_t* src = j.dpat + (uint64_t)cls * rw;
+        for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) tile[r * rw + u] = src[u];
+        if (threadIdx.x == 0) {
+          const uint32_t pc = j.dpat_cnt[cls];
+          cnt[r] = pc;
+          n_marks += pc;
+        }
+      }
+      __syncthreads();
+    }
 
     // dense primes: one wave per prime, lanes stride over its multiples in each row
     const uint64_t d_hi = min(s_hi, max(c.small_dense, s_lo));
@@ -569,6 +637,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
       const uint64_t p = j.primes[i];
       const uint64_t k = j.kmod[i];
       if (k == 0) continue;                         // p | K: never divides a column's N + X
+      if (dpat && p <= j.P) continue;               // p | d: marked by the class pattern
       const double pinv = 1.0 / (double)p;
       const uint64_t mk = j.mk[i];
       const uint64_t slp = mod64(j.sl, p, pinv);
@@ -600,7 +669,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
       bool act = i < s_hi;
       uint64_t p = 3, k = 0, mk = 0;
       if (act) { p = j.primes[i]; k = j.kmod[i]; mk = j.mk[i]; }
-      act = act && k != 0;
+      act = act && k != 0 && !(dpat && p <= j.P);
       const double pinv = 1.0 / (double)p;
       uint64_t s = 0;
       uint32_t o_prev = 0;
@@ -968,6 +1037,14 @@ hipError_t launch_rows_cols(const JobDev* jobs, uint32_t n_jobs, uint64_t max_m_
   if (cb > 4096) cb = 4096;
   hipLaunchKernelGGL(k_cols_mask, dim3(cb, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_cols_mask"); if (e_ != hipSuccess) return e_; }
   hipLaunchKernelGGL(k_cols_prefix, dim3(1, n_jobs), dim3(1024), 0, s, jobs); { hipError_t e_ = note("k_cols_prefix"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_dpattern(const JobDev* jobs, uint32_t n_jobs, uint32_t max_phi, uint32_t max_row_words,
+                           hipStream_t s) {
+  if (max_phi == 0) return hipSuccess;
+  const uint32_t blocks = max_phi < 1024 ? max_phi : 1024;
+  hipLaunchKernelGGL(k_dpattern, dim3(blocks, n_jobs), dim3(256), max_row_words * 4u, s, jobs); { hipError_t e_ = note("k_dpattern"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 

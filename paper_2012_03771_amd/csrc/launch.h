@@ -40,6 +40,9 @@ hipError_t launch_kmod_list(const uint64_t* primes, uint64_t n, const uint64_t* 
                             uint64_t* out, int n_cu, hipStream_t s);
 hipError_t launch_rows_cols(const JobDev* jobs, uint32_t n_jobs, uint64_t max_m_inc, uint32_t max_sl, int n_cu,
                             hipStream_t s);
+// Per-class patterns of the primes dividing d (jobs with dpat_on); LDS of max_row_words words.
+hipError_t launch_dpattern(const JobDev* jobs, uint32_t n_jobs, uint32_t max_phi, uint32_t max_row_words,
+                           hipStream_t s);
 hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s);
 hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,

@@ -20,7 +20,7 @@ constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024)
 
 struct WsLayout {
   uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
-      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, total;
+      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, total;
 };
 
 struct Plan {
@@ -41,6 +41,8 @@ struct Plan {
   uint64_t dense_max;
   uint32_t phi_d, r0_d;
   std::vector<uint16_t> dpre;       // residue table when d <= kDSmall
+  std::vector<uint16_t> dres;       // residues coprime to d (d <= kDSmall)
+  bool dpat_on = false;             // per-class pattern of the primes dividing d
   std::vector<uint32_t> kq;         // primes dividing K
   std::vector<uint32_t> dq;         // primes dividing d
   WsLayout ws;

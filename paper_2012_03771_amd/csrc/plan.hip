@@ -175,7 +175,12 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     }
     pl.phi_d = c;
     pl.r0_d = (uint32_t)(j.m_start % j.d);
+    pl.dres.clear();
+    for (uint32_t r = 0; r < d32; ++r)
+      if (pl.dpre[r] & 0x8000u) pl.dres.push_back((uint16_t)r);
   }
+  pl.dpat_on = !pl.dpre.empty() && j.d > 1 && pl.n_m > 0 &&
+               (uint64_t)pl.phi_d * pl.row_words * 4ull <= (64ull << 20);
   {
     const uint32_t ct_b = pl.ct_words * 8u;
     const uint32_t dp_b = (uint32_t)pl.dpre.size() * 2u;
@@ -213,6 +218,9 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.kgroups = take((pl.kq.size() + 1) * 8ull);
   L.kq = take((pl.kq.size() + 1) * 4ull);
   L.dpre = take(std::max<uint64_t>(pl.dpre.size(), 1) * 2ull);
+  L.dres = take(std::max<uint64_t>(pl.dres.size(), 1) * 2ull);
+  L.dpat = take(pl.dpat_on ? (uint64_t)pl.phi_d * pl.row_words * 4ull : 0);
+  L.dpat_cnt = take(pl.dpat_on ? (uint64_t)pl.phi_d * 4ull : 0);
   L.total = o;
   return CS_OK;
 }
@@ -220,6 +228,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
 void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
   const uint64_t lo = std::max<uint64_t>(pl.thr, p_lo > 0 ? p_lo - 1 : 0);
   const uint64_t hi = std::min<uint64_t>(p_hi, pl.job.limit);
+  jd->dpat_apply = (pl.dpat_on && !pl.dq.empty() && p_lo <= pl.dq.front() &&
+                    (uint64_t)pl.dq.back() <= std::min<uint64_t>(p_hi, pl.job.limit)) ? 1u : 0u;
   jd->tier_lo = lo;
   jd->n_tiers = 0;
   if (hi <= lo || pl.n_m == 0) return;
@@ -291,6 +301,10 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.pre_r0 = pl.dpre.empty() ? 0u : (uint32_t)(pl.dpre[pl.r0_d] & 0x7fffu);
   jd.inv_d = 1.0 / (double)j.d;
   jd.dpre = reinterpret_cast<const uint16_t*>(ws + L.dpre);
+  jd.dres = reinterpret_cast<const uint16_t*>(ws + L.dres);
+  jd.dpat_on = pl.dpat_on ? 1u : 0u;
+  jd.dpat = reinterpret_cast<uint32_t*>(ws + L.dpat);
+  jd.dpat_cnt = reinterpret_cast<uint32_t*>(ws + L.dpat_cnt);
   fill_tiers(pl, 2, j.limit, &jd);
   return jd;
 }

@@ -276,14 +276,20 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
     if (!J->prepped) fresh.push_back(J);
   if (!fresh.empty()) {
     uint64_t kcap = 0, max_words = 0, max_m = 0;
-    uint32_t max_sl = 0;
+    uint32_t max_sl = 0, max_phi = 0, max_rw = 0;
     for (uint32_t i = 0; i < fresh.size(); ++i) {
       SJob& J = *fresh[i];
       if (launch_write_job(J.jd, s->prep_dev + i, st) != hipSuccess) return false;
       if (!J.plan.dpre.empty() &&
-          launch_upload(s->arena_mem + J.off_tab + J.plan.ws.dpre, J.plan.dpre.data(), J.plan.dpre.size() * 2ull,
-                        st) != hipSuccess)
+          (launch_upload(s->arena_mem + J.off_tab + J.plan.ws.dpre, J.plan.dpre.data(), J.plan.dpre.size() * 2ull,
+                         st) != hipSuccess ||
+           launch_upload(s->arena_mem + J.off_tab + J.plan.ws.dres, J.plan.dres.data(), J.plan.dres.size() * 2ull,
+                         st) != hipSuccess))
         return false;
+      if (J.plan.dpat_on) {
+        max_phi = std::max(max_phi, J.plan.phi_d);
+        max_rw = std::max(max_rw, J.plan.row_words);
+      }
       kcap += pi_upper(J.job.limit);
       max_words = std::max<uint64_t>(max_words, J.plan.n_m * (uint64_t)J.plan.row_words);
       max_m = std::max<uint64_t>(max_m, J.job.m_inc);
@@ -295,6 +301,7 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
     if (launch_prep_tables(s->prep_dev, nf, st) != hipSuccess) return false;
     if (launch_kmod(s->prep_dev, nf, s->lim_base, kcap, s->n_cu, st) != hipSuccess) return false;
     if (launch_rows_cols(s->prep_dev, nf, max_m, max_sl, s->n_cu, st) != hipSuccess) return false;
+    if (launch_dpattern(s->prep_dev, nf, max_phi, max_rw, st) != hipSuccess) return false;
     for (SJob* J : fresh) J->prepped = true;
   }
   // the sieve: every active job's current chunk, fused

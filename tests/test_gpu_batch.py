@@ -93,3 +93,20 @@ def test_mixed_64_job_batch_against_oracle_rows():
         a_b, a_c = _alone(jobs[i], tunes[i])
         assert np.array_equal(_np(bm[i]), a_b) and np.array_equal(_np(ct[i]), a_c), i
     batch.close()
+
+
+def test_autotuned_batch_equals_alone():
+    from paper_2012_03771_amd.autotune import Autotuner
+    jobs = [W.Job(307, 2, 12345, 4000, 2500, 10**7), W.Job(401, 210, 99, 30000, 3000, 10**7),
+            W.Job(131, 1, 7, 5000, 900, 2 * 10**6)]
+    tuner = Autotuner()
+    tunes = tuner.tune_all(jobs)
+    assert len(tuner.cache) >= 1 and all(len(t) == len(tuner.candidates) for t in tuner.timings.values())
+    batch = cs.Batch(jobs, tunes)
+    bm, ct = batch.alloc_outputs()
+    batch.run(bm, ct, use_graph=True)
+    torch.cuda.synchronize()
+    for i, job in enumerate(jobs):
+        a_b, a_c = _alone(job)                    # default tuning: outputs do not depend on it
+        assert np.array_equal(_np(bm[i]), a_b) and np.array_equal(_np(ct[i]), a_c), job
+    batch.close()
