@@ -152,4 +152,51 @@ CS_HD int three_gap_setup(uint64_t p, uint64_t k, uint64_t kinv, double pinv, ui
   return 1;
 }
 
+// k^-1 mod p and the three-gap constants of the window [0, w] in one extended Euclidean pass
+// over (p, k).  The remainders r_i = s_i * k (mod p) alternate sides: s_i > 0 gives
+// t = s_i with t*k mod p = r_i, s_i < 0 gives t = -s_i with t*k mod p = p - r_i.  Along each
+// side the one-sided best approximations are the semiconvergents r_{i-1} - j r_i with
+// t = |s_{i-1}| + j |s_i|, 1 <= j <= q_i, so the least t whose residue on a side falls to w or
+// below is the first such semiconvergent: j = ceil((r_{i-1} - w) / r_i) at the first step whose
+// remainder on that side drops to w or below.  Requires 1 <= k < p < 2^40 prime, 1 <= w,
+// p > 2w.  Returns 0 only on an internal failure.
+CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_t* kinv_out, int* steps_out) {
+  const double wd = (double)w;
+  double a = (double)p, b = (double)k;        // r_{i-1}, r_i
+  double sa = 0.0, sb = 1.0;                  // s_{i-1}, s_i
+  bool fa = false, fb = false;                // positive side (t*k mod p small), negative side
+  if (b <= wd) {                              // t = 1
+    g->ta = 1;
+    g->a = k;
+    fa = true;
+  }
+  int it = 0;
+  for (; it < 160 && b != 0.0; ++it) {
+    const double inv = 1.0 / b;
+    double q = floor(a * inv);
+    double r = fma(-q, b, a);
+    if (r < 0.0) { r += b; q -= 1.0; }
+    if (r >= b) { r -= b; q += 1.0; }
+    const double sn = fma(-q, sb, sa);        // s_{i+1}, same side as s_{i-1}
+    const bool pos = sa > 0.0;                // side of r_{i-1} and r_{i+1} (s_{-1} = 0: negative)
+    if (r <= wd && (pos ? !fa : !fb)) {
+      double j = floor((a - wd + b - 1.0) * inv);   // ceil((a - w) / b), a > w on this side
+      double rem = fma(-j, b, a - wd + b - 1.0);
+      if (rem < 0.0) j -= 1.0;
+      if (rem >= b) j += 1.0;
+      const double t = fabs(sa) + j * fabs(sb);
+      const double v = a - j * b;                   // residue on this side, in [1, w]
+      if (pos) { g->ta = (uint64_t)t; g->a = (uint64_t)v; fa = true; }
+      else { g->tb = (uint64_t)t; g->b = (uint64_t)v; fb = true; }
+    }
+    a = b; b = r; sa = sb; sb = sn;
+  }
+  if (steps_out) *steps_out = it;
+  // a = gcd = 1 and sa * k == 1 (mod p)
+  if (a != 1.0 || !fa || !fb) return 0;
+  const double pd = (double)p;
+  *kinv_out = (uint64_t)(sa < 0.0 ? sa + pd : sa);
+  return 1;
+}
+
 }  // namespace cs

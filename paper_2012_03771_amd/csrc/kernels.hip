@@ -829,8 +829,12 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
     const uint64_t li = local - c.tier_item_base[t];
     const uint32_t C = j.tier_chunks[t];
-    const uint64_t pi = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]) + li / C;
-    const uint32_t chunk = (uint32_t)(li % C);
+    // chunk-major order: lanes running at the same time share an m-chunk, so their scattered
+    // marks stay within 1/C of the bitmap rows
+    const uint64_t t0 = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]);
+    const uint64_t npt = c.tier_idx[t] - t0;
+    const uint64_t chunk = li / npt;
+    const uint64_t pi = t0 + (li - chunk * npt);
     const uint64_t L = (j.m_inc + C - 1) / C;
     const uint64_t o_lo = (uint64_t)chunk * L;
     const uint64_t o_hi = min(o_lo + L, j.m_inc);
@@ -841,7 +845,15 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
     const uint32_t d32 = (uint32_t)j.d;
-    const uint64_t kinv = modinv(k, p);
+    // k^-1 mod p (and, for three-gap stepping, the two return times) from one Euclid pass
+    uint64_t kinv = 0;
+    gaps3 g = {0, 0, 0, 0};
+    if (j.large_mode == 0) {
+      kinv = modinv(k, p);
+    } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
+      err |= E_SOLVE;
+      continue;
+    }
     // residue of m*K + SL at m = m_start + o_lo
     uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
     r = r >= p ? r - p : r;
@@ -878,15 +890,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         r = r >= p ? r - p : r;
       }
     } else {
-      // three-gap stepping: solve for the first hit and the two return times only
-      gaps3 g;
-      int lv = 0;
-      if (!three_gap_setup(p, k, kinv, pinv, w, &g, &lv)) { err |= E_SOLVE; continue; }
-      calls += 2;
-      levels += (unsigned)lv;
+      // three-gap stepping: one solve for the first hit, then the return times
       if (r > w) {
         uint64_t rn;
-        lv = 0;
+        int lv = 0;
         const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
         ++calls;
         levels += (unsigned)lv;

@@ -126,6 +126,32 @@ int main(int argc, char** argv) {
     }
     if (!bad && got3 != want) bad = fail("three_gap", p, k, w, m_inc);
   }
+  // one-pass Euclid: inverse and three-gap constants against brute force and the G-based setup
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t w = 1 + rng() % (i % 3 == 0 ? 4 : 3000);
+    uint64_t p;
+    do { p = 2 * w + 1 + rng() % (i % 5 == 0 ? 200 : 2000000); } while (!is_prime(p));
+    uint64_t k = (i % 7 == 0) ? 1 + rng() % std::min<uint64_t>(3, p - 1) : 1 + rng() % (p - 1);
+    if (i % 11 == 0) k = p - 1 - rng() % std::min<uint64_t>(3, p - 2);
+    cs::gaps3 g1, g2;
+    uint64_t kinv = 0;
+    int st;
+    if (!cs::three_gap_euclid(p, k, w, &g1, &kinv, &st)) { bad = fail("euclid", p, k, w, 0); break; }
+    if ((uint64_t)((u128)kinv * k % p) != 1) { bad = fail("euclid_inv", p, k, kinv, 0); break; }
+    double pinv = 1.0 / (double)p;
+    int lv;
+    if (!cs::three_gap_setup(p, k, cs::modinv(k, p), pinv, w, &g2, &lv)) { bad = fail("setup", p, k, w, 0); break; }
+    if (g1.ta != g2.ta || g1.a != g2.a || g1.tb != g2.tb || g1.b != g2.b) { bad = fail("euclid_vs_g", p, k, w, g1.ta); break; }
+    if (p < 300000) {   // brute force of the definitions
+      uint64_t ta = 0, tb = 0;
+      for (uint64_t t = 1; t < p && (!ta || !tb); ++t) {
+        uint64_t v = (uint64_t)((u128)t * k % p);
+        if (!ta && v >= 1 && v <= w) ta = t;
+        if (!tb && v >= p - w) tb = t;
+      }
+      if (ta != g1.ta || tb != g1.tb) { bad = fail("euclid_brute", p, k, w, ta); break; }
+    }
+  }
   if (!bad) std::printf("OK\n");
   return bad;
 }
