@@ -35,7 +35,7 @@ static uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
 void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune) {
   const uint32_t ct_bytes = lds_ct_words * 8u;
   uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
-  rows = std::max(1u, std::min(rows, 64u));
+  rows = std::max(1u, std::min(rows, kTileRowsMax));
   if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
   pl.tile_rows = rows;
   pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
@@ -137,7 +137,8 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
     }
   }
   b.units = unit_base;
-  b.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b.units, 1), (uint64_t)b.n_cu * 2);
+  const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(b.lds_bytes, 1u)));
+  b.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b.units, 1), (uint64_t)b.n_cu * per_cu);
   b.large_blocks = (uint32_t)b.n_cu * 8u;
   return CS_OK;
 }

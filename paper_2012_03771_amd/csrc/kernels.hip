@@ -236,31 +236,31 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Ordered compaction of the prime flags: 256 consecutive words per step, so reads are
+// coalesced and each step's primes land in one contiguous run of the table.
 __global__ __launch_bounds__(256) void k_compact_primes(uint64_t n_seg, const uint32_t* __restrict__ flags,
                                                         const uint64_t* __restrict__ off,
                                                         uint64_t* __restrict__ primes, uint64_t cap) {
   __shared__ uint32_t sh[32];
-  constexpr uint32_t per = kSegWords / 256;                 // 32 words per thread
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
-    const uint32_t* f = flags + s * kSegWords + threadIdx.x * per;
-    uint32_t c = 0;
-    for (uint32_t u = 0; u < per; ++u) c += __popc(f[u]);
-    uint32_t tot;
-    uint64_t pos = off[s] + block_exclusive_scan(c, sh, &tot);
+    uint64_t base = off[s];
     if (s == 0) {
       if (threadIdx.x == 0 && cap > 0) primes[0] = 2;
-      pos += 1;
+      base += 1;
     }
     const uint64_t lo = s << kSegLog;
-    for (uint32_t u = 0; u < per; ++u) {
-      uint32_t m = f[u];
-      const uint32_t word = threadIdx.x * per + u;
+    for (uint32_t step = 0; step < kSegWords / 256; ++step) {
+      const uint32_t word = step * 256 + threadIdx.x;
+      uint32_t m = flags[s * kSegWords + word];
+      uint32_t tot;
+      uint64_t pos = base + block_exclusive_scan(__popc(m), sh, &tot);
       while (m) {
-        uint32_t b = __ffs(m) - 1;
+        const uint32_t b = __ffs(m) - 1;
         m &= m - 1;
         if (pos < cap) primes[pos] = lo + 2ull * (word * 32 + b) + 1;
         ++pos;
       }
+      base += tot;
     }
   }
 }
@@ -315,31 +315,61 @@ __global__ void k_lim_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base) 
 
 // K mod p and m_start*K mod p for every prime index < n_lim of every job (Eq. 1's cached
 // residue); the index space of all jobs is flattened so one launch covers a whole batch.
+__device__ __forceinline__ const JobDev& job_of_index(const JobDev* __restrict__ jobs, uint32_t n_jobs,
+                                                      const uint64_t* __restrict__ lim_base, uint64_t g,
+                                                      uint64_t* i) {
+  uint32_t lo = 0, hi = n_jobs;                     // job: last base <= g
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (lim_base[mid] <= g) lo = mid; else hi = mid;
+  }
+  *i = g - lim_base[lo];
+  return jobs[lo];
+}
+
+// K mod p and m_start*K mod p for every prime index < n_lim of every job (Eq. 1's cached
+// residue); the index space of all jobs is flattened so one launch covers a whole batch.  Each
+// thread takes two indices and interleaves their multiplication chains.
 __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                               const uint64_t* __restrict__ lim_base) {
   const uint64_t total = lim_base[n_jobs];
-  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
-       g += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t lo = 0, hi = n_jobs;                   // job: last base <= g
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (lim_base[mid] <= g) lo = mid; else hi = mid;
-    }
-    const JobDev& j = jobs[lo];
-    const uint64_t i = g - lim_base[lo];
-    const uint64_t p = j.primes[i];
-    const double pinv = 1.0 / (double)p;
-    uint64_t r;
-    if (j.kmod_cached) {
-      r = j.kmod[i];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g0 < total; g0 += 2 * stride) {
+    const uint64_t g1 = g0 + stride;
+    uint64_t i0, i1 = 0;
+    const JobDev& j0 = job_of_index(jobs, n_jobs, lim_base, g0, &i0);
+    const bool two = g1 < total;
+    const JobDev& j1 = two ? job_of_index(jobs, n_jobs, lim_base, g1, &i1) : j0;
+    if (!two) i1 = i0;
+    const uint64_t p0 = j0.primes[i0], p1 = j1.primes[i1];
+    const double v0 = 1.0 / (double)p0, v1 = 1.0 / (double)p1;
+    uint64_t r0, r1;
+    if (&j0 == &j1 && !j0.kmod_cached) {
+      const uint32_t ng = j0.ctrl->n_kgroups;
+      const uint64_t* __restrict__ G = j0.kgroups;
+      r0 = 1 % p0;
+      r1 = 1 % p1;
+      for (uint32_t t = 0; t < ng; ++t) {
+        const uint64_t gg = G[t];
+        r0 = mulmod(r0, gg, p0, v0);
+        r1 = mulmod(r1, gg, p1, v1);
+      }
     } else {
-      const uint32_t ng = j.ctrl->n_kgroups;
-      const uint64_t* __restrict__ G = j.kgroups;
-      r = 1 % p;
-      for (uint32_t t = 0; t < ng; ++t) r = mulmod(r, G[t], p, pinv);
-      j.kmod[i] = r;
+      auto kof = [](const JobDev& j, uint64_t i, uint64_t p, double v) {
+        if (j.kmod_cached) return j.kmod[i];
+        uint64_t r = 1 % p;
+        for (uint32_t t = 0; t < j.ctrl->n_kgroups; ++t) r = mulmod(r, j.kgroups[t], p, v);
+        return r;
+      };
+      r0 = kof(j0, i0, p0, v0);
+      r1 = kof(j1, i1, p1, v1);
     }
-    j.mk[i] = mulmod(mod64(j.m_start, p, pinv), r, p, pinv);
+    if (!j0.kmod_cached) j0.kmod[i0] = r0;
+    j0.mk[i0] = mulmod(mod64(j0.m_start, p0, v0), r0, p0, v0);
+    if (two) {
+      if (!j1.kmod_cached) j1.kmod[i1] = r1;
+      j1.mk[i1] = mulmod(mod64(j1.m_start, p1, v1), r1, p1, v1);
+    }
   }
 }
 

@@ -16,6 +16,7 @@ constexpr uint32_t kSmallBlock = 512;
 constexpr uint32_t kLargeBlock = 256;
 constexpr uint32_t kLdsBudget = 64 * 1024;
 constexpr uint32_t kLdsCtMax = 32 * 1024;
+constexpr uint32_t kTileRowsMax = 16;          // rows per small-branch tile (more workgroups per CU beat bigger tiles)
 constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024) plus slack
 
 struct WsLayout {

@@ -141,7 +141,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   const bool ct_lds = pl.ct_words * 8u <= kLdsCtMax;
   const uint32_t ct_bytes = ct_lds ? pl.ct_words * 8u : 0u;
   uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
-  rows = std::max(1u, std::min(rows, 64u));
+  rows = std::max(1u, std::min(rows, kTileRowsMax));
   if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
   pl.tile_rows = rows;
   pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
@@ -154,7 +154,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
   pl.n_slices = slices;
   const uint64_t units = (uint64_t)pl.n_windows * slices;
-  pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, (uint64_t)n_cu * 2);
+  const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(pl.lds_bytes, 1u)));
+  pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, (uint64_t)n_cu * per_cu);
   pl.dense_max = std::max<uint64_t>(1, pl.w / 32);
 
   // residue table of d: m -> row without a per-m lookup

@@ -330,7 +330,8 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
   if (launch_prep_bounds(s->run_dev, n, st) != hipSuccess) return false;
   if (launch_items_scan(s->run_dev, n, s->items_base, st) != hipSuccess) return false;
   if (units) {
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, (uint64_t)s->n_cu * 2);
+    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(lds, 1u)));
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, (uint64_t)s->n_cu * per_cu);
     if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, st) != hipSuccess) return false;
   }
   if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * 8u, 0, 0, 0, st) != hipSuccess)
