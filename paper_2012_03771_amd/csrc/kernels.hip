@@ -859,12 +859,20 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
     const uint64_t li = local - c.tier_item_base[t];
     const uint32_t C = j.tier_chunks[t];
-    // chunk-major order: lanes running at the same time share an m-chunk, so their scattered
-    // marks stay within 1/C of the bitmap rows
+    // Item order.  One solve per hit: prime-major, so neighbouring lanes share (p, K mod p)
+    // and walk the same sequence of moduli in Eq. 5's descent (less divergence).  Three-gap
+    // stepping: chunk-major, so lanes running at the same time share an m-chunk and their
+    // scattered marks stay within 1/C of the bitmap rows.
     const uint64_t t0 = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]);
-    const uint64_t npt = c.tier_idx[t] - t0;
-    const uint64_t chunk = li / npt;
-    const uint64_t pi = t0 + (li - chunk * npt);
+    uint64_t chunk, pi;
+    if (j.large_mode == 0) {
+      pi = t0 + li / C;
+      chunk = li % C;
+    } else {
+      const uint64_t npt = c.tier_idx[t] - t0;
+      chunk = li / npt;
+      pi = t0 + (li - chunk * npt);
+    }
     const uint64_t L = (j.m_inc + C - 1) / C;
     const uint64_t o_lo = (uint64_t)chunk * L;
     const uint64_t o_hi = min(o_lo + L, j.m_inc);
