@@ -82,6 +82,22 @@ def _cpu_baseline(job, n_rows, p_max):
                       f"(direct mode), {dt:.1f} s wall"}
 
 
+def _kernel_traffic(mode):
+    """HBM bytes (GB) of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile, or
+    None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(mode)
+    m = hashlib.sha256()
+    for f in ("kernels.hip", "arith.h", "device.h"):
+        m.update(open(os.path.join(ROOT, "paper_2012_03771_amd", "csrc", f), "rb").read())
+    if not rec or rec.get("hash") != m.hexdigest()[:16]:
+        return None
+    return rec["traffic_gb"]
+
+
 def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
     """64 seeded mixed jobs: one fused launch sequence replayed from a hipGraph, against 64
     sequential cs_sieve calls on the same GPU (both with the same tunings)."""
@@ -251,7 +267,9 @@ def main():
     t_large = phases["large"] / 1e3
     ops = RL.large_branch_ops(diag_ph, args.mode == "three_gap")
     roof = {"bound": "alu", "kernel": "k_large", "achieved": ops / t_large / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS, "traffic": args.traffic_gb,
+            "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS,
+            "traffic": args.traffic_gb if args.traffic_gb is not None else _kernel_traffic(args.mode),
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, profiles/)",
             "ops_per_launch": ops, "launch_ms": phases["large"]}
 
     out = {
@@ -292,6 +310,7 @@ def main():
                          "roofline": {"bound": "alu", "kernel": "k_large", "achieved": og / tlg / 1e12,
                                       "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
                                       "frac": og / tlg / ALU_PEAK_OPS, "ops_per_launch": og,
+                                      "traffic": _kernel_traffic("g"),
                                       "launch_ms": ph["large"]}}
     mode_b = cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP
     del bitmap, counts, ws, ref_bitmap, ref_counts
