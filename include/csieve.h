@@ -79,7 +79,23 @@ typedef struct cs_tune {
   uint32_t small_slices;   /* prime slices per small-branch tile; 0 = automatic */
   uint32_t branches;       /* cs_sieve_range only: CS_BRANCH_ALL (0), CS_BRANCH_SMALL or
                               CS_BRANCH_LARGE, to run one branch per call (e.g. to time it) */
+  uint32_t scatter;        /* how large-prime hits reach the bitmap: CS_SCATTER_AUTO (0),
+                              CS_SCATTER_ATOMIC or CS_SCATTER_BYTES */
+  uint32_t reserved;
 } cs_tune;
+
+/* Large-prime hit scatter.  ATOMIC: per hit, a device-scope atomic OR into the packed bitmap and
+ * an atomic add into the row's count.  BYTES: per hit, one atomic add into a byte counter per
+ * (row, column) in the workspace (n_m * row_words * 32 bytes, included in cs_layout.ws_bytes);
+ * one coalesced pass after the branch ORs the nonzero counters into the bitmap, adds their sums
+ * to the counts and clears them.  BYTES is exact only while no number m K + X of the interval can
+ * have 256 distinct prime factors above the threshold, i.e. while
+ * floor(log2((m_start + m_inc + 1) K) / log2(thr + 1)) < 256; requesting it otherwise gives
+ * CS_EINVAL.  AUTO: BYTES where exact for cs_sieve / cs_prepare / cs_sieve_range, ATOMIC inside
+ * batches and the server (which ignore BYTES).  Outputs are identical in every mode. */
+#define CS_SCATTER_AUTO   0u
+#define CS_SCATTER_ATOMIC 1u
+#define CS_SCATTER_BYTES  2u
 
 #define CS_BRANCH_ALL   0u
 #define CS_BRANCH_SMALL 1u
@@ -94,6 +110,8 @@ typedef struct cs_layout {
   uint64_t ws_bytes;       /* device workspace needed by cs_sieve / cs_prepare / cs_sieve_range */
   uint64_t prime_cap;      /* capacity of the prime table: an upper bound of pi(max(limit, P)) */
   uint64_t thr;            /* effective small/large threshold for the given tuning */
+  uint32_t scatter;        /* large-hit scatter cs_sieve uses: CS_SCATTER_ATOMIC or CS_SCATTER_BYTES */
+  uint32_t reserved;
 } cs_layout;
 
 /* Counters accumulated by the kernels of the last cs_prepare + cs_sieve_range calls on a

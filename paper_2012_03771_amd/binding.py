@@ -13,6 +13,9 @@ LARGE_THREE_GAP = 1
 BRANCH_ALL = 0
 BRANCH_SMALL = 1
 BRANCH_LARGE = 2
+SCATTER_AUTO = 0
+SCATTER_ATOMIC = 1
+SCATTER_BYTES = 2
 
 _ERRORS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ERANGE", -3: "CS_ENOMEM", -4: "CS_EDEVICE", -5: "CS_EBUSY"}
 
@@ -31,13 +34,13 @@ class cs_job(C.Structure):
 class cs_tune(C.Structure):
     _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
                 ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
-                ("branches", C.c_uint32)]
+                ("branches", C.c_uint32), ("scatter", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class cs_layout(C.Structure):
     _fields_ = [("n_m", C.c_uint64), ("n_x", C.c_uint32), ("row_words", C.c_uint32),
                 ("bitmap_bytes", C.c_uint64), ("counts_bytes", C.c_uint64), ("ws_bytes", C.c_uint64),
-                ("prime_cap", C.c_uint64), ("thr", C.c_uint64)]
+                ("prime_cap", C.c_uint64), ("thr", C.c_uint64), ("scatter", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class cs_diag(C.Structure):
@@ -71,10 +74,11 @@ class Tune:
     large_blocks: int = 0
     small_slices: int = 0
     branches: int = 0
+    scatter: int = 0
 
     def c(self):
         return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
-                       self.small_slices, self.branches)
+                       self.small_slices, self.branches, self.scatter, 0)
 
 
 @dataclass
@@ -87,6 +91,7 @@ class Layout:
     ws_bytes: int
     prime_cap: int
     thr: int
+    scatter: int
 
 
 @dataclass
@@ -193,7 +198,7 @@ def plan(job, tune: Tune | None = None) -> Layout:
     out = cs_layout()
     _check(lib().cs_plan(C.byref(_cjob(job)), _ctune(tune), C.byref(out)), "cs_plan")
     return Layout(out.n_m, out.n_x, out.row_words, out.bitmap_bytes, out.counts_bytes, out.ws_bytes,
-                  out.prime_cap, out.thr)
+                  out.prime_cap, out.thr, out.scatter)
 
 
 def columns(job):
@@ -310,7 +315,7 @@ class Batch:
             out = cs_layout()
             _check(lib().cs_batch_layout(self.h, i, C.byref(out)), "cs_batch_layout")
             self.layouts.append(Layout(out.n_m, out.n_x, out.row_words, out.bitmap_bytes, out.counts_bytes,
-                                       out.ws_bytes, out.prime_cap, out.thr))
+                                       out.ws_bytes, out.prime_cap, out.thr, out.scatter))
 
     def alloc_outputs(self):
         import torch

@@ -44,6 +44,8 @@ extern "C" cs_status cs_plan(const cs_job* job, const cs_tune* tune, cs_layout* 
   out->ws_bytes = pl.ws.total;
   out->prime_cap = pl.cap;
   out->thr = pl.thr;
+  out->scatter = pl.scatter_bytes ? CS_SCATTER_BYTES : CS_SCATTER_ATOMIC;
+  out->reserved = 0;
   return CS_OK;
 }
 
@@ -111,6 +113,7 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
     CS_TRY(launch_upload(ws + L.dres, pl.dres.data(), pl.dres.size() * 2ull, s));
   }
   if (pl.dpat_on) CS_TRY(launch_dpattern(jdp, 1, pl.phi_d, pl.row_words, s));
+  if (pl.scatter_bytes) CS_TRY(launch_zero_bytes(jdp, 1, pl.n_m * (uint64_t)pl.row_words, n_cu, s));
   return CS_OK;
 }
 
@@ -134,9 +137,11 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   if (branches != CS_BRANCH_LARGE)
     CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s));
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
-  if (branches != CS_BRANCH_SMALL)
+  if (branches != CS_BRANCH_SMALL) {
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, pl.large_lds_bytes,
-                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), s));
+                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), pl.scatter_bytes, s));
+    if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jdp, 1, pl.n_m, device_cu_count(), s));
+  }
   return CS_OK;
 }
 

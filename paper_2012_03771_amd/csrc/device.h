@@ -80,6 +80,7 @@ struct JobDev {
   uint32_t* kq;                      // primes dividing K (q <= P, q not dividing d)
   uint32_t* bitmap;
   uint32_t* counts;
+  uint8_t* hitbytes;                 // one byte per (row, column slot) or null: large hits by store
   JobCtrl* ctrl;
 };
 

@@ -799,7 +799,10 @@ struct LargeTables {
   const uint16_t* dp;
 };
 
-template <bool kLds>
+// kCnt: one atomic add per hit into a byte counter per (row, column) (folded into the bitmap and
+// the counts after the launch); otherwise an atomic OR into the bitmap and an atomic add into
+// the row's count.
+template <bool kLds, bool kCnt>
 __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
                                            uint32_t jj, unsigned long long& useful) {
   uint64_t row;
@@ -814,8 +817,13 @@ __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kL
   }
   uint32_t col;
   if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
-  atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
-  atomicAdd(&j.counts[row], 1u);
+  if constexpr (kCnt) {
+    uint32_t* cell = reinterpret_cast<uint32_t*>(j.hitbytes + row * j.row_words * 32ull + (col & ~3u));
+    atomicAdd(cell, 1u << (8 * (col & 3u)));
+  } else {
+    atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
+    atomicAdd(&j.counts[row], 1u);
+  }
   ++useful;
 }
 
@@ -824,7 +832,7 @@ __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kL
 // From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
 // G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
 // ------------------------------------------------------------------------------------------
-template <bool kLds>
+template <bool kLds, bool kCnt>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
                                                unsigned long long* __restrict__ diag, uint32_t lds_ct_words,
@@ -921,7 +929,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
           }
         }
         ++raw;
-        record_hit<kLds>(j, T, o, mp, (uint32_t)(w - r), useful);
+        record_hit<kLds, kCnt>(j, T, o, mp, (uint32_t)(w - r), useful);
         if (++o >= o_hi) break;
         if (j.d_small) mpos_add(mp, 0, 1, d32);
         r += k;
@@ -953,7 +961,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       const bool a_first = g.ta < g.tb;
       while (o < o_hi) {
         ++raw;
-        record_hit<kLds>(j, T, o, mp, (uint32_t)(w - r), useful);
+        record_hit<kLds, kCnt>(j, T, o, mp, (uint32_t)(w - r), useful);
         const bool fa = r + g.a <= w, fb = r >= g.b;
         if (fa && (a_first || !fb)) { o += g.ta; r += g.a; mpos_add(mp, aq, ar, d32); }
         else if (fb) { o += g.tb; r -= g.b; mpos_add(mp, bq, br, d32); }
@@ -972,6 +980,54 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     atomicAdd(&diag[D_G_LEVELS], levels);
   }
   if (err) atomicOr(reinterpret_cast<unsigned long long*>(&diag[D_ERROR]), (unsigned long long)err);
+}
+
+// Folds the byte counters of large-prime hits into the bitmap and the counts, one wavefront per
+// row (each lane takes 32 columns = one bitmap word at a time), and clears them for the next call.
+// Every counter is below 256 (the plan admits the counters only when no number of the interval
+// can have more distinct prime factors above the threshold), so the byte sums never carry.
+__global__ __launch_bounds__(256) void k_fold_bytes(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  if (!j.hitbytes) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t waves = blockDim.x / kWave;
+  for (uint64_t row = blockIdx.x * (uint64_t)waves + threadIdx.x / kWave; row < j.n_m;
+       row += (uint64_t)gridDim.x * waves) {
+    uint4* __restrict__ src = reinterpret_cast<uint4*>(j.hitbytes + row * j.row_words * 32ull);
+    uint32_t* __restrict__ dst = j.bitmap + row * j.row_words;
+    unsigned long long sum = 0;
+    for (uint32_t wi = lane; wi < j.row_words; wi += kWave) {
+      const uint4 a = src[2 * wi], b = src[2 * wi + 1];
+      const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      uint32_t bits = 0, s = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t x = v[q];
+        bits |= (((x & 0xffu) ? 1u : 0u) | ((x & 0xff00u) ? 2u : 0u) | ((x & 0xff0000u) ? 4u : 0u) |
+                 ((x & 0xff000000u) ? 8u : 0u)) << (4 * q);
+        const uint32_t h = (x & 0x00ff00ffu) + ((x >> 8) & 0x00ff00ffu);   // two 16-bit pair sums
+        s += (h & 0xffffu) + (h >> 16);
+      }
+      if (bits) {
+        src[2 * wi] = make_uint4(0, 0, 0, 0);
+        src[2 * wi + 1] = make_uint4(0, 0, 0, 0);
+        dst[wi] |= bits;
+      }
+      sum += s;
+    }
+    sum = wave_sum_u64(sum);
+    if (lane == 0 && sum) j.counts[row] += (uint32_t)sum;
+  }
+}
+
+// Clears the byte buffer of every job that has one.
+__global__ __launch_bounds__(256) void k_zero_bytes(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  if (!j.hitbytes) return;
+  const uint64_t n = j.n_m * (uint64_t)j.row_words * 8;
+  uint32_t* __restrict__ p = reinterpret_cast<uint32_t*>(j.hitbytes);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1093,6 +1149,22 @@ hipError_t launch_dpattern(const JobDev* jobs, uint32_t n_jobs, uint32_t max_phi
   return hipGetLastError();
 }
 
+hipError_t launch_fold_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_rows, int n_cu, hipStream_t s) {
+  uint64_t blocks = (max_rows + 3) / 4;
+  if (blocks > (uint64_t)n_cu * 16) blocks = (uint64_t)n_cu * 16;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fold_bytes, dim3((uint32_t)blocks, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_fold_bytes"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_words, int n_cu, hipStream_t s) {
+  uint64_t blocks = (max_words * 8 + 255) / 256;
+  if (blocks > (uint64_t)n_cu * 16) blocks = (uint64_t)n_cu * 16;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_zero_bytes, dim3((uint32_t)blocks, n_jobs), dim3(256), 0, s, jobs); { hipError_t e_ = note("k_zero_bytes"); if (e_ != hipSuccess) return e_; }
+  return hipGetLastError();
+}
+
 hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_bounds, dim3(1, n_jobs), dim3(64), 0, s, jobs); { hipError_t e_ = note("k_prep_bounds"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
@@ -1112,13 +1184,22 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, hipStream_t s) {
+                        uint32_t dpre_n, bool counters, hipStream_t s) {
   if (lds_bytes && n_jobs == 1) {
-    hipLaunchKernelGGL(k_large<true>, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base, diag,
-                       lds_ct_words, dpre_n);
+    if (counters)
+      hipLaunchKernelGGL((k_large<true, true>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base,
+                         diag, lds_ct_words, dpre_n);
+    else
+      hipLaunchKernelGGL((k_large<true, false>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base,
+                         diag, lds_ct_words, dpre_n);
     { hipError_t e_ = note("k_large<lds>"); if (e_ != hipSuccess) return e_; }
   } else {
-    hipLaunchKernelGGL(k_large<false>, dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag, 0u, 0u);
+    if (counters)
+      hipLaunchKernelGGL((k_large<false, true>), dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag,
+                         0u, 0u);
+    else
+      hipLaunchKernelGGL((k_large<false, false>), dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag,
+                         0u, 0u);
     { hipError_t e_ = note("k_large"); if (e_ != hipSuccess) return e_; }
   }
   return hipSuccess;

@@ -43,15 +43,21 @@ hipError_t launch_rows_cols(const JobDev* jobs, uint32_t n_jobs, uint64_t max_m_
 // Per-class patterns of the primes dividing d (jobs with dpat_on); LDS of max_row_words words.
 hipError_t launch_dpattern(const JobDev* jobs, uint32_t n_jobs, uint32_t max_phi, uint32_t max_row_words,
                            hipStream_t s);
+// Byte-counter scatter: clear the counters (once, after allocation; max_words = the largest
+// n_m * row_words over the jobs) / fold them into the bitmaps and counts and clear them again
+// (max_rows = the largest n_m).
+hipError_t launch_zero_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_words, int n_cu, hipStream_t s);
+hipError_t launch_fold_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_rows, int n_cu, hipStream_t s);
 hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s);
 hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
                         uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
 // lds_bytes = 0: tables read from global memory (any number of jobs); otherwise n_jobs must be 1
 // and the column table (lds_ct_words uint2, 0 = global) and residue table (dpre_n entries) of
-// that job are staged in LDS.
+// that job are staged in LDS.  counters: hits go to every job's byte counters (all jobs must
+// have them), else atomic OR/add into the bitmaps and counts.
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, hipStream_t s);
+                        uint32_t dpre_n, bool counters, hipStream_t s);
 
 }  // namespace cs

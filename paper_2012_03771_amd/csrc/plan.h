@@ -21,7 +21,7 @@ constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024)
 
 struct WsLayout {
   uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
-      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, total;
+      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, hitbytes, total;
 };
 
 struct Plan {
@@ -44,6 +44,8 @@ struct Plan {
   std::vector<uint16_t> dpre;       // residue table when d <= kDSmall
   std::vector<uint16_t> dres;       // residues coprime to d (d <= kDSmall)
   bool dpat_on = false;             // per-class pattern of the primes dividing d
+  bool scatter_bytes = false;       // large hits via byte counters (see CS_SCATTER_BYTES)
+  double cell_max = 0;              // bound on large-prime hits of one (row, column)
   std::vector<uint32_t> kq;         // primes dividing K
   std::vector<uint32_t> dq;         // primes dividing d
   WsLayout ws;

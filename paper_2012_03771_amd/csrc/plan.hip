@@ -81,6 +81,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (j.limit >= kMaxLimit) return CS_ERANGE;
   const uint32_t mode = tune ? tune->large_mode : CS_LARGE_G;
   if (mode > CS_LARGE_THREE_GAP) return CS_EINVAL;
+  const uint32_t scatter = tune ? tune->scatter : CS_SCATTER_AUTO;
+  if (scatter > CS_SCATTER_BYTES) return CS_EINVAL;
 
   Plan& pl = *out;
   pl.job = j;
@@ -222,6 +224,19 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.dres = take(std::max<uint64_t>(pl.dres.size(), 1) * 2ull);
   L.dpat = take(pl.dpat_on ? (uint64_t)pl.phi_d * pl.row_words * 4ull : 0);
   L.dpat_cnt = take(pl.dpat_on ? (uint64_t)pl.phi_d * 4ull : 0);
+  // Byte counters are exact when no number m K + X of the interval has 256 or more distinct prime
+  // factors above the threshold: their product exceeds thr^c, and m K + X < (m_start + m_inc) K.
+  // Batches and the server share tables across jobs and keep the atomic scatter.
+  {
+    double log2_n = log2((double)j.m_start + (double)j.m_inc + 1.0);
+    for (uint32_t q : pl.kq) log2_n += log2((double)q);
+    const double c_max = floor(log2_n * (1.0 + 1e-12) / log2((double)pl.thr + 1.0));
+    pl.cell_max = c_max;
+    const bool fits = c_max < 256.0;
+    if (scatter == CS_SCATTER_BYTES && !fits) return CS_EINVAL;
+    pl.scatter_bytes = own_primes && fits && scatter != CS_SCATTER_ATOMIC;
+  }
+  L.hitbytes = take(pl.scatter_bytes ? pl.n_m * (uint64_t)pl.row_words * 32ull : 0);
   L.total = o;
   return CS_OK;
 }
@@ -306,6 +321,7 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.dpat_on = pl.dpat_on ? 1u : 0u;
   jd.dpat = reinterpret_cast<uint32_t*>(ws + L.dpat);
   jd.dpat_cnt = reinterpret_cast<uint32_t*>(ws + L.dpat_cnt);
+  jd.hitbytes = pl.scatter_bytes ? ws + L.hitbytes : nullptr;
   fill_tiers(pl, 2, j.limit, &jd);
   return jd;
 }

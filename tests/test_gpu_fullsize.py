@@ -36,10 +36,11 @@ def _run(job, tune):
     return b, c, diag
 
 
-MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP)]
+MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP),
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC)]
 
 
-@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap"])
+@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap", "three_gap_atomic"])
 def test_medium_503_every_row(tune):
     g = load("medium_503_rows.npz")
     job = W.Job(*[int(x) for x in g["job"]])
@@ -56,7 +57,7 @@ def test_medium_503_every_row(tune):
     assert diag.n_primes == 5761455
 
 
-@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap"])
+@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap", "three_gap_atomic"])
 def test_paper_953_sampled_rows_and_invariants(tune):
     g = load("paper_953_rows.npz")
     job = W.Job(*[int(x) for x in g["job"]])

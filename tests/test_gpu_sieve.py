@@ -89,7 +89,7 @@ TINY = W.tiny_jobs(seed=5, n=40, max_P=31) + [W.Job(11, d, 7, 40, 60, 3000) for 
 def test_tiny_jobs(job):
     want_b, want_c = _oracle(job, mode=coracle.DIRECT)
     for tune in (None, cs.Tune(thr=1), cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP),
-                 cs.Tune(thr=10**9)):
+                 cs.Tune(thr=10**9), cs.Tune(thr=1, scatter=cs.SCATTER_ATOMIC)):
         b, c, _, _ = _run(job, tune)
         _assert_same(job, b, c, want_b, want_c)
 
@@ -104,7 +104,8 @@ def test_mixed_jobs_both_modes(job):
     _say("mixed", job)
     want_b, want_c = _oracle(job)
     for tune in (None, cs.Tune(large_mode=cs.LARGE_THREE_GAP), cs.Tune(thr=1, hits_per_item=8),
-                 cs.Tune(tile_rows=3, small_slices=5)):
+                 cs.Tune(tile_rows=3, small_slices=5), cs.Tune(scatter=cs.SCATTER_ATOMIC),
+                 cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC, thr=1)):
         b, c, diag, _ = _run(job, tune)
         _assert_same(job, b, c, want_b, want_c)
         assert diag.small_marks + diag.large_hits == int(want_c.sum())

@@ -101,3 +101,36 @@ def test_three_gap_threshold_floor():
 def test_zero_row_job_is_valid():
     lay = cs.plan(W.Job(11, 2, 4, 1, 5, 100))     # m = 4 only, even, d = 2
     assert lay.n_m == 0 and lay.bitmap_bytes == 0
+
+
+def _cell_bound(job, thr):
+    """Distinct prime factors above thr that a number m K + X of the interval can have."""
+    import math
+    ps = [q for q in range(2, job.P + 1) if all(q % r for r in range(2, int(q ** 0.5) + 1))]
+    log2_n = math.log2(job.m_start + job.m_inc + 1) + sum(math.log2(q) for q in ps if job.d % q)
+    return math.floor(log2_n / math.log2(thr + 1))
+
+
+@pytest.mark.parametrize("job", [W.SMALL, W.MEDIUM, W.PAPER_SCALE, W.Job(4001, 1, 1, 100, 1000, 10**6),
+                                 W.Job(1511, 30, 10, 2000, 300, 10**7)],
+                         ids=["small", "medium", "paper", "p4001", "p1511"])
+@pytest.mark.parametrize("mode", [cs.LARGE_G, cs.LARGE_THREE_GAP], ids=["g", "three_gap"])
+def test_scatter_choice_follows_the_counter_bound(job, mode):
+    lay = cs.plan(job, cs.Tune(large_mode=mode))
+    fits = _cell_bound(job, lay.thr) < 256
+    assert lay.scatter == (cs.SCATTER_BYTES if fits else cs.SCATTER_ATOMIC)
+    assert cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_ATOMIC)).scatter == cs.SCATTER_ATOMIC
+    if fits:
+        lb = cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_BYTES))
+        la = cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_ATOMIC))
+        assert lb.ws_bytes + 256 >= la.ws_bytes + lay.n_m * lay.row_words * 32   # 256-byte aligned regions
+    else:
+        with pytest.raises(cs.CsError) as e:
+            cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_BYTES))
+        assert e.value.status == -1
+
+
+def test_paper_scale_uses_byte_counters():
+    for mode in (cs.LARGE_G, cs.LARGE_THREE_GAP):
+        assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode)).scatter == cs.SCATTER_BYTES
+    assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6)).scatter == cs.SCATTER_ATOMIC
