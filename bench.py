@@ -22,6 +22,9 @@ METRIC = "factors found/s + primes/s on 953#/210 sieve; served-job p50/p99 laten
 # (the fp64 FMA rate, 78.6 TFLOP/s, counts two flops per such operation).
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
+# v_mad_u64_u32 (32 x 32 -> 64-bit multiply-add, the limb product of the probable-prime test)
+# issues at the full VALU rate on gfx950 (an independent-chain probe measured 3.4e13/s).
+MAD_PEAK = 256 * 64 * 2.4e9
 
 
 def _args():
@@ -45,6 +48,8 @@ def _args():
     ap.add_argument("--no-serve", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--serve-jobs", type=int, default=512)
     ap.add_argument("--serve-warmup", type=int, default=32)
+    ap.add_argument("--prp-rows", type=int, default=16384,
+                    help="rows of the sieved job searched for their surrounding probable primes (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (a known-size reference for "
                          "HBM byte counters)")
@@ -96,6 +101,34 @@ def _kernel_traffic(mode):
     if not rec or rec.get("hash") != m.hexdigest()[:16]:
         return None
     return rec["traffic_gb"]
+
+
+def _prp_leg(cs, torch, np, job, bitmap, n_rows, stream):
+    """Surrounding probable primes of the first n_rows sieved rows (cs_surround): each side of a
+    row is searched outward among its unmarked columns with the strong base-2 test."""
+    ms = cs.rows(job)[:n_rows]
+    m_dev = torch.from_numpy(ms.astype(np.int64)).cuda()
+    rows = bitmap[:n_rows]
+    ws = torch.empty((cs.surround_ws_bytes(job, n_rows),), dtype=torch.uint8, device="cuda")
+    cs.surround(job, rows, m_dev, ws, stream)                       # warm-up
+    t0 = time.perf_counter()
+    out, st = cs.surround(job, rows, m_dev, ws, stream)
+    t1 = time.perf_counter()
+    o = out.cpu().numpy().astype(np.int64)
+    useful = int(o[:, 2:].sum())
+    both = (o[:, 0] != 0) & (o[:, 1] != 0)
+    gaps = (o[:, 1] - o[:, 0])[both]
+    # algorithmic multiply-adds of one test: one Montgomery squaring (2 NL^2 limb products, CIOS)
+    # per bit of N - 1 below the top one
+    mads = st.tests * (st.bits - 1) * 2 * st.limbs ** 2
+    sec = t1 - t0
+    return {"rows": n_rows, "s": sec, "rows_per_s": n_rows / sec, "useful_tests": useful,
+            "tests_run": st.tests, "tests_per_s": st.tests / sec, "useful_tests_per_s": useful / sec,
+            "rounds": st.rounds, "limbs": st.limbs, "bits": st.bits, "rows_both_found": int(both.sum()),
+            "mean_gap": float(gaps.mean()) if len(gaps) else None, "max_gap": int(gaps.max()) if len(gaps) else None,
+            "roofline": {"bound": "alu", "kernel": "k_sv_test", "achieved": mads / (st.test_ms / 1e3) / 1e12,
+                         "peak": MAD_PEAK / 1e12, "unit": "T v_mad_u64_u32/s",
+                         "frac": mads / (st.test_ms / 1e3) / MAD_PEAK, "test_ms": st.test_ms, "traffic": None}}
 
 
 def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
@@ -285,6 +318,11 @@ def main():
                                                   "g_calls", "g_levels")},
         "roofline": roof,
     }
+    if args.prp_rows > 0:
+        print(f"# prp leg on {min(args.prp_rows, lay.n_m)} rows ...", file=sys.stderr, flush=True)
+        out["prp"] = _prp_leg(cs, torch, np, job, bitmap, min(args.prp_rows, lay.n_m), stream)
+        print(f"# prp {out['prp']['s']:.3f} s, {out['prp']['tests_per_s']:.3e} tests/s, "
+              f"frac {out['prp']['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
     if args.also_g and args.mode != "g":
         tg = cs.Tune(large_mode=cs.LARGE_G)
         ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

@@ -188,6 +188,56 @@ cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, 
                   void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Probable-prime stage (after the sieve).  Section 2 ("Larger Gaps", "Sieving"): the numbers
+ * of an interval that the sieve left unmarked are tested for primality walking away from N on
+ * both sides until the surrounding primes are found; their distance is the gap containing N and
+ * gap / log(lower prime) its merit (Section 1).  Section 2.2: the test is probabilistic; the
+ * one here is the strong probable-prime test to base 2 (the first half of BPSW): with
+ * n - 1 = 2^s t, t odd, n passes iff 2^t = 1 or 2^(2^r t) = -1 (mod n) for some 0 <= r < s.
+ * Primes always pass; so do the (rare) strong pseudoprimes to base 2, e.g. 2047 = 23 * 89.
+ * ------------------------------------------------------------------------------------------ */
+
+/* The test for n numbers of n_limbs 32-bit limbs each (little endian; number i at
+ * d_limbs + i * n_limbs): d_out[i] = 1 if it passes, else 0 (also for 0, 1 and even numbers
+ * other than 2).  1 <= n_limbs <= 64 (numbers below 2^2048), CS_ERANGE otherwise.  Device
+ * buffers; enqueued on `stream`, no workspace. */
+cs_status cs_prp_numbers(const uint32_t* d_limbs, uint32_t n_limbs, uint64_t n, uint8_t* d_out, void* stream);
+
+/* Result of the surrounding-prime search for one row, N = m*K. */
+typedef struct cs_surround_row {
+  int32_t prev;         /* largest X < 0 with N + X a probable prime, searched among the unmarked
+                           columns in [-sl, -1]; 0 if there is none */
+  int32_t next;         /* smallest such X > 0 in [1, sl]; 0 if none */
+  uint32_t tests_prev;  /* unmarked columns on that side up to and including prev (all of them
+                           when prev = 0): the tests a sequential search runs */
+  uint32_t tests_next;
+} cs_surround_row;
+
+typedef struct cs_surround_stats {
+  uint64_t rounds;      /* gather/test/resolve rounds run */
+  uint64_t tests;       /* tests run, including those past a side's first probable prime */
+  uint64_t limbs;       /* 32-bit limbs per number in the test kernel */
+  uint64_t bits;        /* bit length of K plus that of the largest m: every N + X tested has
+                           this many bits or one fewer (one more only if X > 0 carries) */
+  double test_ms;       /* time of the test kernels alone (HIP events on `stream`) */
+} cs_surround_stats;
+
+/* Workspace bytes of cs_surround for n_rows rows of this job (host only). */
+cs_status cs_surround_ws(const cs_job* job, uint64_t n_rows, uint64_t* ws_bytes);
+
+/* Surrounding probable primes of n_rows rows of a sieved job.
+ * d_bitmap: n_rows rows of row_words words in cs_sieve's layout (1 = marked composite), the
+ * rows to search (e.g. a slice of cs_sieve's bitmap); d_m[i]: the m of row i, within
+ * [m_start, m_start + m_inc) (a device-side check reports CS_EDEVICE otherwise); d_out: n_rows
+ * results.  Candidates per side are tested in rounds of up to 1024 at once and the first
+ * probable prime in walking order wins, so results equal a sequential search's.
+ * N = m K + sl must stay below 2^2048 (CS_ERANGE).  Synchronous: returns after the work has
+ * completed (one host read of a counter per round).  stats may be NULL. */
+cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, const uint64_t* d_m, uint64_t n_rows,
+                      cs_surround_row* d_out, void* d_ws, uint64_t ws_bytes, cs_surround_stats* stats,
+                      void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * Batches: many jobs (different P, d, m ranges, sl, limits) sieved by one sequence of fused
  * launches.  The prime table is built once up to the largest limit and shared; the per-job
  * preparation kernels and the two sieve kernels each cover every job in a single launch

@@ -108,6 +108,20 @@ class Diag:
     error_flags: int
 
 
+class cs_surround_stats(C.Structure):
+    _fields_ = [("rounds", C.c_uint64), ("tests", C.c_uint64), ("limbs", C.c_uint64), ("bits", C.c_uint64),
+                ("test_ms", C.c_double)]
+
+
+@dataclass
+class SurroundStats:
+    rounds: int
+    tests: int
+    limbs: int
+    bits: int
+    test_ms: float
+
+
 _lib = None
 
 
@@ -151,6 +165,9 @@ def lib():
         "cs_server_release": ([vp, u64], i32),
         "cs_server_stats": ([vp, P(cs_server_counters)], i32),
         "cs_server_destroy": ([vp], i32),
+        "cs_prp_numbers": ([vp, u32, u64, vp, vp], i32),
+        "cs_surround_ws": ([P(cs_job), u64, P(u64)], i32),
+        "cs_surround": ([P(cs_job), vp, vp, u64, vp, vp, u64, P(cs_surround_stats), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -403,3 +420,35 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def prp_numbers(limbs, stream=None):
+    """Strong probable-prime test to base 2 (cs_prp_numbers) of the numbers in a device int32
+    tensor [n, n_limbs] of little-endian 32-bit limbs.  Returns a device uint8 tensor [n]."""
+    import torch
+    n, nl = limbs.shape
+    out = torch.empty((n,), dtype=torch.uint8, device=limbs.device)
+    _check(lib().cs_prp_numbers(_ptr(limbs.contiguous()), nl, n, _ptr(out), _stream(stream)), "cs_prp_numbers")
+    return out
+
+
+def surround_ws_bytes(job, n_rows: int) -> int:
+    out = C.c_uint64()
+    _check(lib().cs_surround_ws(C.byref(_cjob(job)), n_rows, C.byref(out)), "cs_surround_ws")
+    return out.value
+
+
+def surround(job, bitmap, m_rows, ws=None, stream=None):
+    """Nearest probable primes below and above N = m*K for each row (cs_surround).  bitmap: device
+    int32 [n_rows, row_words] (sieved rows); m_rows: device int64 [n_rows] (the m of each row).
+    Returns (device int32 tensor [n_rows, 4] = prev, next, tests_prev, tests_next; SurroundStats).
+    The call returns after the work has completed."""
+    import torch
+    n = int(m_rows.numel())
+    out = torch.empty((max(n, 1), 4), dtype=torch.int32, device=m_rows.device)
+    if ws is None:
+        ws = torch.empty((max(surround_ws_bytes(job, n), 1),), dtype=torch.uint8, device=m_rows.device)
+    st = cs_surround_stats()
+    _check(lib().cs_surround(C.byref(_cjob(job)), _ptr(bitmap), _ptr(m_rows), n, _ptr(out), _ptr(ws), ws.numel(),
+                             C.byref(st), _stream(stream)), "cs_surround")
+    return out[:n], SurroundStats(st.rounds, st.tests, st.limbs, st.bits, st.test_ms)

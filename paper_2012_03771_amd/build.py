@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libcsieve.so")
-SOURCES = ["kernels.hip", "plan.hip", "api.hip", "batch.hip", "server.hip"]
+SOURCES = ["kernels.hip", "plan.hip", "api.hip", "batch.hip", "server.hip", "prp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

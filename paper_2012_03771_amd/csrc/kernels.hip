@@ -1044,6 +1044,8 @@ static hipError_t note(const char* what) {
 
 const char* last_error_detail() { return g_last_error; }
 
+hipError_t record_launch(const char* what) { return note(what); }
+
 hipError_t launch_write_job(const JobDev& jd, JobDev* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_write_job, dim3(1), dim3(1), 0, s, jd, dst); { hipError_t e_ = note("k_write_job"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();

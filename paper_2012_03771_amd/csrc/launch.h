@@ -21,6 +21,8 @@ struct PrimeWs {
 
 // Name and message of the last failed launch in this thread (empty if none).
 const char* last_error_detail();
+// Checks the last launch and records "what: message" for cs_last_error if it failed.
+hipError_t record_launch(const char* what);
 
 hipError_t launch_write_job(const JobDev& jd, JobDev* dst, hipStream_t s);
 // Copies a small host table to device memory through kernel arguments (2 KB per launch):

@@ -1,0 +1,617 @@
+// Probable-prime stage after the sieve: a strong test to base 2 per candidate on the GPU, and the
+// search for the nearest probable prime below and above each N = m*K among the unmarked columns
+// of a sieved row (Section 2: after sieving, the survivors are tested walking away from N until
+// both surrounding primes are found; Section 2.2: a probabilistic test, as the first half of BPSW).
+//
+// Arithmetic: one lane per candidate, numbers of NL 32-bit limbs (NL fixed per instantiation),
+// Montgomery squaring by coarsely integrated operand scanning.  The multiplicand and the modulus
+// live in registers (compile-time limb indices); the multiplier limb of the outer loop is read
+// from this lane's column of LDS (lane-strided, conflict-free), so only the inner loops are
+// unrolled and the code of one squaring stays a few KB.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/csieve.h"
+#include "device.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace cs {
+namespace {
+
+constexpr int kPrpBlock = 256;
+constexpr uint32_t kSurroundB0 = 8;        // candidates per side and round while many sides are open
+constexpr uint32_t kSurroundBMax = 1024;   // ... and at most, once few are left
+constexpr uint64_t kSurroundSlotsMin = 1u << 18;
+
+// out = v - n if (v >= n or hi_set) else v, for v < 2n given as NL limbs plus the bit hi_set.
+// The comparison runs as a borrow-only pass and the subtraction of n & mask as a second pass, so
+// no second NL-limb temporary is live.
+template <int NL>
+__device__ __forceinline__ void sub_if_ge(const uint32_t* v, bool hi_set, const uint32_t (&n)[NL], uint32_t (&out)[NL]) {
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) br = (uint32_t)(((uint64_t)v[j] - n[j] - br) >> 32) & 1u;
+  const uint32_t mask = (hi_set || br == 0) ? 0xffffffffu : 0u;
+  br = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const uint64_t d = (uint64_t)v[j] - (n[j] & mask) - br;
+    out[j] = (uint32_t)d;
+    br = (uint32_t)(d >> 32) & 1u;
+  }
+}
+
+// a = a*a/R mod n, R = 2^(32 NL); requires a < n, n odd; b = this lane's LDS column.
+template <int NL>
+__device__ __forceinline__ void mont_sqr(uint32_t (&a)[NL], const uint32_t (&n)[NL], uint32_t ninv,
+                                         uint32_t* __restrict__ b) {
+#pragma unroll
+  for (int j = 0; j < NL; ++j) b[j * kPrpBlock] = a[j];
+  uint32_t t[NL + 2];
+#pragma unroll
+  for (int j = 0; j < NL + 2; ++j) t[j] = 0;
+#pragma unroll 1
+  for (int i = 0; i < NL; ++i) {
+    const uint32_t bi = b[i * kPrpBlock];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {                 // t += a * b_i
+      const uint64_t s = (uint64_t)a[j] * bi + t[j] + c;
+      t[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    uint64_t s = (uint64_t)t[NL] + c;
+    t[NL] = (uint32_t)s;
+    t[NL + 1] = (uint32_t)(s >> 32);
+    const uint32_t q = t[0] * ninv;                // t + q n = 0 (mod 2^32)
+    s = (uint64_t)q * n[0] + t[0];
+    c = (uint32_t)(s >> 32);
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {                 // t = (t + q n) / 2^32
+      s = (uint64_t)q * n[j] + t[j] + c;
+      t[j - 1] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    s = (uint64_t)t[NL] + c;
+    t[NL - 1] = (uint32_t)s;
+    t[NL] = t[NL + 1] + (uint32_t)(s >> 32);
+  }
+  sub_if_ge<NL>(t, t[NL] != 0, n, a);
+}
+
+// a = 2a mod n for a < n.
+template <int NL>
+__device__ __forceinline__ void mod_dbl(uint32_t (&a)[NL], const uint32_t (&n)[NL]) {
+  const uint32_t top = a[NL - 1] >> 31;
+#pragma unroll
+  for (int j = NL - 1; j > 0; --j) a[j] = (a[j] << 1) | (a[j - 1] >> 31);
+  a[0] <<= 1;
+  sub_if_ge<NL>(a, top != 0, n, a);
+}
+
+// x * R^-1 mod n (Montgomery reduction) for x < n.
+template <int NL>
+__device__ __forceinline__ void mont_redc(const uint32_t (&x)[NL], const uint32_t (&n)[NL], uint32_t ninv,
+                                          uint32_t (&y)[NL]) {
+  uint32_t t[NL + 1];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) t[j] = x[j];
+  t[NL] = 0;
+#pragma unroll 1
+  for (int i = 0; i < NL; ++i) {
+    const uint32_t q = t[0] * ninv;
+    uint64_t s = (uint64_t)q * n[0] + t[0];
+    uint32_t c = (uint32_t)(s >> 32);
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {
+      s = (uint64_t)q * n[j] + t[j] + c;
+      t[j - 1] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    s = (uint64_t)t[NL] + c;
+    t[NL - 1] = (uint32_t)s;
+    t[NL] = (uint32_t)(s >> 32);
+  }
+  sub_if_ge<NL>(t, t[NL] != 0, n, y);
+}
+
+// y == 1 / y == n - 1 (n odd).
+template <int NL>
+__device__ __forceinline__ bool is_one(const uint32_t (&y)[NL]) {
+  uint32_t x = y[0] ^ 1u;
+#pragma unroll
+  for (int j = 1; j < NL; ++j) x |= y[j];
+  return x == 0;
+}
+template <int NL>
+__device__ __forceinline__ bool is_minus_one(const uint32_t (&y)[NL], const uint32_t (&n)[NL]) {
+  uint32_t x = y[0] ^ (n[0] - 1u);
+#pragma unroll
+  for (int j = 1; j < NL; ++j) x |= y[j] ^ n[j];
+  return x == 0;
+}
+
+// Limb i of n - 1 (n odd, so only limb 0 changes), i a runtime index.
+template <int NL>
+__device__ __forceinline__ uint32_t nm1_limb(const uint32_t (&n)[NL], int i) {
+  uint32_t e = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) e = (j == i) ? n[j] : e;
+  return i == 0 ? e - 1u : e;
+}
+
+// Strong probable-prime test to base 2 of n (any value below 2^(32 NL)).
+template <int NL>
+__device__ bool sprp2(const uint32_t (&n)[NL], uint32_t* __restrict__ b) {
+  uint32_t hi = 0;
+#pragma unroll
+  for (int j = 1; j < NL; ++j) hi |= n[j];
+  if (!(n[0] & 1u)) return hi == 0 && n[0] == 2u;
+  if (hi == 0 && n[0] < 3u) return false;          // 1
+  uint32_t inv = n[0];                              // n[0]^-1 mod 2^32 by Newton (3 -> 48 bits)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) inv *= 2u - n[0] * inv;
+  const uint32_t ninv = 0u - inv;
+  int top = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) top = n[j] ? j : top;
+  uint32_t ntop = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) ntop = (j == top) ? n[j] : ntop;
+  const int bits = 32 * top + 32 - __clz(ntop);
+  int s = 0;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {                    // n - 1 = 2^s t, t odd
+    const uint32_t e = (j == 0) ? n[0] - 1u : n[j];
+    if (!found && e) { s = 32 * j + __ffs(e) - 1; found = true; }
+  }
+  // x = 2R mod n (2 in Montgomery form): 2^(bits-1) < n doubled up to 2^(32 NL + 1)
+  uint32_t x[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) x[j] = (j == ((bits - 1) >> 5)) ? (1u << ((bits - 1) & 31)) : 0u;
+  for (int k = 0; k < 32 * NL - bits + 2; ++k) mod_dbl<NL>(x, n);
+  // 2^t, left to right over the bits of t = bits [s, bits-1] of n - 1; the top bit (bits - 1)
+  // is 1 and gave the starting value 2.
+  uint32_t e = nm1_limb<NL>(n, (bits - 2) >> 5);
+  for (int bit = bits - 2; bit >= s; --bit) {
+    if ((bit & 31) == 31) e = nm1_limb<NL>(n, bit >> 5);
+    mont_sqr<NL>(x, n, ninv, b);
+    if ((e >> (bit & 31)) & 1u) mod_dbl<NL>(x, n);
+  }
+  uint32_t y[NL];
+  mont_redc<NL>(x, n, ninv, y);
+  if (is_one<NL>(y) || is_minus_one<NL>(y, n)) return true;
+  for (int r = 1; r < s; ++r) {
+    mont_sqr<NL>(x, n, ninv, b);
+    mont_redc<NL>(x, n, ninv, y);
+    if (is_minus_one<NL>(y, n)) return true;
+    if (is_one<NL>(y)) return false;
+  }
+  return false;
+}
+
+template <int NL>
+__global__ __launch_bounds__(kPrpBlock) void k_prp_numbers(const uint32_t* __restrict__ limbs, uint32_t n_limbs,
+                                                           uint64_t count, uint8_t* __restrict__ out) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t i = blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x;
+  if (i >= count) return;
+  uint32_t v[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) v[j] = (uint32_t)j < n_limbs ? limbs[i * n_limbs + j] : 0u;
+  out[i] = sprp2<NL>(v, lds + threadIdx.x) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Surrounding primes.  A task is one side of one row: task = 2 row + side (side 0 walks down from
+// the largest negative column, side 1 up from the smallest positive one).  Each round gathers the
+// next B unmarked columns of every open task, tests them all, and closes the tasks whose batch
+// holds a probable prime (the first one in walking order) or that ran out of columns.
+// ---------------------------------------------------------------------------------------------
+struct SurroundDev {
+  const uint32_t* bitmap;     // n_rows x row_words, bit = 1: marked composite
+  const uint64_t* m;          // m of each row
+  const uint32_t* klimbs;     // K, NL limbs
+  const int32_t* x_of_col;    // n_x
+  int32_t* cur;               // per task: next column to look at
+  int32_t* nxt;               // per task: where the current batch ended
+  int32_t* slot_col;          // per slot: column, or -1
+  uint8_t* slot_res;          // per slot: 1 if probable prime
+  uint32_t* act[2];           // open-task lists (ping-pong)
+  uint32_t* n_act;            // [0], [1] list sizes; [2] error flags
+  unsigned long long* tests;  // tests run
+  cs_surround_row* out;
+  uint64_t n_rows, m_lo, m_hi;
+  uint32_t row_words, n_x;
+  int32_t c_neg, c_pos;       // largest column with X < 0, smallest with X > 0 (-1 / n_x if none)
+};
+
+__global__ void k_sv_init(SurroundDev sv) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t >= 2 * sv.n_rows) return;
+  sv.cur[t] = (t & 1) ? sv.c_pos : sv.c_neg;
+  sv.act[0][t] = (uint32_t)t;
+  if ((t & 1) == 0) {
+    cs_surround_row z;
+    z.prev = 0;
+    z.next = 0;
+    z.tests_prev = 0;
+    z.tests_next = 0;
+    sv.out[t >> 1] = z;
+  }
+}
+
+// Up to B unmarked columns of each open task, in walking order, into slots [i B, i B + B).
+__global__ void k_sv_gather(SurroundDev sv, uint32_t in, uint32_t n_open, uint32_t B) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_open) return;
+  const uint32_t task = sv.act[in][i];
+  const uint64_t row = task >> 1;
+  const uint32_t* __restrict__ w = sv.bitmap + row * sv.row_words;
+  int32_t* __restrict__ slots = sv.slot_col + (uint64_t)i * B;
+  int32_t c = sv.cur[task];
+  uint32_t k = 0;
+  if (task & 1) {                                   // upwards to n_x - 1
+    while (k < B && c < (int32_t)sv.n_x) {
+      const int32_t wbase = c & ~31;
+      uint32_t free_bits = ~w[c >> 5] & (0xffffffffu << (c & 31));
+      while (free_bits && k < B) {
+        const int32_t col = wbase + __ffs(free_bits) - 1;
+        if (col >= (int32_t)sv.n_x) { free_bits = 0; break; }   // padding bits of the last word
+        slots[k++] = col;
+        free_bits &= free_bits - 1;
+        c = col + 1;
+      }
+      if (k < B) c = wbase + 32;                    // this word has no free column left
+    }
+  } else {                                          // downwards to 0
+    while (k < B && c >= 0) {
+      const int32_t wbase = c & ~31;
+      uint32_t free_bits = ~w[c >> 5] & (0xffffffffu >> (31 - (c & 31)));
+      while (free_bits && k < B) {
+        const int32_t col = wbase + 31 - __clz(free_bits);
+        slots[k++] = col;
+        free_bits &= ~(1u << (col & 31));
+        c = col - 1;
+      }
+      if (k < B) c = wbase - 1;
+    }
+  }
+  sv.nxt[task] = c;
+  for (uint32_t r = k; r < B; ++r) slots[r] = -1;
+}
+
+template <int NL>
+__global__ __launch_bounds__(kPrpBlock) void k_sv_test(SurroundDev sv, uint32_t in, uint64_t n_slots, uint32_t B) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t sidx = blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x;
+  if (sidx >= n_slots) return;
+  const int32_t col = sv.slot_col[sidx];
+  const unsigned long long live = __ballot(col >= 0);
+  if ((threadIdx.x & (kWave - 1)) == 0 && live) atomicAdd(sv.tests, (unsigned long long)__popcll(live));
+  if (col < 0) {
+    sv.slot_res[sidx] = 0;
+    return;
+  }
+  const uint32_t task = sv.act[in][sidx / B];
+  const uint64_t m = sv.m[task >> 1];
+  if (m < sv.m_lo || m >= sv.m_hi) {                // outside the job's range: no result
+    atomicOr(&sv.n_act[2], 1u);
+    sv.slot_res[sidx] = 0;
+    return;
+  }
+  const int32_t X = sv.x_of_col[col];
+  // N = m K + X
+  uint32_t v[NL];
+  const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const uint64_t s = (uint64_t)sv.klimbs[j] * mlo + c;
+    v[j] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  if (mhi) {
+    c = 0;
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {
+      const uint64_t s = (uint64_t)sv.klimbs[j - 1] * mhi + v[j] + c;
+      v[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+  }
+  if (X >= 0) {
+    uint32_t cy = (uint32_t)X;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const uint64_t s = (uint64_t)v[j] + cy;
+      v[j] = (uint32_t)s;
+      cy = (uint32_t)(s >> 32);
+    }
+  } else {
+    uint32_t bw = (uint32_t)(-X);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const uint64_t s = (uint64_t)v[j] - bw;
+      v[j] = (uint32_t)s;
+      bw = (uint32_t)(s >> 32) & 1u;
+    }
+  }
+  sv.slot_res[sidx] = sprp2<NL>(v, lds + threadIdx.x) ? 1 : 0;
+}
+
+__global__ void k_sv_resolve(SurroundDev sv, uint32_t in, uint32_t n_open, uint32_t B) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_open) return;
+  const uint32_t task = sv.act[in][i];
+  const uint64_t row = task >> 1;
+  const uint64_t base = (uint64_t)i * B;
+  uint32_t k = 0;
+  int32_t hit = 0;
+  bool closed = false;
+  for (; k < B; ++k) {
+    const int32_t col = sv.slot_col[base + k];
+    if (col < 0) { closed = true; break; }          // no columns left on this side
+    if (sv.slot_res[base + k]) { hit = sv.x_of_col[col]; ++k; closed = true; break; }
+  }
+  cs_surround_row& o = sv.out[row];
+  if (task & 1) o.tests_next += k;
+  else o.tests_prev += k;
+  if (closed) {
+    if (task & 1) o.next = hit;
+    else o.prev = hit;
+  } else {
+    sv.cur[task] = sv.nxt[task];
+    const uint32_t at = atomicAdd(&sv.n_act[in ^ 1], 1u);
+    sv.act[in ^ 1][at] = task;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------
+#define PRP_INSTANCES(X) X(2) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(36) X(40) X(44) X(48) X(52) X(56) X(60) X(64)
+
+uint32_t pick_nl(uint32_t limbs) {
+  static const uint32_t nls[] = {2, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52, 56, 60, 64};
+  for (uint32_t nl : nls)
+    if (nl >= limbs) return nl;
+  return 0;
+}
+
+hipError_t launch_prp_numbers(uint32_t nl, const uint32_t* limbs, uint32_t n_limbs, uint64_t count, uint8_t* out,
+                              hipStream_t s) {
+  const uint32_t blocks = (uint32_t)((count + kPrpBlock - 1) / kPrpBlock);
+  const size_t lds = (size_t)nl * kPrpBlock * 4;
+  switch (nl) {
+#define CASE(N)                                                                                             \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL(k_prp_numbers<N>, dim3(blocks), dim3(kPrpBlock), lds, s, limbs, n_limbs, count, out); \
+    break;
+    PRP_INSTANCES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return record_launch("k_prp_numbers");
+}
+
+hipError_t launch_sv_test(uint32_t nl, const SurroundDev& sv, uint32_t in, uint64_t n_slots, uint32_t B,
+                          hipStream_t s) {
+  const uint32_t blocks = (uint32_t)((n_slots + kPrpBlock - 1) / kPrpBlock);
+  const size_t lds = (size_t)nl * kPrpBlock * 4;
+  switch (nl) {
+#define CASE(N)                                                                                      \
+  case N:                                                                                            \
+    hipLaunchKernelGGL(k_sv_test<N>, dim3(blocks), dim3(kPrpBlock), lds, s, sv, in, n_slots, B);      \
+    break;
+    PRP_INSTANCES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return record_launch("k_sv_test");
+}
+
+// K = product of the primes dividing K, as 32-bit limbs (little endian).
+std::vector<uint32_t> k_limbs(const std::vector<uint32_t>& kq) {
+  std::vector<uint32_t> k(1, 1u);
+  for (uint32_t q : kq) {
+    uint64_t c = 0;
+    for (auto& l : k) {
+      const uint64_t s = (uint64_t)l * q + c;
+      l = (uint32_t)s;
+      c = s >> 32;
+    }
+    if (c) k.push_back((uint32_t)c);
+  }
+  return k;
+}
+
+uint32_t bit_length(const std::vector<uint32_t>& v) {
+  for (size_t i = v.size(); i-- > 0;)
+    if (v[i]) return (uint32_t)(32 * i + 32 - __builtin_clz(v[i]));
+  return 0;
+}
+
+struct SvLayout {
+  uint64_t klimbs, xcol, cur, nxt, act0, act1, n_act, slot_col, slot_res, total, slots;
+};
+
+SvLayout sv_layout(uint32_t nl, uint32_t n_x, uint64_t n_rows) {
+  SvLayout L;
+  uint64_t o = 0;
+  auto take = [&](uint64_t b) { uint64_t at = o; o = (o + std::max<uint64_t>(b, 8) + 255) & ~255ull; return at; };
+  const uint64_t tasks = 2 * n_rows;
+  L.slots = std::max<uint64_t>(tasks * kSurroundB0, kSurroundSlotsMin);
+  L.klimbs = take(nl * 4ull);
+  L.xcol = take(n_x * 4ull);
+  L.cur = take(tasks * 4);
+  L.nxt = take(tasks * 4);
+  L.act0 = take(tasks * 4);
+  L.act1 = take(tasks * 4);
+  L.n_act = take(32);
+  L.slot_col = take(L.slots * 4);
+  L.slot_res = take(L.slots);
+  L.total = o;
+  return L;
+}
+
+// Host description of a surround call: plan, K limbs, limb count.
+cs_status surround_setup(const cs_job* job, Plan* pl, std::vector<uint32_t>* kl, uint32_t* nl) {
+  cs_status st = make_plan(job, nullptr, 256, pl);
+  if (st) return st;
+  *kl = k_limbs(pl->kq);
+  const uint64_t m_max = pl->job.m_start + pl->job.m_inc - 1;
+  const uint32_t bits = bit_length(*kl) + (64 - __builtin_clzll(m_max)) + 1;   // m K + sl < 2^bits
+  *nl = pick_nl((bits + 31) / 32);
+  return *nl ? CS_OK : CS_ERANGE;
+}
+
+}  // namespace
+}  // namespace cs
+
+using namespace cs;
+
+extern "C" cs_status cs_prp_numbers(const uint32_t* d_limbs, uint32_t n_limbs, uint64_t n, uint8_t* d_out,
+                                    void* stream) {
+  if (n == 0) return CS_OK;
+  if (!d_limbs || !d_out || n_limbs == 0) return CS_EINVAL;
+  const uint32_t nl = pick_nl(n_limbs);
+  if (!nl) return CS_ERANGE;
+  if (n > (1ull << 40)) return CS_ERANGE;
+  return launch_prp_numbers(nl, d_limbs, n_limbs, n, d_out, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? CS_OK
+             : CS_EDEVICE;
+}
+
+extern "C" cs_status cs_surround_ws(const cs_job* job, uint64_t n_rows, uint64_t* ws_bytes) {
+  if (!job || !ws_bytes) return CS_EINVAL;
+  if (n_rows >= (1ull << 30)) return CS_ERANGE;
+  Plan pl;
+  std::vector<uint32_t> kl;
+  uint32_t nl = 0;
+  cs_status st = surround_setup(job, &pl, &kl, &nl);
+  if (st) return st;
+  *ws_bytes = sv_layout(nl, pl.n_x, n_rows).total;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, const uint64_t* d_m, uint64_t n_rows,
+                                 cs_surround_row* d_out, void* d_ws, uint64_t ws_bytes, cs_surround_stats* stats,
+                                 void* stream) {
+  if (!job) return CS_EINVAL;
+  if (stats) memset(stats, 0, sizeof *stats);
+  if (n_rows >= (1ull << 30)) return CS_ERANGE;
+  Plan pl;
+  std::vector<uint32_t> kl;
+  uint32_t nl = 0;
+  cs_status st = surround_setup(job, &pl, &kl, &nl);
+  if (st) return st;
+  if (n_rows == 0) return CS_OK;
+  if (!d_bitmap || !d_m || !d_out || !d_ws) return CS_EINVAL;
+  const SvLayout L = sv_layout(nl, pl.n_x, n_rows);
+  if (ws_bytes < L.total) return CS_ERANGE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+
+  std::vector<int32_t> xs;
+  host_columns(pl.job, pl.kq, &xs);
+  int32_t c_neg = -1, c_pos = (int32_t)xs.size();
+  for (size_t c = 0; c < xs.size(); ++c) {
+    if (xs[c] < 0) c_neg = (int32_t)c;
+    if (xs[c] > 0 && c_pos == (int32_t)xs.size()) c_pos = (int32_t)c;
+  }
+  kl.resize(nl, 0u);
+
+  SurroundDev sv;
+  sv.bitmap = d_bitmap;
+  sv.m = d_m;
+  sv.klimbs = reinterpret_cast<const uint32_t*>(ws + L.klimbs);
+  sv.x_of_col = reinterpret_cast<const int32_t*>(ws + L.xcol);
+  sv.cur = reinterpret_cast<int32_t*>(ws + L.cur);
+  sv.nxt = reinterpret_cast<int32_t*>(ws + L.nxt);
+  sv.slot_col = reinterpret_cast<int32_t*>(ws + L.slot_col);
+  sv.slot_res = ws + L.slot_res;
+  sv.act[0] = reinterpret_cast<uint32_t*>(ws + L.act0);
+  sv.act[1] = reinterpret_cast<uint32_t*>(ws + L.act1);
+  sv.n_act = reinterpret_cast<uint32_t*>(ws + L.n_act);
+  sv.tests = reinterpret_cast<unsigned long long*>(ws + L.n_act + 16);
+  sv.out = d_out;
+  sv.n_rows = n_rows;
+  sv.m_lo = pl.job.m_start;
+  sv.m_hi = pl.job.m_start + pl.job.m_inc;
+  sv.row_words = pl.row_words;
+  sv.n_x = pl.n_x;
+  sv.c_neg = c_neg;
+  sv.c_pos = c_pos;
+
+#define SV_TRY(expr)                                 \
+  do {                                               \
+    if ((expr) != hipSuccess) return CS_EDEVICE;     \
+  } while (0)
+  SV_TRY(launch_upload(ws + L.klimbs, kl.data(), nl * 4ull, s));
+  if (!xs.empty()) SV_TRY(launch_upload(ws + L.xcol, xs.data(), xs.size() * 4ull, s));
+  const uint64_t tasks = 2 * n_rows;
+  SV_TRY(launch_fill_u32(sv.n_act, 8, 0u, s));
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return CS_EDEVICE;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return CS_EDEVICE;
+  }
+  double test_ms = 0.0;
+  cs_status result = CS_OK;
+  uint32_t n_open = (uint32_t)tasks;
+  uint32_t in = 0;
+  uint64_t rounds = 0;
+  unsigned long long run = 0;
+  uint32_t err = 0;
+  do {
+    hipLaunchKernelGGL(k_sv_init, dim3((uint32_t)((tasks + 255) / 256)), dim3(256), 0, s, sv);
+    if (record_launch("k_sv_init") != hipSuccess) { result = CS_EDEVICE; break; }
+    while (n_open) {
+      uint64_t B = L.slots / n_open;
+      B = std::min<uint64_t>(std::max<uint64_t>(B, 1), kSurroundBMax);
+      const uint32_t b32 = (uint32_t)B;
+      const uint32_t g = (n_open + 255) / 256;
+      if (launch_fill_u32(sv.n_act + (in ^ 1), 1, 0u, s) != hipSuccess) { result = CS_EDEVICE; break; }
+      hipLaunchKernelGGL(k_sv_gather, dim3(g), dim3(256), 0, s, sv, in, n_open, b32);
+      if (record_launch("k_sv_gather") != hipSuccess) { result = CS_EDEVICE; break; }
+      if (hipEventRecord(ev[0], s) != hipSuccess) { result = CS_EDEVICE; break; }
+      if (launch_sv_test(nl, sv, in, (uint64_t)n_open * B, b32, s) != hipSuccess) { result = CS_EDEVICE; break; }
+      if (hipEventRecord(ev[1], s) != hipSuccess) { result = CS_EDEVICE; break; }
+      hipLaunchKernelGGL(k_sv_resolve, dim3(g), dim3(256), 0, s, sv, in, n_open, b32);
+      if (record_launch("k_sv_resolve") != hipSuccess) { result = CS_EDEVICE; break; }
+      uint32_t next = 0;
+      if (hipMemcpyAsync(&next, sv.n_act + (in ^ 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { result = CS_EDEVICE; break; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) test_ms += ms;
+      ++rounds;
+      n_open = next;
+      in ^= 1;
+    }
+    if (result) break;
+    if (hipMemcpyAsync(&err, sv.n_act + 2, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&run, sv.tests, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      result = CS_EDEVICE;
+  } while (0);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+#undef SV_TRY
+  if (result) return result;
+  if (stats) {
+    stats->rounds = rounds;
+    stats->tests = run;
+    stats->limbs = nl;
+    stats->bits = bit_length(kl) + (64 - __builtin_clzll(pl.job.m_start + pl.job.m_inc - 1));
+    stats->test_ms = test_ms;
+  }
+  return err ? CS_EDEVICE : CS_OK;
+}
