@@ -80,8 +80,9 @@ typedef struct cs_tune {
   uint32_t branches;       /* cs_sieve_range only: CS_BRANCH_ALL (0), CS_BRANCH_SMALL or
                               CS_BRANCH_LARGE, to run one branch per call (e.g. to time it) */
   uint32_t scatter;        /* how large-prime hits reach the bitmap: CS_SCATTER_AUTO (0),
-                              CS_SCATTER_ATOMIC or CS_SCATTER_BYTES */
-  uint32_t reserved;
+                              CS_SCATTER_ATOMIC, CS_SCATTER_BYTES or CS_SCATTER_LIST */
+  uint32_t list_chunks;    /* CS_SCATTER_LIST: pool capacity in chunks of 4096 hits; 0 = automatic
+                              (a smaller pool only moves hits to the atomic fallback) */
 } cs_tune;
 
 /* Large-prime hit scatter.  ATOMIC: per hit, a device-scope atomic OR into the packed bitmap and
@@ -91,11 +92,20 @@ typedef struct cs_tune {
  * to the counts and clears them.  BYTES is exact only while no number m K + X of the interval can
  * have 256 distinct prime factors above the threshold, i.e. while
  * floor(log2((m_start + m_inc + 1) K) / log2(thr + 1)) < 256; requesting it otherwise gives
- * CS_EINVAL.  AUTO: BYTES where exact for cs_sieve / cs_prepare / cs_sieve_range, ATOMIC inside
- * batches and the server (which ignore BYTES).  Outputs are identical in every mode. */
+ * CS_EINVAL.  LIST: no atomic per hit: each wavefront appends its hits as 32-bit cells
+ * (row << s | column, 2^s >= n_x) to a chunk of a workspace pool with coalesced stores; after the
+ * branch the cells are grouped by buckets of rows in two counting-sort passes and applied through
+ * LDS tiles.  The pool holds about
+ * 1.15x the expected number of large hits (n_m n_x (log log limit - log log thr), Mertens); hits
+ * beyond it fall back to the atomic path, so results stay exact.  LIST needs n_m * 2^s <= 2^32 and
+ * at most 8192 row buckets (CS_EINVAL when requested otherwise).  AUTO, for cs_sieve / cs_prepare
+ * / cs_sieve_range: LIST with CS_LARGE_THREE_GAP where possible, else BYTES where exact, else
+ * ATOMIC; inside batches and the server ATOMIC (they ignore BYTES and LIST).  Outputs are
+ * identical in every mode. */
 #define CS_SCATTER_AUTO   0u
 #define CS_SCATTER_ATOMIC 1u
 #define CS_SCATTER_BYTES  2u
+#define CS_SCATTER_LIST   3u
 
 #define CS_BRANCH_ALL   0u
 #define CS_BRANCH_SMALL 1u
@@ -110,7 +120,7 @@ typedef struct cs_layout {
   uint64_t ws_bytes;       /* device workspace needed by cs_sieve / cs_prepare / cs_sieve_range */
   uint64_t prime_cap;      /* capacity of the prime table: an upper bound of pi(max(limit, P)) */
   uint64_t thr;            /* effective small/large threshold for the given tuning */
-  uint32_t scatter;        /* large-hit scatter cs_sieve uses: CS_SCATTER_ATOMIC or CS_SCATTER_BYTES */
+  uint32_t scatter;        /* large-hit scatter cs_sieve uses: CS_SCATTER_ATOMIC, _BYTES or _LIST */
   uint32_t reserved;
 } cs_layout;
 

@@ -16,6 +16,7 @@ BRANCH_LARGE = 2
 SCATTER_AUTO = 0
 SCATTER_ATOMIC = 1
 SCATTER_BYTES = 2
+SCATTER_LIST = 3
 
 _ERRORS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ERANGE", -3: "CS_ENOMEM", -4: "CS_EDEVICE", -5: "CS_EBUSY"}
 
@@ -34,7 +35,7 @@ class cs_job(C.Structure):
 class cs_tune(C.Structure):
     _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
                 ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
-                ("branches", C.c_uint32), ("scatter", C.c_uint32), ("reserved", C.c_uint32)]
+                ("branches", C.c_uint32), ("scatter", C.c_uint32), ("list_chunks", C.c_uint32)]
 
 
 class cs_layout(C.Structure):
@@ -75,10 +76,11 @@ class Tune:
     small_slices: int = 0
     branches: int = 0
     scatter: int = 0
+    list_chunks: int = 0
 
     def c(self):
         return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
-                       self.small_slices, self.branches, self.scatter, 0)
+                       self.small_slices, self.branches, self.scatter, self.list_chunks)
 
 
 @dataclass

@@ -44,7 +44,7 @@ extern "C" cs_status cs_plan(const cs_job* job, const cs_tune* tune, cs_layout* 
   out->ws_bytes = pl.ws.total;
   out->prime_cap = pl.cap;
   out->thr = pl.thr;
-  out->scatter = pl.scatter_bytes ? CS_SCATTER_BYTES : CS_SCATTER_ATOMIC;
+  out->scatter = pl.scatter_list ? CS_SCATTER_LIST : (pl.scatter_bytes ? CS_SCATTER_BYTES : CS_SCATTER_ATOMIC);
   out->reserved = 0;
   return CS_OK;
 }
@@ -138,9 +138,15 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s));
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
   if (branches != CS_BRANCH_SMALL) {
+    if (pl.scatter_list) {
+      CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.list_cursor), 2, 0u, s));
+      CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.bkt_count), pl.n_bkt + 1ull, 0u, s));
+    }
+    const uint32_t kind = pl.scatter_list ? 2u : (pl.scatter_bytes ? 1u : 0u);
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, pl.large_lds_bytes,
-                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), pl.scatter_bytes, s));
+                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, s));
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jdp, 1, pl.n_m, device_cu_count(), s));
+    if (pl.scatter_list) CS_TRY(launch_list_group(jdp, pl.list_chunks, pl.n_bkt, pl.bkt_rows, pl.super_shift, pl.row_words, s));
   }
   return CS_OK;
 }

@@ -168,7 +168,7 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   CS_TRY(launch_items_scan(b.jobs_dev, n, b.items_base, s));
   CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));
   JobCtrl* c0 = b.jds[0].ctrl;
-  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, false, s));
+  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, 0u, s));
   return CS_OK;
 }
 

@@ -81,7 +81,31 @@ struct JobDev {
   uint32_t* bitmap;
   uint32_t* counts;
   uint8_t* hitbytes;                 // one byte per (row, column slot) or null: large hits by store
+  // List scatter: large hits appended as cells (row << cell_shift) | col into chunks of kListChunk cells
+  // (one chunk open per wavefront), then grouped by buckets of bkt_rows rows and OR-ed / counted
+  // into the outputs through LDS tiles.
+  uint32_t* list_pool;               // list_chunks * kListChunk cells
+  uint32_t* list_fill;               // per chunk: cells written
+  unsigned long long* list_cursor;   // chunks handed out (beyond list_chunks: pool exhausted)
+  uint32_t* list_sorted;             // cells grouped by bucket
+  uint32_t* bkt_count;               // n_bkt + 1
+  uint32_t* bkt_base;                // n_bkt + 1: exclusive prefix of bkt_count
+  uint32_t* bkt_cursor;              // n_bkt + 1 bucket cursors, then kListSupers group cursors
+  uint64_t list_chunks;
+  uint32_t n_bkt, bkt_rows;          // bkt_rows = 2^(bkt_shift - cell_shift)
+  uint32_t bkt_per_super;            // 2^super_shift buckets per first-level group
+  uint32_t cell_shift;               // cell = (row << cell_shift) | col, 2^cell_shift >= n_x
+  uint32_t bkt_shift, super_shift;
   JobCtrl* ctrl;
 };
+
+constexpr uint32_t kListChunk = 4096;        // cells per list chunk
+constexpr uint32_t kMaxBuckets = 8192;       // row buckets of the list scatter
+constexpr uint32_t kListTileBytes = 60 * 1024;   // LDS tile of one bucket: rows x row_words words + counts
+constexpr uint32_t kListChunksPerBlock = 256;    // chunks per block of the grouping kernels
+constexpr uint32_t kListSupers = 64;             // first-level groups of buckets
+constexpr uint32_t kListMaxPerSuper = kMaxBuckets / kListSupers;
+constexpr uint32_t kListPiece = 1u << 18;        // cells per second-level block step
+constexpr uint32_t kListPart2X = 32;             // second-level blocks per group
 
 }  // namespace cs

@@ -799,12 +799,87 @@ struct LargeTables {
   const uint16_t* dp;
 };
 
-// kCnt: one atomic add per hit into a byte counter per (row, column) (folded into the bitmap and
-// the counts after the launch); otherwise an atomic OR into the bitmap and an atomic add into
-// the row's count.
-template <bool kLds, bool kCnt>
+// Large-hit scatter variants (template argument kSc): 0 = atomic OR into the bitmap and atomic add
+// into the row's count; 1 = one atomic add into a byte counter per (row, column), folded into the
+// bitmap and the counts after the launch; 2 = append the cell row * n_x + col to this wavefront's
+// chunk of the list pool (no atomic per hit), grouped and applied after the launch.
+constexpr uint32_t kNoChunk = 0xffffffffu;
+constexpr uint32_t kPoolFull = 0xfffffffeu;
+
+// The open list chunk of a wavefront and the cells written to it.  Kept in registers, identical
+// in every lane that takes part in a step; lanes that left the walking loop early catch up at the
+// end of the item (list_sync).
+struct ListReg {
+  uint32_t chunk, fill;
+};
+
+// One append step, taken by every lane of the walking loop (ok = this lane has a hit): one ballot,
+// consecutive slots in the open chunk, one 4-byte store per hit (one contiguous run per
+// wavefront).  A full chunk is closed (its fill recorded) and a new one taken from the pool
+// cursor; when the pool is exhausted, hits take the atomic path instead.
+__device__ __forceinline__ void list_step(const JobDev& j, ListReg& lr, bool ok,
+                                          uint32_t cell, uint64_t row, uint32_t col) {
+  const unsigned long long act = __ballot(ok);
+  if (act == 0) return;
+  const uint32_t lane = __lane_id();
+  const uint32_t n = (uint32_t)__popcll(act);
+  const uint32_t rank = (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+  const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1u;
+  if (lr.chunk == kNoChunk || (lr.chunk != kPoolFull && lr.fill + n > kListChunk)) {
+    uint32_t nc = kPoolFull;
+    if (lane == leader) {
+      if (lr.chunk != kNoChunk) j.list_fill[lr.chunk] = lr.fill;
+      const unsigned long long c = atomicAdd(j.list_cursor, 1ull);
+      if (c < j.list_chunks) nc = (uint32_t)c;
+    }
+    lr.chunk = __shfl(nc, (int)leader);
+    lr.fill = 0;
+  }
+  if (ok) {
+    if (lr.chunk != kPoolFull) {
+      j.list_pool[(uint64_t)lr.chunk * kListChunk + lr.fill + rank] = cell;
+    } else {
+      atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
+      atomicAdd(&j.counts[row], 1u);
+    }
+  }
+  lr.fill += n;
+}
+
+// Brings every lane that ran this item to the wavefront's latest list state: chunk ids grow with
+// each allocation and fills grow within a chunk, so the latest state has the largest key
+// (chunk + 1) << 32 | fill (kNoChunk maps to 0, kPoolFull to the top).  lkey: this wavefront's
+// LDS slot, only ever raised.
+__device__ __forceinline__ void list_sync(ListReg& lr, unsigned long long* lkey) {
+  const unsigned long long key = ((unsigned long long)(uint32_t)(lr.chunk + 1u) << 32) | lr.fill;
+  atomicMax(lkey, key);
+  const unsigned long long k = *reinterpret_cast<volatile unsigned long long*>(lkey);
+  lr.chunk = (uint32_t)(k >> 32) - 1u;
+  lr.fill = (uint32_t)k;
+}
+
+template <bool kLds, int kSc>
 __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
-                                           uint32_t jj, unsigned long long& useful) {
+                                           uint32_t jj, unsigned long long& useful, ListReg& lr) {
+  if constexpr (kSc == 2) {
+    // every lane of the loop takes the step, with or without a hit
+    bool ok;
+    uint64_t row;
+    if (j.d_small) {
+      const uint32_t e = T.dp[mp.rd];
+      ok = (e >> 15) != 0;                          // m shares a factor with d (Section 3.2)
+      row = (uint64_t)j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
+    } else {
+      const int32_t r = j.row_of[o];
+      ok = r >= 0;
+      row = ok ? (uint64_t)r : 0ull;
+    }
+    uint32_t col = 0;
+    if (ok) ok = lookup_col(T.ct, jj, &col);        // X shares a factor with K
+    list_step(j, lr, ok, ok ? (uint32_t)((row << j.cell_shift) | col) : 0u, row, col);
+    if (ok) ++useful;
+    return;
+  }
   uint64_t row;
   if (j.d_small) {
     const uint32_t e = T.dp[mp.rd];
@@ -817,7 +892,7 @@ __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kL
   }
   uint32_t col;
   if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
-  if constexpr (kCnt) {
+  if constexpr (kSc == 1) {
     uint32_t* cell = reinterpret_cast<uint32_t*>(j.hitbytes + row * j.row_words * 32ull + (col & ~3u));
     atomicAdd(cell, 1u << (8 * (col & 3u)));
   } else {
@@ -832,12 +907,16 @@ __device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kL
 // From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
 // G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
 // ------------------------------------------------------------------------------------------
-template <bool kLds, bool kCnt>
+template <bool kLds, int kSc>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
                                                unsigned long long* __restrict__ diag, uint32_t lds_ct_words,
                                                uint32_t dpre_n) {
   extern __shared__ uint32_t lds[];
+  __shared__ unsigned long long s_list[256 / kWave];   // per wavefront: latest list state (see list_sync)
+  unsigned long long* lkey = s_list + threadIdx.x / kWave;
+  if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
+  if constexpr (!kLds) __syncthreads();
   LargeTables<kLds> T;
   if constexpr (kLds) {
     const JobDev& j0 = jobs[0];
@@ -852,8 +931,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
   const uint64_t total = job_item_base[n_jobs];
   unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
   uint32_t err = 0;
+  ListReg lreg = {kNoChunk, 0u};
   for (uint64_t item = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; item < total;
        item += (uint64_t)gridDim.x * blockDim.x) {
+    do {   // one item; every exit leads to the per-item list sync below
     uint32_t ji = 0;
     while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
     const JobDev& j = jobs[ji];
@@ -884,7 +965,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const uint64_t L = (j.m_inc + C - 1) / C;
     const uint64_t o_lo = (uint64_t)chunk * L;
     const uint64_t o_hi = min(o_lo + L, j.m_inc);
-    if (o_lo >= o_hi) continue;
+    if (o_lo >= o_hi) break;
 
     const uint64_t p = j.primes[pi];
     const uint64_t k = j.kmod[pi];
@@ -898,7 +979,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       kinv = modinv(k, p);
     } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
       err |= E_SOLVE;
-      continue;
+      break;
     }
     // residue of m*K + SL at m = m_start + o_lo
     uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
@@ -929,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
           }
         }
         ++raw;
-        record_hit<kLds, kCnt>(j, T, o, mp, (uint32_t)(w - r), useful);
+        record_hit<kLds, kSc>(j, T, o, mp, (uint32_t)(w - r), useful, lreg);
         if (++o >= o_hi) break;
         if (j.d_small) mpos_add(mp, 0, 1, d32);
         r += k;
@@ -943,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
         ++calls;
         levels += (unsigned)lv;
-        if (tstep == 0) { err |= E_SOLVE; continue; }
+        if (tstep == 0) { err |= E_SOLVE; break; }
         o += tstep;
         r = rn;
         if (j.d_small && o < o_hi) {
@@ -961,12 +1042,22 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       const bool a_first = g.ta < g.tb;
       while (o < o_hi) {
         ++raw;
-        record_hit<kLds, kCnt>(j, T, o, mp, (uint32_t)(w - r), useful);
+        record_hit<kLds, kSc>(j, T, o, mp, (uint32_t)(w - r), useful, lreg);
         const bool fa = r + g.a <= w, fb = r >= g.b;
         if (fa && (a_first || !fb)) { o += g.ta; r += g.a; mpos_add(mp, aq, ar, d32); }
         else if (fb) { o += g.tb; r -= g.b; mpos_add(mp, bq, br, d32); }
         else { o += g.ta + g.tb; r = r + g.a - g.b; mpos_add(mp, abq, abr, d32); }
       }
+    }
+    } while (0);
+    if constexpr (kSc == 2) list_sync(lreg, lkey);
+  }
+  if constexpr (kSc == 2) {
+    // close the wavefront's last chunk; the LDS slot holds the latest state of all its lanes
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      const unsigned long long k = *reinterpret_cast<volatile unsigned long long*>(lkey);
+      const uint32_t ch = (uint32_t)(k >> 32) - 1u;
+      if (ch < kPoolFull) jobs[0].list_fill[ch] = (uint32_t)k;
     }
   }
   raw = wave_sum_u64(raw);
@@ -1028,6 +1119,209 @@ __global__ __launch_bounds__(256) void k_zero_bytes(const JobDev* __restrict__ j
   uint32_t* __restrict__ p = reinterpret_cast<uint32_t*>(j.hitbytes);
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Grouping of the list scatter.  Cells are (row << cell_shift) | col, buckets are 2^k rows and
+// groups are 2^g buckets, so bucket = cell >> bkt_shift and group = bucket >> super_shift.  Count
+// the cells of each bucket, scan, move every cell to its group's range, then to its bucket's
+// range, then one block per bucket ORs its cells into an LDS tile of the bucket's rows and merges
+// the tile into the bitmap and the counts (the block owns those rows).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t list_n_chunks(const JobDev& j) {
+  const unsigned long long c = *j.list_cursor;
+  return c < j.list_chunks ? c : j.list_chunks;
+}
+
+__global__ __launch_bounds__(256) void k_list_count(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  extern __shared__ uint32_t hist[];
+  const uint64_t n_chunks = list_n_chunks(j);
+  const uint64_t c0 = blockIdx.x * (uint64_t)kListChunksPerBlock;
+  if (c0 >= n_chunks) return;
+  const uint64_t c1 = min(c0 + kListChunksPerBlock, n_chunks);
+  const uint32_t bsh = j.bkt_shift;
+  for (uint32_t i = threadIdx.x; i < j.n_bkt; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (uint64_t c = c0; c < c1; ++c) {
+    const uint32_t nf = min(j.list_fill[c], kListChunk);
+    const uint32_t* __restrict__ src = j.list_pool + c * kListChunk;
+    for (uint32_t e = threadIdx.x; e < nf; e += blockDim.x) atomicAdd(&hist[src[e] >> bsh], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < j.n_bkt; i += blockDim.x)
+    if (hist[i]) atomicAdd(&j.bkt_count[i], hist[i]);
+}
+
+// Exclusive scan of n_bkt <= kMaxBuckets counts by one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_list_scan(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  __shared__ uint32_t part[1024];
+  constexpr uint32_t per = kMaxBuckets / 1024;
+  uint32_t v[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t i = threadIdx.x * per + k;
+    v[k] = i < j.n_bkt ? j.bkt_count[i] : 0u;
+    sum += v[k];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t i = threadIdx.x * per + k;
+    if (i < j.n_bkt) {
+      j.bkt_base[i] = run;
+      j.bkt_cursor[i] = run;
+    }
+    run += v[k];
+  }
+  if (threadIdx.x == 1023) j.bkt_base[j.n_bkt] = part[1023];
+  __syncthreads();
+  // super-bucket cursors: the base of each group's first bucket
+  const uint32_t g = j.bkt_per_super;
+  for (uint32_t q = threadIdx.x; q * g < j.n_bkt; q += blockDim.x) j.bkt_cursor[j.n_bkt + 1 + q] = j.bkt_base[q * g];
+}
+
+// Counting sort of up to 4096 cells (16 per thread of a 256-thread block) by key in LDS, then
+// each key's segment is written to dst at run[key] onwards by consecutive threads (contiguous
+// stores), and run[key] advances.  hist/start/run: n_keys LDS words each; stg: 4096 LDS words.
+template <typename KeyOf>
+__device__ __forceinline__ void sort_write_batch(const uint32_t* __restrict__ src, uint32_t nf, uint32_t n_keys,
+                                                 KeyOf key_of, uint32_t* hist, uint32_t* start, uint32_t* run,
+                                                 uint32_t* stg, uint32_t* __restrict__ dst) {
+  for (uint32_t i = threadIdx.x; i < n_keys; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  uint32_t cell[16], rk[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t i = threadIdx.x + 256u * k;
+    cell[k] = i < nf ? src[i] : 0u;
+    rk[k] = i < nf ? atomicAdd(&hist[key_of(cell[k])], 1u) : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t q = 0; q < n_keys; ++q) {
+      start[q] = acc;
+      acc += hist[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t i = threadIdx.x + 256u * k;
+    if (i < nf) stg[start[key_of(cell[k])] + rk[k]] = cell[k];
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) {
+    const uint32_t c = stg[i];
+    const uint32_t q = key_of(c);
+    dst[run[q] + (i - start[q])] = c;
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < n_keys; q += blockDim.x) run[q] += hist[q];
+  __syncthreads();
+}
+
+// First level: cells of the pool -> their super-bucket (kListSupers groups of buckets) in
+// list_sorted.  Each block takes kListChunksPerBlock chunks, counts them per super-bucket,
+// reserves its ranges with one atomic per super-bucket, then writes chunk by chunk.
+__global__ __launch_bounds__(256) void k_list_part1(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  __shared__ uint32_t hist[kListSupers], start[kListSupers], run[kListSupers], tot[kListSupers];
+  __shared__ uint32_t stg[kListChunk];
+  const uint64_t n_chunks = list_n_chunks(j);
+  const uint64_t c0 = blockIdx.x * (uint64_t)kListChunksPerBlock;
+  if (c0 >= n_chunks) return;
+  const uint64_t c1 = min(c0 + kListChunksPerBlock, n_chunks);
+  const uint32_t g = j.bkt_per_super;
+  const uint32_t n_sup = (j.n_bkt + g - 1) / g;
+  const uint32_t ssh = j.bkt_shift + j.super_shift;
+  auto key_of = [&](uint32_t cell) { return cell >> ssh; };
+  for (uint32_t i = threadIdx.x; i < n_sup; i += blockDim.x) tot[i] = 0;
+  __syncthreads();
+  for (uint64_t c = c0; c < c1; ++c) {
+    const uint32_t nf = min(j.list_fill[c], kListChunk);
+    const uint32_t* __restrict__ src = j.list_pool + c * kListChunk;
+    for (uint32_t e = threadIdx.x; e < nf; e += blockDim.x) atomicAdd(&tot[key_of(src[e])], 1u);
+  }
+  __syncthreads();
+  uint32_t* super_cursor = j.bkt_cursor + j.n_bkt + 1;
+  for (uint32_t i = threadIdx.x; i < n_sup; i += blockDim.x) run[i] = tot[i] ? atomicAdd(&super_cursor[i], tot[i]) : 0u;
+  __syncthreads();
+  for (uint64_t c = c0; c < c1; ++c)
+    sort_write_batch(j.list_pool + c * kListChunk, min(j.list_fill[c], kListChunk), n_sup, key_of, hist, start, run,
+                     stg, j.list_sorted);
+}
+
+// Second level: each super-bucket's range of list_sorted -> its buckets, into list_pool (free by
+// now).  Block (x, s) takes pieces x, x + gridDim.x, ... of kListPiece cells of super-bucket s.
+__global__ __launch_bounds__(256) void k_list_part2(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  __shared__ uint32_t hist[kListMaxPerSuper], start[kListMaxPerSuper], run[kListMaxPerSuper], tot[kListMaxPerSuper];
+  __shared__ uint32_t stg[kListChunk];
+  const uint32_t g = j.bkt_per_super;
+  const uint32_t sup = blockIdx.y;
+  const uint32_t b0 = sup * g;
+  if (b0 >= j.n_bkt) return;
+  const uint32_t b1 = min(b0 + g, j.n_bkt);
+  const uint32_t nk = b1 - b0;
+  const uint32_t lo = j.bkt_base[b0], hi = j.bkt_base[b1];
+  const uint32_t bsh = j.bkt_shift;
+  auto key_of = [&](uint32_t cell) { return (cell >> bsh) - b0; };
+  for (uint64_t p0 = lo + (uint64_t)blockIdx.x * kListPiece; p0 < hi; p0 += (uint64_t)gridDim.x * kListPiece) {
+    const uint32_t p1 = (uint32_t)min<uint64_t>(p0 + kListPiece, hi);
+    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) tot[i] = 0;
+    __syncthreads();
+    for (uint32_t e = (uint32_t)p0 + threadIdx.x; e < p1; e += blockDim.x) atomicAdd(&tot[key_of(j.list_sorted[e])], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) run[i] = tot[i] ? atomicAdd(&j.bkt_cursor[b0 + i], tot[i]) : 0u;
+    __syncthreads();
+    for (uint32_t e = (uint32_t)p0; e < p1; e += kListChunk)
+      sort_write_batch(j.list_sorted + e, min(kListChunk, p1 - e), nk, key_of, hist, start, run, stg, j.list_pool);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_list_apply(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  extern __shared__ uint32_t tile[];   // bkt_rows x row_words words, then bkt_rows counts
+  const uint32_t b = blockIdx.x;
+  if (b >= j.n_bkt) return;
+  const uint64_t row0 = (uint64_t)b * j.bkt_rows;
+  const uint32_t rows = (uint32_t)min<uint64_t>(j.bkt_rows, j.n_m - row0);
+  const uint32_t words = rows * j.row_words;
+  uint32_t* cnt = tile + j.bkt_rows * j.row_words;
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) tile[i] = 0;
+  for (uint32_t i = threadIdx.x; i < rows; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const uint32_t e0 = j.bkt_base[b], e1 = j.bkt_base[b + 1];
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const uint32_t cell = j.list_pool[e];
+    const uint32_t row = cell >> j.cell_shift;
+    const uint32_t col = cell & ((1u << j.cell_shift) - 1u);
+    const uint32_t lr = row - (uint32_t)row0;
+    if (lr < rows && col < j.n_x) {
+      atomicOr(&tile[lr * j.row_words + (col >> 5)], 1u << (col & 31));
+      atomicAdd(&cnt[lr], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* __restrict__ dst = j.bitmap + row0 * j.row_words;
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
+    const uint32_t v = tile[i];
+    if (v) dst[i] |= v;
+  }
+  for (uint32_t i = threadIdx.x; i < rows; i += blockDim.x)
+    if (cnt[i]) j.counts[row0 + i] += cnt[i];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1186,25 +1480,44 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, bool counters, hipStream_t s) {
-  if (lds_bytes && n_jobs == 1) {
-    if (counters)
-      hipLaunchKernelGGL((k_large<true, true>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base,
-                         diag, lds_ct_words, dpre_n);
-    else
-      hipLaunchKernelGGL((k_large<true, false>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, job_item_base,
-                         diag, lds_ct_words, dpre_n);
-    { hipError_t e_ = note("k_large<lds>"); if (e_ != hipSuccess) return e_; }
+                        uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
+  if (n_jobs != 1) scatter_kind = 0;
+  const bool lds = lds_bytes && n_jobs == 1;
+#define LARGE_CASE(L, K)                                                                                       \
+  hipLaunchKernelGGL((k_large<L, K>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs, job_item_base, \
+                     diag, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
+  if (lds) {
+    if (scatter_kind == 2) LARGE_CASE(true, 2);
+    else if (scatter_kind == 1) LARGE_CASE(true, 1);
+    else LARGE_CASE(true, 0);
   } else {
-    if (counters)
-      hipLaunchKernelGGL((k_large<false, true>), dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag,
-                         0u, 0u);
-    else
-      hipLaunchKernelGGL((k_large<false, false>), dim3(blocks), dim3(256), 0, s, jobs, n_jobs, job_item_base, diag,
-                         0u, 0u);
-    { hipError_t e_ = note("k_large"); if (e_ != hipSuccess) return e_; }
+    if (scatter_kind == 2) LARGE_CASE(false, 2);
+    else if (scatter_kind == 1) LARGE_CASE(false, 1);
+    else LARGE_CASE(false, 0);
   }
-  return hipSuccess;
+#undef LARGE_CASE
+  return note(lds ? "k_large<lds>" : "k_large");
+}
+
+hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,
+                             uint32_t super_shift, uint32_t row_words, hipStream_t s) {
+  if (n_bkt == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)((list_chunks + kListChunksPerBlock - 1) / kListChunksPerBlock);
+  if (blocks) {
+    hipLaunchKernelGGL(k_list_count, dim3(blocks), dim3(256), n_bkt * 4u, s, job);
+    { hipError_t e_ = note("k_list_count"); if (e_ != hipSuccess) return e_; }
+  }
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, job);
+  { hipError_t e_ = note("k_list_scan"); if (e_ != hipSuccess) return e_; }
+  if (blocks) {
+    hipLaunchKernelGGL(k_list_part1, dim3(blocks), dim3(256), 0, s, job);
+    { hipError_t e_ = note("k_list_part1"); if (e_ != hipSuccess) return e_; }
+    const uint32_t n_sup = (n_bkt + (1u << super_shift) - 1) >> super_shift;
+    hipLaunchKernelGGL(k_list_part2, dim3(kListPart2X, n_sup), dim3(256), 0, s, job);
+    { hipError_t e_ = note("k_list_part2"); if (e_ != hipSuccess) return e_; }
+  }
+  hipLaunchKernelGGL(k_list_apply, dim3(n_bkt), dim3(256), (bkt_rows * row_words + bkt_rows) * 4u, s, job);
+  return note("k_list_apply");
 }
 
 }  // namespace cs

@@ -56,10 +56,14 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
                         uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
 // lds_bytes = 0: tables read from global memory (any number of jobs); otherwise n_jobs must be 1
 // and the column table (lds_ct_words uint2, 0 = global) and residue table (dpre_n entries) of
-// that job are staged in LDS.  counters: hits go to every job's byte counters (all jobs must
-// have them), else atomic OR/add into the bitmaps and counts.
+// that job are staged in LDS.  scatter_kind (single-job launches only; 0 otherwise): 0 = atomic
+// OR/add into the bitmap and counts, 1 = the job's byte counters, 2 = the job's list pool.
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, bool counters, hipStream_t s);
+                        uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s);
+// Groups the list pool of one job by row bucket and applies it to the bitmap and counts.  The
+// caller cleared the pool cursor and the bucket counts before the k_large launch.
+hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,
+                             uint32_t super_shift, uint32_t row_words, hipStream_t s);
 
 }  // namespace cs

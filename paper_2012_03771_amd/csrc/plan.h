@@ -21,7 +21,8 @@ constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024)
 
 struct WsLayout {
   uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
-      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, hitbytes, total;
+      kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, hitbytes, list_pool,
+      list_fill, list_cursor, list_sorted, bkt_count, bkt_base, bkt_cursor, total;
 };
 
 struct Plan {
@@ -46,6 +47,10 @@ struct Plan {
   bool dpat_on = false;             // per-class pattern of the primes dividing d
   bool scatter_bytes = false;       // large hits via byte counters (see CS_SCATTER_BYTES)
   double cell_max = 0;              // bound on large-prime hits of one (row, column)
+  bool scatter_list = false;        // large hits via the list scatter (see CS_SCATTER_LIST)
+  uint64_t list_chunks = 0;         // pool capacity in chunks
+  uint32_t n_bkt = 0, bkt_rows = 0; // row buckets of the list scatter (bkt_rows a power of two)
+  uint32_t cell_shift = 0, super_shift = 0;
   std::vector<uint32_t> kq;         // primes dividing K
   std::vector<uint32_t> dq;         // primes dividing d
   WsLayout ws;

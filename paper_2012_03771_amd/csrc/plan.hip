@@ -82,7 +82,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   const uint32_t mode = tune ? tune->large_mode : CS_LARGE_G;
   if (mode > CS_LARGE_THREE_GAP) return CS_EINVAL;
   const uint32_t scatter = tune ? tune->scatter : CS_SCATTER_AUTO;
-  if (scatter > CS_SCATTER_BYTES) return CS_EINVAL;
+  if (scatter > CS_SCATTER_LIST) return CS_EINVAL;
 
   Plan& pl = *out;
   pl.job = j;
@@ -234,9 +234,49 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     pl.cell_max = c_max;
     const bool fits = c_max < 256.0;
     if (scatter == CS_SCATTER_BYTES && !fits) return CS_EINVAL;
-    pl.scatter_bytes = own_primes && fits && scatter != CS_SCATTER_ATOMIC;
+    // List scatter: a pool of about 1.15x the expected large hits, n_m n_x times the sum of 1/p
+    // over the large primes (log log limit - log log thr by Mertens), plus one open chunk per
+    // wavefront of the large-branch grid.
+    // Cells are (row << cell_shift) | col; buckets hold 2^k rows whose LDS tile fits
+    // kListTileBytes (at most 64 rows); groups hold 2^g buckets, at most kListSupers groups.
+    pl.scatter_list = false;
+    pl.list_chunks = 0;
+    pl.cell_shift = 0;
+    while ((1ull << pl.cell_shift) < std::max<uint64_t>(pl.n_x, 1)) ++pl.cell_shift;
+    uint32_t lb = 0;
+    while (lb < 6 && (2ull << lb) * (pl.row_words * 4ull + 4ull) <= kListTileBytes) ++lb;
+    pl.bkt_rows = 1u << lb;
+    pl.n_bkt = (uint32_t)std::min<uint64_t>((pl.n_m + pl.bkt_rows - 1) >> lb, 0xffffffffull);
+    pl.super_shift = 0;
+    while (((uint64_t)pl.n_bkt + (1ull << pl.super_shift) - 1) >> pl.super_shift > kListSupers) ++pl.super_shift;
+    {
+      const double sum_inv = j.limit > pl.thr + 1 ? std::max(0.0, log(log((double)j.limit)) - log(log((double)pl.thr + 1.0)))
+                                                  : 0.0;
+      const double expect = (double)pl.n_m * (double)pl.n_x * sum_inv;
+      const uint64_t slack = std::max<uint64_t>(pl.large_blocks, 2048) * 4ull + 4ull;   // open chunks
+      const uint64_t chunks = (uint64_t)(expect * 1.15 / kListChunk) + slack;
+      const bool ok = own_primes && pl.n_m > 0 && (pl.n_m << pl.cell_shift) <= (1ull << 32) &&
+                      pl.n_bkt <= kMaxBuckets && (1u << pl.super_shift) <= kListMaxPerSuper &&
+                      (double)chunks * kListChunk < 4294967296.0;
+      if (scatter == CS_SCATTER_LIST && !ok) return CS_EINVAL;
+      // AUTO takes the list with three-gap stepping only: with one Eq. 5 solve per hit the atomics
+      // hide behind the solver's latency and the byte counters measured faster.
+      if (ok && (scatter == CS_SCATTER_LIST || (scatter == CS_SCATTER_AUTO && mode == CS_LARGE_THREE_GAP))) {
+        pl.scatter_list = true;
+        pl.list_chunks = tune && tune->list_chunks ? std::min<uint64_t>(tune->list_chunks, chunks) : chunks;
+      }
+    }
+    pl.scatter_bytes = !pl.scatter_list && own_primes && fits &&
+                       (scatter == CS_SCATTER_AUTO || scatter == CS_SCATTER_BYTES);
   }
   L.hitbytes = take(pl.scatter_bytes ? pl.n_m * (uint64_t)pl.row_words * 32ull : 0);
+  L.list_pool = take(pl.list_chunks * kListChunk * 4ull);
+  L.list_fill = take(pl.list_chunks * 4ull);
+  L.list_cursor = take(8);
+  L.list_sorted = take(pl.list_chunks * kListChunk * 4ull);
+  L.bkt_count = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
+  L.bkt_base = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
+  L.bkt_cursor = take(pl.scatter_list ? (pl.n_bkt + 1ull + kListSupers) * 4ull : 0);
   L.total = o;
   return CS_OK;
 }
@@ -322,6 +362,20 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.dpat = reinterpret_cast<uint32_t*>(ws + L.dpat);
   jd.dpat_cnt = reinterpret_cast<uint32_t*>(ws + L.dpat_cnt);
   jd.hitbytes = pl.scatter_bytes ? ws + L.hitbytes : nullptr;
+  jd.list_pool = pl.scatter_list ? reinterpret_cast<uint32_t*>(ws + L.list_pool) : nullptr;
+  jd.list_fill = reinterpret_cast<uint32_t*>(ws + L.list_fill);
+  jd.list_cursor = reinterpret_cast<unsigned long long*>(ws + L.list_cursor);
+  jd.list_sorted = reinterpret_cast<uint32_t*>(ws + L.list_sorted);
+  jd.bkt_count = reinterpret_cast<uint32_t*>(ws + L.bkt_count);
+  jd.bkt_base = reinterpret_cast<uint32_t*>(ws + L.bkt_base);
+  jd.bkt_cursor = reinterpret_cast<uint32_t*>(ws + L.bkt_cursor);
+  jd.list_chunks = pl.list_chunks;
+  jd.n_bkt = pl.n_bkt;
+  jd.bkt_rows = pl.bkt_rows;
+  jd.bkt_per_super = 1u << pl.super_shift;
+  jd.cell_shift = pl.cell_shift;
+  jd.bkt_shift = pl.cell_shift + (uint32_t)__builtin_ctz(pl.bkt_rows);
+  jd.super_shift = pl.super_shift;
   fill_tiers(pl, 2, j.limit, &jd);
   return jd;
 }

@@ -334,7 +334,7 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, (uint64_t)s->n_cu * per_cu);
     if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, st) != hipSuccess) return false;
   }
-  if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * 8u, 0, 0, 0, false, st) != hipSuccess)
+  if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * 8u, 0, 0, 0, 0u, st) != hipSuccess)
     return false;
   if (hipStreamSynchronize(st) != hipSuccess) return false;
   return true;

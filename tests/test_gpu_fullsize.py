@@ -37,10 +37,13 @@ def _run(job, tune):
 
 
 MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP),
-         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC)]
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC),
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_BYTES),
+         cs.Tune(large_mode=cs.LARGE_G, scatter=cs.SCATTER_LIST)]
+MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_bytes", "g_list"]
 
 
-@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap", "three_gap_atomic"])
+@pytest.mark.parametrize("tune", MODES, ids=MODE_IDS)
 def test_medium_503_every_row(tune):
     g = load("medium_503_rows.npz")
     job = W.Job(*[int(x) for x in g["job"]])
@@ -57,7 +60,7 @@ def test_medium_503_every_row(tune):
     assert diag.n_primes == 5761455
 
 
-@pytest.mark.parametrize("tune", MODES, ids=["g", "three_gap", "three_gap_atomic"])
+@pytest.mark.parametrize("tune", MODES, ids=MODE_IDS)
 def test_paper_953_sampled_rows_and_invariants(tune):
     g = load("paper_953_rows.npz")
     job = W.Job(*[int(x) for x in g["job"]])

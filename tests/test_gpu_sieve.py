@@ -89,7 +89,10 @@ TINY = W.tiny_jobs(seed=5, n=40, max_P=31) + [W.Job(11, d, 7, 40, 60, 3000) for 
 def test_tiny_jobs(job):
     want_b, want_c = _oracle(job, mode=coracle.DIRECT)
     for tune in (None, cs.Tune(thr=1), cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP),
-                 cs.Tune(thr=10**9), cs.Tune(thr=1, scatter=cs.SCATTER_ATOMIC)):
+                 cs.Tune(thr=10**9), cs.Tune(thr=1, scatter=cs.SCATTER_ATOMIC),
+                 cs.Tune(thr=1, scatter=cs.SCATTER_BYTES), cs.Tune(thr=1, scatter=cs.SCATTER_LIST, list_chunks=1),
+                 cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP, list_chunks=2),
+                 cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST)):
         b, c, _, _ = _run(job, tune)
         _assert_same(job, b, c, want_b, want_c)
 
@@ -105,7 +108,9 @@ def test_mixed_jobs_both_modes(job):
     want_b, want_c = _oracle(job)
     for tune in (None, cs.Tune(large_mode=cs.LARGE_THREE_GAP), cs.Tune(thr=1, hits_per_item=8),
                  cs.Tune(tile_rows=3, small_slices=5), cs.Tune(scatter=cs.SCATTER_ATOMIC),
-                 cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC, thr=1)):
+                 cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC, thr=1),
+                 cs.Tune(scatter=cs.SCATTER_BYTES), cs.Tune(thr=1, hits_per_item=8, scatter=cs.SCATTER_LIST, list_chunks=3),
+                 cs.Tune(large_mode=cs.LARGE_THREE_GAP, thr=1, hits_per_item=8)):
         b, c, diag, _ = _run(job, tune)
         _assert_same(job, b, c, want_b, want_c)
         assert diag.small_marks + diag.large_hits == int(want_c.sum())
@@ -154,8 +159,11 @@ def test_window_hits_503_from_large_branch(paper_values):
     count of Eq. 3 solutions (one m, so each hit is one prime dividing the interval)."""
     w = paper_values["window_hits_503"]
     job = W.Job(w["P"], w["d"], w["m"], 1, w["sl"], 10**9)
-    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job)
     tune = cs.Tune(thr=2 * w["sl"])
+    lay, bitmap, counts, _ = cs.binding.alloc_outputs(job, tune)
+    ws_bytes = max(cs.plan(job, cs.Tune(thr=2 * w["sl"])).ws_bytes,
+                   cs.plan(job, cs.Tune(thr=4 * w["sl"] + 1, large_mode=cs.LARGE_THREE_GAP)).ws_bytes)
+    ws = torch.empty((ws_bytes,), dtype=torch.uint8, device="cuda")    # fits both tunings
     for mode in (cs.LARGE_G, cs.LARGE_THREE_GAP):
         tune.large_mode = mode
         tune.thr = 2 * w["sl"] if mode == cs.LARGE_G else 4 * w["sl"] + 1

@@ -118,10 +118,20 @@ def _cell_bound(job, thr):
 def test_scatter_choice_follows_the_counter_bound(job, mode):
     lay = cs.plan(job, cs.Tune(large_mode=mode))
     fits = _cell_bound(job, lay.thr) < 256
-    assert lay.scatter == (cs.SCATTER_BYTES if fits else cs.SCATTER_ATOMIC)
+    lb = 0
+    while lb < 6 and (2 << lb) * (lay.row_words * 4 + 4) <= 60 * 1024:
+        lb += 1
+    shift = max(lay.n_x - 1, 0).bit_length()
+    list_ok = lay.n_m > 0 and (lay.n_m << shift) <= 2**32 and -(-lay.n_m // (1 << lb)) <= 8192
+    auto_list = list_ok and mode == cs.LARGE_THREE_GAP
+    assert lay.scatter == (cs.SCATTER_LIST if auto_list else cs.SCATTER_BYTES if fits else cs.SCATTER_ATOMIC)
     assert cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_ATOMIC)).scatter == cs.SCATTER_ATOMIC
+    if list_ok:
+        ll = cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_LIST))
+        assert ll.scatter == cs.SCATTER_LIST and (ll.ws_bytes == lay.ws_bytes or not auto_list)
     if fits:
         lb = cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_BYTES))
+        assert lb.scatter == cs.SCATTER_BYTES
         la = cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_ATOMIC))
         assert lb.ws_bytes + 256 >= la.ws_bytes + lay.n_m * lay.row_words * 32   # 256-byte aligned regions
     else:
@@ -130,7 +140,20 @@ def test_scatter_choice_follows_the_counter_bound(job, mode):
         assert e.value.status == -1
 
 
-def test_paper_scale_uses_byte_counters():
+def test_paper_scale_scatter_modes():
+    assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_LIST
+    assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_G)).scatter == cs.SCATTER_BYTES
     for mode in (cs.LARGE_G, cs.LARGE_THREE_GAP):
-        assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode)).scatter == cs.SCATTER_BYTES
-    assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6)).scatter == cs.SCATTER_ATOMIC
+        assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode, scatter=cs.SCATTER_LIST)).scatter == cs.SCATTER_LIST
+        assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode, scatter=cs.SCATTER_BYTES)).scatter == cs.SCATTER_BYTES
+    # the list pool holds ~1.15x the expected large hits (n_m n_x (log log limit - log log thr))
+    import math
+    lay = cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP))
+    atom = cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC))
+    expect = lay.n_m * lay.n_x * (math.log(math.log(1e10)) - math.log(math.log(lay.thr + 1)))
+    assert 2 * 4 * 1.15 * expect < lay.ws_bytes - atom.ws_bytes < 2 * 4 * 1.2 * expect + 2**30
+    # a job with 228,573 rows of 13,102 columns fits 32-bit cells; a wider one does not
+    assert cs.plan(W.Job(953, 210, 10**8, 4 * 10**6, 20000, 10**9)).scatter != cs.SCATTER_LIST
+    with pytest.raises(cs.CsError):
+        cs.plan(W.Job(953, 210, 10**8, 4 * 10**6, 20000, 10**9), cs.Tune(scatter=cs.SCATTER_LIST))
+    assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6), cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_LIST
