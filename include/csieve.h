@@ -137,6 +137,8 @@ typedef struct cs_diag {
   uint64_t g_calls;         /* solves of Eq. 3 by the recursion of Eq. 5 */
   uint64_t g_levels;        /* recursion levels summed over those solves */
   uint64_t error_flags;     /* nonzero: a device-side consistency check failed */
+  double large_kernel_ms;   /* duration of the last large-branch kernel launched on this workspace
+                               (HIP events on its stream; 0 if none, or launched under capture) */
 } cs_diag;
 
 /* Human-readable name of a status code (static string). */

@@ -47,7 +47,7 @@ class cs_layout(C.Structure):
 class cs_diag(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("n_primes", "small_primes", "large_primes", "small_pairs",
                                           "small_marks", "large_raw_hits", "large_hits", "g_calls",
-                                          "g_levels", "error_flags")]
+                                          "g_levels", "error_flags")] + [("large_kernel_ms", C.c_double)]
 
 
 class cs_server_config(C.Structure):
@@ -108,6 +108,7 @@ class Diag:
     g_calls: int
     g_levels: int
     error_flags: int
+    large_kernel_ms: float = 0.0
 
 
 class cs_surround_stats(C.Structure):

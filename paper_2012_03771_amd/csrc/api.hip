@@ -3,6 +3,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/csieve.h"
@@ -117,6 +119,22 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
   return CS_OK;
 }
 
+// HIP events around the last k_large launch of each workspace (read by cs_diag_read).  One pair
+// per workspace address, created on first use and kept for the life of the process.
+struct LargeEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool recorded = false;
+};
+std::mutex g_ev_mu;
+std::map<const void*, LargeEvents> g_large_ev;
+
+LargeEvents* large_events(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  LargeEvents& e = g_large_ev[ws];
+  if (!e.start && (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess)) return nullptr;
+  return &e;
+}
+
 cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
                         uint8_t* ws, hipStream_t s, uint32_t branches) {
   const WsLayout& L = pl.ws;
@@ -143,8 +161,16 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
       CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.bkt_count), pl.n_bkt + 1ull, 0u, s));
     }
     const uint32_t kind = pl.scatter_list ? 2u : (pl.scatter_bytes ? 1u : 0u);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    LargeEvents* ev = nullptr;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) ev = large_events(ws);
+    if (ev) CS_TRY(hipEventRecord(ev->start, s));
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, pl.large_lds_bytes,
                         pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, s));
+    if (ev) {
+      CS_TRY(hipEventRecord(ev->stop, s));
+      ev->recorded = true;
+    }
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jdp, 1, pl.n_m, device_cu_count(), s));
     if (pl.scatter_list) CS_TRY(launch_list_group(jdp, pl.list_chunks, pl.n_bkt, pl.bkt_rows, pl.super_shift, pl.row_words, s));
   }
@@ -215,6 +241,15 @@ extern "C" cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream) 
   out->g_calls = c.diag[D_G_CALLS];
   out->g_levels = c.diag[D_G_LEVELS];
   out->error_flags = c.diag[D_ERROR] | c.error;
+  out->large_kernel_ms = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    auto it = g_large_ev.find(d_ws);
+    float ms = 0.f;
+    if (it != g_large_ev.end() && it->second.recorded &&
+        hipEventElapsedTime(&ms, it->second.start, it->second.stop) == hipSuccess)
+      out->large_kernel_ms = ms;
+  }
   return out->error_flags ? CS_EDEVICE : CS_OK;
 }
 

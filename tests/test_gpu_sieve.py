@@ -189,3 +189,17 @@ def test_zero_rows():
     bitmap, counts, ws = cs.sieve(job)
     torch.cuda.synchronize()
     assert bitmap.numel() == 0 and counts.numel() == 0
+
+
+def test_large_kernel_time_is_reported():
+    """cs_diag.large_kernel_ms: the last large-branch launch on the workspace, timed by HIP events."""
+    job = W.MEDIUM
+    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cs.sieve_into(job, bitmap, counts, ws)
+    e0.record(s)
+    cs.sieve_into(job, bitmap, counts, ws)
+    e1.record(s)
+    d = cs.diag_read(ws)
+    assert 0.0 < d.large_kernel_ms <= e0.elapsed_time(e1)
