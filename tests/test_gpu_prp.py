@@ -162,3 +162,32 @@ def test_surround_empty_sides_and_validation():
     bad_m = torch.full((b.shape[0],), 10**6, dtype=torch.int64, device="cuda")
     with pytest.raises(cs.CsError):
         cs.surround(job, b, bad_m)
+
+
+def test_advisor_sieve_limit_and_interval():
+    """Section 4: the sieve-limit advice stops where the tests saved per second of sieving fall
+    below the probable-prime rate; the interval check counts rows whose surrounding primes lie
+    beyond sl."""
+    from paper_2012_03771_amd import advisor as A
+    job = W.Job(503, 210, 10**6, 2000, 7000, 10**8)
+    rate = A.prp_rate(job, n_tests=4096)
+    assert rate > 1e4
+    adv = A.advise_sieve_limit(job, prp_tests_per_s=rate)
+    assert adv.steps[0].p_lo == 1 and adv.steps[-1].p_hi == job.limit
+    assert all(s.ms > 0 for s in adv.steps)
+    assert all(a.p_hi == b.p_lo for a, b in zip(adv.steps, adv.steps[1:]))
+    saved = [s.tests_saved for s in adv.steps[1:]]
+    assert all(x > 0 for x in saved)
+    # the advice is the end of the last range that beat the rate
+    keep = [s.p_hi for s in adv.steps if s.p_lo == 1 or s.saved_per_s >= rate]
+    assert adv.limit == keep[-1]
+    assert A.advise_sieve_limit(job, prp_tests_per_s=0.0).limit == job.limit
+    assert A.advise_sieve_limit(job, prp_tests_per_s=float("inf")).limit == adv.steps[0].p_hi
+    # interval: sl = 7000 > 10 log N for 503#/210: almost every row finds both primes
+    ok = A.check_interval(job, rows=128)
+    assert ok.rows == 128 and not ok.warn
+    # sl below 6 log N: many rows reach beyond it
+    narrow = A.check_interval(W.Job(503, 210, 10**6, 2000, 300, 10**8), rows=128)
+    assert narrow.warn and narrow.beyond > 10
+    _, want = _oracle_rows(W.Job(503, 210, 10**6, 300, 300, 10**8), cs.rows(W.Job(503, 210, 10**6, 300, 300, 10**8))[:32])
+    assert sum(1 for p, n, _, _ in want if p == 0 or n == 0) > 0
