@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/csieve.h"
@@ -135,6 +136,30 @@ LargeEvents* large_events(const void* ws) {
   return &e;
 }
 
+// A second stream per device for running the small branch beside the large one (default
+// priority, non-blocking), created on first use and kept for the life of the process, with a
+// fork/join event pair per calling thread.
+struct AuxStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_aux_mu;
+std::map<std::pair<int, std::thread::id>, AuxStream> g_aux;
+
+AuxStream* aux_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  AuxStream& a = g_aux[{dev, std::this_thread::get_id()}];
+  if (!a.s) {
+    if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) { a.s = nullptr; return nullptr; }
+    if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess)
+      return nullptr;
+  }
+  return &a;
+}
+
 cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
                         uint8_t* ws, hipStream_t s, uint32_t branches) {
   const WsLayout& L = pl.ws;
@@ -152,8 +177,20 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   CS_TRY(launch_items_scan(jdp, 1, items_base, s));
   if (pl.n_m == 0) return CS_OK;
   const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
-  if (branches != CS_BRANCH_LARGE)
-    CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s));
+  // With the byte counters the large branch writes only the counters until the fold, so the
+  // small branch (which read-modify-writes bitmap words) can run beside it on a second stream.
+  hipStreamCaptureStatus cap0 = hipStreamCaptureStatusNone;
+  AuxStream* aux = nullptr;
+  if (branches == CS_BRANCH_ALL && pl.scatter_bytes && hipStreamIsCapturing(s, &cap0) == hipSuccess &&
+      cap0 == hipStreamCaptureStatusNone)
+    aux = aux_stream();
+  if (aux) {
+    CS_TRY(hipEventRecord(aux->fork, s));
+    CS_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
+  }
+  hipStream_t s_small = aux ? aux->s : s;
+  if (branches != CS_BRANCH_LARGE && !aux)
+    CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s_small));
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
   if (branches != CS_BRANCH_SMALL) {
     if (pl.scatter_list) {
@@ -170,6 +207,11 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     if (ev) {
       CS_TRY(hipEventRecord(ev->stop, s));
       ev->recorded = true;
+    }
+    if (aux) {   // small branch queued after the large kernel so the large one starts first
+      CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, aux->s));
+      CS_TRY(hipEventRecord(aux->join, aux->s));
+      CS_TRY(hipStreamWaitEvent(s, aux->join, 0));
     }
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jdp, 1, pl.n_m, device_cu_count(), s));
     if (pl.scatter_list) CS_TRY(launch_list_group(jdp, pl.list_chunks, pl.n_bkt, pl.bkt_rows, pl.super_shift, pl.row_words, s));

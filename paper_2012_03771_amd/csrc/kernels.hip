@@ -806,6 +806,39 @@ struct LargeTables {
 constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr uint32_t kPoolFull = 0xfffffffeu;
 
+// What the hit path needs of a job, copied into registers once per item: the kernel's own stores
+// (bitmap, counts, list cells) could alias a JobDev in global memory as far as the compiler knows,
+// so reading these through the JobDev inside the walking loop reloads them at every step.
+struct HitCtx {
+  const int32_t* row_of;
+  uint32_t* bitmap;
+  uint32_t* counts;
+  uint8_t* hitbytes;
+  uint32_t* list_pool;
+  uint32_t* list_fill;
+  unsigned long long* list_cursor;
+  uint64_t list_chunks;
+  uint32_t d_small, phi_d, pre_r0, row_words, cell_shift;
+};
+
+__device__ __forceinline__ HitCtx hit_ctx(const JobDev& j) {
+  HitCtx h;
+  h.row_of = j.row_of;
+  h.bitmap = j.bitmap;
+  h.counts = j.counts;
+  h.hitbytes = j.hitbytes;
+  h.list_pool = j.list_pool;
+  h.list_fill = j.list_fill;
+  h.list_cursor = j.list_cursor;
+  h.list_chunks = j.list_chunks;
+  h.d_small = j.d_small;
+  h.phi_d = j.phi_d;
+  h.pre_r0 = j.pre_r0;
+  h.row_words = j.row_words;
+  h.cell_shift = j.cell_shift;
+  return h;
+}
+
 // The open list chunk of a wavefront and the cells written to it.  Kept in registers, identical
 // in every lane that takes part in a step; lanes that left the walking loop early catch up at the
 // end of the item (list_sync).
@@ -817,7 +850,7 @@ struct ListReg {
 // consecutive slots in the open chunk, one 4-byte store per hit (one contiguous run per
 // wavefront).  A full chunk is closed (its fill recorded) and a new one taken from the pool
 // cursor; when the pool is exhausted, hits take the atomic path instead.
-__device__ __forceinline__ void list_step(const JobDev& j, ListReg& lr, bool ok,
+__device__ __forceinline__ void list_step(const HitCtx& j, ListReg& lr, bool ok,
                                           uint32_t cell, uint64_t row, uint32_t col) {
   const unsigned long long act = __ballot(ok);
   if (act == 0) return;
@@ -825,25 +858,30 @@ __device__ __forceinline__ void list_step(const JobDev& j, ListReg& lr, bool ok,
   const uint32_t n = (uint32_t)__popcll(act);
   const uint32_t rank = (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
   const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1u;
-  if (lr.chunk == kNoChunk || (lr.chunk != kPoolFull && lr.fill + n > kListChunk)) {
+  // the state is the same in every participating lane: scalar copies make the tests below
+  // uniform branches
+  uint32_t chunk = __builtin_amdgcn_readfirstlane(lr.chunk);
+  uint32_t fill = __builtin_amdgcn_readfirstlane(lr.fill);
+  if (chunk == kNoChunk || (chunk != kPoolFull && fill + n > kListChunk)) {
     uint32_t nc = kPoolFull;
     if (lane == leader) {
-      if (lr.chunk != kNoChunk) j.list_fill[lr.chunk] = lr.fill;
+      if (chunk != kNoChunk) j.list_fill[chunk] = fill;
       const unsigned long long c = atomicAdd(j.list_cursor, 1ull);
       if (c < j.list_chunks) nc = (uint32_t)c;
     }
-    lr.chunk = __shfl(nc, (int)leader);
-    lr.fill = 0;
+    chunk = __builtin_amdgcn_readlane(nc, leader);
+    fill = 0;
   }
   if (ok) {
-    if (lr.chunk != kPoolFull) {
-      j.list_pool[(uint64_t)lr.chunk * kListChunk + lr.fill + rank] = cell;
+    if (chunk != kPoolFull) {
+      j.list_pool[(uint64_t)chunk * kListChunk + fill + rank] = cell;
     } else {
       atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
       atomicAdd(&j.counts[row], 1u);
     }
   }
-  lr.fill += n;
+  lr.chunk = chunk;
+  lr.fill = fill + n;
 }
 
 // Brings every lane that ran this item to the wavefront's latest list state: chunk ids grow with
@@ -859,7 +897,7 @@ __device__ __forceinline__ void list_sync(ListReg& lr, unsigned long long* lkey)
 }
 
 template <bool kLds, int kSc>
-__device__ __forceinline__ void record_hit(const JobDev& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
+__device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
                                            uint32_t jj, unsigned long long& useful, ListReg& lr) {
   if constexpr (kSc == 2) {
     // every lane of the loop takes the step, with or without a hit
@@ -925,7 +963,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     for (uint32_t i = threadIdx.x; i < lds_ct_words; i += blockDim.x) ctl[i] = j0.coltab[i];
     for (uint32_t i = threadIdx.x; i < dpre_n; i += blockDim.x) dpl[i] = j0.dpre[i];
     __syncthreads();
-    T.ct = lds_ct_words ? ctl : j0.coltab;
+    T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
   }
   const uint64_t total = job_item_base[n_jobs];
@@ -972,6 +1010,9 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
     const uint32_t d32 = (uint32_t)j.d;
+    const double inv_d = j.inv_d;
+    const bool d_small = j.d_small != 0;
+    const HitCtx hc = hit_ctx(j);
     // k^-1 mod p (and, for three-gap stepping, the two return times) from one Euclid pass
     uint64_t kinv = 0;
     gaps3 g = {0, 0, 0, 0};
@@ -988,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     r = r >= p ? r - p : r;
     uint64_t o = o_lo;
     MPos mp = {0, 0};
-    if (j.d_small) mpos_divmod(j.r0_d + o_lo, d32, j.inv_d, &mp.dq, &mp.rd);
+    if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
 
     if (j.large_mode == 0) {
       // one solve of Eq. 3 per hit
@@ -1003,16 +1044,16 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
           o += tstep;
           if (o >= o_hi) break;
           r = rn;
-          if (j.d_small) {
+          if (d_small) {
             uint32_t tq, tr;
-            mpos_divmod(tstep, d32, j.inv_d, &tq, &tr);
+            mpos_divmod(tstep, d32, inv_d, &tq, &tr);
             mpos_add(mp, tq, tr, d32);
           }
         }
         ++raw;
-        record_hit<kLds, kSc>(j, T, o, mp, (uint32_t)(w - r), useful, lreg);
+        record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
         if (++o >= o_hi) break;
-        if (j.d_small) mpos_add(mp, 0, 1, d32);
+        if (d_small) mpos_add(mp, 0, 1, d32);
         r += k;
         r = r >= p ? r - p : r;
       }
@@ -1027,22 +1068,22 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         if (tstep == 0) { err |= E_SOLVE; break; }
         o += tstep;
         r = rn;
-        if (j.d_small && o < o_hi) {
+        if (d_small && o < o_hi) {
           uint32_t tq, tr;
-          mpos_divmod(tstep, d32, j.inv_d, &tq, &tr);
+          mpos_divmod(tstep, d32, inv_d, &tq, &tr);
           mpos_add(mp, tq, tr, d32);
         }
       }
       uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
-      if (j.d_small) {
-        mpos_divmod(g.ta, d32, j.inv_d, &aq, &ar);
-        mpos_divmod(g.tb, d32, j.inv_d, &bq, &br);
-        mpos_divmod(g.ta + g.tb, d32, j.inv_d, &abq, &abr);
+      if (d_small) {
+        mpos_divmod(g.ta, d32, inv_d, &aq, &ar);
+        mpos_divmod(g.tb, d32, inv_d, &bq, &br);
+        mpos_divmod(g.ta + g.tb, d32, inv_d, &abq, &abr);
       }
       const bool a_first = g.ta < g.tb;
       while (o < o_hi) {
         ++raw;
-        record_hit<kLds, kSc>(j, T, o, mp, (uint32_t)(w - r), useful, lreg);
+        record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
         const bool fa = r + g.a <= w, fb = r >= g.b;
         if (fa && (a_first || !fb)) { o += g.ta; r += g.a; mpos_add(mp, aq, ar, d32); }
         else if (fb) { o += g.tb; r -= g.b; mpos_add(mp, bq, br, d32); }
@@ -1482,7 +1523,7 @@ hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
                         uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
   if (n_jobs != 1) scatter_kind = 0;
-  const bool lds = lds_bytes && n_jobs == 1;
+  const bool lds = lds_bytes && lds_ct_words && n_jobs == 1;
 #define LARGE_CASE(L, K)                                                                                       \
   hipLaunchKernelGGL((k_large<L, K>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs, job_item_base, \
                      diag, L ? lds_ct_words : 0u, L ? dpre_n : 0u)

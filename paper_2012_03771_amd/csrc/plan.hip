@@ -259,9 +259,10 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
                       pl.n_bkt <= kMaxBuckets && (1u << pl.super_shift) <= kListMaxPerSuper &&
                       (double)chunks * kListChunk < 4294967296.0;
       if (scatter == CS_SCATTER_LIST && !ok) return CS_EINVAL;
-      // AUTO takes the list with three-gap stepping only: with one Eq. 5 solve per hit the atomics
-      // hide behind the solver's latency and the byte counters measured faster.
-      if (ok && (scatter == CS_SCATTER_LIST || (scatter == CS_SCATTER_AUTO && mode == CS_LARGE_THREE_GAP))) {
+      // AUTO does not take the list: its grouping passes cost more than the atomics they remove
+      // (measured at the paper scale: large branch 145 ms with the list, 131 ms with the byte
+      // counters).
+      if (ok && scatter == CS_SCATTER_LIST) {
         pl.scatter_list = true;
         pl.list_chunks = tune && tune->list_chunks ? std::min<uint64_t>(tune->list_chunks, chunks) : chunks;
       }

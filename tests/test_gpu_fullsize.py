@@ -38,9 +38,9 @@ def _run(job, tune):
 
 MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP),
          cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC),
-         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_BYTES),
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST),
          cs.Tune(large_mode=cs.LARGE_G, scatter=cs.SCATTER_LIST)]
-MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_bytes", "g_list"]
+MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_list", "g_list"]
 
 
 @pytest.mark.parametrize("tune", MODES, ids=MODE_IDS)

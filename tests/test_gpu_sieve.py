@@ -91,7 +91,7 @@ def test_tiny_jobs(job):
     for tune in (None, cs.Tune(thr=1), cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP),
                  cs.Tune(thr=10**9), cs.Tune(thr=1, scatter=cs.SCATTER_ATOMIC),
                  cs.Tune(thr=1, scatter=cs.SCATTER_BYTES), cs.Tune(thr=1, scatter=cs.SCATTER_LIST, list_chunks=1),
-                 cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP, list_chunks=2),
+                 cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST, list_chunks=2),
                  cs.Tune(thr=1, large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST)):
         b, c, _, _ = _run(job, tune)
         _assert_same(job, b, c, want_b, want_c)

@@ -123,7 +123,7 @@ def test_scatter_choice_follows_the_counter_bound(job, mode):
         lb += 1
     shift = max(lay.n_x - 1, 0).bit_length()
     list_ok = lay.n_m > 0 and (lay.n_m << shift) <= 2**32 and -(-lay.n_m // (1 << lb)) <= 8192
-    auto_list = list_ok and mode == cs.LARGE_THREE_GAP
+    auto_list = False                      # the list is taken only on request
     assert lay.scatter == (cs.SCATTER_LIST if auto_list else cs.SCATTER_BYTES if fits else cs.SCATTER_ATOMIC)
     assert cs.plan(job, cs.Tune(large_mode=mode, scatter=cs.SCATTER_ATOMIC)).scatter == cs.SCATTER_ATOMIC
     if list_ok:
@@ -141,14 +141,14 @@ def test_scatter_choice_follows_the_counter_bound(job, mode):
 
 
 def test_paper_scale_scatter_modes():
-    assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_LIST
+    assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_BYTES
     assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_G)).scatter == cs.SCATTER_BYTES
     for mode in (cs.LARGE_G, cs.LARGE_THREE_GAP):
         assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode, scatter=cs.SCATTER_LIST)).scatter == cs.SCATTER_LIST
         assert cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=mode, scatter=cs.SCATTER_BYTES)).scatter == cs.SCATTER_BYTES
     # the list pool holds ~1.15x the expected large hits (n_m n_x (log log limit - log log thr))
     import math
-    lay = cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP))
+    lay = cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST))
     atom = cs.plan(W.PAPER_SCALE, cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC))
     expect = lay.n_m * lay.n_x * (math.log(math.log(1e10)) - math.log(math.log(lay.thr + 1)))
     assert 2 * 4 * 1.15 * expect < lay.ws_bytes - atom.ws_bytes < 2 * 4 * 1.2 * expect + 2**30
@@ -156,4 +156,4 @@ def test_paper_scale_scatter_modes():
     assert cs.plan(W.Job(953, 210, 10**8, 4 * 10**6, 20000, 10**9)).scatter != cs.SCATTER_LIST
     with pytest.raises(cs.CsError):
         cs.plan(W.Job(953, 210, 10**8, 4 * 10**6, 20000, 10**9), cs.Tune(scatter=cs.SCATTER_LIST))
-    assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6), cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_LIST
+    assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6), cs.Tune(scatter=cs.SCATTER_LIST)).scatter == cs.SCATTER_LIST
