@@ -902,39 +902,39 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
   if constexpr (kSc == 2) {
     // every lane of the loop takes the step, with or without a hit
     bool ok;
-    uint64_t row;
+    uint32_t row;
     if (j.d_small) {
       const uint32_t e = T.dp[mp.rd];
       ok = (e >> 15) != 0;                          // m shares a factor with d (Section 3.2)
-      row = (uint64_t)j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
+      row = j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
     } else {
       const int32_t r = j.row_of[o];
       ok = r >= 0;
-      row = ok ? (uint64_t)r : 0ull;
+      row = ok ? (uint32_t)r : 0u;
     }
     uint32_t col = 0;
     if (ok) ok = lookup_col(T.ct, jj, &col);        // X shares a factor with K
-    list_step(j, lr, ok, ok ? (uint32_t)((row << j.cell_shift) | col) : 0u, row, col);
+    list_step(j, lr, ok, ok ? ((row << j.cell_shift) | col) : 0u, row, col);
     if (ok) ++useful;
     return;
   }
-  uint64_t row;
+  uint32_t row;                                     // rows < m_inc < 2^32
   if (j.d_small) {
     const uint32_t e = T.dp[mp.rd];
     if (!(e >> 15)) return;                         // m shares a factor with d (Section 3.2)
-    row = (uint64_t)j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
+    row = j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
   } else {
     const int32_t r = j.row_of[o];
     if (r < 0) return;
-    row = (uint64_t)r;
+    row = (uint32_t)r;
   }
   uint32_t col;
   if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
   if constexpr (kSc == 1) {
-    uint32_t* cell = reinterpret_cast<uint32_t*>(j.hitbytes + row * j.row_words * 32ull + (col & ~3u));
+    uint32_t* cell = reinterpret_cast<uint32_t*>(j.hitbytes + (uint64_t)row * (j.row_words * 32u) + (col & ~3u));
     atomicAdd(cell, 1u << (8 * (col & 3u)));
   } else {
-    atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
+    atomicOr(&j.bitmap[(uint64_t)row * j.row_words + (col >> 5)], 1u << (col & 31));
     atomicAdd(&j.counts[row], 1u);
   }
   ++useful;
@@ -974,8 +974,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
        item += (uint64_t)gridDim.x * blockDim.x) {
     do {   // one item; every exit leads to the per-item list sync below
     uint32_t ji = 0;
-    while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
-    const JobDev& j = jobs[ji];
+    if constexpr (!kLds) {
+      while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
+    }
+    const JobDev& j = jobs[kLds ? 0 : ji];          // the LDS variant runs one job: uniform fields
     if constexpr (!kLds) {
       T.ct = j.coltab;
       T.dp = j.dpre;
@@ -1081,13 +1083,20 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         mpos_divmod(g.ta + g.tb, d32, inv_d, &abq, &abr);
       }
       const bool a_first = g.ta < g.tb;
+      // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
+      // arithmetic, and the three cases by selects rather than branches
+      const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
+      uint32_t r32 = (uint32_t)r;
+      const uint64_t tab = g.ta + g.tb;
       while (o < o_hi) {
         ++raw;
-        record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
-        const bool fa = r + g.a <= w, fb = r >= g.b;
-        if (fa && (a_first || !fb)) { o += g.ta; r += g.a; mpos_add(mp, aq, ar, d32); }
-        else if (fb) { o += g.tb; r -= g.b; mpos_add(mp, bq, br, d32); }
-        else { o += g.ta + g.tb; r = r + g.a - g.b; mpos_add(mp, abq, abr, d32); }
+        record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, useful, lreg);
+        const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
+        const bool ua = fa && (a_first || !fb);
+        const bool ub = !ua && fb;
+        o += ua ? g.ta : (ub ? g.tb : tab);
+        r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
+        mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
       }
     }
     } while (0);
