@@ -806,6 +806,16 @@ struct LargeTables {
 constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr uint32_t kPoolFull = 0xfffffffeu;
 
+// floor(a / b) for a, b < 2^52 through the fp64 quotient and one exact correction each way
+// (a 64-bit integer division is a long emulated sequence on the GPU).
+__device__ __forceinline__ uint64_t div_small(uint64_t a, uint64_t b) {
+  const double bd = (double)b;
+  double q = floor((double)a / bd);
+  const double r = fma(-q, bd, (double)a);
+  q += (r < 0.0) ? -1.0 : ((r >= bd) ? 1.0 : 0.0);
+  return (uint64_t)q;
+}
+
 // What the hit path needs of a job, copied into registers once per item: the kernel's own stores
 // (bitmap, counts, list cells) could alias a JobDev in global memory as far as the compiler knows,
 // so reading these through the JobDev inside the walking loop reloads them at every step.
@@ -970,6 +980,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
   unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
   uint32_t err = 0;
   ListReg lreg = {kNoChunk, 0u};
+  uint32_t t_last = 0, ji_last = 0;                  // a lane's items only grow: resume the tier search
   for (uint64_t item = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; item < total;
        item += (uint64_t)gridDim.x * blockDim.x) {
     do {   // one item; every exit leads to the per-item list sync below
@@ -984,8 +995,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     }
     const JobCtrl& c = *j.ctrl;
     const uint64_t local = item - job_item_base[ji];
-    uint32_t t = 0;
+    uint32_t t = ji == ji_last ? t_last : 0u;
     while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
+    t_last = t;
+    ji_last = ji;
     const uint64_t li = local - c.tier_item_base[t];
     const uint32_t C = j.tier_chunks[t];
     // Item order.  One solve per hit: prime-major, so neighbouring lanes share (p, K mod p)
@@ -994,15 +1007,19 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     // scattered marks stay within 1/C of the bitmap rows.
     const uint64_t t0 = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]);
     uint64_t chunk, pi;
-    if (j.large_mode == 0) {
-      pi = t0 + li / C;
-      chunk = li % C;
+    if (C == 1) {
+      chunk = 0;
+      pi = t0 + li;
+    } else if (j.large_mode == 0) {
+      const uint64_t q = div_small(li, C);
+      pi = t0 + q;
+      chunk = li - q * C;
     } else {
       const uint64_t npt = c.tier_idx[t] - t0;
-      chunk = li / npt;
+      chunk = div_small(li, npt);
       pi = t0 + (li - chunk * npt);
     }
-    const uint64_t L = (j.m_inc + C - 1) / C;
+    const uint64_t L = C == 1 ? j.m_inc : div_small(j.m_inc + C - 1, C);
     const uint64_t o_lo = (uint64_t)chunk * L;
     const uint64_t o_hi = min(o_lo + L, j.m_inc);
     if (o_lo >= o_hi) break;
@@ -1027,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     // residue of m*K + SL at m = m_start + o_lo
     uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
     r = r >= p ? r - p : r;
-    r += mod64(j.sl, p, pinv);
+    r += j.sl;                                       // sl < w < thr < p
     r = r >= p ? r - p : r;
     uint64_t o = o_lo;
     MPos mp = {0, 0};
