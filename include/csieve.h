@@ -99,10 +99,11 @@ typedef struct cs_tune {
  * 1.15x the expected number of large hits (n_m n_x (log log limit - log log thr), Mertens); hits
  * beyond it fall back to the atomic path, so results stay exact.  LIST needs n_m * 2^s <= 2^32 and
  * at most 8192 row buckets (CS_EINVAL when requested otherwise).  AUTO, for cs_sieve / cs_prepare
- * / cs_sieve_range: BYTES where exact, else ATOMIC; inside batches and the server ATOMIC (they
- * ignore BYTES and LIST).  With BYTES, a whole-range call runs the small-prime branch on a second
- * stream beside the large one (the large branch writes only its counters until the fold), joined
- * back into `stream` before the call's last kernel.  Outputs are identical in every mode. */
+ * / cs_sieve_range: BYTES where exact, else ATOMIC.  Batches use BYTES when every job can, else
+ * ATOMIC (they ignore LIST); the server uses ATOMIC.  With BYTES, a whole-range call runs the
+ * small-prime branch on a second stream beside the large one (the large branch writes only its
+ * counters until the fold), joined back into `stream` before the call's last kernel.  Outputs are
+ * identical in every mode. */
 #define CS_SCATTER_AUTO   0u
 #define CS_SCATTER_ATOMIC 1u
 #define CS_SCATTER_BYTES  2u

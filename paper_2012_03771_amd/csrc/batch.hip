@@ -34,13 +34,13 @@ static uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
 // Re-derives the small-branch tiles of a plan for a shared LDS column-table size.
 void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune) {
   const uint32_t ct_bytes = lds_ct_words * 8u;
-  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
+  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 8u);
   rows = std::max(1u, std::min(rows, kTileRowsMax));
   if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
   pl.tile_rows = rows;
   pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
   pl.lds_ct_words = lds_ct_words;
-  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 4u * rows;
+  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 8u * rows;   // tile, counts, m offsets
   const double est_small = (double)pl.thr / std::max(1.0, log((double)pl.thr));
   uint32_t max_slices = (uint32_t)std::max(1.0, std::min(64.0, est_small / 512.0));
   uint32_t slices = pl.n_windows ? (uint32_t)((4u * (uint32_t)n_cu + pl.n_windows - 1) / pl.n_windows) : 1;
@@ -56,12 +56,25 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
   b.plans.assign(n, Plan());
   uint64_t Lp = std::max<uint64_t>(prime_extent, 2);
   uint32_t max_ct = 0;
+  // byte counters for the large hits when every job with rows can use them (one kernel variant
+  // serves all jobs of the fused launch), else the atomic scatter for all
+  b.bytes = true;
+  for (uint32_t pass = 0; pass < 2; ++pass) {
+    for (uint32_t i = 0; i < n; ++i) {
+      cs_status st = make_plan(&jobs[i], tunes ? &tunes[i] : nullptr, n_cu, &b.plans[i], false, true, b.bytes);
+      if (st) return st;
+    }
+    bool all = true;
+    for (uint32_t i = 0; i < n; ++i) all = all && (b.plans[i].n_m == 0 || b.plans[i].scatter_bytes);
+    if (all || !b.bytes) break;
+    b.bytes = false;
+  }
   for (uint32_t i = 0; i < n; ++i) {
-    cs_status st = make_plan(&jobs[i], tunes ? &tunes[i] : nullptr, n_cu, &b.plans[i], false);
-    if (st) return st;
     Lp = std::max(Lp, b.plans[i].Lp);
     max_ct = std::max(max_ct, b.plans[i].ct_words);
   }
+  b.max_rows = 0;
+  for (uint32_t i = 0; i < n; ++i) b.max_rows = std::max<uint64_t>(b.max_rows, b.plans[i].n_m);
   if (Lp >= kMaxLimit) return CS_ERANGE;
   b.Lp = Lp;
   b.lds_ct_words = max_ct * 8u <= kLdsCtMax ? max_ct : 0u;
@@ -124,6 +137,8 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
     const Plan& pl = b.plans[i];
     uint8_t* ws = m + b.job_off[i];
     b.jds[i] = make_jobdev(pl, ws, b.pw.primes, b.pw.n_primes);
+    if (pl.scatter_bytes)   // the counters start cleared; every run's fold clears them again
+      CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + pl.ws.hitbytes), pl.n_m * (uint64_t)pl.row_words * 8ull, 0u, s));
     b.jds[i].small_unit_base = unit_base;
     b.jds[i].prime_cap = b.cap;
     unit_base += (uint64_t)pl.n_windows * pl.n_slices;
@@ -166,9 +181,21 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   CS_TRY(launch_dpattern(b.jobs_dev, n, b.max_phi, b.max_rw, s));
   CS_TRY(launch_prep_bounds(b.jobs_dev, n, s));
   CS_TRY(launch_items_scan(b.jobs_dev, n, b.items_base, s));
-  CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));
   JobCtrl* c0 = b.jds[0].ctrl;
-  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, 0u, s));
+  const bool fork = b.bytes && b.aux;
+  if (fork) {
+    CS_TRY(hipEventRecord(b.ev_fork, s));
+    CS_TRY(hipStreamWaitEvent(b.aux, b.ev_fork, 0));
+  } else {
+    CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));
+  }
+  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, b.bytes ? 1u : 0u, s));
+  if (fork) {
+    CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, b.aux));
+    CS_TRY(hipEventRecord(b.ev_join, b.aux));
+    CS_TRY(hipStreamWaitEvent(s, b.ev_join, 0));
+  }
+  if (b.bytes) CS_TRY(launch_fold_bytes(b.jobs_dev, n, b.max_rows, b.n_cu, s));
   return CS_OK;
 }
 
@@ -224,11 +251,23 @@ extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tu
   cs_status st = multi_build(b->mj, jobs, tunes, n, device_cu_count(), 2);
   if (st) { delete b; return st; }
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return CS_EDEVICE; }
+  if (hipStreamCreateWithFlags(&b->mj.aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->mj.ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->mj.ev_join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(b->cap_stream);
+    if (b->mj.aux) (void)hipStreamDestroy(b->mj.aux);
+    if (b->mj.ev_fork) (void)hipEventDestroy(b->mj.ev_fork);
+    delete b;
+    return CS_EDEVICE;
+  }
   st = multi_alloc(b->mj, b->cap_stream);
   if (st == CS_OK && hipStreamSynchronize(b->cap_stream) != hipSuccess) st = CS_EDEVICE;
   if (st) {
     if (b->mj.mem) (void)hipFree(b->mj.mem);
     (void)hipStreamDestroy(b->cap_stream);
+    (void)hipStreamDestroy(b->mj.aux);
+    (void)hipEventDestroy(b->mj.ev_fork);
+    (void)hipEventDestroy(b->mj.ev_join);
     delete b;
     return st;
   }
@@ -247,7 +286,7 @@ extern "C" cs_status cs_batch_layout(const cs_batch* b, uint32_t i, cs_layout* o
   out->ws_bytes = b->mj.mem_bytes;
   out->prime_cap = b->mj.cap;
   out->thr = pl.thr;
-  out->scatter = CS_SCATTER_ATOMIC;
+  out->scatter = pl.scatter_bytes ? CS_SCATTER_BYTES : CS_SCATTER_ATOMIC;
   out->reserved = 0;
   return CS_OK;
 }
@@ -301,6 +340,12 @@ extern "C" cs_status cs_batch_destroy(cs_batch* b) {
     (void)hipStreamSynchronize(b->cap_stream);
     (void)hipStreamDestroy(b->cap_stream);
   }
+  if (b->mj.aux) {
+    (void)hipStreamSynchronize(b->mj.aux);
+    (void)hipStreamDestroy(b->mj.aux);
+  }
+  if (b->mj.ev_fork) (void)hipEventDestroy(b->mj.ev_fork);
+  if (b->mj.ev_join) (void)hipEventDestroy(b->mj.ev_join);
   if (b->mj.mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(b->mj.mem);

@@ -28,9 +28,14 @@ struct MultiJob {
   uint64_t* items_base = nullptr;
   std::vector<JobDev> jds;
   // launch shapes
-  uint64_t units = 0, max_words = 0, max_m_inc = 0, kmod_cap = 0;
+  uint64_t units = 0, max_words = 0, max_m_inc = 0, kmod_cap = 0, max_rows = 0;
+  bool bytes = false;                  // large hits through every job's byte counters
   uint32_t small_blocks = 1, large_blocks = 1, lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
   uint32_t max_phi = 0, max_rw = 0;   // class-pattern launch shape
+  // second stream and fork/join events: with the byte counters the small branch runs beside the
+  // large one (also inside a captured graph: the fork and join are events)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune);

@@ -606,14 +606,123 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t p) 
   return a >= b ? a - b : a + p - b;
 }
 
+// Marks of the small primes [s_lo, s_hi) in one tile (rows row_lo.. of the job), into the LDS tile
+// and row counts.  Inlined once with the column table in LDS and once in global memory so that
+// each copy reads it through its own address space.
+struct SmallArgs {
+  const JobDev& j;
+  const JobCtrl& c;
+  uint32_t* tile;
+  uint32_t* cnt;
+  const uint32_t* moff;
+  uint32_t R, rw, w;
+  uint64_t s_lo, s_hi;
+  bool dpat;
+  uint32_t lane, wid, nwaves;
+};
+
+__device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __restrict__ ct,
+                                            unsigned long long& n_pairs, unsigned long long& n_marks) {
+  const JobDev& j = a.j;
+  const JobCtrl& c = a.c;
+  uint32_t* tile = a.tile;
+  uint32_t* cnt = a.cnt;
+  const uint32_t R = a.R, rw = a.rw, w = a.w, lane = a.lane, wid = a.wid, nwaves = a.nwaves;
+  const uint64_t s_lo = a.s_lo, s_hi = a.s_hi;
+  const bool dpat = a.dpat;
+  const uint64_t sl = j.sl;
+  const uint32_t P = j.P;
+  const uint64_t* __restrict__ primes = j.primes;
+  const uint64_t* __restrict__ kmod = j.kmod;
+  const uint64_t* __restrict__ mkp = j.mk;
+  // dense primes: one wave per prime, lanes stride over its multiples in each row
+  const uint64_t d_hi = min(s_hi, max(c.small_dense, s_lo));
+  for (uint64_t i = s_lo + wid; i < d_hi; i += nwaves) {
+    const uint64_t p = primes[i];
+    const uint64_t k = kmod[i];
+    if (k == 0) continue;                         // p | K: never divides a column's N + X
+    if (dpat && p <= P) continue;               // p | d: marked by the class pattern
+    const double pinv = 1.0 / (double)p;
+    const uint64_t mk = mkp[i];
+    const uint64_t slp = mod64(sl, p, pinv);
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint32_t o = a.moff[r];
+      uint64_t rn = mk + mulmod(o, k, p, pinv);
+      rn = rn >= p ? rn - p : rn;                 // N mod p
+      const uint64_t s0 = sub_mod(slp, rn, p);    // first offset j = X + sl with p | N + X
+      uint32_t cc = 0;
+      for (uint64_t jj = s0 + (uint64_t)lane * p; jj <= w; jj += (uint64_t)kWave * p) {
+        uint32_t col;
+        if (lookup_col(ct, (uint32_t)jj, &col)) {
+          atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+          ++cc;
+        }
+      }
+      cc = wave_sum_u32(cc);
+      if (lane == 0) {
+        if (cc) atomicAdd(&cnt[r], cc);
+        n_pairs += 1;
+        n_marks += cc;
+      }
+    }
+  }
+  // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
+  const uint64_t sp_lo = max(s_lo, min(c.small_dense, s_hi));
+  for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
+    const uint64_t i = ib + threadIdx.x;
+    bool act = i < s_hi;
+    uint64_t p = 3, k = 0, mk = 0;
+    if (act) { p = primes[i]; k = kmod[i]; mk = mkp[i]; }
+    act = act && k != 0 && !(dpat && p <= P);
+    const double pinv = 1.0 / (double)p;
+    uint64_t s = 0;
+    uint32_t o_prev = 0;
+    if (R > 0) {
+      o_prev = a.moff[0];
+      uint64_t rn = mk + mulmod(o_prev, k, p, pinv);
+      rn = rn >= p ? rn - p : rn;
+      s = sub_mod(mod64(sl, p, pinv), rn, p);
+    }
+    for (uint32_t r = 0; r < R; ++r) {
+      if (r > 0) {
+        const uint32_t o = a.moff[r];
+        const uint32_t dm = o - o_prev;           // same for every lane
+        o_prev = o;
+        if (dm <= 12) {
+          for (uint32_t t = 0; t < dm; ++t) s = sub_mod(s, k, p);
+        } else {
+          s = sub_mod(s, mulmod(dm, k, p, pinv), p);
+        }
+      }
+      uint32_t cc = 0;
+      if (act) {
+        for (uint64_t jj = s; jj <= w; jj += p) {
+          uint32_t col;
+          if (lookup_col(ct, (uint32_t)jj, &col)) {
+            atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+            ++cc;
+          }
+        }
+      }
+      const uint32_t na = (uint32_t)__popcll(__ballot(act));
+      cc = wave_sum_u32(cc);
+      if (lane == 0) {
+        if (cc) atomicAdd(&cnt[r], cc);
+        n_pairs += na;
+        n_marks += cc;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                uint64_t total_units, uint32_t lds_ct_words) {
   extern __shared__ uint32_t lds[];
   const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const uint32_t nwaves = blockDim.x / kWave;
   unsigned long long n_pairs = 0, n_marks = 0;
+  uint32_t ji = 0;                                   // units only grow: resume the job search
   for (uint64_t unit = blockIdx.x; unit < total_units; unit += gridDim.x) {
-    uint32_t ji = 0;
     while (ji + 1 < n_jobs && jobs[ji + 1].small_unit_base <= unit) ++ji;
     const JobDev& j = jobs[ji];
     const JobCtrl& c = *j.ctrl;
@@ -635,12 +744,15 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
     uint2* ct_l = reinterpret_cast<uint2*>(lds);
     uint32_t* tile = lds + 2 * lds_ct_words;
     uint32_t* cnt = tile + (uint32_t)j.tile_rows * rw;
+    uint32_t* moff = cnt + j.tile_rows;            // m - m_start of the tile's rows
     if (ct_in_lds)
       for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = j.coltab[i];
     for (uint32_t i = threadIdx.x; i < R * rw; i += blockDim.x) tile[i] = 0;
-    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) cnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) {
+      cnt[i] = 0;
+      moff[i] = j.m_off[row_lo + i];
+    }
     __syncthreads();
-    const uint2* ct = ct_in_lds ? ct_l : j.coltab;
     const bool dpat = j.dpat_apply != 0;
     if (dpat && slice == 0) {
       // primes dividing d: the row of this m's residue class (tile rows start cleared)
@@ -661,83 +773,10 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
       __syncthreads();
     }
 
-    // dense primes: one wave per prime, lanes stride over its multiples in each row
-    const uint64_t d_hi = min(s_hi, max(c.small_dense, s_lo));
-    for (uint64_t i = s_lo + wid; i < d_hi; i += nwaves) {
-      const uint64_t p = j.primes[i];
-      const uint64_t k = j.kmod[i];
-      if (k == 0) continue;                         // p | K: never divides a column's N + X
-      if (dpat && p <= j.P) continue;               // p | d: marked by the class pattern
-      const double pinv = 1.0 / (double)p;
-      const uint64_t mk = j.mk[i];
-      const uint64_t slp = mod64(j.sl, p, pinv);
-      for (uint32_t r = 0; r < R; ++r) {
-        const uint32_t o = j.m_off[row_lo + r];
-        uint64_t rn = mk + mulmod(o, k, p, pinv);
-        rn = rn >= p ? rn - p : rn;                 // N mod p
-        const uint64_t s0 = sub_mod(slp, rn, p);    // first offset j = X + sl with p | N + X
-        uint32_t cc = 0;
-        for (uint64_t jj = s0 + (uint64_t)lane * p; jj <= w; jj += (uint64_t)kWave * p) {
-          uint32_t col;
-          if (lookup_col(ct, (uint32_t)jj, &col)) {
-            atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
-            ++cc;
-          }
-        }
-        cc = wave_sum_u32(cc);
-        if (lane == 0) {
-          if (cc) atomicAdd(&cnt[r], cc);
-          n_pairs += 1;
-          n_marks += cc;
-        }
-      }
-    }
-    // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
-    const uint64_t sp_lo = max(s_lo, min(c.small_dense, s_hi));
-    for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
-      const uint64_t i = ib + threadIdx.x;
-      bool act = i < s_hi;
-      uint64_t p = 3, k = 0, mk = 0;
-      if (act) { p = j.primes[i]; k = j.kmod[i]; mk = j.mk[i]; }
-      act = act && k != 0 && !(dpat && p <= j.P);
-      const double pinv = 1.0 / (double)p;
-      uint64_t s = 0;
-      uint32_t o_prev = 0;
-      if (R > 0) {
-        o_prev = j.m_off[row_lo];
-        uint64_t rn = mk + mulmod(o_prev, k, p, pinv);
-        rn = rn >= p ? rn - p : rn;
-        s = sub_mod(mod64(j.sl, p, pinv), rn, p);
-      }
-      for (uint32_t r = 0; r < R; ++r) {
-        if (r > 0) {
-          const uint32_t o = j.m_off[row_lo + r];
-          const uint32_t dm = o - o_prev;           // same for every lane
-          o_prev = o;
-          if (dm <= 12) {
-            for (uint32_t t = 0; t < dm; ++t) s = sub_mod(s, k, p);
-          } else {
-            s = sub_mod(s, mulmod(dm, k, p, pinv), p);
-          }
-        }
-        uint32_t cc = 0;
-        if (act) {
-          for (uint64_t jj = s; jj <= w; jj += p) {
-            uint32_t col;
-            if (lookup_col(ct, (uint32_t)jj, &col)) {
-              atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
-              ++cc;
-            }
-          }
-        }
-        const uint32_t na = (uint32_t)__popcll(__ballot(act));
-        cc = wave_sum_u32(cc);
-        if (lane == 0) {
-          if (cc) atomicAdd(&cnt[r], cc);
-          n_pairs += na;
-          n_marks += cc;
-        }
-      }
+    {
+      SmallArgs a{j, c, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
+      if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
+      else small_marks(a, j.coltab, n_pairs, n_marks);         // global column table
     }
     __syncthreads();
     // write the tile: rows of this unit belong to it alone unless the primes are sliced
@@ -986,6 +1025,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     do {   // one item; every exit leads to the per-item list sync below
     uint32_t ji = 0;
     if constexpr (!kLds) {
+      ji = ji_last;                                  // items only grow: resume the job search
       while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
     }
     const JobDev& j = jobs[kLds ? 0 : ji];          // the LDS variant runs one job: uniform fields
@@ -1548,7 +1588,7 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
                         uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
-  if (n_jobs != 1) scatter_kind = 0;
+  if (n_jobs != 1 && scatter_kind == 2) scatter_kind = 0;   // the list serves single jobs only
   const bool lds = lds_bytes && lds_ct_words && n_jobs == 1;
 #define LARGE_CASE(L, K)                                                                                       \
   hipLaunchKernelGGL((k_large<L, K>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs, job_item_base, \

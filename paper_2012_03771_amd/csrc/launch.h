@@ -56,8 +56,9 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
                         uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
 // lds_bytes = 0: tables read from global memory (any number of jobs); otherwise n_jobs must be 1
 // and the column table (lds_ct_words uint2, 0 = global) and residue table (dpre_n entries) of
-// that job are staged in LDS.  scatter_kind (single-job launches only; 0 otherwise): 0 = atomic
-// OR/add into the bitmap and counts, 1 = the job's byte counters, 2 = the job's list pool.
+// that job are staged in LDS.  scatter_kind: 0 = atomic OR/add into the bitmaps and counts,
+// 1 = every job's byte counters (all jobs must have them), 2 = the job's list pool (single-job
+// launches only; 0 otherwise).
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
                         uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s);

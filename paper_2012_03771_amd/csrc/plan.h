@@ -61,9 +61,10 @@ uint64_t pi_upper(uint64_t x);
 
 // Validates the job and fills everything except the range-dependent tiers.  With own_primes
 // false the workspace layout leaves out the prime table (a batch or server shares one); with
-// own_kmod false it leaves out the K mod p table (a server shares one per (P, d)).
+// own_kmod false it leaves out the K mod p table (a server shares one per (P, d)); with bytes_ok
+// false the large-hit byte counters are not used (the server, which folds nothing).
 cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes = true,
-                    bool own_kmod = true);
+                    bool own_kmod = true, bool bytes_ok = true);
 
 // Host count of rows and columns (also used by cs_rows / cs_columns).
 void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs);

@@ -69,7 +69,8 @@ uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq) {
   return (uint64_t)(coprime_below((u128)job.m_start + job.m_inc, dq) - coprime_below(job.m_start, dq));
 }
 
-cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes, bool own_kmod) {
+cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes, bool own_kmod,
+                    bool bytes_ok) {
   if (!job || !out) return CS_EINVAL;
   const cs_job j = *job;
   if (j.P < 2 || j.P >= kMaxP) return CS_EINVAL;
@@ -142,13 +143,13 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   // small branch tiles
   const bool ct_lds = pl.ct_words * 8u <= kLdsCtMax;
   const uint32_t ct_bytes = ct_lds ? pl.ct_words * 8u : 0u;
-  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 4u);
+  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 8u);
   rows = std::max(1u, std::min(rows, kTileRowsMax));
   if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
   pl.tile_rows = rows;
   pl.n_windows = (uint32_t)((pl.n_m + rows - 1) / rows);
   pl.lds_ct_words = ct_lds ? pl.ct_words : 0;
-  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 4u * rows;
+  pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 8u * rows;   // tile, counts, m offsets
   const double est_small = (double)pl.thr / std::max(1.0, log((double)pl.thr));
   uint32_t max_slices = (uint32_t)std::max(1.0, std::min(64.0, est_small / 512.0));
   uint32_t slices = pl.n_windows ? (uint32_t)((4u * (uint32_t)n_cu + pl.n_windows - 1) / pl.n_windows) : 1;
@@ -226,7 +227,6 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.dpat_cnt = take(pl.dpat_on ? (uint64_t)pl.phi_d * 4ull : 0);
   // Byte counters are exact when no number m K + X of the interval has 256 or more distinct prime
   // factors above the threshold: their product exceeds thr^c, and m K + X < (m_start + m_inc) K.
-  // Batches and the server share tables across jobs and keep the atomic scatter.
   {
     double log2_n = log2((double)j.m_start + (double)j.m_inc + 1.0);
     for (uint32_t q : pl.kq) log2_n += log2((double)q);
@@ -267,7 +267,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
         pl.list_chunks = tune && tune->list_chunks ? std::min<uint64_t>(tune->list_chunks, chunks) : chunks;
       }
     }
-    pl.scatter_bytes = !pl.scatter_list && own_primes && fits &&
+    pl.scatter_bytes = !pl.scatter_list && bytes_ok && fits &&
                        (scatter == CS_SCATTER_AUTO || scatter == CS_SCATTER_BYTES);
   }
   L.hitbytes = take(pl.scatter_bytes ? pl.n_m * (uint64_t)pl.row_words * 32ull : 0);

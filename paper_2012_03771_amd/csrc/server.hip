@@ -154,7 +154,7 @@ struct cs_server {
 namespace {
 
 cs_status plan_for_server(const cs_server* s, const cs_job* job, Plan* pl) {
-  cs_status st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, false);
+  cs_status st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, false, false);
   if (st) return st;
   if (pl->Lp > s->cfg.max_limit) return CS_ERANGE;
   return CS_OK;
