@@ -139,7 +139,7 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
     b.jds[i] = make_jobdev(pl, ws, b.pw.primes, b.pw.n_primes);
     if (pl.scatter_bytes)   // the counters start cleared; every run's fold clears them again
       CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + pl.ws.hitbytes), pl.n_m * (uint64_t)pl.row_words * 8ull, 0u, s));
-    b.jds[i].small_unit_base = unit_base;
+    b.jds[i].small_unit_base = 0;             // each job's small branch is its own launch
     b.jds[i].prime_cap = b.cap;
     unit_base += (uint64_t)pl.n_windows * pl.n_slices;
     if (!pl.dpre.empty()) {
@@ -180,22 +180,30 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   CS_TRY(launch_rows_cols(b.jobs_dev, n, b.max_m_inc, b.max_sl, b.n_cu, s));
   CS_TRY(launch_dpattern(b.jobs_dev, n, b.max_phi, b.max_rw, s));
   CS_TRY(launch_prep_bounds(b.jobs_dev, n, s));
-  CS_TRY(launch_items_scan(b.jobs_dev, n, b.items_base, s));
-  JobCtrl* c0 = b.jds[0].ctrl;
-  const bool fork = b.bytes && b.aux;
-  if (fork) {
-    CS_TRY(hipEventRecord(b.ev_fork, s));
-    CS_TRY(hipStreamWaitEvent(b.aux, b.ev_fork, 0));
-  } else {
-    CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, s));
+  // Each job's branches as single-job launches (LDS tables, uniform job fields, byte counters),
+  // jobs spread over the lanes so several run at once.
+  const uint32_t nl = (uint32_t)b.lanes.size();
+  CS_TRY(hipEventRecord(b.ev_fork, s));
+  for (uint32_t l = 0; l < nl; ++l) CS_TRY(hipStreamWaitEvent(b.lanes[l], b.ev_fork, 0));
+  for (uint32_t i = 0; i < n; ++i) {
+    const Plan& pl = b.plans[i];
+    if (pl.n_m == 0) continue;
+    hipStream_t ls = b.lanes[i % nl];
+    const JobDev* jd = b.jobs_dev + i;
+    uint64_t* ib = reinterpret_cast<uint64_t*>(b.mem + b.job_off[i] + pl.ws.items_base);
+    CS_TRY(launch_items_scan(jd, 1, ib, ls));
+    const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
+    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(pl.lds_bytes, 1u)));
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(units, 1), (uint64_t)b.n_cu * per_cu);
+    CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, blocks, ls));
+    CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
+                        (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, ls));
+    if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jd, 1, pl.n_m, b.n_cu, ls));
   }
-  CS_TRY(launch_large(b.jobs_dev, n, b.items_base, c0->diag, b.large_blocks, 0, 0, 0, b.bytes ? 1u : 0u, s));
-  if (fork) {
-    CS_TRY(launch_small(b.jobs_dev, n, b.units, b.lds_bytes, b.lds_ct_words, b.small_blocks, b.aux));
-    CS_TRY(hipEventRecord(b.ev_join, b.aux));
-    CS_TRY(hipStreamWaitEvent(s, b.ev_join, 0));
+  for (uint32_t l = 0; l < nl; ++l) {
+    CS_TRY(hipEventRecord(b.ev_done[l], b.lanes[l]));
+    CS_TRY(hipStreamWaitEvent(s, b.ev_done[l], 0));
   }
-  if (b.bytes) CS_TRY(launch_fold_bytes(b.jobs_dev, n, b.max_rows, b.n_cu, s));
   return CS_OK;
 }
 
@@ -205,16 +213,14 @@ cs_status multi_diag(const MultiJob& b, cs_diag* out) {
   for (uint32_t i = 0; i < b.n; ++i) {
     JobCtrl c;
     if (hipMemcpy(&c, b.jds[i].ctrl, sizeof(JobCtrl), hipMemcpyDeviceToHost) != hipSuccess) return CS_EDEVICE;
-    if (i == 0) {
-      out->n_primes = c.diag[D_NPRIMES];
-      out->small_pairs = c.diag[D_SMALL_PAIRS];
-      out->small_marks = c.diag[D_SMALL_MARKS];
-      out->large_raw_hits = c.diag[D_LARGE_RAW];
-      out->large_hits = c.diag[D_LARGE_HITS];
-      out->g_calls = c.diag[D_G_CALLS];
-      out->g_levels = c.diag[D_G_LEVELS];
-      err |= c.diag[D_ERROR];
-    }
+    if (i == 0) out->n_primes = c.diag[D_NPRIMES];
+    out->small_pairs += c.diag[D_SMALL_PAIRS];
+    out->small_marks += c.diag[D_SMALL_MARKS];
+    out->large_raw_hits += c.diag[D_LARGE_RAW];
+    out->large_hits += c.diag[D_LARGE_HITS];
+    out->g_calls += c.diag[D_G_CALLS];
+    out->g_levels += c.diag[D_G_LEVELS];
+    err |= c.diag[D_ERROR];
     out->small_primes += c.diag[D_SMALL_PRIMES];
     out->large_primes += c.diag[D_LARGE_PRIMES];
     err |= c.error;
@@ -235,6 +241,31 @@ struct cs_batch {
   bool bound = false;
 };
 
+static cs_status create_lanes(MultiJob& m, uint32_t n) {
+  if (hipEventCreateWithFlags(&m.ev_fork, hipEventDisableTiming) != hipSuccess) return CS_EDEVICE;
+  for (uint32_t l = 0; l < n; ++l) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return CS_EDEVICE;
+    m.lanes.push_back(st);
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return CS_EDEVICE;
+    m.ev_done.push_back(ev);
+  }
+  return CS_OK;
+}
+
+static void destroy_lanes(MultiJob& m) {
+  for (hipStream_t st : m.lanes) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t ev : m.ev_done) (void)hipEventDestroy(ev);
+  if (m.ev_fork) (void)hipEventDestroy(m.ev_fork);
+  m.lanes.clear();
+  m.ev_done.clear();
+  m.ev_fork = nullptr;
+}
+
 static void drop_graph(cs_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -251,12 +282,9 @@ extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tu
   cs_status st = multi_build(b->mj, jobs, tunes, n, device_cu_count(), 2);
   if (st) { delete b; return st; }
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return CS_EDEVICE; }
-  if (hipStreamCreateWithFlags(&b->mj.aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->mj.ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->mj.ev_join, hipEventDisableTiming) != hipSuccess) {
+  if (create_lanes(b->mj, std::min<uint32_t>(kBatchLanes, n)) != CS_OK) {
     (void)hipStreamDestroy(b->cap_stream);
-    if (b->mj.aux) (void)hipStreamDestroy(b->mj.aux);
-    if (b->mj.ev_fork) (void)hipEventDestroy(b->mj.ev_fork);
+    destroy_lanes(b->mj);
     delete b;
     return CS_EDEVICE;
   }
@@ -265,9 +293,7 @@ extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tu
   if (st) {
     if (b->mj.mem) (void)hipFree(b->mj.mem);
     (void)hipStreamDestroy(b->cap_stream);
-    (void)hipStreamDestroy(b->mj.aux);
-    (void)hipEventDestroy(b->mj.ev_fork);
-    (void)hipEventDestroy(b->mj.ev_join);
+    destroy_lanes(b->mj);
     delete b;
     return st;
   }
@@ -340,12 +366,7 @@ extern "C" cs_status cs_batch_destroy(cs_batch* b) {
     (void)hipStreamSynchronize(b->cap_stream);
     (void)hipStreamDestroy(b->cap_stream);
   }
-  if (b->mj.aux) {
-    (void)hipStreamSynchronize(b->mj.aux);
-    (void)hipStreamDestroy(b->mj.aux);
-  }
-  if (b->mj.ev_fork) (void)hipEventDestroy(b->mj.ev_fork);
-  if (b->mj.ev_join) (void)hipEventDestroy(b->mj.ev_join);
+  destroy_lanes(b->mj);
   if (b->mj.mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(b->mj.mem);

@@ -32,11 +32,14 @@ struct MultiJob {
   bool bytes = false;                  // large hits through every job's byte counters
   uint32_t small_blocks = 1, large_blocks = 1, lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
   uint32_t max_phi = 0, max_rw = 0;   // class-pattern launch shape
-  // second stream and fork/join events: with the byte counters the small branch runs beside the
-  // large one (also inside a captured graph: the fork and join are events)
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // lanes: streams that run the jobs' branches side by side (forked from and joined back into
+  // the launch stream by events, so a captured graph holds them as parallel branches)
+  std::vector<hipStream_t> lanes;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_done;
 };
+
+constexpr uint32_t kBatchLanes = 4;
 
 void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune);
 // Plans every job (tables without a prime table) and lays out one device allocation whose
