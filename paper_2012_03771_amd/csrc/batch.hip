@@ -47,6 +47,7 @@ void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune
   slices = std::max(1u, std::min(slices, max_slices));
   if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
   pl.n_slices = slices;
+  pl.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((uint64_t)pl.n_windows * slices, 1), 1ull << 31);
 }
 
 cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uint32_t n, int n_cu,
@@ -152,9 +153,6 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
     }
   }
   b.units = unit_base;
-  const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(b.lds_bytes, 1u)));
-  b.small_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b.units, 1), (uint64_t)b.n_cu * per_cu);
-  b.large_blocks = (uint32_t)b.n_cu * 8u;
   return CS_OK;
 }
 
@@ -193,9 +191,7 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
     uint64_t* ib = reinterpret_cast<uint64_t*>(b.mem + b.job_off[i] + pl.ws.items_base);
     CS_TRY(launch_items_scan(jd, 1, ib, ls));
     const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
-    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(pl.lds_bytes, 1u)));
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(units, 1), (uint64_t)b.n_cu * per_cu);
-    CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, blocks, ls));
+    CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, ls));
     CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
                         (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, ls));
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jd, 1, pl.n_m, b.n_cu, ls));

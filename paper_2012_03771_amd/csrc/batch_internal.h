@@ -30,7 +30,7 @@ struct MultiJob {
   // launch shapes
   uint64_t units = 0, max_words = 0, max_m_inc = 0, kmod_cap = 0, max_rows = 0;
   bool bytes = false;                  // large hits through every job's byte counters
-  uint32_t small_blocks = 1, large_blocks = 1, lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
+  uint32_t lds_bytes = 0, lds_ct_words = 0, max_sl = 0;
   uint32_t max_phi = 0, max_rw = 0;   // class-pattern launch shape
   // lanes: streams that run the jobs' branches side by side (forked from and joined back into
   // the launch stream by events, so a captured graph holds them as parallel branches)

@@ -797,9 +797,17 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
     }
     __syncthreads();
   }
-  if (lane == 0 && n_jobs > 0) {
-    atomicAdd(&jobs[0].ctrl->diag[D_SMALL_PAIRS], n_pairs);
-    atomicAdd(&jobs[0].ctrl->diag[D_SMALL_MARKS], n_marks);
+  // counters: one atomic per workgroup and counter (lane 0 of each wavefront holds its sums)
+  __shared__ unsigned long long s_cnt[2][256 / kWave];
+  if (lane == 0) {
+    s_cnt[0][wid] = n_pairs;
+    s_cnt[1][wid] = n_marks;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 && n_jobs > 0) {
+    unsigned long long v = 0;
+    for (uint32_t i = 0; i < nwaves; ++i) v += s_cnt[threadIdx.x][i];
+    if (v) atomicAdd(&jobs[0].ctrl->diag[threadIdx.x == 0 ? D_SMALL_PAIRS : D_SMALL_MARKS], v);
   }
 }
 
@@ -1001,6 +1009,9 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
                                                uint32_t dpre_n) {
   extern __shared__ uint32_t lds[];
   __shared__ unsigned long long s_list[256 / kWave];   // per wavefront: latest list state (see list_sync)
+  __shared__ unsigned long long s_diag[4][256 / kWave];
+  const uint64_t total = job_item_base[n_jobs];
+  if ((uint64_t)blockIdx.x * blockDim.x >= total) return;   // workgroups past the last item (uniform)
   unsigned long long* lkey = s_list + threadIdx.x / kWave;
   if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
   if constexpr (!kLds) __syncthreads();
@@ -1015,7 +1026,6 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
   }
-  const uint64_t total = job_item_base[n_jobs];
   unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
   uint32_t err = 0;
   ListReg lreg = {kNoChunk, 0u};
@@ -1167,15 +1177,25 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       if (ch < kPoolFull) jobs[0].list_fill[ch] = (uint32_t)k;
     }
   }
+  // counters: one atomic per workgroup and counter (many short workgroups share four addresses)
   raw = wave_sum_u64(raw);
   useful = wave_sum_u64(useful);
   calls = wave_sum_u64(calls);
   levels = wave_sum_u64(levels);
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    atomicAdd(&diag[D_LARGE_RAW], raw);
-    atomicAdd(&diag[D_LARGE_HITS], useful);
-    atomicAdd(&diag[D_G_CALLS], calls);
-    atomicAdd(&diag[D_G_LEVELS], levels);
+    const uint32_t wv = threadIdx.x / kWave;
+    s_diag[0][wv] = raw;
+    s_diag[1][wv] = useful;
+    s_diag[2][wv] = calls;
+    s_diag[3][wv] = levels;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long v = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) v += s_diag[threadIdx.x][i];
+    const uint32_t at = threadIdx.x == 0 ? D_LARGE_RAW : threadIdx.x == 1 ? D_LARGE_HITS
+                      : threadIdx.x == 2 ? D_G_CALLS : D_G_LEVELS;
+    if (v) atomicAdd(&diag[at], v);
   }
   if (err) atomicOr(reinterpret_cast<unsigned long long*>(&diag[D_ERROR]), (unsigned long long)err);
 }

@@ -14,7 +14,11 @@ constexpr uint32_t kMaxP = 1u << 24;
 constexpr uint64_t kMaxMInc = 1ull << 32;
 constexpr uint32_t kSmallBlock = 512;
 constexpr uint32_t kLargeBlock = 256;
-constexpr uint32_t kLdsBudget = 64 * 1024;
+// Default grid of the large branch: many short workgroups, so the hardware scheduler evens out
+// the items' unequal costs (a persistent grid of a few workgroups per CU left a long tail).
+constexpr uint32_t kLargeBlocksPerCu = 128;
+constexpr uint32_t kListBlocksPerCu = 8;      // with the list scatter (one part-filled chunk per wavefront)
+constexpr uint32_t kLdsBudget = 64 * 1024 - 256;   // dynamic LDS of a small-branch tile (the kernel keeps 256 B of its own)
 constexpr uint32_t kLdsCtMax = 32 * 1024;
 constexpr uint32_t kTileRowsMax = 16;          // rows per small-branch tile (more workgroups per CU beat bigger tiles)
 constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024) plus slack

@@ -157,8 +157,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
   pl.n_slices = slices;
   const uint64_t units = (uint64_t)pl.n_windows * slices;
-  const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(pl.lds_bytes, 1u)));
-  pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, (uint64_t)n_cu * per_cu);
+  pl.small_blocks = (uint32_t)std::min<uint64_t>(units ? units : 1, 1ull << 31);   // one workgroup per unit
   pl.dense_max = std::max<uint64_t>(1, pl.w / 32);
 
   // residue table of d: m -> row without a per-m lookup
@@ -194,7 +193,6 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
 
   pl.hits_per_item = tune && tune->hits_per_item ? tune->hits_per_item
                                                  : (mode == CS_LARGE_G ? 128u : 1024u);
-  pl.large_blocks = tune && tune->large_blocks ? tune->large_blocks : (uint32_t)n_cu * 8u;
 
   // workspace layout
   WsLayout& L = pl.ws;
@@ -241,6 +239,9 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     // kListTileBytes (at most 64 rows); groups hold 2^g buckets, at most kListSupers groups.
     pl.scatter_list = false;
     pl.list_chunks = 0;
+    // every wavefront of the large branch may leave one chunk part-filled: the list keeps a
+    // smaller grid than the default
+    const uint32_t list_blocks = tune && tune->large_blocks ? tune->large_blocks : (uint32_t)n_cu * kListBlocksPerCu;
     pl.cell_shift = 0;
     while ((1ull << pl.cell_shift) < std::max<uint64_t>(pl.n_x, 1)) ++pl.cell_shift;
     uint32_t lb = 0;
@@ -253,7 +254,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
       const double sum_inv = j.limit > pl.thr + 1 ? std::max(0.0, log(log((double)j.limit)) - log(log((double)pl.thr + 1.0)))
                                                   : 0.0;
       const double expect = (double)pl.n_m * (double)pl.n_x * sum_inv;
-      const uint64_t slack = std::max<uint64_t>(pl.large_blocks, 2048) * 4ull + 4ull;   // open chunks
+      const uint64_t slack = std::max<uint64_t>(list_blocks, 2048) * 4ull + 4ull;   // open chunks
       const uint64_t chunks = (uint64_t)(expect * 1.15 / kListChunk) + slack;
       const bool ok = own_primes && pl.n_m > 0 && (pl.n_m << pl.cell_shift) <= (1ull << 32) &&
                       pl.n_bkt <= kMaxBuckets && (1u << pl.super_shift) <= kListMaxPerSuper &&
@@ -269,6 +270,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     }
     pl.scatter_bytes = !pl.scatter_list && bytes_ok && fits &&
                        (scatter == CS_SCATTER_AUTO || scatter == CS_SCATTER_BYTES);
+    pl.large_blocks = pl.scatter_list ? list_blocks
+                    : tune && tune->large_blocks ? tune->large_blocks : (uint32_t)n_cu * kLargeBlocksPerCu;
   }
   L.hitbytes = take(pl.scatter_bytes ? pl.n_m * (uint64_t)pl.row_words * 32ull : 0);
   L.list_pool = take(pl.list_chunks * kListChunk * 4ull);

@@ -330,11 +330,11 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
   if (launch_prep_bounds(s->run_dev, n, st) != hipSuccess) return false;
   if (launch_items_scan(s->run_dev, n, s->items_base, st) != hipSuccess) return false;
   if (units) {
-    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / std::max(lds, 1u)));
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, (uint64_t)s->n_cu * per_cu);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, 1ull << 31);   // one workgroup per unit
     if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, st) != hipSuccess) return false;
   }
-  if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * 8u, 0, 0, 0, 0u, st) != hipSuccess)
+  if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u, st) !=
+      hipSuccess)
     return false;
   if (hipStreamSynchronize(st) != hipSuccess) return false;
   return true;
