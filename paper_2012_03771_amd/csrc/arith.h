@@ -1,8 +1,9 @@
 // Exact integer arithmetic for the sieve kernels, written for gfx950's full-rate fp64 VALU.
 //
 // All residues handled here are below 2^40 (the library's documented sieve-limit range), so
-// they are exactly representable as doubles.  Quotients come from a correctly rounded fp64
-// reciprocal and are corrected by one exact fma step, so every remainder is exact.
+// they are exactly representable as doubles.  Quotients come from an fp64 reciprocal within a
+// unit in the last place and are corrected by one exact fma step, so every remainder is exact;
+// Euclidean steps on remainders below 2^20 run in fp32 the same way.
 // Products beyond 2^53 (a*b mod p) take an fp64 quotient estimate and an exact 64-bit
 // wrapping difference (the classic floating-point-quotient modular multiplication).
 //
@@ -20,9 +21,62 @@
 
 namespace cs {
 
-// 1/x, correctly rounded (the IEEE fp64 division; measured faster on gfx950 than a hardware
-// reciprocal seed refined by Newton steps inside the dependent chains of the solver).
-CS_HD double recip(double x) { return 1.0 / x; }
+// 1/x for 1 <= x < 2^52.  On the device: the hardware reciprocal (relative error about 2^-24 on
+// gfx950) refined by two Newton steps, each squaring the error, so the result is within a unit
+// in the last place (five instructions against eleven for the IEEE division with its scaling and
+// fix-up, which positive normal arguments do not need).  Callers only rely on a relative error
+// far below 2^-46.  The host build, which only serves tests, moves the correctly rounded quotient
+// by one unit in either direction so that the quotient corrections that depend on the rounding
+// are exercised.
+CS_HD double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  const double r = 1.0 / x;
+  const uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull;   // direction by a hash of the argument
+  return nextafter(r, (h >> 63) ? 0.0 : 2.0 * r);
+#endif
+}
+
+// 1/x in fp32 to within one unit in the last place (the device's hardware reciprocal).  The host
+// build, which only serves tests, perturbs the correctly rounded quotient by one unit in either
+// direction so that callers are checked against the worst error they allow.
+CS_HD float rcp_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  const float r = 1.0f / x;
+  const uint32_t h = (uint32_t)x * 2654435761u;   // direction by a hash of the (integer) argument
+  return nextafterf(r, (h >> 31) ? 0.0f : 2.0f * r);
+#endif
+}
+
+// The rest of an extended Euclidean pass once the remainders (a, b) are below 2^20, for the
+// Bezout coefficients alone: (a, b, sa, sb) with sa*k == a and sb*k == b (mod p) become
+// (gcd, 0, s, .) with s*k == gcd (mod p).  Integers below 2^20 are exact in fp32; the product of
+// a and the one-ulp reciprocal of b is within a relative 2^-22 of a/b < 2^20, so its floor is off
+// by at most one and one exact fma and one correction each way give the quotient.  The
+// coefficients stay below p in magnitude and are updated in fp64.
+CS_HD void euclid_tail_f32(double* a, double* b, double* sa, double* sb) {
+  float af = (float)*a, bf = (float)*b;
+  double s0 = *sa, s1 = *sb;
+  for (int it = 0; it < 64 && bf != 0.0f; ++it) {   // at most 30 steps below 2^20 (Fibonacci)
+    float q = floorf(af * rcp_f32(bf));
+    float r = fmaf(-q, bf, af);
+    if (r < 0.0f) { r += bf; q -= 1.0f; }
+    if (r >= bf) { r -= bf; q += 1.0f; }
+    const double s2 = fma(-(double)q, s1, s0);
+    af = bf; bf = r; s0 = s1; s1 = s2;
+  }
+  *a = (double)af;
+  *b = 0.0;
+  *sa = s0;
+  *sb = s1;
+}
 
 // x mod m for 0 <= x < 2^52, 1 <= m < 2^52, with inv = 1/m to a relative error below 2^-46
 // and x/m < 2^40: |x/m - x*inv| < 1 so the floor is off by at most one; one exact fma and one
@@ -62,7 +116,7 @@ CS_HD uint64_t mod64(uint64_t x, uint64_t p, double pinv) {
 CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
   double a = (double)p, b = (double)k;
   double s0 = 0.0, s1 = 1.0;          // s_i * k == r_i (mod p)
-  for (int it = 0; it < 128 && b != 0.0; ++it) {
+  for (int it = 0; it < 128 && b != 0.0 && a >= 1048576.0; ++it) {
     double inv = recip(b);
     double q = floor(a * inv);
     double r = fma(-q, b, a);
@@ -71,6 +125,7 @@ CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
     double s2 = fma(-q, s1, s0);
     a = b; b = r; s0 = s1; s1 = s2;
   }
+  euclid_tail_f32(&a, &b, &s0, &s1);  // the remaining steps in fp32, with the lanes reconverged
   // a == gcd == 1 and s0 * k == 1 (mod p)
   double pd = (double)p;
   if (s0 < 0.0) s0 += pd;
@@ -80,13 +135,17 @@ CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
 // Offset part of the modular-equation solver G(p, K, L, R) of Eq. 4-5: the smallest t >= 0
 // with L <= t*K mod p <= R = L + width.  Instead of unwinding the recursion this returns
 // off = v - L, where v = t*K mod p is the value the minimal t reaches; the caller recovers
-// t = v * K^-1 mod p.  Case by case (first match wins, as in Eq. 5):
+// t = v * K^-1 mod p.  The cases of Eq. 5, one level per pass:
 //   (a) L = 0                        -> v = 0.
-//   (c) a multiple of K lies in [L, R] -> v = ceil(L/K)*K, off = K - (L mod K) or 0.
 //   (d) 2K >= p: (p, K, L, R) -> (p, p-K, p-R, p-L); the offset is mirrored: off -> width-off.
+//   (c) a multiple of K lies in [L, R] -> v = ceil(L/K)*K, off = K - (L mod K) or 0.
 //   (e) (p, K, L, R) -> (K, (-p) mod K, L mod K, R mod K); the offset is unchanged because the
 //       solution value satisfies v = floor(L/K)*K + v' with [L, R] free of multiples of K.
-// Case (b) (K >= p) is never met: callers pass K < p and (e) keeps the new K below the new p.
+// (d) is applied before (c) within a level, by selects, so that a wavefront's lanes follow one
+// instruction stream whichever case they are in.  Each case maps the problem to one with the
+// same least t (the mirror needs 0 outside [L, R], which (a) guarantees), so the order does
+// not change the result.  Case (b) (K >= p) is never met: callers pass K < p and (e) keeps the
+// new K below the new p.
 // Preconditions: gcd(p, K) = 1, 1 <= K < p < 2^40, 0 <= L, L + width < p.
 // Returns -1 (never for valid input) if the descent exceeds `max_levels`.
 CS_HD double g_offset(double p, double K, double L, double width, int* levels_out,
@@ -95,18 +154,15 @@ CS_HD double g_offset(double p, double K, double L, double width, int* levels_ou
   double off = -1.0;
   for (; lv < max_levels; ++lv) {
     if (L == 0.0) { off = 0.0; break; }                       // (a)
-    double inv = recip(K);
-    double rem = fmod_inv(L, K, inv);                          // L mod K
-    if (rem == 0.0) { off = 0.0; break; }                      // (c): K | L
-    double up = K - rem;                                       // ceil(L/K)*K - L
+    const bool mir = K + K >= p;                               // (d)
+    L = mir ? p - L - width : L;
+    K = mir ? p - K : K;
+    par ^= mir ? 1 : 0;
+    const double inv = recip(K);
+    const double rem = fmod_inv(L, K, inv);                    // L mod K
+    const double up = rem == 0.0 ? 0.0 : K - rem;              // ceil(L/K)*K - L
     if (up <= width) { off = up; break; }                      // (c)
-    if (K + K >= p) {                                          // (d)
-      L = p - L - width;
-      K = p - K;
-      par ^= 1;
-      continue;
-    }
-    double pm = fmod_inv(p, K, inv);                           // p mod K (nonzero: gcd = 1)
+    const double pm = fmod_inv(p, K, inv);                     // p mod K (nonzero: gcd = 1)
     p = K;                                                      // (e)
     K = (pm == 0.0) ? 0.0 : K - pm;
     L = rem;
@@ -163,42 +219,74 @@ CS_HD int three_gap_setup(uint64_t p, uint64_t k, uint64_t kinv, double pinv, ui
 // side the one-sided best approximations are the semiconvergents r_{i-1} - j r_i with
 // t = |s_{i-1}| + j |s_i|, 1 <= j <= q_i, so the least t whose residue on a side falls to w or
 // below is the first such semiconvergent: j = ceil((r_{i-1} - w) / r_i) at the first step whose
-// remainder on that side drops to w or below.  Requires 1 <= k < p < 2^40 prime, 1 <= w,
-// p > 2w.  Returns 0 only on an internal failure.
+// remainder on that side drops to w or below.  The remainders decrease, so the first remainder
+// r_{i+1} <= w settles the side of r_{i-1} and the next one, r_{i+2} <= r_{i+1}, the other side:
+// the loop runs plain Euclidean steps up to that point and both constants are taken after it
+// (when k <= w, t = 1 is the positive side's and the step from (p, k) gives the other).
+// Requires 1 <= k < p < 2^40 prime, 1 <= w, p > 2w.  Returns 0 only on an internal failure.
+CS_HD void tg_side(double a, double b, double inv, double sa, double sb, double wd, double* t, double* v) {
+  const double num = a - wd + b - 1.0;          // j = ceil((a - w) / b), a > w
+  double j = floor(num * inv);
+  const double rj = fma(-j, b, num);
+  j = rj < 0.0 ? j - 1.0 : (rj >= b ? j + 1.0 : j);
+  *t = fma(j, fabs(sb), fabs(sa));
+  *v = fma(-j, b, a);                           // residue on this side, in [1, w]
+}
+
 CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_t* kinv_out, int* steps_out) {
   const double wd = (double)w;
   double a = (double)p, b = (double)k;        // r_{i-1}, r_i
   double sa = 0.0, sb = 1.0;                  // s_{i-1}, s_i
-  bool fa = false, fb = false;                // positive side (t*k mod p small), negative side
-  if (b <= wd) {                              // t = 1
-    g->ta = 1;
-    g->a = k;
-    fa = true;
-  }
+  double inv = 0.0, r = 0.0, sn = 0.0;
   int it = 0;
-  for (; it < 160 && b != 0.0; ++it) {
-    const double inv = recip(b);
+  if (b > wd) {
+    for (; it < 160; ++it) {
+      inv = recip(b);
+      double q = floor(a * inv);
+      r = fma(-q, b, a);
+      if (r < 0.0) { r += b; q -= 1.0; }
+      if (r >= b) { r -= b; q += 1.0; }
+      sn = fma(-q, sb, sa);                   // s_{i+1}, same side as s_{i-1}
+      if (r <= wd) break;                     // the first remainder at or below w
+      a = b; b = r; sa = sb; sb = sn;
+    }
+    if (it == 160) return 0;
+  }
+  double t1, v1, t2, v2;
+  bool pos1;
+  if (b <= wd) {                              // k <= w: t = 1 on the positive side
+    t1 = 1.0;
+    v1 = b;
+    pos1 = true;
+    inv = recip(b);
     double q = floor(a * inv);
-    double r = fma(-q, b, a);
+    r = fma(-q, b, a);
     if (r < 0.0) { r += b; q -= 1.0; }
     if (r >= b) { r -= b; q += 1.0; }
-    const double sn = fma(-q, sb, sa);        // s_{i+1}, same side as s_{i-1}
-    const bool pos = sa > 0.0;                // side of r_{i-1} and r_{i+1} (s_{-1} = 0: negative)
-    if (r <= wd && (pos ? !fa : !fb)) {
-      double j = floor((a - wd + b - 1.0) * inv);   // ceil((a - w) / b), a > w on this side
-      double rem = fma(-j, b, a - wd + b - 1.0);
-      if (rem < 0.0) j -= 1.0;
-      if (rem >= b) j += 1.0;
-      const double t = fabs(sa) + j * fabs(sb);
-      const double v = a - j * b;                   // residue on this side, in [1, w]
-      if (pos) { g->ta = (uint64_t)t; g->a = (uint64_t)v; fa = true; }
-      else { g->tb = (uint64_t)t; g->b = (uint64_t)v; fb = true; }
-    }
+    sn = fma(-q, sb, sa);
+    tg_side(a, b, inv, sa, sb, wd, &t2, &v2); // negative side from the step (p, k)
+  } else {
+    pos1 = sa > 0.0;                          // side of r_{i-1} and r_{i+1}
+    tg_side(a, b, inv, sa, sb, wd, &t1, &v1);
+    // one more exact step: (r_i, r_{i+1}) gives the other side
     a = b; b = r; sa = sb; sb = sn;
+    inv = recip(b);
+    double q = floor(a * inv);
+    r = fma(-q, b, a);
+    if (r < 0.0) { r += b; q -= 1.0; }
+    if (r >= b) { r -= b; q += 1.0; }
+    sn = fma(-q, sb, sa);
+    tg_side(a, b, inv, sa, sb, wd, &t2, &v2);
   }
+  a = b; b = r; sa = sb; sb = sn;             // a <= w < 2^20
+  euclid_tail_f32(&a, &b, &sa, &sb);          // the rest, for k^-1 only, in fp32
   if (steps_out) *steps_out = it;
   // a = gcd = 1 and sa * k == 1 (mod p)
-  if (a != 1.0 || !fa || !fb) return 0;
+  if (a != 1.0) return 0;
+  g->ta = (uint64_t)(pos1 ? t1 : t2);
+  g->a = (uint64_t)(pos1 ? v1 : v2);
+  g->tb = (uint64_t)(pos1 ? t2 : t1);
+  g->b = (uint64_t)(pos1 ? v2 : v1);
   const double pd = (double)p;
   *kinv_out = (uint64_t)(sa < 0.0 ? sa + pd : sa);
   return 1;

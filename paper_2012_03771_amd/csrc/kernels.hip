@@ -21,6 +21,15 @@ namespace cs {
 // ------------------------------------------------------------------------------------------
 // helpers
 // ------------------------------------------------------------------------------------------
+// A device-memory pointer typed as global (address space 1).  Pointers read from a JobDev are
+// generic, and accesses through them compile to flat instructions, which also count against the
+// LDS wait counter: an LDS read behind a flat atomic then waits for the atomic to reach memory.
+// Through a global pointer the same accesses are global instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gbl(T* p) { return (gptr<T>)p; }
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -44,11 +53,20 @@ __device__ uint64_t upper_index(const uint64_t* t, uint64_t n, uint64_t x) {
 
 // Column of offset j = X + sl from the table {mask, columns before} per 32 offsets, or false
 // if X is not a column (gcd(X, K) > 1).
-__device__ __forceinline__ bool lookup_col(const uint2* ct, uint32_t jj, uint32_t* col) {
-  const uint2 e = ct[jj >> 5];
+// Column-table entry {mask, columns before} as one 64-bit word (mask in the low half).
+__device__ __forceinline__ uint64_t ct_entry(const uint2* ct, uint32_t i) {
+  return reinterpret_cast<const uint64_t*>(ct)[i];
+}
+__device__ __forceinline__ uint64_t ct_entry(gptr<const uint2> ct, uint32_t i) {
+  return ((gptr<const uint64_t>)ct)[i];
+}
+template <class CT>
+__device__ __forceinline__ bool lookup_col(CT ct, uint32_t jj, uint32_t* col) {
+  const uint64_t e = ct_entry(ct, jj >> 5);
+  const uint32_t mask = (uint32_t)e, before = (uint32_t)(e >> 32);
   const uint32_t b = jj & 31;
-  if (!((e.x >> b) & 1u)) return false;
-  *col = e.y + __popc(e.x & ((1u << b) - 1u));
+  if (!((mask >> b) & 1u)) return false;
+  *col = before + __popc(mask & ((1u << b) - 1u));
   return true;
 }
 
@@ -341,12 +359,12 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
     const bool two = g1 < total;
     const JobDev& j1 = two ? job_of_index(jobs, n_jobs, lim_base, g1, &i1) : j0;
     if (!two) i1 = i0;
-    const uint64_t p0 = j0.primes[i0], p1 = j1.primes[i1];
+    const uint64_t p0 = gbl(j0.primes)[i0], p1 = gbl(j1.primes)[i1];
     const double v0 = 1.0 / (double)p0, v1 = 1.0 / (double)p1;
     uint64_t r0, r1;
     if (&j0 == &j1 && !j0.kmod_cached) {
-      const uint32_t ng = j0.ctrl->n_kgroups;
-      const uint64_t* __restrict__ G = j0.kgroups;
+      const uint32_t ng = gbl(j0.ctrl)->n_kgroups;
+      const gptr<const uint64_t> G = gbl(j0.kgroups);
       r0 = 1 % p0;
       r1 = 1 % p1;
       for (uint32_t t = 0; t < ng; ++t) {
@@ -356,19 +374,19 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
       }
     } else {
       auto kof = [](const JobDev& j, uint64_t i, uint64_t p, double v) {
-        if (j.kmod_cached) return j.kmod[i];
+        if (j.kmod_cached) return (uint64_t)gbl(j.kmod)[i];
         uint64_t r = 1 % p;
-        for (uint32_t t = 0; t < j.ctrl->n_kgroups; ++t) r = mulmod(r, j.kgroups[t], p, v);
+        for (uint32_t t = 0; t < gbl(j.ctrl)->n_kgroups; ++t) r = mulmod(r, gbl(j.kgroups)[t], p, v);
         return r;
       };
       r0 = kof(j0, i0, p0, v0);
       r1 = kof(j1, i1, p1, v1);
     }
-    if (!j0.kmod_cached) j0.kmod[i0] = r0;
-    j0.mk[i0] = mulmod(mod64(j0.m_start, p0, v0), r0, p0, v0);
+    if (!j0.kmod_cached) gbl(j0.kmod)[i0] = r0;
+    gbl(j0.mk)[i0] = mulmod(mod64(j0.m_start, p0, v0), r0, p0, v0);
     if (two) {
-      if (!j1.kmod_cached) j1.kmod[i1] = r1;
-      j1.mk[i1] = mulmod(mod64(j1.m_start, p1, v1), r1, p1, v1);
+      if (!j1.kmod_cached) gbl(j1.kmod)[i1] = r1;
+      gbl(j1.mk)[i1] = mulmod(mod64(j1.m_start, p1, v1), r1, p1, v1);
     }
   }
 }
@@ -611,7 +629,7 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t p) 
 // each copy reads it through its own address space.
 struct SmallArgs {
   const JobDev& j;
-  const JobCtrl& c;
+  uint64_t small_dense;
   uint32_t* tile;
   uint32_t* cnt;
   const uint32_t* moff;
@@ -624,7 +642,6 @@ struct SmallArgs {
 __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __restrict__ ct,
                                             unsigned long long& n_pairs, unsigned long long& n_marks) {
   const JobDev& j = a.j;
-  const JobCtrl& c = a.c;
   uint32_t* tile = a.tile;
   uint32_t* cnt = a.cnt;
   const uint32_t R = a.R, rw = a.rw, w = a.w, lane = a.lane, wid = a.wid, nwaves = a.nwaves;
@@ -632,11 +649,11 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
   const bool dpat = a.dpat;
   const uint64_t sl = j.sl;
   const uint32_t P = j.P;
-  const uint64_t* __restrict__ primes = j.primes;
-  const uint64_t* __restrict__ kmod = j.kmod;
-  const uint64_t* __restrict__ mkp = j.mk;
+  const gptr<const uint64_t> primes = gbl(j.primes);
+  const gptr<const uint64_t> kmod = gbl(j.kmod);
+  const gptr<const uint64_t> mkp = gbl(j.mk);
   // dense primes: one wave per prime, lanes stride over its multiples in each row
-  const uint64_t d_hi = min(s_hi, max(c.small_dense, s_lo));
+  const uint64_t d_hi = min(s_hi, max(a.small_dense, s_lo));
   for (uint64_t i = s_lo + wid; i < d_hi; i += nwaves) {
     const uint64_t p = primes[i];
     const uint64_t k = kmod[i];
@@ -667,7 +684,7 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
     }
   }
   // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
-  const uint64_t sp_lo = max(s_lo, min(c.small_dense, s_hi));
+  const uint64_t sp_lo = max(s_lo, min(a.small_dense, s_hi));
   for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
     const uint64_t i = ib + threadIdx.x;
     bool act = i < s_hi;
@@ -725,7 +742,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
   for (uint64_t unit = blockIdx.x; unit < total_units; unit += gridDim.x) {
     while (ji + 1 < n_jobs && jobs[ji + 1].small_unit_base <= unit) ++ji;
     const JobDev& j = jobs[ji];
-    const JobCtrl& c = *j.ctrl;
+    const auto& c = *gbl(j.ctrl);
     const uint64_t local = unit - j.small_unit_base;
     const uint64_t window = local / j.n_slices;
     const uint32_t slice = (uint32_t)(local % j.n_slices);
@@ -746,11 +763,11 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
     uint32_t* cnt = tile + (uint32_t)j.tile_rows * rw;
     uint32_t* moff = cnt + j.tile_rows;            // m - m_start of the tile's rows
     if (ct_in_lds)
-      for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = j.coltab[i];
+      for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = ((const uint2*)gbl(j.coltab))[i];
     for (uint32_t i = threadIdx.x; i < R * rw; i += blockDim.x) tile[i] = 0;
     for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) {
       cnt[i] = 0;
-      moff[i] = j.m_off[row_lo + i];
+      moff[i] = gbl(j.m_off)[row_lo + i];
     }
     __syncthreads();
     const bool dpat = j.dpat_apply != 0;
@@ -758,14 +775,14 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
       // primes dividing d: the row of this m's residue class (tile rows start cleared)
       const double dd = (double)j.d;
       for (uint32_t r = 0; r < R; ++r) {
-        const double x = (double)j.r0_d + (double)j.m_off[row_lo + r];
+        const double x = (double)j.r0_d + (double)moff[r];
         double rr = fma(-floor(x * j.inv_d), dd, x);
         rr = rr < 0.0 ? rr + dd : (rr >= dd ? rr - dd : rr);
-        const uint32_t cls = j.dpre[(uint32_t)rr] & 0x7fffu;
-        const uint32_t* src = j.dpat + (uint64_t)cls * rw;
+        const uint32_t cls = gbl(j.dpre)[(uint32_t)rr] & 0x7fffu;
+        const gptr<const uint32_t> src = gbl(j.dpat) + (uint64_t)cls * rw;
         for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) tile[r * rw + u] = src[u];
         if (threadIdx.x == 0) {
-          const uint32_t pc = j.dpat_cnt[cls];
+          const uint32_t pc = gbl(j.dpat_cnt)[cls];
           cnt[r] = pc;
           n_marks += pc;
         }
@@ -774,26 +791,26 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
     }
 
     {
-      SmallArgs a{j, c, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
+      SmallArgs a{j, c.small_dense, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
       if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
-      else small_marks(a, j.coltab, n_pairs, n_marks);         // global column table
+      else small_marks(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
     }
     __syncthreads();
     // write the tile: rows of this unit belong to it alone unless the primes are sliced
     for (uint32_t r = 0; r < R; ++r) {
-      uint32_t* dst = j.bitmap + (row_lo + r) * (uint64_t)rw;
+      const gptr<uint32_t> dst = gbl(j.bitmap) + (row_lo + r) * (uint64_t)rw;
       for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) {
         const uint32_t v = tile[r * rw + u];
         if (!v) continue;
         if (j.n_slices == 1) dst[u] |= v;
-        else atomicOr(&dst[u], v);
+        else atomicOr((uint32_t*)(dst + u), v);
       }
     }
     for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
       const uint32_t v = cnt[r];
       if (!v) continue;
-      if (j.n_slices == 1) j.counts[row_lo + r] += v;
-      else atomicAdd(&j.counts[row_lo + r], v);
+      if (j.n_slices == 1) gbl(j.counts)[row_lo + r] += v;
+      else atomicAdd((uint32_t*)(gbl(j.counts) + row_lo + r), v);
     }
     __syncthreads();
   }
@@ -807,7 +824,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
   if (threadIdx.x < 2 && n_jobs > 0) {
     unsigned long long v = 0;
     for (uint32_t i = 0; i < nwaves; ++i) v += s_cnt[threadIdx.x][i];
-    if (v) atomicAdd(&jobs[0].ctrl->diag[threadIdx.x == 0 ? D_SMALL_PAIRS : D_SMALL_MARKS], v);
+    if (v) atomicAdd((unsigned long long*)(gbl(jobs[0].ctrl->diag) + (threadIdx.x == 0 ? D_SMALL_PAIRS : D_SMALL_MARKS)), v);
   }
 }
 
@@ -845,6 +862,11 @@ struct LargeTables {
   const uint2* ct;
   const uint16_t* dp;
 };
+template <>
+struct LargeTables<false> {
+  gptr<const uint2> ct;
+  gptr<const uint16_t> dp;
+};
 
 // Large-hit scatter variants (template argument kSc): 0 = atomic OR into the bitmap and atomic add
 // into the row's count; 1 = one atomic add into a byte counter per (row, column), folded into the
@@ -867,26 +889,26 @@ __device__ __forceinline__ uint64_t div_small(uint64_t a, uint64_t b) {
 // (bitmap, counts, list cells) could alias a JobDev in global memory as far as the compiler knows,
 // so reading these through the JobDev inside the walking loop reloads them at every step.
 struct HitCtx {
-  const int32_t* row_of;
-  uint32_t* bitmap;
-  uint32_t* counts;
-  uint8_t* hitbytes;
-  uint32_t* list_pool;
-  uint32_t* list_fill;
-  unsigned long long* list_cursor;
+  gptr<const int32_t> row_of;
+  gptr<uint32_t> bitmap;
+  gptr<uint32_t> counts;
+  gptr<uint8_t> hitbytes;
+  gptr<uint32_t> list_pool;
+  gptr<uint32_t> list_fill;
+  gptr<unsigned long long> list_cursor;
   uint64_t list_chunks;
   uint32_t d_small, phi_d, pre_r0, row_words, cell_shift;
 };
 
 __device__ __forceinline__ HitCtx hit_ctx(const JobDev& j) {
   HitCtx h;
-  h.row_of = j.row_of;
-  h.bitmap = j.bitmap;
-  h.counts = j.counts;
-  h.hitbytes = j.hitbytes;
-  h.list_pool = j.list_pool;
-  h.list_fill = j.list_fill;
-  h.list_cursor = j.list_cursor;
+  h.row_of = gbl(j.row_of);
+  h.bitmap = gbl(j.bitmap);
+  h.counts = gbl(j.counts);
+  h.hitbytes = gbl(j.hitbytes);
+  h.list_pool = gbl(j.list_pool);
+  h.list_fill = gbl(j.list_fill);
+  h.list_cursor = gbl(j.list_cursor);
   h.list_chunks = j.list_chunks;
   h.d_small = j.d_small;
   h.phi_d = j.phi_d;
@@ -923,7 +945,7 @@ __device__ __forceinline__ void list_step(const HitCtx& j, ListReg& lr, bool ok,
     uint32_t nc = kPoolFull;
     if (lane == leader) {
       if (chunk != kNoChunk) j.list_fill[chunk] = fill;
-      const unsigned long long c = atomicAdd(j.list_cursor, 1ull);
+      const unsigned long long c = atomicAdd((unsigned long long*)j.list_cursor, 1ull);
       if (c < j.list_chunks) nc = (uint32_t)c;
     }
     chunk = __builtin_amdgcn_readlane(nc, leader);
@@ -933,8 +955,8 @@ __device__ __forceinline__ void list_step(const HitCtx& j, ListReg& lr, bool ok,
     if (chunk != kPoolFull) {
       j.list_pool[(uint64_t)chunk * kListChunk + fill + rank] = cell;
     } else {
-      atomicOr(&j.bitmap[row * j.row_words + (col >> 5)], 1u << (col & 31));
-      atomicAdd(&j.counts[row], 1u);
+      atomicOr((uint32_t*)(j.bitmap + row * j.row_words + (col >> 5)), 1u << (col & 31));
+      atomicAdd((uint32_t*)(j.counts + row), 1u);
     }
   }
   lr.chunk = chunk;
@@ -988,11 +1010,11 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
   uint32_t col;
   if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
   if constexpr (kSc == 1) {
-    uint32_t* cell = reinterpret_cast<uint32_t*>(j.hitbytes + (uint64_t)row * (j.row_words * 32u) + (col & ~3u));
-    atomicAdd(cell, 1u << (8 * (col & 3u)));
+    gptr<uint32_t> cell = (gptr<uint32_t>)(j.hitbytes + (uint64_t)row * (j.row_words * 32u) + (col & ~3u));
+    atomicAdd((uint32_t*)cell, 1u << (8 * (col & 3u)));
   } else {
-    atomicOr(&j.bitmap[(uint64_t)row * j.row_words + (col >> 5)], 1u << (col & 31));
-    atomicAdd(&j.counts[row], 1u);
+    atomicOr((uint32_t*)(j.bitmap + (uint64_t)row * j.row_words + (col >> 5)), 1u << (col & 31));
+    atomicAdd((uint32_t*)(j.counts + row), 1u);
   }
   ++useful;
 }
@@ -1020,8 +1042,8 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const JobDev& j0 = jobs[0];
     uint2* ctl = reinterpret_cast<uint2*>(lds);
     uint16_t* dpl = reinterpret_cast<uint16_t*>(lds + 2 * lds_ct_words);
-    for (uint32_t i = threadIdx.x; i < lds_ct_words; i += blockDim.x) ctl[i] = j0.coltab[i];
-    for (uint32_t i = threadIdx.x; i < dpre_n; i += blockDim.x) dpl[i] = j0.dpre[i];
+    for (uint32_t i = threadIdx.x; i < lds_ct_words; i += blockDim.x) ctl[i] = ((const uint2*)gbl(j0.coltab))[i];
+    for (uint32_t i = threadIdx.x; i < dpre_n; i += blockDim.x) dpl[i] = gbl(j0.dpre)[i];
     __syncthreads();
     T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
@@ -1040,10 +1062,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     }
     const JobDev& j = jobs[kLds ? 0 : ji];          // the LDS variant runs one job: uniform fields
     if constexpr (!kLds) {
-      T.ct = j.coltab;
-      T.dp = j.dpre;
+      T.ct = gbl(j.coltab);
+      T.dp = gbl(j.dpre);
     }
-    const JobCtrl& c = *j.ctrl;
+    const auto& c = *gbl(j.ctrl);
     const uint64_t local = item - job_item_base[ji];
     uint32_t t = ji == ji_last ? t_last : 0u;
     while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
@@ -1074,8 +1096,8 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     const uint64_t o_hi = min(o_lo + L, j.m_inc);
     if (o_lo >= o_hi) break;
 
-    const uint64_t p = j.primes[pi];
-    const uint64_t k = j.kmod[pi];
+    const uint64_t p = gbl(j.primes)[pi];
+    const uint64_t k = gbl(j.kmod)[pi];
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
     const uint32_t d32 = (uint32_t)j.d;
@@ -1092,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       break;
     }
     // residue of m*K + SL at m = m_start + o_lo
-    uint64_t r = j.mk[pi] + mulmod(o_lo, k, p, pinv);
+    uint64_t r = gbl(j.mk)[pi] + mulmod(o_lo, k, p, pinv);
     r = r >= p ? r - p : r;
     r += j.sl;                                       // sl < w < thr < p
     r = r >= p ? r - p : r;
@@ -1211,8 +1233,8 @@ __global__ __launch_bounds__(256) void k_fold_bytes(const JobDev* __restrict__ j
   const uint32_t waves = blockDim.x / kWave;
   for (uint64_t row = blockIdx.x * (uint64_t)waves + threadIdx.x / kWave; row < j.n_m;
        row += (uint64_t)gridDim.x * waves) {
-    uint4* __restrict__ src = reinterpret_cast<uint4*>(j.hitbytes + row * j.row_words * 32ull);
-    uint32_t* __restrict__ dst = j.bitmap + row * j.row_words;
+    uint4* __restrict__ src = (uint4*)(gbl(j.hitbytes) + row * j.row_words * 32ull);
+    const gptr<uint32_t> dst = gbl(j.bitmap) + row * j.row_words;
     unsigned long long sum = 0;
     for (uint32_t wi = lane; wi < j.row_words; wi += kWave) {
       const uint4 a = src[2 * wi], b = src[2 * wi + 1];
@@ -1234,7 +1256,7 @@ __global__ __launch_bounds__(256) void k_fold_bytes(const JobDev* __restrict__ j
       sum += s;
     }
     sum = wave_sum_u64(sum);
-    if (lane == 0 && sum) j.counts[row] += (uint32_t)sum;
+    if (lane == 0 && sum) gbl(j.counts)[row] += (uint32_t)sum;
   }
 }
 
@@ -1243,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_zero_bytes(const JobDev* __restrict__ j
   const JobDev& j = jobs[blockIdx.y];
   if (!j.hitbytes) return;
   const uint64_t n = j.n_m * (uint64_t)j.row_words * 8;
-  uint32_t* __restrict__ p = reinterpret_cast<uint32_t*>(j.hitbytes);
+  const gptr<uint32_t> p = (gptr<uint32_t>)gbl(j.hitbytes);
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0;
 }

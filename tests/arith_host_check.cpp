@@ -18,6 +18,36 @@ static bool is_prime(uint64_t n) {
   return true;
 }
 
+static uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  for (; e; e >>= 1, b = (uint64_t)((u128)b * b % m))
+    if (e & 1) r = (uint64_t)((u128)r * b % m);
+  return r;
+}
+
+// deterministic Miller-Rabin for 64-bit n (the first twelve prime bases)
+static bool is_prime_mr(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t q : bases)
+    if (n % q == 0) return n == q;
+  uint64_t d = n - 1;
+  int s = 0;
+  while (!(d & 1)) { d >>= 1; ++s; }
+  for (uint64_t a : bases) {
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s && comp; ++r) {
+      x = (uint64_t)((u128)x * x % n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
 static uint64_t brute_G(uint64_t p, uint64_t K, uint64_t L, uint64_t R) {
   for (uint64_t m = 0; m < p; ++m) {
     uint64_t v = (uint64_t)((u128)m * K % p);
@@ -151,6 +181,54 @@ int main(int argc, char** argv) {
       }
       if (ta != g1.ta || tb != g1.tb) { bad = fail("euclid_brute", p, k, w, ta); break; }
     }
+  }
+  // the same at the sizes of the sieve (primes up to 2^40, windows up to 2^18 - 2), where the
+  // Euclidean pass finishes in fp32: inverse exact, constants equal to the G-based setup
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t w = 1 + rng() % (i % 3 == 0 ? 40000 : (1u << 18) - 2);
+    uint64_t p;
+    do { p = 2 * w + 1 + (rng() >> (24 + rng() % 26)); } while (p >= (1ull << 40) || !is_prime_mr(p));
+    uint64_t k = 1 + rng() % (p - 1);
+    if (i % 13 == 0) k = 1 + rng() % 5;
+    if (i % 17 == 0) k = p - 1 - rng() % 5;
+    cs::gaps3 g1, g2;
+    uint64_t kinv = 0;
+    if (!cs::three_gap_euclid(p, k, w, &g1, &kinv, nullptr)) { bad = fail("euclid_big", p, k, w, 0); break; }
+    if ((uint64_t)((u128)kinv * k % p) != 1) { bad = fail("euclid_big_inv", p, k, kinv, 0); break; }
+    const uint64_t inv2 = cs::modinv(k, p);
+    if ((uint64_t)((u128)inv2 * k % p) != 1) { bad = fail("modinv_big", p, k, inv2, 0); break; }
+    double pinv = 1.0 / (double)p;
+    int lv;
+    if (!cs::three_gap_setup(p, k, inv2, pinv, w, &g2, &lv)) { bad = fail("setup_big", p, k, w, 0); break; }
+    if (g1.ta != g2.ta || g1.a != g2.a || g1.tb != g2.tb || g1.b != g2.b) { bad = fail("euclid_vs_g_big", p, k, w, g1.ta); break; }
+  }
+  // the fp32 tail alone on every pair below 2^11 and on random pairs below 2^20 (gcd and Bezout)
+  for (uint64_t a = 1; a < 2048 && !bad; ++a)
+    for (uint64_t b = 0; b <= a && !bad; ++b) {
+      double x = (double)a, y = (double)b, s0 = 0.0, s1 = 1.0;
+      cs::euclid_tail_f32(&x, &y, &s0, &s1);
+      uint64_t g = a, h = b;
+      while (h) { uint64_t t = g % h; g = h; h = t; }
+      if ((uint64_t)x != g) bad = fail("tail_gcd", a, b, (uint64_t)x, g);
+    }
+  for (int i = 0; i < 200000 && !bad; ++i) {
+    // random pairs below 2^20; the coefficients follow the same recurrence as the Bezout pair
+    // (u, v) of the integer Euclidean algorithm: s_final = u*s_a + v*s_b, gcd = u*a + v*b
+    const uint64_t a = 1 + rng() % ((1u << 20) - 1), b = rng() % (a + 1);
+    const int64_t ca = (int64_t)(rng() % (1u << 20)) - (1 << 19), cb = (int64_t)(rng() % (1u << 20)) - (1 << 19);
+    int64_t u0 = 1, v0 = 0, u1 = 0, v1 = 1;
+    uint64_t g = a, h = b;
+    while (h) {
+      const int64_t q = (int64_t)(g / h);
+      const uint64_t t = g - (uint64_t)q * h;
+      g = h; h = t;
+      const int64_t u2 = u0 - q * u1, v2 = v0 - q * v1;
+      u0 = u1; v0 = v1; u1 = u2; v1 = v2;
+    }
+    double x = (double)a, y = (double)b, s0 = (double)ca, s1 = (double)cb;
+    cs::euclid_tail_f32(&x, &y, &s0, &s1);
+    if ((uint64_t)x != g || y != 0.0) { bad = fail("tail_gcd_rand", a, b, (uint64_t)x, g); break; }
+    if ((int64_t)s0 != u0 * ca + v0 * cb) { bad = fail("tail_bezout", a, b, (uint64_t)s0, 0); break; }
   }
   if (!bad) std::printf("OK\n");
   return bad;
