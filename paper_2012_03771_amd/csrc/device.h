@@ -12,6 +12,7 @@ constexpr uint32_t kSegBits = 1u << (kSegLog - 1);
 constexpr uint32_t kSegWords = kSegBits / 32;
 constexpr int kWave = 64;
 constexpr uint64_t kGroupMax = 1ull << 50;   // K-prime products stay below 2^50 (mulmod bound)
+constexpr uint32_t kKmodLdsGroups = 2048;     // K groups staged in LDS by the K mod p kernel (16 KB)
 constexpr uint32_t kDSmall = 4096;            // d <= kDSmall: m -> row from a residue table of d entries
 
 // Counters in cs_diag order.

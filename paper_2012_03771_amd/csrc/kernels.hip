@@ -350,6 +350,14 @@ __device__ __forceinline__ const JobDev& job_of_index(const JobDev* __restrict__
 // thread takes two indices and interleaves their multiplication chains.
 __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                               const uint64_t* __restrict__ lim_base) {
+  // a single job's K groups as doubles in LDS: the product chain below then reads no memory
+  __shared__ double s_g[kKmodLdsGroups];
+  const uint32_t ng_lds = n_jobs == 1 && !jobs[0].kmod_cached ? gbl(jobs[0].ctrl)->n_kgroups : 0u;
+  const bool g_lds = ng_lds > 0 && ng_lds <= kKmodLdsGroups;
+  if (g_lds) {
+    for (uint32_t i = threadIdx.x; i < ng_lds; i += blockDim.x) s_g[i] = (double)gbl(jobs[0].kgroups)[i];
+    __syncthreads();
+  }
   const uint64_t total = lim_base[n_jobs];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g0 < total; g0 += 2 * stride) {
@@ -363,15 +371,26 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
     const double v0 = 1.0 / (double)p0, v1 = 1.0 / (double)p1;
     uint64_t r0, r1;
     if (&j0 == &j1 && !j0.kmod_cached) {
+      // Eq. 1: the product of K's prime groups (each below 2^50) mod p, all in fp64
       const uint32_t ng = gbl(j0.ctrl)->n_kgroups;
       const gptr<const uint64_t> G = gbl(j0.kgroups);
-      r0 = 1 % p0;
-      r1 = 1 % p1;
-      for (uint32_t t = 0; t < ng; ++t) {
-        const uint64_t gg = G[t];
-        r0 = mulmod(r0, gg, p0, v0);
-        r1 = mulmod(r1, gg, p1, v1);
+      const double pd0 = (double)p0, pd1 = (double)p1;
+      double x0 = p0 == 1 ? 0.0 : 1.0, x1 = p1 == 1 ? 0.0 : 1.0;
+      if (g_lds) {
+        for (uint32_t t = 0; t < ng; ++t) {
+          const double gg = s_g[t];
+          x0 = mulmod_f64(x0, gg, pd0, v0);
+          x1 = mulmod_f64(x1, gg, pd1, v1);
+        }
+      } else {
+        for (uint32_t t = 0; t < ng; ++t) {
+          const double gg = (double)G[t];
+          x0 = mulmod_f64(x0, gg, pd0, v0);
+          x1 = mulmod_f64(x1, gg, pd1, v1);
+        }
       }
+      r0 = (uint64_t)x0;
+      r1 = (uint64_t)x1;
     } else {
       auto kof = [](const JobDev& j, uint64_t i, uint64_t p, double v) {
         if (j.kmod_cached) return (uint64_t)gbl(j.kmod)[i];

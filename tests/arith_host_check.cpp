@@ -80,6 +80,19 @@ int main(int argc, char** argv) {
     uint64_t o = rng() & 0xffffffffull;
     if (cs::mulmod(o, a, p, pinv) != (uint64_t)((u128)o * a % p)) bad = fail("mulmod_o", o, a, p, 0);
   }
+  // fp64-only modular product for the K mod p chain: r < p < 2^40, g < 2^50
+  for (int i = 0; i < 400000 && !bad; ++i) {
+    uint64_t p = (rng() >> (24 + rng() % 40)) | 1;
+    if (p >= (1ull << 40)) p &= (1ull << 40) - 1;
+    if (p < 3) p = 3;
+    const uint64_t r = (i % 5 == 0) ? p - 1 - rng() % std::min<uint64_t>(p, 3) : rng() % p;
+    uint64_t g = (rng() >> (14 + rng() % 50)) | 1;
+    if (g >= (1ull << 50)) g &= (1ull << 50) - 1;
+    if (i % 7 == 0) g = (1ull << 50) - 1 - rng() % 1000;
+    const double pinv = 1.0 / (double)p;
+    const double got = cs::mulmod_f64((double)r, (double)g, (double)p, pinv);
+    if ((uint64_t)got != (uint64_t)((u128)r * g % p) || got < 0.0) { bad = fail("mulmod_f64", r, g, p, (uint64_t)got); break; }
+  }
   for (int i = 0; i < 20000 && !bad; ++i) {
     uint64_t p;
     do { p = (rng() >> (24 + rng() % 30)) | 1; } while (!is_prime(p));
