@@ -128,13 +128,15 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
 
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 5 M / M_c (half the paper's 10 M / M_c, measured faster on gfx950); with three-gap stepping
-  // a hit costs a few operations, so the paper's naive 10 S is used.  Clamped so that a large
-  // prime divides at most one number of an interval (p > 2 sl), or (three-gap) p > 4 sl.
+  // a hit costs a few operations and the small branch runs beside the large one, so twice the
+  // paper's naive 10 S is used (measured at 953#/210: step 113 ms at 10 S, 108 ms at 20 S,
+  // 124 ms at 30 S).  Clamped so that a large prime divides at most one number of an interval
+  // (p > 2 sl), or (three-gap) p > 4 sl.
   uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
   uint64_t thr = tune && tune->thr ? tune->thr : 0;
   if (!thr) {
-    double cm = mode == CS_LARGE_THREE_GAP ? 10.0
+    double cm = mode == CS_LARGE_THREE_GAP ? 20.0
                                            : (pl.n_m ? 5.0 * (double)j.m_inc / (double)pl.n_m : 5.0);
     thr = (uint64_t)(cm * (double)pl.S);
   }
