@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -53,7 +54,95 @@ def _args():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (a known-size reference for "
                          "HBM byte counters)")
+    ap.add_argument("--mc-curve", action="store_true",
+                    help="instead of the step benchmark: speedup of the combined sieve over a per-interval "
+                         "sieve against the number of intervals M_c (K = 1511#/7#, X = 18,000)")
+    ap.add_argument("--curve-limit", type=int, default=10**11)
+    ap.add_argument("--curve-mc", default="1,10,100,1000,10000,100000,1000000")
     return ap.parse_args()
+
+
+def _mc_curve(cs, torch, W, np, args):
+    """Speedup of the Combined Sieve over sieving each interval on its own, against M_c, on the
+    configuration of the paper's speedup figure (Section 3: K = 1511#/7#, X = 18,000,
+    P_limit = 1e11).  The per-interval sieve is this library on a job of one interval with every
+    prime below the threshold: K mod p is taken for every prime and every multiple is marked from
+    the residue, which is the traditional sieve's work for one interval.  The prime table is a
+    one-time cost shared by any number of intervals in both methods and is left out of both
+    times.  speedup(M_c) = M_c * T(one interval) / T(M_c intervals)."""
+    P, d, sl, limit = 1511, 210, 18000, args.curve_limit
+    mcs = [int(x) for x in args.curve_mc.split(",")]
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    tp = timed(lambda: cs.primes(limit, s))
+    torch.cuda.empty_cache()
+    print(f"# curve: prime table to {limit:.3g} {tp * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    def m_inc_for(mc):      # smallest M with mc multipliers in [1, M] coprime to d
+        phi = sum(1 for r in range(d) if math.gcd(r, d) == 1)
+        M = (mc // phi) * d
+        c = (mc // phi) * phi
+        while c < mc:
+            M += 1
+            if math.gcd(M, d) == 1:
+                c += 1
+        return max(M, 1)
+
+    def run(job, tune):
+        lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
+        t = timed(lambda: cs.sieve_into(job, bitmap, counts, ws, tune, s))
+        return t, lay, bitmap, counts, ws
+
+    # one interval, every prime in the per-interval (small) branch
+    one = W.Job(P, d, 1, 1, sl, limit)
+    t1, lay1, *_ = run(one, cs.Tune(thr=limit))
+    torch.cuda.empty_cache()
+    per_interval = t1 - tp
+    print(f"# curve: one interval {t1 * 1e3:.1f} ms ({per_interval * 1e3:.1f} ms without the prime table)",
+          file=sys.stderr, flush=True)
+    points = []
+    check = None
+    for mc in mcs:
+        job = W.Job(P, d, 1, m_inc_for(mc), sl, limit)
+        t, lay, bitmap, counts, ws = run(job, cs.Tune(large_mode=cs.LARGE_THREE_GAP))
+        comb = t - tp
+        pt = {"m_c": lay.n_m, "m_inc": job.m_inc, "ms": t * 1e3, "ms_without_primes": comb * 1e3,
+              "speedup": lay.n_m * per_interval / comb, "factors": int(counts.to(torch.int64).sum().item())}
+        points.append(pt)
+        print(f"# curve: M_c {lay.n_m} {t * 1e3:.1f} ms speedup {pt['speedup']:.0f}", file=sys.stderr, flush=True)
+        want = None
+        if check is None and lay.n_m >= 1000:
+            ms = cs.rows(job)
+            idx = [0, lay.n_m // 2, lay.n_m - 1]
+            want = ([int(ms[i]) for i in idx], bitmap[idx].cpu(), counts[idx].cpu())
+        del bitmap, counts, ws
+        torch.cuda.empty_cache()
+        if want is not None:
+            # the two enumerations agree bit for bit: sampled rows against one-interval runs of their m
+            ok = True
+            for k, m in enumerate(want[0]):
+                o = W.Job(P, d, m, 1, sl, limit)
+                b1, c1, w1 = cs.sieve(o, cs.Tune(thr=limit), s)
+                ok = ok and torch.equal(b1.cpu()[0], want[1][k]) and int(c1[0].item()) == int(want[2][k].item())
+                del b1, c1, w1
+                torch.cuda.empty_cache()
+            check = {"m_c": lay.n_m, "rows": want[0], "identical": ok}
+    return {"metric": "combined-sieve speedup over a per-interval sieve", "unit": "x", "n_gpus": 1,
+            "config": {"workload": "1511#/7#, X = 18000, m_start = 1", "P": P, "d": d, "sl": sl, "limit": limit},
+            "prime_table_ms": tp * 1e3, "one_interval_ms": t1 * 1e3, "per_interval_ms": per_interval * 1e3,
+            "points": points, "rows_checked": check}
 
 
 def _cpu_baseline(job, n_rows, p_max):
@@ -249,6 +338,10 @@ def main():
     import workloads as W
     import paper_2012_03771_amd as cs
 
+    if args.mc_curve:
+        torch.cuda.set_device(0)
+        print(json.dumps(_mc_curve(cs, torch, W, np, args)), flush=True)
+        return
     job = W.SINGLE_JOBS[args.workload]
     tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP)
     torch.cuda.set_device(0)

@@ -1048,18 +1048,24 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
     if (ok) ++useful;
     return;
   }
+  // Both table reads are issued before either test, and the two tests (m coprime to d,
+  // Section 3.2; X coprime to K) are one condition: one LDS round trip and one branch per step.
+  const uint64_t ce = ct_entry(T.ct, jj >> 5);
   uint32_t row;                                     // rows < m_inc < 2^32
+  bool ok;
   if (j.d_small) {
     const uint32_t e = T.dp[mp.rd];
-    if (!(e >> 15)) return;                         // m shares a factor with d (Section 3.2)
+    ok = (e >> 15) != 0;
     row = j.phi_d * mp.dq + (e & 0x7fffu) - j.pre_r0;
   } else {
     const int32_t r = j.row_of[o];
-    if (r < 0) return;
+    ok = r >= 0;
     row = (uint32_t)r;
   }
-  uint32_t col;
-  if (!lookup_col(T.ct, jj, &col)) return;          // X shares a factor with K
+  const uint32_t mask = (uint32_t)ce, b = jj & 31;
+  ok = ok && ((mask >> b) & 1u);
+  if (!ok) return;
+  const uint32_t col = (uint32_t)(ce >> 32) + __popc(mask & ((1u << b) - 1u));
   if constexpr (kSc == 1) {
     gptr<uint32_t> cell = (gptr<uint32_t>)(j.hitbytes + (uint64_t)row * (j.row_words * 32u) + (col & ~3u));
     atomicAdd((uint32_t*)cell, 1u << (8 * (col & 3u)));

@@ -153,7 +153,9 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   pl.lds_ct_words = ct_lds ? pl.ct_words : 0;
   pl.lds_bytes = ct_bytes + 4u * rows * pl.row_words + 8u * rows;   // tile, counts, m offsets
   const double est_small = (double)pl.thr / std::max(1.0, log((double)pl.thr));
-  uint32_t max_slices = (uint32_t)std::max(1.0, std::min(64.0, est_small / 512.0));
+  // prime slices per row window (at least 512 primes each) so that a job of few windows still
+  // fills the GPU: up to 4 workgroups per CU in all
+  uint32_t max_slices = (uint32_t)std::max(1.0, std::min(4096.0, est_small / 512.0));
   uint32_t slices = pl.n_windows ? (uint32_t)((4u * (uint32_t)n_cu + pl.n_windows - 1) / pl.n_windows) : 1;
   slices = std::max(1u, std::min(slices, max_slices));
   if (tune && tune->small_slices) slices = std::min(tune->small_slices, 256u);
