@@ -57,9 +57,42 @@ def _args():
     ap.add_argument("--mc-curve", action="store_true",
                     help="instead of the step benchmark: speedup of the combined sieve over a per-interval "
                          "sieve against the number of intervals M_c (K = 1511#/7#, X = 18,000)")
+    ap.add_argument("--table-a2", action="store_true",
+                    help="instead of the step benchmark: the first configuration of the paper's amortized "
+                         "runtime table (1511#/(7#*1009), X = 16,000, M = 1e7, primes to 1e11)")
     ap.add_argument("--curve-limit", type=int, default=10**11)
     ap.add_argument("--curve-mc", default="1,10,100,1000,10000,100000,1000000")
     return ap.parse_args()
+
+
+def _table_a2(cs, torch, W):
+    """The first row of the paper's amortized-runtime table (Appendix, Table A.2): K = 1511#/d with
+    d = 7#*1009 (a large prime factor: rows come from the dense m -> row table), X = 16,000,
+    M = 1e7 multipliers from m = 1, primes to 1e11.  One cs_sieve call timed after a warm-up;
+    the paper's figure for the same configuration is 0.0112 s of sieving per coprime m on a CPU
+    whose type it does not state."""
+    job = W.Job(1511, 2 * 3 * 5 * 7 * 1009, 1, 10**7, 16000, 10**11)
+    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
+    s = torch.cuda.current_stream()
+    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
+    print(f"# table A.2: rows {lay.n_m} cols {lay.n_x} ws {lay.ws_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    cs.sieve_into(job, bitmap, counts, ws, tune, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cs.sieve_into(job, bitmap, counts, ws, tune, s)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    factors = int(counts.to(torch.int64).sum().item())
+    d = cs.diag_read(ws, s)
+    out = {"metric": "sieve time per coprime m", "value": t / lay.n_m, "unit": "s", "n_gpus": 1,
+           "config": {"workload": "1511#/(7#*1009), X = 16000, M = 1e7, m from 1, primes to 1e11",
+                      "P": job.P, "d": job.d, "m_start": job.m_start, "m_inc": job.m_inc, "sl": job.sl,
+                      "limit": job.limit, "rows": lay.n_m, "cols": lay.n_x, "thr": lay.thr},
+           "total_s": t, "factors": factors, "factors_per_s": factors / t, "n_primes": d.n_primes,
+           "primes_per_s": d.n_primes / t, "paper_s_per_m": 0.0112, "paper_hardware": "not stated (CPU)"}
+    del bitmap, counts, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def _mc_curve(cs, torch, W, np, args):
@@ -341,6 +374,10 @@ def main():
     if args.mc_curve:
         torch.cuda.set_device(0)
         print(json.dumps(_mc_curve(cs, torch, W, np, args)), flush=True)
+        return
+    if args.table_a2:
+        torch.cuda.set_device(0)
+        print(json.dumps(_table_a2(cs, torch, W)), flush=True)
         return
     job = W.SINGLE_JOBS[args.workload]
     tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP)

@@ -99,7 +99,10 @@ def test_tiny_jobs(job):
 
 MIXED = [W.Job(61, 6, 1000, 3000, 500, 10**6), W.Job(97, 30, 10**6, 20000, 1200, 5 * 10**6),
          W.Job(131, 1, 7, 5000, 900, 2 * 10**6), W.Job(307, 2, 12345, 4000, 2500, 10**7),
-         W.Job(401, 210, 99, 30000, 3000, 10**7)]
+         W.Job(401, 210, 99, 30000, 3000, 10**7),
+         # d with a large prime factor (the form of the paper's amortized-runtime table, d = 7#*q):
+         # rows come from the dense m -> row table rather than the d-residue table
+         W.Job(211, 2 * 3 * 5 * 7 * 101, 1, 6000, 2000, 10**6), W.Job(409, 2 * 3 * 5 * 7 * 401, 777, 20000, 1500, 3 * 10**6)]
 
 
 @pytest.mark.parametrize("job", MIXED, ids=lambda j: "P%d_d%d_m%d+%d_sl%d_L%d" % j.as_tuple())
