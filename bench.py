@@ -58,41 +58,69 @@ def _args():
                     help="instead of the step benchmark: speedup of the combined sieve over a per-interval "
                          "sieve against the number of intervals M_c (K = 1511#/7#, X = 18,000)")
     ap.add_argument("--table-a2", action="store_true",
-                    help="instead of the step benchmark: the first configuration of the paper's amortized "
-                         "runtime table (1511#/(7#*1009), X = 16,000, M = 1e7, primes to 1e11)")
+                    help="instead of the step benchmark: configurations of the paper's amortized runtime "
+                         "table (row 10: 1511#/(7#*1009), X = 16,000, M = 1e7, primes to 1e11)")
+    ap.add_argument("--a2-rows", default="10", help="rows of that table: any of 10, 11, 12, 15")
     ap.add_argument("--curve-limit", type=int, default=10**11)
     ap.add_argument("--curve-mc", default="1,10,100,1000,10000,100000,1000000")
     return ap.parse_args()
 
 
-def _table_a2(cs, torch, W):
-    """The first row of the paper's amortized-runtime table (Appendix, Table A.2): K = 1511#/d with
-    d = 7#*1009 (a large prime factor: rows come from the dense m -> row table), X = 16,000,
-    M = 1e7 multipliers from m = 1, primes to 1e11.  One cs_sieve call timed after a warm-up;
-    the paper's figure for the same configuration is 0.0112 s of sieving per coprime m on a CPU
-    whose type it does not state."""
-    job = W.Job(1511, 2 * 3 * 5 * 7 * 1009, 1, 10**7, 16000, 10**11)
-    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
-    s = torch.cuda.current_stream()
-    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
-    print(f"# table A.2: rows {lay.n_m} cols {lay.n_x} ws {lay.ws_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
-    cs.sieve_into(job, bitmap, counts, ws, tune, s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cs.sieve_into(job, bitmap, counts, ws, tune, s)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    factors = int(counts.to(torch.int64).sum().item())
-    d = cs.diag_read(ws, s)
-    out = {"metric": "sieve time per coprime m", "value": t / lay.n_m, "unit": "s", "n_gpus": 1,
-           "config": {"workload": "1511#/(7#*1009), X = 16000, M = 1e7, m from 1, primes to 1e11",
-                      "P": job.P, "d": job.d, "m_start": job.m_start, "m_inc": job.m_inc, "sl": job.sl,
-                      "limit": job.limit, "rows": lay.n_m, "cols": lay.n_x, "thr": lay.thr},
-           "total_s": t, "factors": factors, "factors_per_s": factors / t, "n_primes": d.n_primes,
-           "primes_per_s": d.n_primes / t, "paper_s_per_m": 0.0112, "paper_hardware": "not stated (CPU)"}
-    del bitmap, counts, ws
-    torch.cuda.empty_cache()
-    return out
+# The paper's amortized-runtime table (Appendix, Table A.2): (P, d, X, M, limit, seconds per coprime m).
+TABLE_A2 = {
+    10: (1511, 2 * 3 * 5 * 7 * 1009, 16000, 10**7, 10**11, 0.0112),
+    11: (1511, 2 * 3 * 5 * 7 * 1009, 16000, 10**7, 25 * 10**10, 0.0129),
+    12: (2221, 2 * 3 * 5 * 2027, 23000, 10**7, 8 * 10**11, 0.0252),
+    15: (8887, 2 * 3 * 5 * 7 * 11 * 13 * 17 * 8009, 100000, 10**5, 10**12, 0.709),
+}
+
+
+def _table_a2(cs, torch, W, rows):
+    """Rows of the paper's amortized-runtime table (Appendix, Table A.2): K = P#/d with d of a
+    large prime factor (rows come from the dense m -> row table), M multipliers from m = 1, every
+    prime up to the limit.  Where the whole prime, K mod p and m_start*K mod p tables would exceed
+    160 GiB the prime range is taken in chunks of 2^36 integers (cs_sieve_chunked).  One call
+    timed after a warm-up call.  The paper's seconds per coprime m come from a CPU whose type it
+    does not state.  Rows 13 and 14 (limit 2e12) are above this library's 2^40 range."""
+    out = []
+    for r in rows:
+        P, d, X, M, limit, paper = TABLE_A2[r]
+        job = W.Job(P, d, 1, M, X, limit)
+        tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
+        s = torch.cuda.current_stream()
+        whole = cs.plan(job, tune)
+        span = 1 << 36 if whole.ws_bytes > (160 << 30) else 0
+        lay = cs.plan_chunked(job, span, tune) if span else whole
+        print(f"# table A.2 row {r}: rows {lay.n_m} cols {lay.n_x} ws {lay.ws_bytes / 2**30:.1f} GiB"
+              f" chunks of {span or limit + 1:.3g}", file=sys.stderr, flush=True)
+        bitmap = torch.empty((lay.n_m, lay.row_words), dtype=torch.int32, device="cuda")
+        counts = torch.empty((lay.n_m,), dtype=torch.int32, device="cuda")
+        ws = torch.empty((lay.ws_bytes,), dtype=torch.uint8, device="cuda")
+
+        def run():
+            if span:
+                cs.sieve_chunked_into(job, span, bitmap, counts, ws, tune, s)
+            else:
+                cs.sieve_into(job, bitmap, counts, ws, tune, s)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        factors = int(counts.to(torch.int64).sum().item())
+        dg = cs.diag_read(ws, s)
+        out.append({"row": r, "s_per_m": t / lay.n_m, "total_s": t, "paper_s_per_m": paper,
+                    "config": {"P": P, "d": d, "sl": X, "m_start": 1, "m_inc": M, "limit": limit, "rows": lay.n_m,
+                               "cols": lay.n_x, "thr": lay.thr, "scatter": lay.scatter, "span": span},
+                    "factors": factors, "factors_per_s": factors / t, "n_primes": dg.n_primes,
+                    "primes_per_s": dg.n_primes / t})
+        print(f"# row {r}: {t:.3f} s, {t / lay.n_m * 1e6:.3f} us per m (paper {paper} s)", file=sys.stderr, flush=True)
+        del bitmap, counts, ws
+        torch.cuda.empty_cache()
+    return {"metric": "sieve time per coprime m", "unit": "s", "n_gpus": 1,
+            "workload": "rows of the paper's amortized-runtime table, m from 1",
+            "paper_hardware": "not stated (CPU)", "rows": out}
 
 
 def _mc_curve(cs, torch, W, np, args):
@@ -377,7 +405,7 @@ def main():
         return
     if args.table_a2:
         torch.cuda.set_device(0)
-        print(json.dumps(_table_a2(cs, torch, W)), flush=True)
+        print(json.dumps(_table_a2(cs, torch, W, [int(x) for x in args.a2_rows.split(",")])), flush=True)
         return
     job = W.SINGLE_JOBS[args.workload]
     tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP)

@@ -182,6 +182,20 @@ cs_status cs_sieve_range(const cs_job* job, const cs_tune* tune, uint64_t p_lo, 
                          uint32_t* d_bitmap, uint32_t* d_counts, void* d_ws, uint64_t ws_bytes,
                          void* stream);
 
+/* The whole sieve with the prime range taken in chunks of `span` integers: for each chunk
+ * [a, a + span) in turn, its primes (the segmented sieve restarted at a), their K mod p (Eq. 1),
+ * then both branches over them, exactly as cs_sieve_range with [a, a + span - 1].  Only one
+ * chunk's prime, K mod p and m_start*K mod p tables (24 bytes a prime) are held, so limits whose
+ * tables would exceed device memory fit (Section 3.1's space-time tradeoff, applied per chunk).
+ * The result is exactly cs_sieve's.  span: a multiple of 2^19, at least 2^25 and above P
+ * (CS_EINVAL otherwise); span > limit is the unchunked sieve.  d_ws: cs_plan_chunked's
+ * ws_bytes for the same span (CS_ERANGE if smaller); layout.prime_cap is then the capacity of
+ * one chunk's table (a chunk with more primes than [0, span) sets error_flags' prime-table bit,
+ * reported by cs_diag_read).  cs_diag's large_kernel_ms covers the last chunk's launch. */
+cs_status cs_plan_chunked(const cs_job* job, const cs_tune* tune, uint64_t span, cs_layout* out);
+cs_status cs_sieve_chunked(const cs_job* job, const cs_tune* tune, uint64_t span, uint32_t* d_bitmap,
+                           uint32_t* d_counts, void* d_ws, uint64_t ws_bytes, void* stream);
+
 /* Waits for `stream`, then copies the counters kept in d_ws (see cs_diag).  Returns
  * CS_EDEVICE if the stream reported an error or error_flags is nonzero. */
 cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream);

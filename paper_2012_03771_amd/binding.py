@@ -150,6 +150,8 @@ def lib():
         "cs_sieve": ([P(cs_job), P(cs_tune), vp, vp, vp, u64, vp], i32),
         "cs_prepare": ([P(cs_job), P(cs_tune), vp, u64, vp], i32),
         "cs_sieve_range": ([P(cs_job), P(cs_tune), u64, u64, vp, vp, vp, u64, vp], i32),
+        "cs_plan_chunked": ([P(cs_job), P(cs_tune), u64, P(cs_layout)], i32),
+        "cs_sieve_chunked": ([P(cs_job), P(cs_tune), u64, vp, vp, vp, u64, vp], i32),
         "cs_diag_read": ([vp, P(cs_diag), vp], i32),
         "cs_primes_ws": ([u64, P(u64), P(u64)], i32),
         "cs_primes": ([u64, vp, u64, vp, vp, u64, vp], i32),
@@ -221,6 +223,14 @@ def plan(job, tune: Tune | None = None) -> Layout:
                   out.prime_cap, out.thr, out.scatter)
 
 
+def plan_chunked(job, span: int, tune: Tune | None = None) -> Layout:
+    """Layout of cs_sieve_chunked with chunks of `span` integers of the prime range."""
+    out = cs_layout()
+    _check(lib().cs_plan_chunked(C.byref(_cjob(job)), _ctune(tune), span, C.byref(out)), "cs_plan_chunked")
+    return Layout(out.n_m, out.n_x, out.row_words, out.bitmap_bytes, out.counts_bytes, out.ws_bytes,
+                  out.prime_cap, out.thr, out.scatter)
+
+
 def columns(job):
     import numpy as np
     lay = plan(job)
@@ -256,6 +266,22 @@ def sieve(job, tune: Tune | None = None, stream=None):
     holding the uint32 words, counts int32 [n_m], workspace)."""
     lay, bitmap, counts, ws = alloc_outputs(job, tune)
     sieve_into(job, bitmap, counts, ws, tune, stream)
+    return bitmap, counts, ws
+
+
+def sieve_chunked_into(job, span: int, bitmap, counts, ws, tune: Tune | None = None, stream=None):
+    _check(lib().cs_sieve_chunked(C.byref(_cjob(job)), _ctune(tune), span, _ptr(bitmap), _ptr(counts), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "cs_sieve_chunked")
+
+
+def sieve_chunked(job, span: int, tune: Tune | None = None, stream=None):
+    """cs_sieve_chunked on freshly allocated device tensors: (bitmap, counts, workspace)."""
+    import torch
+    lay = plan_chunked(job, span, tune)
+    bitmap = torch.empty((lay.n_m, lay.row_words), dtype=torch.int32, device="cuda")
+    counts = torch.empty((lay.n_m,), dtype=torch.int32, device="cuda")
+    ws = torch.empty((lay.ws_bytes,), dtype=torch.uint8, device="cuda")
+    sieve_chunked_into(job, span, bitmap, counts, ws, tune, stream)
     return bitmap, counts, ws
 
 

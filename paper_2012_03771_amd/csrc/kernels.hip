@@ -197,7 +197,7 @@ __device__ __forceinline__ uint32_t pattern_word(uint32_t u, uint32_t b0) {
   return every_qth(Q) << ph;
 }
 
-__global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n_seg,
+__global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t seg0, uint64_t n_seg,
                                                         const uint32_t* __restrict__ base,
                                                         const uint32_t* __restrict__ n_base_p,
                                                         uint32_t* __restrict__ flags,
@@ -206,7 +206,8 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n
   __shared__ uint32_t sh[32];
   const uint32_t n_base = *n_base_p;
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
-    const uint64_t lo = s << kSegLog;
+    const uint64_t gs = seg0 + s;                                  // segment of the whole range
+    const uint64_t lo = gs << kSegLog;
     const uint64_t hi = min(lo + (1ull << kSegLog) - 1, lim);     // inclusive
     // The odd multiples of 3, 5, 7, 11 and 13 (over 40% of all marks, and the ones whose
     // atomics collide most) come from periodic word patterns; q | lo + 2b + 1 iff
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n
       for (uint32_t u = threadIdx.x; u < kSegWords; u += blockDim.x) {
         uint32_t w = pattern_word<3>(u, b3) | pattern_word<5>(u, b5) | pattern_word<7>(u, b7) |
                      pattern_word<11>(u, b11) | pattern_word<13>(u, b13);
-        if (s == 0 && u == 0) w &= ~0x6Eu;                          // 3, 5, 7, 11, 13 are prime
+        if (gs == 0 && u == 0) w &= ~0x6Eu;                         // 3, 5, 7, 11, 13 are prime
         bits[u] = w;
       }
     }
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n
     uint32_t c = 0;
     for (uint32_t u = threadIdx.x; u < kSegWords; u += blockDim.x) {
       uint32_t m = ~bits[u];
-      if (s == 0 && u == 0) m &= ~1u;                               // n = 1 is not prime
+      if (gs == 0 && u == 0) m &= ~1u;                              // n = 1 is not prime
       const uint32_t first = u * 32;
       if (first >= nbits) m = 0;
       else if (nbits - first < 32) m &= (1u << (nbits - first)) - 1;
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t n
     }
     uint32_t tot;
     block_exclusive_scan(c, sh, &tot);
-    if (threadIdx.x == 0) seg_count[s] = tot + ((s == 0 && lim >= 2) ? 1u : 0u);   // the prime 2
+    if (threadIdx.x == 0) seg_count[s] = tot + ((gs == 0 && lim >= 2) ? 1u : 0u);  // the prime 2
     __syncthreads();
   }
 }
@@ -288,17 +289,17 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 
 // Ordered compaction of the prime flags: 256 consecutive words per step, so reads are
 // coalesced and each step's primes land in one contiguous run of the table.
-__global__ __launch_bounds__(256) void k_compact_primes(uint64_t n_seg, const uint32_t* __restrict__ flags,
+__global__ __launch_bounds__(256) void k_compact_primes(uint64_t seg0, uint64_t n_seg, const uint32_t* __restrict__ flags,
                                                         const uint64_t* __restrict__ off,
                                                         uint64_t* __restrict__ primes, uint64_t cap) {
   __shared__ uint32_t sh[32];
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     uint64_t base = off[s];
-    if (s == 0) {
+    if (seg0 + s == 0) {
       if (threadIdx.x == 0 && cap > 0) primes[0] = 2;
       base += 1;
     }
-    const uint64_t lo = s << kSegLog;
+    const uint64_t lo = (seg0 + s) << kSegLog;
     for (uint32_t step = 0; step < kSegWords / 256; ++step) {
       const uint32_t word = step * 256 + threadIdx.x;
       uint32_t m = flags[s * kSegWords + word];
@@ -350,6 +351,22 @@ __global__ void k_prep_tables(JobDev* jobs) {
   c.n_kq = nkq;
   c.n_dq = ndq;
   c.diag[D_NPRIMES] = np;
+}
+
+// A later chunk of the prime range (the chunked sieve): the table now holds the primes of the
+// chunk alone, so only its length and the primes it counts change; K's groups, the prime factors
+// of d and the row and column tables stay those derived from the first chunk.
+__global__ void k_chunk_bounds(JobDev* jobs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  JobDev& j = jobs[blockIdx.y];
+  JobCtrl& c = *j.ctrl;
+  uint64_t np = *j.n_primes;
+  if (np > j.prime_cap) {
+    atomicOr(&c.error, (uint32_t)E_PRIMES);
+    np = j.prime_cap;
+  }
+  c.n_lim = upper_index(j.primes, np, j.limit);
+  c.diag[D_NPRIMES] += c.n_lim;
 }
 
 // Prefix of the per-job prime counts (primes <= limit) over the jobs of a launch.
@@ -1577,16 +1594,25 @@ hipError_t launch_zero_ctrl(JobCtrl* c, hipStream_t s) {
 }
 
 hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s) {
+  return launch_primes_range(0, lim, pw, s);
+}
+
+hipError_t launch_primes_range(uint64_t seg0, uint64_t lim, const PrimeWs& pw, hipStream_t s) {
   hipLaunchKernelGGL(k_base_primes, dim3(1), dim3(1024), 0, s, lim, pw.base, pw.n_base); { hipError_t e_ = note("k_base_primes"); if (e_ != hipSuccess) return e_; }
-  const uint64_t n_seg = (lim >> kSegLog) + 1;
+  const uint64_t n_seg = (lim >> kSegLog) + 1 - seg0;
   uint32_t blocks = (uint32_t)(n_seg < 8192 ? n_seg : 8192);
   const uint32_t seg_blocks = (uint32_t)(n_seg < (1ull << 31) ? n_seg : (1ull << 31));   // one per segment
-  hipLaunchKernelGGL(k_sieve_segments, dim3(seg_blocks), dim3(512), 0, s, lim, n_seg, pw.base, pw.n_base,
+  hipLaunchKernelGGL(k_sieve_segments, dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg, pw.base, pw.n_base,
                      pw.flags, pw.seg_count); { hipError_t e_ = note("k_sieve_segments"); if (e_ != hipSuccess) return e_; }
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pw.seg_count, n_seg, pw.seg_off, pw.n_primes); { hipError_t e_ = note("k_scan_counts"); if (e_ != hipSuccess) return e_; }
-  hipLaunchKernelGGL(k_compact_primes, dim3(blocks), dim3(256), 0, s, n_seg, pw.flags, pw.seg_off,
+  hipLaunchKernelGGL(k_compact_primes, dim3(blocks), dim3(256), 0, s, seg0, n_seg, pw.flags, pw.seg_off,
                      pw.primes, pw.cap); { hipError_t e_ = note("k_compact_primes"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
+}
+
+hipError_t launch_chunk_bounds(JobDev* jobs, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_bounds, dim3(1, 1), dim3(64), 0, s, jobs);
+  return note("k_chunk_bounds");
 }
 
 hipError_t launch_prep_tables(JobDev* jobs, uint32_t n_jobs, hipStream_t s) {

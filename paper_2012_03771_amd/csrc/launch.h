@@ -31,6 +31,10 @@ hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_zero_ctrl(JobCtrl* c, hipStream_t s);
 hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s);
+// The primes of segments seg0 .. lim >> kSegLog (integers seg0 * 2^kSegLog .. lim) into pw.primes.
+hipError_t launch_primes_range(uint64_t seg0, uint64_t lim, const PrimeWs& pw, hipStream_t s);
+// Table bounds of a later chunk of the prime range (chunked sieve).
+hipError_t launch_chunk_bounds(JobDev* jobs, hipStream_t s);
 // Kernels over a job array take the job from blockIdx.y (grid.y = n_jobs).
 hipError_t launch_prep_tables(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 // lim_base: n_jobs + 1 device words; total_cap: an upper bound of all jobs' primes <= limit.

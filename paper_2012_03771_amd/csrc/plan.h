@@ -31,7 +31,8 @@ struct WsLayout {
 
 struct Plan {
   cs_job job;
-  uint64_t Lp;              // max(limit, P): extent of the prime table
+  uint64_t Lp;              // max(limit, P): extent of the prime table (one chunk when span > 0)
+  uint64_t span;            // chunked sieve: integers per chunk of the prime range; 0 = whole range
   uint64_t n_seg;
   uint64_t cap;             // prime table capacity
   uint64_t n_m;
@@ -68,7 +69,10 @@ uint64_t pi_upper(uint64_t x);
 // own_kmod false it leaves out the K mod p table (a server shares one per (P, d)); with bytes_ok
 // false the large-hit byte counters are not used (the server, which folds nothing).
 cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes = true,
-                    bool own_kmod = true, bool bytes_ok = true);
+                    bool own_kmod = true, bool bytes_ok = true, uint64_t span = 0);
+// Smallest and largest chunk of the prime range accepted by the chunked sieve (integers).
+constexpr uint64_t kMinSpan = 1ull << 25;
+constexpr uint64_t kSpanAlign = 1ull << 19;   // one prime-sieve segment
 
 // Host count of rows and columns (also used by cs_rows / cs_columns).
 void host_columns(const cs_job& job, const std::vector<uint32_t>& kq, std::vector<int32_t>* xs);

@@ -70,7 +70,7 @@ uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq) {
 }
 
 cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out, bool own_primes, bool own_kmod,
-                    bool bytes_ok) {
+                    bool bytes_ok, uint64_t span) {
   if (!job || !out) return CS_EINVAL;
   const cs_job j = *job;
   if (j.P < 2 || j.P >= kMaxP) return CS_EINVAL;
@@ -114,8 +114,19 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   }
 
   pl.Lp = std::max<uint64_t>(j.limit, j.P);
+  pl.span = 0;
+  if (span) {
+    // chunks of the prime range: segment-aligned, and the first one holds every prime <= P
+    if (span % kSpanAlign || span < kMinSpan || span <= j.P) return CS_EINVAL;
+    if (span < pl.Lp + 1) {
+      pl.span = span;
+      pl.Lp = span - 1;
+    }
+  }
   pl.n_seg = (pl.Lp >> kSegLog) + 1;
-  pl.cap = pi_upper(pl.Lp);
+  // A chunk [x, x + span) holds no more primes than [0, span) in practice; a denser chunk would
+  // be reported (E_PRIMES), never written past the table.
+  pl.cap = pi_upper(pl.Lp) + (pl.span ? 1024 : 0);
   pl.n_m = host_row_count(j, pl.dq);
   std::vector<int32_t> xs;
   host_columns(j, pl.kq, &xs);
@@ -202,7 +213,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   WsLayout& L = pl.ws;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t at = o; o = align256(o + std::max<uint64_t>(bytes, 8)); return at; };
-  const uint64_t cap_lim = pi_upper(j.limit);
+  const uint64_t cap_lim = pl.span ? pl.cap : pi_upper(j.limit);
   L.ctrl = take(sizeof(JobCtrl));
   L.jobdev = take(sizeof(JobDev));
   L.items_base = take(2 * sizeof(uint64_t));

@@ -157,3 +157,18 @@ def test_paper_scale_scatter_modes():
     with pytest.raises(cs.CsError):
         cs.plan(W.Job(953, 210, 10**8, 4 * 10**6, 20000, 10**9), cs.Tune(scatter=cs.SCATTER_LIST))
     assert cs.plan(W.Job(4001, 1, 1, 100, 1000, 10**6), cs.Tune(scatter=cs.SCATTER_LIST)).scatter == cs.SCATTER_LIST
+
+
+def test_chunked_plan():
+    """cs_plan_chunked: spans must be segment-aligned, at least 2^25 and above P; a span above
+    the limit is the whole sieve; smaller spans hold one chunk's tables."""
+    job = W.PAPER_SCALE
+    whole = cs.plan(job)
+    for bad in (0, (1 << 25) + 1, 1 << 24, 3 << 19):
+        with pytest.raises(cs.CsError):
+            cs.plan_chunked(job, bad)
+    assert cs.plan_chunked(job, 1 << 34).ws_bytes == whole.ws_bytes
+    lay = cs.plan_chunked(job, 1 << 31)
+    assert lay.ws_bytes < whole.ws_bytes / 2
+    assert 105_000_000 < lay.prime_cap < 106_000_000          # pi(2^31) = 105,097,565, plus a margin
+    assert (lay.n_m, lay.n_x, lay.row_words) == (whole.n_m, whole.n_x, whole.row_words)
