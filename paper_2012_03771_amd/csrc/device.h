@@ -51,7 +51,9 @@ struct JobDev {
   uint64_t small_unit_base;          // first small-branch unit of this job in a fused launch
   uint64_t dense_max;                // small primes <= dense_max are marked cooperatively
   uint64_t prime_cap;                // capacity of the prime table
-  uint32_t n_tiers, pad1;
+  uint32_t n_tiers;
+  uint32_t small_atomic;             // 1: the small branch merges its tiles with atomics (it runs
+                                     // beside a large branch that ORs into the same bitmap)
   uint32_t d_small;                  // 1 if d <= kDSmall (rows from dpre, no per-m table lookups)
   uint32_t phi_d;                    // residues mod d coprime to d
   uint32_t r0_d;                     // m_start mod d

@@ -870,14 +870,14 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
       for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) {
         const uint32_t v = tile[r * rw + u];
         if (!v) continue;
-        if (j.n_slices == 1) dst[u] |= v;
+        if (j.n_slices == 1 && !j.small_atomic) dst[u] |= v;
         else atomicOr((uint32_t*)(dst + u), v);
       }
     }
     for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
       const uint32_t v = cnt[r];
       if (!v) continue;
-      if (j.n_slices == 1) gbl(j.counts)[row_lo + r] += v;
+      if (j.n_slices == 1 && !j.small_atomic) gbl(j.counts)[row_lo + r] += v;
       else atomicAdd((uint32_t*)(gbl(j.counts) + row_lo + r), v);
     }
     __syncthreads();

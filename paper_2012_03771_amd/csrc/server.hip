@@ -128,6 +128,8 @@ struct cs_server {
   int device = 0;
   int n_cu = 256;
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;           // the small branch beside the large one (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   uint8_t* arena_mem = nullptr;
   uint8_t* fixed_mem = nullptr;
   Arena arena;
@@ -321,6 +323,7 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
     jd.p_hi = J.bounds[J.chunk + 1];
     fill_tiers(J.plan, jd.p_lo, jd.p_hi, &jd);
     jd.small_unit_base = units;
+    jd.small_atomic = 1;
     if (J.chunk == 0) {
       units += (uint64_t)J.plan.n_windows * J.plan.n_slices;
       lds = std::max(lds, J.plan.lds_bytes);
@@ -329,12 +332,18 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
   }
   if (launch_prep_bounds(s->run_dev, n, st) != hipSuccess) return false;
   if (launch_items_scan(s->run_dev, n, s->items_base, st) != hipSuccess) return false;
+  // the small branch on the second stream beside the large one: both merge into the bitmap and
+  // counts with atomics (small_atomic), so the order of their updates does not matter
   if (units) {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, 1ull << 31);   // one workgroup per unit
-    if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, st) != hipSuccess) return false;
+    if (hipEventRecord(s->ev_fork, st) != hipSuccess || hipStreamWaitEvent(s->aux, s->ev_fork, 0) != hipSuccess)
+      return false;
+    if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, s->aux) != hipSuccess) return false;
   }
   if (launch_large(s->run_dev, n, s->items_base, s->diag, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u, st) !=
       hipSuccess)
+    return false;
+  if (units && (hipEventRecord(s->ev_join, s->aux) != hipSuccess || hipStreamWaitEvent(st, s->ev_join, 0) != hipSuccess))
     return false;
   if (hipStreamSynchronize(st) != hipSuccess) return false;
   return true;
@@ -430,11 +439,17 @@ extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** o
   s->items_base = reinterpret_cast<uint64_t*>(m + o_it);
   s->diag = reinterpret_cast<unsigned long long*>(m + o_dg);
   bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) == hipSuccess;
   // the resident prime table (the paper's one-time cost, Section 5)
   ok = ok && launch_primes(cfg->max_limit, s->pw, s->stream) == hipSuccess;
   ok = ok && launch_fill_u32(reinterpret_cast<uint32_t*>(s->diag), 2ull * D_COUNT, 0u, s->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
   if (!ok) {
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     (void)hipFree(s->arena_mem);
     (void)hipFree(s->fixed_mem);
@@ -538,6 +553,10 @@ extern "C" cs_status cs_server_destroy(cs_server* s) {
   }
   if (s->th.joinable()) s->th.join();
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->aux);
+  (void)hipEventDestroy(s->ev_fork);
+  (void)hipEventDestroy(s->ev_join);
+  (void)hipStreamDestroy(s->aux);
   (void)hipStreamDestroy(s->stream);
   (void)hipFree(s->arena_mem);
   (void)hipFree(s->fixed_mem);
