@@ -75,7 +75,8 @@ typedef struct cs_tune {
   uint32_t tile_rows;      /* rows per LDS tile of the small branch; 0 = automatic */
   uint32_t hits_per_item;  /* target expected hits per large-branch work item; 0 = automatic */
   uint32_t large_mode;     /* CS_LARGE_G or CS_LARGE_THREE_GAP */
-  uint32_t large_blocks;   /* persistent grid of the large branch (workgroups); 0 = automatic */
+  uint32_t large_blocks;   /* workgroups of the large branch's grid (each lane takes items with a
+                              grid stride); 0 = automatic (128 per CU, 8 per CU with LIST) */
   uint32_t small_slices;   /* prime slices per small-branch tile; 0 = automatic */
   uint32_t branches;       /* cs_sieve_range only: CS_BRANCH_ALL (0), CS_BRANCH_SMALL or
                               CS_BRANCH_LARGE, to run one branch per call (e.g. to time it) */
@@ -162,7 +163,9 @@ cs_status cs_rows(const cs_job* job, uint64_t* m_of_row, uint64_t cap);
 /* The whole sieve (Sections 3.1-3.3): clears d_bitmap and d_counts, builds the prime table
  * up to max(limit, P), K mod p for every prime (Eq. 1 cache), then runs the small-prime
  * branch (primes <= thr, marked in LDS tiles of rows) and the large-prime branch (primes
- * > thr, Eq. 3 solved by Eq. 5, one atomic mark per hit).
+ * > thr, Eq. 3 solved by Eq. 5; hits reach the bitmap by the scatter of cs_tune.scatter).
+ * With byte counters the small branch runs on a second, library-owned stream beside the large
+ * one (joined back before the call's last launch; not under graph capture).
  * d_bitmap: layout.bitmap_bytes; d_counts: layout.counts_bytes; d_ws: layout.ws_bytes
  * (CS_ERANGE if ws_bytes is smaller).  All three are caller-owned device memory. */
 cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
@@ -268,9 +271,10 @@ cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, const uint64_
 /* ------------------------------------------------------------------------------------------
  * Batches: many jobs (different P, d, m ranges, sl, limits) sieved by one sequence of fused
  * launches.  The prime table is built once up to the largest limit and shared; the per-job
- * preparation kernels and the two sieve kernels each cover every job in a single launch
- * (persistent grids over all jobs' tiles and items).  The sequence is captured once in a
- * hipGraph and replayed.  Outputs are bit-identical to one cs_sieve call per job.
+ * preparation kernels each cover every job in a single launch, then each job's two sieve
+ * branches run as single-job launches spread over lane streams that fork from and join the
+ * caller's stream.  The sequence is captured once in a hipGraph and replayed.  Outputs are
+ * bit-identical to one cs_sieve call per job.
  * ------------------------------------------------------------------------------------------ */
 typedef struct cs_batch cs_batch;
 

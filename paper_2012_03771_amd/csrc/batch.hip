@@ -2,10 +2,10 @@
 // sequence of fused launches, captured once in a hipGraph and replayed.
 //
 // The prime table is built once up to the largest limit and shared; every other table is per
-// job.  Each kernel of the sequence covers all jobs: the per-job preparation kernels take the
-// job from blockIdx.y, K mod p runs over the flattened prime index space of all jobs, and the
-// two sieve kernels are persistent grids over the small-branch tiles and large-branch items of
-// all jobs.
+// job.  The preparation kernels cover all jobs in one launch each: they take the job from
+// blockIdx.y, and K mod p runs over the flattened prime index space of all jobs.  Each job's two
+// sieve branches then run as single-job launches (LDS tables, uniform job fields) spread over
+// lane streams forked from and joined back into the caller's stream inside the graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>

@@ -6,7 +6,8 @@
 //   kmod    K mod p (the cached residue of Eq. 1) and m_start*K mod p per prime
 //   rows    m -> row map (gcd(m, d) = 1) and columns X -> column map (gcd(X, K) = 1)
 //   small   primes p <= thr: every (row, p) residue, offsets marked in LDS row tiles
-//   large   primes p >  thr: Eq. 3 solved by Eq. 5 from hit to hit, one atomic mark per hit
+//   large   primes p >  thr: Eq. 3 solved by Eq. 5 (per hit, or for the first hit with
+//           three-gap steps after it); hits scattered by atomics, byte counters or a cell list
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
