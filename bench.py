@@ -240,9 +240,9 @@ def _cpu_baseline(job, n_rows, p_max):
                       f"(direct mode), {dt:.1f} s wall"}
 
 
-def _kernel_traffic(mode):
-    """HBM bytes (GB) of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile, or
-    None when the kernel sources changed since those counters were taken."""
+def _kernel_profile(mode):
+    """The committed rocprofv3 counters of one k_large launch (profiles/traffic.json), or None when
+    the kernel sources changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -253,7 +253,21 @@ def _kernel_traffic(mode):
         m.update(open(os.path.join(ROOT, "paper_2012_03771_amd", "csrc", f), "rb").read())
     if not rec or rec.get("hash") != m.hexdigest()[:16]:
         return None
-    return rec["traffic_gb"]
+    return rec
+
+
+def _kernel_traffic(mode):
+    """HBM bytes (GB) of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile."""
+    rec = _kernel_profile(mode)
+    return rec["traffic_gb"] if rec else None
+
+
+def _valu_issue(mode):
+    """Measured VALU issue of one k_large launch: SQ_INSTS_VALU (wavefront instructions, each
+    occupying a 16-lane SIMD for 4 cycles) x 4 over the SIMD cycles of the launch (1,024 SIMDs at
+    2.4 GHz times its duration), from the committed SQ-counter profile; None when stale."""
+    rec = _kernel_profile(mode)
+    return rec.get("valu_issue_frac") if rec else None
 
 
 def _prp_leg(cs, torch, np, job, bitmap, n_rows, stream):
@@ -482,7 +496,9 @@ def main():
             "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS,
             "traffic": args.traffic_gb if args.traffic_gb is not None else _kernel_traffic(args.mode),
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, profiles/)",
-            "ops_per_launch": ops, "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"]}
+            "ops_per_launch": ops, "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"],
+            "valu_issue_frac": _valu_issue(args.mode),
+            "valu_issue_source": "rocprofv3 SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time), profiles/"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "factors/s", "n_gpus": 1, "steps": args.steps,
@@ -527,7 +543,7 @@ def main():
                          "roofline": {"bound": "alu", "kernel": "k_large", "achieved": og / tlg / 1e12,
                                       "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
                                       "frac": og / tlg / ALU_PEAK_OPS, "ops_per_launch": og,
-                                      "traffic": _kernel_traffic("g"),
+                                      "traffic": _kernel_traffic("g"), "valu_issue_frac": _valu_issue("g"),
                                       "launch_ms": tlg * 1e3, "large_phase_ms": ph["large"]}}
     mode_b = cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP
     del bitmap, counts, ws, ref_bitmap, ref_counts
