@@ -74,6 +74,8 @@ TABLE_A2 = {
     10: (1511, 2 * 3 * 5 * 7 * 1009, 16000, 10**7, 10**11, 0.0112),
     11: (1511, 2 * 3 * 5 * 7 * 1009, 16000, 10**7, 25 * 10**10, 0.0129),
     12: (2221, 2 * 3 * 5 * 2027, 23000, 10**7, 8 * 10**11, 0.0252),
+    13: (4441, 2 * 3 * 5 * 7 * 11 * 4001, 47000, 10**7, 2 * 10**12, 0.0605),
+    14: (5333, 2 * 3 * 5 * 7 * 11 * 5003, 65000, 10**6, 2 * 10**12, 0.158),
     15: (8887, 2 * 3 * 5 * 7 * 11 * 13 * 17 * 8009, 100000, 10**5, 10**12, 0.709),
 }
 
@@ -84,7 +86,7 @@ def _table_a2(cs, torch, W, rows):
     prime up to the limit.  Where the whole prime, K mod p and m_start*K mod p tables would exceed
     160 GiB the prime range is taken in chunks of 2^36 integers (cs_sieve_chunked).  One call
     timed after a warm-up call.  The paper's seconds per coprime m come from a CPU whose type it
-    does not state.  Rows 13 and 14 (limit 2e12) are above this library's 2^40 range."""
+    does not state."""
     out = []
     for r in rows:
         P, d, X, M, limit, paper = TABLE_A2[r]

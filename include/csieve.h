@@ -52,7 +52,7 @@ typedef int32_t cs_status;
  *   2 <= P < 2^24;  d >= 1 squarefree with every prime factor <= P (d | P#);
  *   m_start >= 1;  1 <= m_inc < 2^32;  m_start + m_inc < 2^63;
  *   1 <= sl < 2^17 (a packed row fits an LDS tile) and sl < m_start*K (every N + X > 0);
- *   2 <= limit and max(limit, P) < 2^40 (CS_ERANGE otherwise).
+ *   2 <= limit and max(limit, P) < 2^42 (CS_ERANGE otherwise).
  * A job whose range holds no m coprime to d is valid and has no rows. */
 typedef struct cs_job {
   uint32_t P;
@@ -199,6 +199,15 @@ cs_status cs_plan_chunked(const cs_job* job, const cs_tune* tune, uint64_t span,
 cs_status cs_sieve_chunked(const cs_job* job, const cs_tune* tune, uint64_t span, uint32_t* d_bitmap,
                            uint32_t* d_counts, void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* The chunked sieve restricted to the primes p in [p_lo, p_hi] (clipped to [2, limit]): ORs their
+ * marks into d_bitmap and adds their factors into d_counts (nothing is cleared), like
+ * cs_sieve_range, with the chunks of the prime range that hold no such prime skipped (the first
+ * chunk is always prepared: it supplies K's prime groups and the row and column tables).
+ * Splitting [2, limit] into ranges gives exactly cs_sieve_chunked's result. */
+cs_status cs_sieve_chunked_range(const cs_job* job, const cs_tune* tune, uint64_t span, uint64_t p_lo,
+                                 uint64_t p_hi, uint32_t* d_bitmap, uint32_t* d_counts, void* d_ws,
+                                 uint64_t ws_bytes, void* stream);
+
 /* Waits for `stream`, then copies the counters kept in d_ws (see cs_diag).  Returns
  * CS_EDEVICE if the stream reported an error or error_flags is nonzero. */
 cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream);
@@ -212,7 +221,7 @@ cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* 
                     void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* K mod p for n primes (Eq. 1: the cached residue, K = P#/d): d_out[i] = K mod d_primes[i].
- * Every d_primes[i] must be a prime below 2^40.  d_ws: cs_kmod_ws bytes (it receives the
+ * Every d_primes[i] must be a prime below 2^42.  d_ws: cs_kmod_ws bytes (it receives the
  * products of the primes dividing K, grouped below 2^50). */
 cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out);
 cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,

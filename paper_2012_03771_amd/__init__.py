@@ -7,5 +7,5 @@ library was not built (there is no fallback path).
 from .binding import (  # noqa: F401
     CsError, Tune, Layout, Diag, LARGE_G, LARGE_THREE_GAP, BRANCH_ALL, BRANCH_SMALL, BRANCH_LARGE, SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_BYTES, SCATTER_LIST, lib, lib_path, plan, columns, rows,
     sieve, sieve_into, prepare, sieve_range, diag_read, primes, kmod, job_tuple, unpack_bits, Batch, Server,
-    prp_numbers, surround, surround_ws_bytes, SurroundStats, plan_chunked, sieve_chunked, sieve_chunked_into,
+    prp_numbers, surround, surround_ws_bytes, SurroundStats, plan_chunked, sieve_chunked, sieve_chunked_into, sieve_chunked_range,
 )

@@ -152,6 +152,7 @@ def lib():
         "cs_sieve_range": ([P(cs_job), P(cs_tune), u64, u64, vp, vp, vp, u64, vp], i32),
         "cs_plan_chunked": ([P(cs_job), P(cs_tune), u64, P(cs_layout)], i32),
         "cs_sieve_chunked": ([P(cs_job), P(cs_tune), u64, vp, vp, vp, u64, vp], i32),
+        "cs_sieve_chunked_range": ([P(cs_job), P(cs_tune), u64, u64, u64, vp, vp, vp, u64, vp], i32),
         "cs_diag_read": ([vp, P(cs_diag), vp], i32),
         "cs_primes_ws": ([u64, P(u64), P(u64)], i32),
         "cs_primes": ([u64, vp, u64, vp, vp, u64, vp], i32),
@@ -272,6 +273,12 @@ def sieve(job, tune: Tune | None = None, stream=None):
 def sieve_chunked_into(job, span: int, bitmap, counts, ws, tune: Tune | None = None, stream=None):
     _check(lib().cs_sieve_chunked(C.byref(_cjob(job)), _ctune(tune), span, _ptr(bitmap), _ptr(counts), _ptr(ws),
                                   ws.numel(), _stream(stream)), "cs_sieve_chunked")
+
+
+def sieve_chunked_range(job, span: int, p_lo: int, p_hi: int, bitmap, counts, ws, tune: Tune | None = None,
+                        stream=None):
+    _check(lib().cs_sieve_chunked_range(C.byref(_cjob(job)), _ctune(tune), span, p_lo, p_hi, _ptr(bitmap),
+                                        _ptr(counts), _ptr(ws), ws.numel(), _stream(stream)), "cs_sieve_chunked_range")
 
 
 def sieve_chunked(job, span: int, tune: Tune | None = None, stream=None):

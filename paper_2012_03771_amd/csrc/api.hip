@@ -282,6 +282,49 @@ extern "C" cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* 
   return range_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL);
 }
 
+namespace {
+cs_status chunked_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* d_bitmap, uint32_t* d_counts,
+                          uint8_t* ws, hipStream_t s, int n_cu) {
+  // the first chunk [0, span) (every prime <= P, so K's groups and the row and column tables
+  // come from it) is an ordinary preparation with a prime table of one chunk
+  cs_status st = prepare_planned(pl, ws, s, n_cu);
+  if (st) return st;
+  const uint64_t limit = pl.job.limit;
+  const uint64_t lo = std::max<uint64_t>(p_lo, 2), hi_all = std::min(p_hi, limit);
+  const uint64_t step = pl.span ? pl.span : limit + 1;
+  for (uint64_t a = 0; a <= hi_all; a += step) {
+    const uint64_t hi = std::min<uint64_t>(a + step - 1, limit);
+    if (hi < lo) continue;                          // no prime of [p_lo, p_hi] in this chunk
+    if (a > 0) {
+      PrimeWs pw = prime_ws_of(pl, ws);
+      JobDev* jdp = reinterpret_cast<JobDev*>(ws + pl.ws.jobdev);
+      CS_TRY(launch_primes_range(a >> kSegLog, hi, pw, s));
+      CS_TRY(launch_chunk_bounds(jdp, s));
+      CS_TRY(launch_kmod(jdp, 1, reinterpret_cast<uint64_t*>(ws + pl.ws.lim_base), pl.cap, n_cu, s));
+    }
+    st = range_planned(pl, std::max<uint64_t>(a, lo), std::min(hi, hi_all), d_bitmap, d_counts, ws, s,
+                       CS_BRANCH_ALL);
+    if (st) return st;
+    if (a + step < a) break;                        // (no wrap-around for limits near 2^64)
+  }
+  return CS_OK;
+}
+}  // namespace
+
+extern "C" cs_status cs_sieve_chunked_range(const cs_job* job, const cs_tune* tune, uint64_t span, uint64_t p_lo,
+                                            uint64_t p_hi, uint32_t* d_bitmap, uint32_t* d_counts, void* d_ws,
+                                            uint64_t ws_bytes, void* stream) {
+  if (!span) return CS_EINVAL;
+  Plan pl;
+  const int n_cu = device_cu_count();
+  cs_status st = make_plan(job, tune, n_cu, &pl, true, true, true, span);
+  if (st) return st;
+  if (!d_ws || (pl.n_m > 0 && (!d_bitmap || !d_counts))) return CS_EINVAL;
+  if (ws_bytes < pl.ws.total) return CS_ERANGE;
+  if (p_hi < p_lo) return CS_OK;
+  return chunked_planned(pl, p_lo, p_hi, d_bitmap, d_counts, static_cast<uint8_t*>(d_ws), (hipStream_t)stream, n_cu);
+}
+
 extern "C" cs_status cs_sieve_chunked(const cs_job* job, const cs_tune* tune, uint64_t span, uint32_t* d_bitmap,
                                       uint32_t* d_counts, void* d_ws, uint64_t ws_bytes, void* stream) {
   if (!span) return CS_EINVAL;
@@ -292,31 +335,11 @@ extern "C" cs_status cs_sieve_chunked(const cs_job* job, const cs_tune* tune, ui
   if (!d_ws || (pl.n_m > 0 && (!d_bitmap || !d_counts))) return CS_EINVAL;
   if (ws_bytes < pl.ws.total) return CS_ERANGE;
   hipStream_t s = (hipStream_t)stream;
-  uint8_t* ws = static_cast<uint8_t*>(d_ws);
   if (pl.n_m > 0) {
     CS_TRY(launch_fill_u32(d_bitmap, pl.n_m * (uint64_t)pl.row_words, 0u, s));
     CS_TRY(launch_fill_u32(d_counts, pl.n_m, 0u, s));
   }
-  // the first chunk [0, span) (every prime <= P, so K's groups and the row and column tables
-  // come from it) is an ordinary preparation with a prime table of one chunk
-  st = prepare_planned(pl, ws, s, n_cu);
-  if (st) return st;
-  const uint64_t limit = pl.job.limit;
-  const uint64_t step = pl.span ? pl.span : limit + 1;
-  for (uint64_t a = 0; a <= limit; a += step) {
-    const uint64_t hi = std::min<uint64_t>(a + step - 1, limit);
-    if (a > 0) {
-      PrimeWs pw = prime_ws_of(pl, ws);
-      JobDev* jdp = reinterpret_cast<JobDev*>(ws + pl.ws.jobdev);
-      CS_TRY(launch_primes_range(a >> kSegLog, hi, pw, s));
-      CS_TRY(launch_chunk_bounds(jdp, s));
-      CS_TRY(launch_kmod(jdp, 1, reinterpret_cast<uint64_t*>(ws + pl.ws.lim_base), pl.cap, n_cu, s));
-    }
-    st = range_planned(pl, std::max<uint64_t>(a, 2), hi, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL);
-    if (st) return st;
-    if (a + step < a) break;                        // (no wrap-around for limits near 2^64)
-  }
-  return CS_OK;
+  return chunked_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, static_cast<uint8_t*>(d_ws), s, n_cu);
 }
 
 extern "C" cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream) {

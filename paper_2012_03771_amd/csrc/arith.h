@@ -1,6 +1,6 @@
 // Exact integer arithmetic for the sieve kernels, written for gfx950's full-rate fp64 VALU.
 //
-// All residues handled here are below 2^40 (the library's documented sieve-limit range), so
+// All residues handled here are below 2^42 (the library's documented sieve-limit range), so
 // they are exactly representable as doubles.  Quotients come from an fp64 reciprocal within a
 // unit in the last place and are corrected by one exact fma step, so every remainder is exact;
 // Euclidean steps on remainders below 2^20 run in fp32 the same way.
@@ -79,7 +79,7 @@ CS_HD void euclid_tail_f32(double* a, double* b, double* sa, double* sb) {
 }
 
 // x mod m for 0 <= x < 2^52, 1 <= m < 2^52, with inv = 1/m to a relative error below 2^-46
-// and x/m < 2^40: |x/m - x*inv| < 1 so the floor is off by at most one; one exact fma and one
+// and x/m < 2^45: |x/m - x*inv| < 1 so the floor is off by at most one; one exact fma and one
 // correction each way make the remainder exact.
 CS_HD double fmod_inv(double x, double m, double inv) {
   double q = floor(x * inv);
@@ -101,7 +101,7 @@ CS_HD uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p, double pinv) {
   return (uint64_t)r;
 }
 
-// r*g mod p in fp64 alone, for 0 <= r < p < 2^40, 1 <= g < 2^50 and pinv = 1/p correctly
+// r*g mod p in fp64 alone, for 0 <= r < p < 2^42, 1 <= g < 2^50 and pinv = 1/p correctly
 // rounded: h + l = r*g exactly (h the rounded product, l = fma(r, g, -h) its error, |l| < p/8
 // because h < p*2^50); the floor of h*pinv is within one of h/p, so h - q*p lies in [-p, 2p) and
 // the fma forms it exactly; adding l gives an exact integer in (-2p, 3p), reduced once more the
@@ -119,7 +119,7 @@ CS_HD double mulmod_f64(double r, double g, double p, double pinv) {
   return y;
 }
 
-// x mod p for any 64-bit x and p < 2^40.
+// x mod p for any 64-bit x and p < 2^42.
 CS_HD uint64_t mod64(uint64_t x, uint64_t p, double pinv) {
   if (x < (1ull << 52)) return (uint64_t)fmod_inv((double)x, (double)p, pinv);
   uint64_t hi = x >> 32, lo = x & 0xffffffffull;
@@ -129,7 +129,7 @@ CS_HD uint64_t mod64(uint64_t x, uint64_t p, double pinv) {
   return v >= p ? v - p : v;
 }
 
-// k^-1 mod p (gcd(k, p) = 1, 1 <= k < p < 2^40) by the extended Euclidean algorithm in
+// k^-1 mod p (gcd(k, p) = 1, 1 <= k < p < 2^42) by the extended Euclidean algorithm in
 // exact fp64: every remainder and Bezout coefficient stays below p in magnitude.
 CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
   double a = (double)p, b = (double)k;
@@ -164,7 +164,7 @@ CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
 // same least t (the mirror needs 0 outside [L, R], which (a) guarantees), so the order does
 // not change the result.  Case (b) (K >= p) is never met: callers pass K < p and (e) keeps the
 // new K below the new p.
-// Preconditions: gcd(p, K) = 1, 1 <= K < p < 2^40, 0 <= L, L + width < p.
+// Preconditions: gcd(p, K) = 1, 1 <= K < p < 2^42, 0 <= L, L + width < p.
 // Returns -1 (never for valid input) if the descent exceeds `max_levels`.
 CS_HD double g_offset(double p, double K, double L, double width, int* levels_out,
                       int max_levels = 160) {
@@ -241,7 +241,7 @@ CS_HD int three_gap_setup(uint64_t p, uint64_t k, uint64_t kinv, double pinv, ui
 // r_{i+1} <= w settles the side of r_{i-1} and the next one, r_{i+2} <= r_{i+1}, the other side:
 // the loop runs plain Euclidean steps up to that point and both constants are taken after it
 // (when k <= w, t = 1 is the positive side's and the step from (p, k) gives the other).
-// Requires 1 <= k < p < 2^40 prime, 1 <= w, p > 2w.  Returns 0 only on an internal failure.
+// Requires 1 <= k < p < 2^42 prime, 1 <= w, p > 2w.  Returns 0 only on an internal failure.
 CS_HD void tg_side(double a, double b, double inv, double sa, double sb, double wd, double* t, double* v) {
   const double num = a - wd + b - 1.0;          // j = ceil((a - w) / b), a > w
   double j = floor(num * inv);

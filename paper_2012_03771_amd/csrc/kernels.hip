@@ -127,59 +127,84 @@ __global__ void k_zero_ctrl(JobCtrl* c) {
 // Segment s covers [s*2^19, (s+1)*2^19); bit i stands for n = s*2^19 + 2i + 1.
 // ------------------------------------------------------------------------------------------
 
-// Odd base primes <= isqrt(lim) (lim < 2^40, so < 2^20), one workgroup, LDS bit sieve.
-// The 64 KB bit array is the whole LDS budget, so the compaction first moves each thread's
-// words to registers and then reuses the array's head as scan scratch.
+// Odd base primes <= isqrt(lim) (lim < 2^42, so < 2^21), one workgroup, LDS bit sieve over
+// windows of 2^20 integers: the first window finds its primes from its own bits, the second
+// marks the multiples of the first window's primes up to its square root (< 1449).
 __global__ __launch_bounds__(1024) void k_base_primes(uint64_t lim, uint32_t* base, uint32_t* n_base) {
-  constexpr uint32_t kWords = (1u << 19) / 32;              // odd numbers below 2^20
+  constexpr uint32_t kWin = 1u << 20;                       // integers per window
+  constexpr uint32_t kWords = (kWin / 2) / 32;              // odd numbers of a window
   constexpr uint32_t kPer = kWords / 1024;                  // 16 words per thread
   __shared__ uint32_t bits[kWords];
   uint64_t root = (uint64_t)sqrt((double)lim);
   while (root * root > lim) --root;
   while ((root + 1) * (root + 1) <= lim) ++root;
-  const uint32_t nb = (uint32_t)((root + 1) / 2);           // bits for 1, 3, ..., <= root
-  const uint32_t nw = (nb + 31) / 32;
-  for (uint32_t i = threadIdx.x; i < kWords; i += blockDim.x) bits[i] = 0;
-  __syncthreads();
-  for (uint32_t q = 3; (uint64_t)q * q <= root; q += 2) {
-    bool comp = (bits[(q >> 1) >> 5] >> ((q >> 1) & 31)) & 1;   // uniform read after barrier
-    if (!comp) {
-      for (uint64_t n = (uint64_t)q * q + 2ull * q * threadIdx.x; n <= root; n += 2ull * q * blockDim.x) {
-        uint32_t b = (uint32_t)(n >> 1);
-        atomicOr(&bits[b >> 5], 1u << (b & 31));
+  uint32_t total = 0;
+  for (uint32_t win = 0; win < 2; ++win) {
+    const uint64_t w_lo = (uint64_t)win * kWin;             // bit b stands for w_lo + 2b + 1
+    if (w_lo > root) break;
+    const uint64_t w_hi = min<uint64_t>(w_lo + kWin - 1, root);
+    const uint32_t nb = (uint32_t)((w_hi - w_lo + 1) / 2);  // odd numbers in [w_lo, w_hi]
+    const uint32_t nw = (nb + 31) / 32;
+    for (uint32_t i = threadIdx.x; i < kWords; i += blockDim.x) bits[i] = 0;
+    __syncthreads();
+    if (win == 0) {
+      for (uint32_t q = 3; (uint64_t)q * q <= w_hi; q += 2) {
+        bool comp = (bits[(q >> 1) >> 5] >> ((q >> 1) & 31)) & 1;   // uniform read after barrier
+        if (!comp) {
+          for (uint64_t n = (uint64_t)q * q + 2ull * q * threadIdx.x; n <= w_hi; n += 2ull * q * blockDim.x) {
+            uint32_t b = (uint32_t)(n >> 1);
+            atomicOr(&bits[b >> 5], 1u << (b & 31));
+          }
+        }
+        __syncthreads();
+      }
+    } else {
+      // the first window's primes (already in base[], written before the last barrier)
+      for (uint32_t i = 0; i < total; ++i) {
+        const uint64_t q = base[i];
+        if (q * q > w_hi) break;
+        uint64_t st = ((w_lo + q - 1) / q) * q;
+        if (st < q * q) st = q * q;
+        if ((st & 1) == 0) st += q;                        // odd multiples only
+        for (uint64_t n = st + 2ull * q * threadIdx.x; n <= w_hi; n += 2ull * q * blockDim.x) {
+          const uint32_t b = (uint32_t)((n - w_lo) >> 1);
+          atomicOr(&bits[b >> 5], 1u << (b & 31));
+        }
+      }
+      __syncthreads();
+    }
+    // bit b unmarked with 3 <= w_lo + 2b + 1 <= root is an odd prime
+    uint32_t mine[kPer];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+      const uint32_t u = threadIdx.x * kPer + t;
+      uint32_t m = 0;
+      if (u < nw) {
+        m = ~bits[u];
+        if (win == 0 && u == 0) m &= ~1u;                    // n = 1
+        if (u == nw - 1 && (nb & 31)) m &= (1u << (nb & 31)) - 1;
+      }
+      mine[t] = m;
+      c += __popc(m);
+    }
+    __syncthreads();                                         // bits[] is free from here on
+    uint32_t tot;
+    uint32_t off = total + block_exclusive_scan(c, bits, &tot);
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+      uint32_t m = mine[t];
+      const uint32_t u = threadIdx.x * kPer + t;
+      while (m) {
+        uint32_t b = __ffs(m) - 1;
+        m &= m - 1;
+        base[off++] = (uint32_t)(w_lo + 2 * (u * 32 + b) + 1);
       }
     }
-    __syncthreads();
+    total += tot;
+    __syncthreads();                                         // base[] written, bits[] reusable
   }
-  // bit b unmarked with 3 <= 2b+1 <= root is an odd prime
-  uint32_t mine[kPer];
-  uint32_t c = 0;
-#pragma unroll
-  for (uint32_t t = 0; t < kPer; ++t) {
-    const uint32_t u = threadIdx.x * kPer + t;
-    uint32_t m = 0;
-    if (u < nw) {
-      m = ~bits[u];
-      if (u == 0) m &= ~1u;                                  // n = 1
-      if (u == nw - 1 && (nb & 31)) m &= (1u << (nb & 31)) - 1;
-    }
-    mine[t] = m;
-    c += __popc(m);
-  }
-  __syncthreads();                                           // bits[] is free from here on
-  uint32_t tot;
-  uint32_t off = block_exclusive_scan(c, bits, &tot);
-#pragma unroll
-  for (uint32_t t = 0; t < kPer; ++t) {
-    uint32_t m = mine[t];
-    const uint32_t u = threadIdx.x * kPer + t;
-    while (m) {
-      uint32_t b = __ffs(m) - 1;
-      m &= m - 1;
-      base[off++] = 2 * (u * 32 + b) + 1;
-    }
-  }
-  if (threadIdx.x == 0) *n_base = tot;
+  if (threadIdx.x == 0) *n_base = total;
 }
 
 // One workgroup per segment: mark odd composites in LDS, write prime flags and the count.
@@ -236,7 +261,7 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t s
     for (; i < n_base; ++i) {
       const uint64_t q = base[i];
       if (q * q > hi || q >= 4096) break;
-      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;         // exact: lo < 2^40
+      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;         // exact: lo < 2^42
       if (st < q * q) st = q * q;
       if ((st & 1) == 0) st += q;
       if (st > hi) continue;

@@ -9,7 +9,7 @@
 namespace cs {
 
 constexpr uint32_t kMaxSl = (1u << 17) - 1;     // a packed row (<= 2^18 bits) fits an LDS tile
-constexpr uint64_t kMaxLimit = 1ull << 40;
+constexpr uint64_t kMaxLimit = 1ull << 42;
 constexpr uint32_t kMaxP = 1u << 24;
 constexpr uint64_t kMaxMInc = 1ull << 32;
 constexpr uint32_t kSmallBlock = 512;
@@ -21,7 +21,7 @@ constexpr uint32_t kListBlocksPerCu = 8;      // with the list scatter (one part
 constexpr uint32_t kLdsBudget = 64 * 1024 - 256;   // dynamic LDS of a small-branch tile (the kernel keeps 256 B of its own)
 constexpr uint32_t kLdsCtMax = 32 * 1024;
 constexpr uint32_t kTileRowsMax = 16;          // rows per small-branch tile (more workgroups per CU beat bigger tiles)
-constexpr uint32_t kBaseCap = 82100;            // odd primes below 2^20 (82024) plus slack
+constexpr uint32_t kBaseCap = 155700;           // odd primes below 2^21 (155,610) plus slack
 
 struct WsLayout {
   uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,

@@ -67,10 +67,10 @@ int main(int argc, char** argv) {
   std::mt19937_64 rng(seed);
   int bad = 0;
 
-  // mulmod / mod64 / modinv against 128-bit integer arithmetic, p up to 2^40
+  // mulmod / mod64 / modinv against 128-bit integer arithmetic, p up to 2^42
   for (int i = 0; i < 200000 && !bad; ++i) {
-    uint64_t p = (rng() >> (24 + rng() % 38)) | 3;
-    if (p >= (1ull << 40)) p &= (1ull << 40) - 1;
+    uint64_t p = (rng() >> (22 + rng() % 40)) | 3;
+    if (p >= (1ull << 42)) p &= (1ull << 42) - 1;
     if (p < 3) p = 3;
     double pinv = 1.0 / (double)p;
     uint64_t a = rng() % p, b = rng() % p;
@@ -80,10 +80,10 @@ int main(int argc, char** argv) {
     uint64_t o = rng() & 0xffffffffull;
     if (cs::mulmod(o, a, p, pinv) != (uint64_t)((u128)o * a % p)) bad = fail("mulmod_o", o, a, p, 0);
   }
-  // fp64-only modular product for the K mod p chain: r < p < 2^40, g < 2^50
+  // fp64-only modular product for the K mod p chain: r < p < 2^42, g < 2^50
   for (int i = 0; i < 400000 && !bad; ++i) {
-    uint64_t p = (rng() >> (24 + rng() % 40)) | 1;
-    if (p >= (1ull << 40)) p &= (1ull << 40) - 1;
+    uint64_t p = (rng() >> (22 + rng() % 42)) | 1;
+    if (p >= (1ull << 42)) p &= (1ull << 42) - 1;
     if (p < 3) p = 3;
     const uint64_t r = (i % 5 == 0) ? p - 1 - rng() % std::min<uint64_t>(p, 3) : rng() % p;
     uint64_t g = (rng() >> (14 + rng() % 50)) | 1;
@@ -195,12 +195,12 @@ int main(int argc, char** argv) {
       if (ta != g1.ta || tb != g1.tb) { bad = fail("euclid_brute", p, k, w, ta); break; }
     }
   }
-  // the same at the sizes of the sieve (primes up to 2^40, windows up to 2^18 - 2), where the
+  // the same at the sizes of the sieve (primes up to 2^42, windows up to 2^18 - 2), where the
   // Euclidean pass finishes in fp32: inverse exact, constants equal to the G-based setup
   for (int i = 0; i < 20000 && !bad; ++i) {
     uint64_t w = 1 + rng() % (i % 3 == 0 ? 40000 : (1u << 18) - 2);
     uint64_t p;
-    do { p = 2 * w + 1 + (rng() >> (24 + rng() % 26)); } while (p >= (1ull << 40) || !is_prime_mr(p));
+    do { p = 2 * w + 1 + (rng() >> (22 + rng() % 28)); } while (p >= (1ull << 42) || !is_prime_mr(p));
     uint64_t k = 1 + rng() % (p - 1);
     if (i % 13 == 0) k = 1 + rng() % 5;
     if (i % 17 == 0) k = p - 1 - rng() % 5;

@@ -68,7 +68,8 @@ def test_kmod_matches_bignum(P, d):
     _say("kmod", P, d)
     ps = np.concatenate([coracle.primes_range(2, 2 * 10**5),
                          coracle.primes_range(10**10 - 10**5, 10**10),
-                         coracle.primes_range(2**39 - 2**14, 2**39)])
+                         coracle.primes_range(2**39 - 2**14, 2**39),
+                         coracle.primes_range(2**42 - 2**13, 2**42 - 1)])
     dev = torch.from_numpy(ps.astype(np.int64)).cuda()
     got = cs.kmod(P, d, dev).cpu().numpy().astype(np.uint64)
     K = 1

@@ -81,7 +81,7 @@ def test_coprime_m_count_13_primorial(paper_values):
     (W.Job(11, 1, 1, 10, 0, 100), -1),               # sl = 0
     (W.Job(11, 1, 1, 10, 2**17, 100), -1),           # sl too large
     (W.Job(11, 1, 1, 10, 10, 1), -1),                # limit < 2
-    (W.Job(11, 1, 1, 10, 10, 2**40), -2),            # limit too large
+    (W.Job(11, 1, 1, 10, 10, 2**42), -2),            # limit too large
     (W.Job(5, 30, 1, 10, 1, 100), -1),               # K = 1, sl >= m_start*K
     (W.Job(7, 6, 1, 10, 35, 100), -1),               # K = 35, sl = 35 >= 1*35
 ])
