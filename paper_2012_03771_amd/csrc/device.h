@@ -59,7 +59,9 @@ struct JobDev {
   uint32_t r0_d;                     // m_start mod d
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
-  uint32_t kmod_cached, pad2;        // 1: kmod already holds K mod p (a shared table); only mk is built
+  uint32_t kmod_cached;              // 1: kmod already holds K mod p (a shared table); only mk is built
+  uint32_t m_step;                   // 2 if d is even (every m coprime to d is odd): the large branch
+                                     // visits only odd m; else 1
   // Marks of the primes dividing d depend only on m mod d: one packed row (and its factor
   // count) per residue class coprime to d, built once per job and OR-ed into each row's tile.
   uint32_t dpat_on;                  // pattern table built for this job

@@ -1123,6 +1123,9 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
 // Large-prime branch (Section 3.2-3.3).  One item = (job, prime, chunk of the m range).
 // From the residue r of m*K + SL the next m with r <= 2*SL (Eq. 3, shifted form) comes from
 // G of Eq. 5; each such m marks X = SL - r when gcd(m, d) = 1 and X is a column.
+// When d is even only odd m can be rows: the walk takes m = m0 + 2u (m0 the first odd m), whose
+// residues step by 2K mod p, so Eq. 5 and the three-gap return times are those of 2K mod p and
+// the even m are never visited.
 // ------------------------------------------------------------------------------------------
 template <bool kLds, int kSc>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
@@ -1191,13 +1194,22 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       chunk = div_small(li, npt);
       pi = t0 + (li - chunk * npt);
     }
-    const uint64_t L = C == 1 ? j.m_inc : div_small(j.m_inc + C - 1, C);
-    const uint64_t o_lo = (uint64_t)chunk * L;
-    const uint64_t o_hi = min(o_lo + L, j.m_inc);
-    if (o_lo >= o_hi) break;
+    // the walk's positions u: m = m_start + o_par + s u, s = m_step, u in [0, U); a chunk is a
+    // range of u
+    const uint32_t s = j.m_step;
+    const uint64_t o_par = (s == 2 && (j.m_start & 1) == 0) ? 1 : 0;
+    const uint64_t U = s == 1 ? j.m_inc : (j.m_inc > o_par ? (j.m_inc - o_par + 1) / 2 : 0);
+    const uint64_t L = C == 1 ? U : div_small(U + C - 1, C);
+    const uint64_t u_lo = (uint64_t)chunk * L;
+    const uint64_t u_hi = min(u_lo + L, U);
+    if (u_lo >= u_hi) break;
+    const uint64_t o_lo = o_par + s * u_lo;          // < m_inc
+    const uint64_t o_hi = o_par + s * u_hi;          // every visited o = o_par + s u < o_hi is < m_inc
 
     const uint64_t p = gbl(j.primes)[pi];
-    const uint64_t k = gbl(j.kmod)[pi];
+    const uint64_t k1 = gbl(j.kmod)[pi];
+    uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
+    k = k >= p ? k - p : k;
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
     const uint32_t d32 = (uint32_t)j.d;
@@ -1214,7 +1226,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       break;
     }
     // residue of m*K + SL at m = m_start + o_lo
-    uint64_t r = gbl(j.mk)[pi] + mulmod(o_lo, k, p, pinv);
+    uint64_t r = gbl(j.mk)[pi] + mulmod(o_lo, k1, p, pinv);
     r = r >= p ? r - p : r;
     r += j.sl;                                       // sl < w < thr < p
     r = r >= p ? r - p : r;
@@ -1232,19 +1244,19 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
           ++calls;
           levels += (unsigned)lv;
           if (tstep == 0) { err |= E_SOLVE; break; }
-          o += tstep;
+          o += s * tstep;
           if (o >= o_hi) break;
           r = rn;
           if (d_small) {
             uint32_t tq, tr;
-            mpos_divmod(tstep, d32, inv_d, &tq, &tr);
+            mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
             mpos_add(mp, tq, tr, d32);
           }
         }
         ++raw;
         record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
-        if (++o >= o_hi) break;
-        if (d_small) mpos_add(mp, 0, 1, d32);
+        if ((o += s) >= o_hi) break;
+        if (d_small) mpos_add(mp, 0, s, d32);        // s <= d: one correction suffices
         r += k;
         r = r >= p ? r - p : r;
       }
@@ -1257,33 +1269,35 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
         ++calls;
         levels += (unsigned)lv;
         if (tstep == 0) { err |= E_SOLVE; break; }
-        o += tstep;
+        o += s * tstep;
         r = rn;
         if (d_small && o < o_hi) {
           uint32_t tq, tr;
-          mpos_divmod(tstep, d32, inv_d, &tq, &tr);
+          mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
           mpos_add(mp, tq, tr, d32);
         }
       }
+      // the return times in offsets of m (a time past the chunk ends the walk, so the quotients
+      // below only matter for the times that are taken)
+      const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
       uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
       if (d_small) {
-        mpos_divmod(g.ta, d32, inv_d, &aq, &ar);
-        mpos_divmod(g.tb, d32, inv_d, &bq, &br);
-        mpos_divmod(g.ta + g.tb, d32, inv_d, &abq, &abr);
+        mpos_divmod(sta, d32, inv_d, &aq, &ar);
+        mpos_divmod(stb, d32, inv_d, &bq, &br);
+        mpos_divmod(tab, d32, inv_d, &abq, &abr);
       }
       const bool a_first = g.ta < g.tb;
       // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
       // arithmetic, and the three cases by selects rather than branches
       const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
       uint32_t r32 = (uint32_t)r;
-      const uint64_t tab = g.ta + g.tb;
       while (o < o_hi) {
         ++raw;
         record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, useful, lreg);
         const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
         const bool ua = fa && (a_first || !fb);
         const bool ub = !ua && fb;
-        o += ua ? g.ta : (ub ? g.tb : tab);
+        o += ua ? sta : (ub ? stb : tab);
         r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
         mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
       }

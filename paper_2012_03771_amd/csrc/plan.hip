@@ -308,7 +308,9 @@ void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
   jd->tier_lo = lo;
   jd->n_tiers = 0;
   if (hi <= lo || pl.n_m == 0) return;
-  const double mw = (double)pl.job.m_inc * (double)(pl.w + 1);
+  // positions the large branch visits per prime: every m, or every odd m when d is even
+  const double walked = (pl.job.d & 1) ? (double)pl.job.m_inc : ceil(0.5 * (double)pl.job.m_inc);
+  const double mw = walked * (double)(pl.w + 1);
   const double H = (double)pl.hits_per_item;
   uint64_t b = lo;
   uint32_t nt = 0;
@@ -340,6 +342,7 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.d = j.d;
   jd.m_start = j.m_start;
   jd.m_inc = j.m_inc;
+  jd.m_step = (j.d & 1) ? 1u : 2u;
   jd.limit = j.limit;
   jd.thr = pl.thr;
   jd.p_lo = 2;
