@@ -54,6 +54,8 @@ def _args():
                          "p50 35 ms, p99 142 ms at 0.8x; 4 chunks: 156 jobs/s, 48 ms, 193 ms)")
     ap.add_argument("--prp-rows", type=int, default=16384,
                     help="rows of the sieved job searched for their surrounding probable primes (0: skip)")
+    ap.add_argument("--no-atomic-probe", action="store_true",
+                    help="skip the random-atomics rate probe that the roofline of the byte-counter scatter uses")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (a known-size reference for "
                          "HBM byte counters)")
@@ -240,6 +242,29 @@ def _cpu_baseline(job, n_rows, p_max):
             "sample": f"{len(ms)} rows of {lay.n_m} (first, last, record-gap row, seeded), primes <= "
                       f"{min(p_max, job.limit)}, plain per-interval sieve with bignum N mod p "
                       f"(direct mode), {dt:.1f} s wall"}
+
+
+def _atomic_probe(torch, n_words, n_atomics, seed=7):
+    """Rate of device-scope 32-bit atomic adds at uniformly random words of an n_words buffer
+    (torch's scatter_add_ on int32, one atomic add per element): the access pattern of the
+    byte-counter scatter, measured on this GPU.  Returns atomics per second."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    buf = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+    idx = torch.randint(0, n_words, (n_atomics,), device="cuda", generator=g)
+    one = torch.ones(n_atomics, dtype=torch.int32, device="cuda")
+    buf.scatter_add_(0, idx, one)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    buf.scatter_add_(0, idx, one)
+    e1.record()
+    torch.cuda.synchronize()
+    assert int(buf.to(torch.int64).sum().item()) == 2 * n_atomics
+    rate = n_atomics / (e0.elapsed_time(e1) / 1e3)
+    del buf, idx, one
+    torch.cuda.empty_cache()
+    return rate
 
 
 def _kernel_profile(mode):
@@ -501,6 +526,17 @@ def main():
             "ops_per_launch": ops, "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"],
             "valu_issue_frac": _valu_issue(args.mode),
             "valu_issue_source": "rocprofv3 SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time), profiles/"}
+    if lay.scatter == cs.SCATTER_BYTES and not args.no_atomic_probe:
+        # the hits are device-scope atomic adds into byte counters: their rate against the rate of
+        # the same atomics at random words of a buffer of the same size
+        n_words = lay.n_m * lay.row_words * 8
+        rate = _atomic_probe(torch, n_words, 1 << 28)
+        hits = diag_ph.large_hits
+        roof["atomics"] = {"count": hits, "achieved_per_s": hits / t_large, "probe_per_s": rate,
+                           "frac": hits / t_large / rate,
+                           "probe": f"torch scatter_add_ of 2^28 int32 ones at uniformly random words of "
+                                    f"{n_words * 4 / 2**30:.2f} GiB (the byte counters' size)"}
+        print(f"# atomics: {hits / t_large:.3e}/s in k_large, probe {rate:.3e}/s", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC, "value": value, "unit": "factors/s", "n_gpus": 1, "steps": args.steps,

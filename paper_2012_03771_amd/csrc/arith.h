@@ -57,17 +57,18 @@ CS_HD float rcp_f32(float x) {
 
 // The rest of an extended Euclidean pass once the remainders (a, b) are below 2^20, for the
 // Bezout coefficients alone: (a, b, sa, sb) with sa*k == a and sb*k == b (mod p) become
-// (gcd, 0, s, .) with s*k == gcd (mod p).  Integers below 2^20 are exact in fp32; the product of
-// a and the one-ulp reciprocal of b is within a relative 2^-22 of a/b < 2^20, so its floor is off
-// by at most one and one exact fma and one correction each way give the quotient.  The
-// coefficients stay below p in magnitude and are updated in fp64.
+// (gcd, 0, s, .) with s*k == gcd (mod p).  Integers below 2^20 are exact in fp32.  The product of
+// a and a reciprocal of b within 1.5 units in the last place is within a relative 2^-22 of a/b,
+// an absolute error below a * 2^-22 / b < 1/b.  The fractional part of a/b is 0 or at least 1/b,
+// so the floor is exact unless b divides a, when it may be one low (remainder b): one exact fma
+// and one upward correction give the quotient.  The coefficients stay below p in magnitude and
+// are updated in fp64.
 CS_HD void euclid_tail_f32(double* a, double* b, double* sa, double* sb) {
   float af = (float)*a, bf = (float)*b;
   double s0 = *sa, s1 = *sb;
   for (int it = 0; it < 64 && bf != 0.0f; ++it) {   // at most 30 steps below 2^20 (Fibonacci)
     float q = floorf(af * rcp_f32(bf));
     float r = fmaf(-q, bf, af);
-    if (r < 0.0f) { r += bf; q -= 1.0f; }
     if (r >= bf) { r -= bf; q += 1.0f; }
     const double s2 = fma(-(double)q, s1, s0);
     af = bf; bf = r; s0 = s1; s1 = s2;
@@ -136,9 +137,8 @@ CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
   double s0 = 0.0, s1 = 1.0;          // s_i * k == r_i (mod p)
   for (int it = 0; it < 128 && b != 0.0 && a >= 1048576.0; ++it) {
     double inv = recip(b);
-    double q = floor(a * inv);
+    double q = floor(a * inv);                 // a < 2^42: exact or one low (as in g_offset)
     double r = fma(-q, b, a);
-    if (r < 0.0) { r += b; q -= 1.0; }
     if (r >= b) { r -= b; q += 1.0; }
     double s2 = fma(-q, s1, s0);
     a = b; b = r; s0 = s1; s1 = s2;
@@ -176,11 +176,16 @@ CS_HD double g_offset(double p, double K, double L, double width, int* levels_ou
     L = mir ? p - L - width : L;
     K = mir ? p - K : K;
     par ^= mir ? 1 : 0;
+    // L, p < 2^42 and inv within 1.5 units in the last place: L*inv is within (L/K) 2^-51 < 1/K
+    // of L/K, whose fractional part is 0 or at least 1/K, so its floor is exact unless K divides
+    // L, when it may be one low.  The remainders below are therefore in [0, K], K standing for 0:
+    // both give up = 0, and p mod K is never 0 or K (gcd(p, K) = 1, K > 1 here since K = 1
+    // always ends in (c)).
     const double inv = recip(K);
-    const double rem = fmod_inv(L, K, inv);                    // L mod K
+    const double rem = fma(-floor(L * inv), K, L);             // L mod K, or K for 0
     const double up = rem == 0.0 ? 0.0 : K - rem;              // ceil(L/K)*K - L
     if (up <= width) { off = up; break; }                      // (c)
-    const double pm = fmod_inv(p, K, inv);                     // p mod K (nonzero: gcd = 1)
+    const double pm = fma(-floor(p * inv), K, p);              // p mod K, in (0, K)
     p = K;                                                      // (e)
     K = (pm == 0.0) ? 0.0 : K - pm;
     L = rem;
@@ -244,9 +249,9 @@ CS_HD int three_gap_setup(uint64_t p, uint64_t k, uint64_t kinv, double pinv, ui
 // Requires 1 <= k < p < 2^42 prime, 1 <= w, p > 2w.  Returns 0 only on an internal failure.
 CS_HD void tg_side(double a, double b, double inv, double sa, double sb, double wd, double* t, double* v) {
   const double num = a - wd + b - 1.0;          // j = ceil((a - w) / b), a > w
-  double j = floor(num * inv);
+  double j = floor(num * inv);                  // num < 2^43: exact or one low
   const double rj = fma(-j, b, num);
-  j = rj < 0.0 ? j - 1.0 : (rj >= b ? j + 1.0 : j);
+  j = rj >= b ? j + 1.0 : j;
   *t = fma(j, fabs(sb), fabs(sa));
   *v = fma(-j, b, a);                           // residue on this side, in [1, w]
 }
@@ -261,8 +266,7 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
     for (; it < 160; ++it) {
       inv = recip(b);
       double q = floor(a * inv);
-      r = fma(-q, b, a);
-      if (r < 0.0) { r += b; q -= 1.0; }
+      r = fma(-q, b, a);                      // a < 2^42: exact or one low
       if (r >= b) { r -= b; q += 1.0; }
       sn = fma(-q, sb, sa);                   // s_{i+1}, same side as s_{i-1}
       if (r <= wd) break;                     // the first remainder at or below w
@@ -279,7 +283,6 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
     inv = recip(b);
     double q = floor(a * inv);
     r = fma(-q, b, a);
-    if (r < 0.0) { r += b; q -= 1.0; }
     if (r >= b) { r -= b; q += 1.0; }
     sn = fma(-q, sb, sa);
     tg_side(a, b, inv, sa, sb, wd, &t2, &v2); // negative side from the step (p, k)
@@ -291,7 +294,6 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
     inv = recip(b);
     double q = floor(a * inv);
     r = fma(-q, b, a);
-    if (r < 0.0) { r += b; q -= 1.0; }
     if (r >= b) { r -= b; q += 1.0; }
     sn = fma(-q, sb, sa);
     tg_side(a, b, inv, sa, sb, wd, &t2, &v2);
