@@ -102,22 +102,33 @@ CS_HD uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p, double pinv) {
   return (uint64_t)r;
 }
 
-// r*g mod p in fp64 alone, for 0 <= r < p < 2^42, 1 <= g < 2^50 and pinv = 1/p correctly
-// rounded: h + l = r*g exactly (h the rounded product, l = fma(r, g, -h) its error, |l| < p/8
-// because h < p*2^50); the floor of h*pinv is within one of h/p, so h - q*p lies in [-p, 2p) and
-// the fma forms it exactly; adding l gives an exact integer in (-2p, 3p), reduced once more the
-// same way.
-// Eleven fp64 operations against about three times as many for mulmod's integer wrap-around.
-CS_HD double mulmod_f64(double r, double g, double p, double pinv) {
+// r*g modulo p up to a small multiple of p, in fp64 alone, for |r| < 2.5p, 1 <= g < 2^50,
+// p < 2^42 and pinv = 1/p correctly rounded: h + l = r*g exactly (h the rounded product,
+// l = fma(r, g, -h) its error, |l| <= |h| 2^-53 < 0.32p); h*pinv is within 0.63 of h/p, so its
+// floor q is within one of floor(h/p), h - q*p lies in [-p, 2p) and the fma forms it exactly.
+// The result h - q*p + l is an exact integer congruent to r*g with |x| < 2.32p, a valid r again:
+// a chain of products needs one full reduction at its end (reduce_f64).
+CS_HD double mulmod_f64_lazy(double r, double g, double p, double pinv) {
   const double h = r * g;
   const double l = fma(r, g, -h);
   const double q = floor(h * pinv);
-  const double x = fma(-q, p, h) + l;
-  const double q2 = floor(x * pinv);
-  double y = fma(-q2, p, x);
+  return fma(-q, p, h) + l;
+}
+
+// x mod p in [0, p) for an integer |x| < 2.5p (p < 2^42, pinv = 1/p correctly rounded): the floor
+// of x*pinv is within one of floor(x/p), and one correction each way finishes.
+CS_HD double reduce_f64(double x, double p, double pinv) {
+  const double q = floor(x * pinv);
+  double y = fma(-q, p, x);
   y = y < 0.0 ? y + p : y;
-  y = y >= p ? y - p : y;
-  return y;
+  return y >= p ? y - p : y;
+}
+
+// r*g mod p in [0, p), for 0 <= r < p < 2^42, 1 <= g < 2^50: one lazy product and one
+// reduction, eleven fp64 operations against about three times as many for mulmod's integer
+// wrap-around.
+CS_HD double mulmod_f64(double r, double g, double p, double pinv) {
+  return reduce_f64(mulmod_f64_lazy(r, g, p, pinv), p, pinv);
 }
 
 // x mod p for any 64-bit x and p < 2^42.

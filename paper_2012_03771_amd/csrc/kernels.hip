@@ -450,22 +450,23 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
       const uint32_t ng = gbl(j0.ctrl)->n_kgroups;
       const gptr<const uint64_t> G = gbl(j0.kgroups);
       const double pd0 = (double)p0, pd1 = (double)p1;
+      // lazily reduced products (|x| < 2.32p all along), one full reduction at the end
       double x0 = p0 == 1 ? 0.0 : 1.0, x1 = p1 == 1 ? 0.0 : 1.0;
       if (g_lds) {
         for (uint32_t t = 0; t < ng; ++t) {
           const double gg = s_g[t];
-          x0 = mulmod_f64(x0, gg, pd0, v0);
-          x1 = mulmod_f64(x1, gg, pd1, v1);
+          x0 = mulmod_f64_lazy(x0, gg, pd0, v0);
+          x1 = mulmod_f64_lazy(x1, gg, pd1, v1);
         }
       } else {
         for (uint32_t t = 0; t < ng; ++t) {
           const double gg = (double)G[t];
-          x0 = mulmod_f64(x0, gg, pd0, v0);
-          x1 = mulmod_f64(x1, gg, pd1, v1);
+          x0 = mulmod_f64_lazy(x0, gg, pd0, v0);
+          x1 = mulmod_f64_lazy(x1, gg, pd1, v1);
         }
       }
-      r0 = (uint64_t)x0;
-      r1 = (uint64_t)x1;
+      r0 = (uint64_t)reduce_f64(x0, pd0, v0);
+      r1 = (uint64_t)reduce_f64(x1, pd1, v1);
     } else {
       auto kof = [](const JobDev& j, uint64_t i, uint64_t p, double v) {
         if (j.kmod_cached) return (uint64_t)gbl(j.kmod)[i];

@@ -1,6 +1,7 @@
 // Host-side check of the kernels' arithmetic header against brute force.
 // Built and run by tests/test_arith_host.py with g++ (the header's functions are plain inline
 // C++ outside hipcc).  Exit status 0 means every case agreed.
+#include <cmath>
 #include <cstdio>
 #include <cstdint>
 #include <cstdlib>
@@ -92,6 +93,28 @@ int main(int argc, char** argv) {
     const double pinv = 1.0 / (double)p;
     const double got = cs::mulmod_f64((double)r, (double)g, (double)p, pinv);
     if ((uint64_t)got != (uint64_t)((u128)r * g % p) || got < 0.0) { bad = fail("mulmod_f64", r, g, p, (uint64_t)got); break; }
+  }
+  // chains of lazily reduced products (the K mod p kernel): |x| stays below 2.32p, and one
+  // reduction at the end gives the product of the chain mod p
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t p = (rng() >> (22 + rng() % 42)) | 1;
+    if (p >= (1ull << 42)) p &= (1ull << 42) - 1;
+    if (i % 9 == 0) p = (1ull << 42) - 1 - 2 * (rng() % 1000);
+    if (p < 3) p = 3;
+    const double pd = (double)p, pinv = 1.0 / pd;
+    const int len = 1 + (int)(rng() % 300);
+    double x = 1.0;
+    uint64_t want = 1 % p;
+    for (int t = 0; t < len && !bad; ++t) {
+      uint64_t g = (rng() >> (14 + rng() % 50)) | 1;
+      if (g >= (1ull << 50)) g &= (1ull << 50) - 1;
+      if (rng() % 3 == 0) g = (1ull << 50) - 1 - rng() % 1000;
+      x = cs::mulmod_f64_lazy(x, (double)g, pd, pinv);
+      want = (uint64_t)((u128)want * g % p);
+      if (!(fabs(x) < 2.32 * pd) || x != floor(x)) bad = fail("mulmod_f64_lazy_bound", p, g, (uint64_t)t, 0);
+    }
+    const double got = cs::reduce_f64(x, pd, pinv);
+    if (!bad && (got < 0.0 || (uint64_t)got != want)) bad = fail("mulmod_f64_lazy_chain", p, want, (uint64_t)got, 0);
   }
   for (int i = 0; i < 20000 && !bad; ++i) {
     uint64_t p;
