@@ -780,6 +780,59 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
   }
   // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
   const uint64_t sp_lo = max(s_lo, min(a.small_dense, s_hi));
+  if (j.thr < (1ull << 31)) {
+    // every small prime (<= thr) is below 2^31: residues in 32-bit registers (s + p - k < 2^32,
+    // jj + p < 2^32), and the marks of a row counted by ballots (a lane marks a row at most
+    // once when p > w; the full reduction runs only for a row where some lane marked twice)
+    for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
+      const uint64_t i = ib + threadIdx.x;
+      bool act = i < s_hi;
+      uint64_t p = 3, k = 0, mk = 0;
+      if (act) { p = primes[i]; k = kmod[i]; mk = mkp[i]; }
+      act = act && k != 0 && !(dpat && p <= P);
+      const double pinv = 1.0 / (double)p;
+      const uint32_t p32 = (uint32_t)p, k32 = (uint32_t)k;
+      uint32_t s32 = 0;
+      uint32_t o_prev = 0;
+      if (R > 0) {
+        o_prev = a.moff[0];
+        uint64_t rn = mk + mulmod(o_prev, k, p, pinv);
+        rn = rn >= p ? rn - p : rn;
+        s32 = (uint32_t)sub_mod(mod64(sl, p, pinv), rn, p);
+      }
+      const uint32_t na = (uint32_t)__popcll(__ballot(act));
+      for (uint32_t r = 0; r < R; ++r) {
+        if (r > 0) {
+          const uint32_t o = a.moff[r];
+          const uint32_t dm = o - o_prev;           // same for every lane
+          o_prev = o;
+          if (dm <= 12) {
+            for (uint32_t t = 0; t < dm; ++t) s32 = s32 >= k32 ? s32 - k32 : s32 + p32 - k32;
+          } else {
+            s32 = (uint32_t)sub_mod(s32, mulmod(dm, k, p, pinv), p);
+          }
+        }
+        uint32_t cc = 0;
+        if (act) {
+          for (uint32_t jj = s32; jj <= w; jj += p32) {
+            uint32_t col;
+            if (lookup_col(ct, jj, &col)) {
+              atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+              ++cc;
+            }
+          }
+        }
+        const unsigned long long many = __ballot(cc > 1);
+        const uint32_t tot = many ? wave_sum_u32(cc) : (uint32_t)__popcll(__ballot(cc != 0));
+        if (lane == 0) {
+          if (tot) atomicAdd(&cnt[r], tot);
+          n_marks += tot;
+        }
+      }
+      if (lane == 0) n_pairs += (unsigned long long)na * R;
+    }
+    return;
+  }
   for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
     const uint64_t i = ib + threadIdx.x;
     bool act = i < s_hi;

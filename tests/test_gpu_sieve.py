@@ -158,6 +158,28 @@ def test_range_calls_compose():
     assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref_c)
 
 
+@pytest.mark.parametrize("thr", [2**31 - 1, 2**32], ids=["thr_below_2^31", "thr_2^32"])
+def test_small_branch_primes_above_2_31(thr):
+    """Small-branch primes just above 2^31 (a threshold set at or beyond 2^31 sends them through
+    the 64-bit residue path of the small branch, one below it through the large branch): the marks
+    of every row equal the oracle's."""
+    lo, hi = 2**31, 2**31 + 2**22
+    job = W.Job(61, 6, 1000, 4000, 3000, hi)
+    tune = cs.Tune(thr=thr, large_mode=cs.LARGE_THREE_GAP)
+    _say("small branch above 2^31", thr)
+    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
+    bitmap.zero_()
+    counts.zero_()
+    cs.prepare(job, ws, tune)
+    cs.sieve_range(job, lo, hi, bitmap, counts, ws, tune)
+    torch.cuda.synchronize()
+    m_all = coracle.rows(job.d, job.m_start, job.m_inc)
+    want_b, want_c = coracle.sieve_rows(job.P, job.d, job.sl, m_all, lo, hi, mode=coracle.CACHED)
+    assert want_c.sum() > 100
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), want_c)
+    assert np.array_equal(bitmap.cpu().numpy().view(np.uint32), want_b)
+
+
 def test_window_hits_503_from_large_branch(paper_values):
     """Section 3.2's statistics for N = 503#/210, X = 1e5, reproduced by the large branch's own
     count of Eq. 3 solutions (one m, so each hit is one prime dividing the interval)."""
