@@ -24,8 +24,11 @@ namespace cs {
 namespace {
 
 constexpr int kPrpBlock = 256;
-constexpr uint32_t kSurroundB0 = 8;        // candidates per side and round while many sides are open
-constexpr uint32_t kSurroundBMax = 1024;   // ... and at most, once few are left
+// Candidates per open side and round: at least kSurroundB0, and enough for one wavefront per SIMD
+// (the test kernel holds one wavefront per SIMD, so a round of fewer candidates costs as much),
+// at most kSurroundBMax.  Small rounds waste few tests past each side's first probable prime.
+constexpr uint32_t kSurroundB0 = 2;
+constexpr uint32_t kSurroundBMax = 1024;
 constexpr uint64_t kSurroundSlotsMin = 1u << 18;
 
 // out = v - n if (v >= n or hi_set) else v, for v < 2n given as NL limbs plus the bit hi_set.
@@ -567,6 +570,7 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
   double test_ms = 0.0;
   cs_status result = CS_OK;
   uint32_t n_open = (uint32_t)tasks;
+  const uint64_t round_target = std::min<uint64_t>(L.slots, (uint64_t)device_cu_count() * 4u * 64u);
   uint32_t in = 0;
   uint64_t rounds = 0;
   unsigned long long run = 0;
@@ -575,8 +579,8 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
     hipLaunchKernelGGL(k_sv_init, dim3((uint32_t)((tasks + 255) / 256)), dim3(256), 0, s, sv);
     if (record_launch("k_sv_init") != hipSuccess) { result = CS_EDEVICE; break; }
     while (n_open) {
-      uint64_t B = L.slots / n_open;
-      B = std::min<uint64_t>(std::max<uint64_t>(B, 1), kSurroundBMax);
+      uint64_t B = std::max<uint64_t>(round_target / n_open, kSurroundB0);
+      B = std::min<uint64_t>(std::min<uint64_t>(B, kSurroundBMax), L.slots / n_open);
       const uint32_t b32 = (uint32_t)B;
       const uint32_t g = (n_open + 255) / 256;
       if (launch_fill_u32(sv.n_act + (in ^ 1), 1, 0u, s) != hipSuccess) { result = CS_EDEVICE; break; }
