@@ -22,7 +22,6 @@ METRIC = "factors found/s + primes/s on 953#/210 sieve; served-job p50/p99 laten
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> 39.3e12 VALU lane-operations per second
 # (the fp64 FMA rate, 78.6 TFLOP/s, counts two flops per such operation).
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
-HBM_PEAK_GB_S = 8000.0        # MI355X HBM3E, published
 HBM_PEAK = 8.0e12
 # v_mad_u64_u32 (32 x 32 -> 64-bit multiply-add, the limb product of the probable-prime test)
 # issues at the full VALU rate on gfx950 (an independent-chain probe measured 3.4e13/s).
@@ -530,7 +529,7 @@ def main():
     if roof["traffic"] is not None:
         # the same launch against the HBM roofline: measured bytes over the launch time
         roof["hbm_achieved_gb_s"] = roof["traffic"] / t_large
-        roof["hbm_frac"] = roof["traffic"] / t_large / (HBM_PEAK_GB_S)
+        roof["hbm_frac"] = roof["traffic"] * 1e9 / t_large / HBM_PEAK
     if lay.scatter == cs.SCATTER_BYTES and not args.no_atomic_probe:
         # the hits are device-scope atomic adds into byte counters: their rate against the rate of
         # the same atomics at random words of a buffer of the same size
