@@ -172,3 +172,18 @@ def test_chunked_plan():
     assert lay.ws_bytes < whole.ws_bytes / 2
     assert 105_000_000 < lay.prime_cap < 106_000_000          # pi(2^31) = 105,097,565, plus a margin
     assert (lay.n_m, lay.n_x, lay.row_words) == (whole.n_m, whole.n_x, whole.row_words)
+
+
+def test_chunked_range_validation():
+    """cs_sieve_chunked_range rejects a zero span and a missing workspace before any device work;
+    chunked plans take limits below 2^42 and reject 2^42."""
+    import ctypes as C
+    L = cs.binding.lib()
+    job = cs.binding._cjob(W.Job(61, 6, 1000, 100, 500, 10**8))
+    assert L.cs_sieve_chunked_range(C.byref(job), None, 0, 2, 100, None, None, None, 0, None) == -1
+    assert L.cs_sieve_chunked_range(C.byref(job), None, 1 << 25, 2, 100, None, None, None, 0, None) == -1
+    lay = cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42 - 1), 1 << 36)
+    assert lay.prime_cap < 3 * 10**9                         # one chunk's table, not pi(2^42)
+    with pytest.raises(cs.CsError) as e:
+        cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42), 1 << 36)
+    assert e.value.status == -2
