@@ -224,3 +224,57 @@ def test_prime_range_split_is_additive():
     hi = coracle.sieve_rows(job.P, job.d, job.sl, ms, 5004, job.limit)
     assert np.array_equal(full[0], lo[0] | hi[0])
     assert np.array_equal(full[1], lo[1] + hi[1])
+
+
+def _is_prime_mr(n: int) -> bool:
+    """Deterministic Miller-Rabin below 3.4e14 (bases 2..17), for pinning the oracle's primes."""
+    if n < 2:
+        return False
+    for q in (2, 3, 5, 7, 11, 13, 17):
+        if n % q == 0:
+            return n == q
+    dd, s = n - 1, 0
+    while dd % 2 == 0:
+        dd //= 2
+        s += 1
+    for a in (2, 3, 5, 7, 11, 13, 17):
+        x = pow(a, dd, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def test_oracle_near_2_42():
+    """At the largest primes the library takes (just below 2^42): the oracle's primes are the
+    primes, its N mod p equals Python's big-integer N mod p, its bignum and cached residues
+    (Eq. 1) give the same rows over a window of primes, and every mark it makes there has a
+    witness prime that divides N + X."""
+    P, d, sl = 61, 6, 131000
+    K = plain.K_of(P, d)
+    lo, hi = 2**42 - 2**20, 2**42 - 1
+    ps = coracle.primes_range(lo, hi)
+    sample = [int(p) for p in ps[:: max(1, len(ps) // 400)]]
+    assert all(_is_prime_mr(p) for p in sample)
+    gaps = [n for n in range(hi - 3000, hi + 1) if _is_prime_mr(n)]
+    assert [int(p) for p in ps if p > hi - 3000] == gaps          # no prime missed at the top
+    m = 10**6 + 1
+    got = coracle.n_mod(P, d, m, ps[:3000])
+    assert [int(v) for v in got] == [(m * K) % int(p) for p in ps[:3000]]
+    ms = coracle.rows(d, 10**6, 48000)
+    a_b, a_c = coracle.sieve_rows(P, d, sl, ms, lo, hi, mode=coracle.DIRECT)
+    b_b, b_c = coracle.sieve_rows(P, d, sl, ms, lo, hi, mode=coracle.CACHED)
+    assert np.array_equal(a_b, b_b) and np.array_equal(a_c, b_c)
+    xs = [int(x) for x in coracle.columns(P, d, sl)]
+    hit = ms[np.nonzero(a_c)[0]]                       # witnesses only for the rows with marks
+    h_b, h_c, wit = coracle.sieve_rows(P, d, sl, hit, lo, hi, mode=coracle.DIRECT, witness=True)
+    marked = np.argwhere(plain.unpack(h_b, len(xs)))
+    assert len(marked) >= 3 and len(marked) == int(a_c.sum()) == int(h_c.sum())
+    for r, c in marked:
+        w = int(wit[r, c])
+        assert lo <= w <= hi and (int(hit[r]) * K + xs[c]) % w == 0
