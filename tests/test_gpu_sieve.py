@@ -229,3 +229,41 @@ def test_large_kernel_time_is_reported():
     e1.record(s)
     d = cs.diag_read(ws)
     assert 0.0 < d.large_kernel_ms <= e0.elapsed_time(e1)
+
+
+def _random_cases(seed, n):
+    """Seeded random small jobs and tunings (P <= 101, d a product of P's smallest primes, m_start
+    and m_inc from 1, limits to 1e6, every enumeration, scatter and threshold kind); invalid
+    combinations (e.g. d not squarefree) are dropped by the planner."""
+    import random
+    rng = random.Random(seed)
+    primes = [int(p) for p in coracle.primes_range(2, 101)]
+    out = []
+    while len(out) < n:
+        P = rng.choice(primes)
+        small = [q for q in primes if q <= P]
+        d = 1
+        for q in small[:6]:
+            if rng.random() < 0.4:
+                d *= q
+        job = W.Job(P, d, rng.choice([1, 2, 3, rng.randrange(1, 10**6)]), rng.choice([1, 2, 3, rng.randrange(1, 400)]),
+                    rng.randrange(1, 600), rng.choice([rng.randrange(2, 2000), rng.randrange(2, 10**6)]))
+        tune = cs.Tune(large_mode=rng.choice([cs.LARGE_G, cs.LARGE_THREE_GAP]),
+                       thr=rng.choice([0, 0, 1, rng.randrange(1, 5000), 10**9]),
+                       scatter=rng.choice([cs.SCATTER_AUTO, cs.SCATTER_ATOMIC, cs.SCATTER_BYTES, cs.SCATTER_LIST]))
+        try:
+            cs.plan(job, tune)
+        except cs.CsError:
+            continue
+        out.append((job, tune))
+    return out
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_random_jobs_match_oracle(seed):
+    """60 seeded random jobs per seed: bitmap and counts equal the oracle's (bignum residues)."""
+    for job, tune in _random_cases(seed, 60):
+        _say("random", seed, job, tune.large_mode, tune.thr, tune.scatter)
+        got_b, got_c, _, _ = _run(job, tune)
+        want_b, want_c = _oracle(job, mode=coracle.DIRECT)
+        _assert_same(job, got_b.reshape(want_b.shape), got_c, want_b, want_c)
