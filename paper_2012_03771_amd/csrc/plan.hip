@@ -140,8 +140,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 5 M / M_c (half the paper's 10 M / M_c, measured faster on gfx950); with three-gap stepping
   // a hit costs a few operations and the small branch runs beside the large one, so twice the
-  // paper's naive 10 S is used (measured at 953#/210: step 113 ms at 10 S, 108 ms at 20 S,
-  // 124 ms at 30 S).  Clamped so that a large prime divides at most one number of an interval
+  // paper's naive 10 S is used (measured at 953#/210: step 101 ms at 20 S, 99 ms at 25 S,
+  // 104 ms at 30 S, 114 ms at 40 S).  Clamped so that a large prime divides at most one number of an interval
   // (p > 2 sl), or (three-gap) p > 4 sl.
   uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
@@ -276,8 +276,9 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
                       (double)chunks * kListChunk < 4294967296.0;
       if (scatter == CS_SCATTER_LIST && !ok) return CS_EINVAL;
       // AUTO does not take the list: its grouping passes cost more than the atomics they remove
-      // (measured at the paper scale: large branch 145 ms with the list, 131 ms with the byte
-      // counters).
+      // (measured at the paper scale: large-prime kernel 53 ms plus 35 ms of grouping with the
+      // list, and a step of 153 ms without the small branch alongside, against 84 ms and a
+      // 101 ms step with the byte counters).
       if (ok && scatter == CS_SCATTER_LIST) {
         pl.scatter_list = true;
         pl.list_chunks = tune && tune->list_chunks ? std::min<uint64_t>(tune->list_chunks, chunks) : chunks;
