@@ -102,7 +102,7 @@ CS_HD uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p, double pinv) {
   return (uint64_t)r;
 }
 
-// r*g modulo p up to a small multiple of p, in fp64 alone, for |r| < 2.5p, 1 <= g < 2^50,
+// r*g modulo p up to a small multiple of p, in fp64 alone, for |r| < 2.5p, 0 <= g < 2^50,
 // p < 2^42 and pinv = 1/p correctly rounded: h + l = r*g exactly (h the rounded product,
 // l = fma(r, g, -h) its error, |l| <= |h| 2^-53 < 0.32p); h*pinv is within 0.63 of h/p, so its
 // floor q is within one of floor(h/p), h - q*p lies in [-p, 2p) and the fma forms it exactly.
@@ -124,7 +124,7 @@ CS_HD double reduce_f64(double x, double p, double pinv) {
   return y >= p ? y - p : y;
 }
 
-// r*g mod p in [0, p), for 0 <= r < p < 2^42, 1 <= g < 2^50: one lazy product and one
+// r*g mod p in [0, p), for 0 <= r < p < 2^42, 0 <= g < 2^50: one lazy product and one
 // reduction, eleven fp64 operations against about three times as many for mulmod's integer
 // wrap-around.
 CS_HD double mulmod_f64(double r, double g, double p, double pinv) {

@@ -477,11 +477,12 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
       r0 = kof(j0, i0, p0, v0);
       r1 = kof(j1, i1, p1, v1);
     }
+    // m_start K mod p: both factors below p < 2^42, so the fp64 product applies
     if (!j0.kmod_cached) gbl(j0.kmod)[i0] = r0;
-    gbl(j0.mk)[i0] = mulmod(mod64(j0.m_start, p0, v0), r0, p0, v0);
+    gbl(j0.mk)[i0] = (uint64_t)mulmod_f64((double)mod64(j0.m_start, p0, v0), (double)r0, (double)p0, v0);
     if (two) {
       if (!j1.kmod_cached) gbl(j1.kmod)[i1] = r1;
-      gbl(j1.mk)[i1] = mulmod(mod64(j1.m_start, p1, v1), r1, p1, v1);
+      gbl(j1.mk)[i1] = (uint64_t)mulmod_f64((double)mod64(j1.m_start, p1, v1), (double)r1, (double)p1, v1);
     }
   }
 }

@@ -90,6 +90,7 @@ int main(int argc, char** argv) {
     uint64_t g = (rng() >> (14 + rng() % 50)) | 1;
     if (g >= (1ull << 50)) g &= (1ull << 50) - 1;
     if (i % 7 == 0) g = (1ull << 50) - 1 - rng() % 1000;
+    if (i % 97 == 0) g = 0;                         // K mod p = 0 (p divides K)
     const double pinv = 1.0 / (double)p;
     const double got = cs::mulmod_f64((double)r, (double)g, (double)p, pinv);
     if ((uint64_t)got != (uint64_t)((u128)r * g % p) || got < 0.0) { bad = fail("mulmod_f64", r, g, p, (uint64_t)got); break; }
