@@ -60,8 +60,13 @@ struct JobDev {
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
   uint32_t kmod_cached;              // 1: kmod already holds K mod p (a shared table); only mk is built
-  uint32_t m_step;                   // 2 if d is even (every m coprime to d is odd): the large branch
-                                     // visits only odd m; else 1
+  // The large branch walks m of the residue classes mod m_step that can hold rows (bit c of
+  // m_classes: m = c mod m_step coprime to it; m_step divides d), one class after the other:
+  // 2 (odd m) when d is even, 6 (m = 1, 5 mod 6) with one solve per hit when 6 divides d, else 1.
+  uint32_t m_step;
+  uint32_t m_classes;
+  uint32_t m0_mod_step;              // m_start mod m_step
+  uint32_t pad_classes;
   // Marks of the primes dividing d depend only on m mod d: one packed row (and its factor
   // count) per residue class coprime to d, built once per job and OR-ed into each row's tile.
   uint32_t dpat_on;                  // pattern table built for this job

@@ -1249,22 +1249,21 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       chunk = div_small(li, npt);
       pi = t0 + (li - chunk * npt);
     }
-    // the walk's positions u: m = m_start + o_par + s u, s = m_step, u in [0, U); a chunk is a
-    // range of u
+    // the walk's positions: for each class c of m mod s (s = m_step), m = m_start + o_c + s u with
+    // o_c = (c - m_start) mod s and u in [0, U); a chunk is a range of u, shared by the classes
     const uint32_t s = j.m_step;
-    const uint64_t o_par = (s == 2 && (j.m_start & 1) == 0) ? 1 : 0;
-    const uint64_t U = s == 1 ? j.m_inc : (j.m_inc > o_par ? (j.m_inc - o_par + 1) / 2 : 0);
+    const uint64_t U = (j.m_inc + s - 1) / s;
     const uint64_t L = C == 1 ? U : div_small(U + C - 1, C);
     const uint64_t u_lo = (uint64_t)chunk * L;
     const uint64_t u_hi = min(u_lo + L, U);
     if (u_lo >= u_hi) break;
-    const uint64_t o_lo = o_par + s * u_lo;          // < m_inc
-    const uint64_t o_hi = o_par + s * u_hi;          // every visited o = o_par + s u < o_hi is < m_inc
 
     const uint64_t p = gbl(j.primes)[pi];
     const uint64_t k1 = gbl(j.kmod)[pi];
     uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
-    k = k >= p ? k - p : k;
+    k -= k >= 4 * p ? 4 * p : 0;                     // s <= 6: s K mod p < 8p before these
+    k -= k >= 2 * p ? 2 * p : 0;
+    k -= k >= p ? p : 0;
     const double pinv = 1.0 / (double)p;
     const uint64_t w = j.w;
     const uint32_t d32 = (uint32_t)j.d;
@@ -1280,81 +1279,94 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       err |= E_SOLVE;
       break;
     }
-    // residue of m*K + SL at m = m_start + o_lo
-    uint64_t r = gbl(j.mk)[pi] + mulmod(o_lo, k1, p, pinv);
-    r = r >= p ? r - p : r;
-    r += j.sl;                                       // sl < w < thr < p
-    r = r >= p ? r - p : r;
-    uint64_t o = o_lo;
-    MPos mp = {0, 0};
-    if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
+    // three-gap return times in offsets of m (a time past the chunk ends the walk, so the
+    // quotients below only matter for the times that are taken)
+    const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
+    uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
+    if (j.large_mode != 0 && d_small) {
+      mpos_divmod(sta, d32, inv_d, &aq, &ar);
+      mpos_divmod(stb, d32, inv_d, &bq, &br);
+      mpos_divmod(tab, d32, inv_d, &abq, &abr);
+    }
+    const uint64_t mk = gbl(j.mk)[pi];
+    for (uint32_t cls = 0; cls < s; ++cls) {
+      // list scatter: lanes that left the previous class's walk early catch up on the wavefront's
+      // chunk state before the next walk appends (every lane reaches this point)
+      if constexpr (kSc == 2) {
+        if (cls > 0) list_sync(lreg, lkey);
+      }
+      const uint64_t o_par = (cls + s - j.m0_mod_step) % s;
+      const uint64_t o_lo = o_par + s * u_lo;
+      // a class that cannot hold rows, or that ends before this chunk, is skipped
+      if (!((j.m_classes >> cls) & 1u) || o_lo >= j.m_inc) continue;
+      const uint64_t o_hi = min(o_par + s * u_hi, j.m_inc);   // visited o = o_par + s u < o_hi
+      // residue of m*K + SL at m = m_start + o_lo
+      uint64_t r = mk + mulmod(o_lo, k1, p, pinv);
+      r = r >= p ? r - p : r;
+      r += j.sl;                                     // sl < w < thr < p
+      r = r >= p ? r - p : r;
+      uint64_t o = o_lo;
+      MPos mp = {0, 0};
+      if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
 
-    if (j.large_mode == 0) {
-      // one solve of Eq. 3 per hit
-      while (true) {
+      if (j.large_mode == 0) {
+        // one solve of Eq. 3 per hit
+        while (true) {
+          if (r > w) {
+            int lv = 0;
+            uint64_t rn;
+            const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+            ++calls;
+            levels += (unsigned)lv;
+            if (tstep == 0) { err |= E_SOLVE; break; }
+            o += s * tstep;
+            if (o >= o_hi) break;
+            r = rn;
+            if (d_small) {
+              uint32_t tq, tr;
+              mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
+              mpos_add(mp, tq, tr, d32);
+            }
+          }
+          ++raw;
+          record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
+          if ((o += s) >= o_hi) break;
+          if (d_small) mpos_add(mp, 0, s, d32);      // s <= d: one correction suffices
+          r += k;
+          r = r >= p ? r - p : r;
+        }
+      } else {
+        // three-gap stepping: one solve for the first hit, then the return times
         if (r > w) {
-          int lv = 0;
           uint64_t rn;
+          int lv = 0;
           const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
           ++calls;
           levels += (unsigned)lv;
           if (tstep == 0) { err |= E_SOLVE; break; }
           o += s * tstep;
-          if (o >= o_hi) break;
           r = rn;
-          if (d_small) {
+          if (d_small && o < o_hi) {
             uint32_t tq, tr;
             mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
             mpos_add(mp, tq, tr, d32);
           }
         }
-        ++raw;
-        record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
-        if ((o += s) >= o_hi) break;
-        if (d_small) mpos_add(mp, 0, s, d32);        // s <= d: one correction suffices
-        r += k;
-        r = r >= p ? r - p : r;
-      }
-    } else {
-      // three-gap stepping: one solve for the first hit, then the return times
-      if (r > w) {
-        uint64_t rn;
-        int lv = 0;
-        const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
-        ++calls;
-        levels += (unsigned)lv;
-        if (tstep == 0) { err |= E_SOLVE; break; }
-        o += s * tstep;
-        r = rn;
-        if (d_small && o < o_hi) {
-          uint32_t tq, tr;
-          mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
-          mpos_add(mp, tq, tr, d32);
+        const bool a_first = g.ta < g.tb;
+        // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
+        // arithmetic, and the three cases by selects rather than branches
+        const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
+        uint32_t r32 = (uint32_t)r;
+        while (o < o_hi) {
+          ++raw;
+          record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, useful, lreg);
+          const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
+          const bool ua = fa && (a_first || !fb);
+          const bool ub = !ua && fb;
+          o += ua ? sta : (ub ? stb : tab);
+          r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
+          mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
         }
-      }
-      // the return times in offsets of m (a time past the chunk ends the walk, so the quotients
-      // below only matter for the times that are taken)
-      const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
-      uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
-      if (d_small) {
-        mpos_divmod(sta, d32, inv_d, &aq, &ar);
-        mpos_divmod(stb, d32, inv_d, &bq, &br);
-        mpos_divmod(tab, d32, inv_d, &abq, &abr);
-      }
-      const bool a_first = g.ta < g.tb;
-      // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
-      // arithmetic, and the three cases by selects rather than branches
-      const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
-      uint32_t r32 = (uint32_t)r;
-      while (o < o_hi) {
-        ++raw;
-        record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, useful, lreg);
-        const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
-        const bool ua = fa && (a_first || !fb);
-        const bool ub = !ua && fb;
-        o += ua ? sta : (ub ? stb : tab);
-        r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
-        mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
       }
     }
     } while (0);

@@ -80,6 +80,9 @@ uint64_t host_row_count(const cs_job& job, const std::vector<uint32_t>& dq);
 
 // Fills the range-dependent part of a job descriptor (tiers for primes in (max(thr, p_lo-1), p_hi]).
 void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd);
+// Residue classes of m the large branch walks: stride *step (dividing d) and the bit mask of the
+// classes coprime to it.
+void walk_classes(const Plan& pl, uint32_t* step, uint32_t* classes);
 
 // Job descriptor with pointers into a workspace at `ws` (outputs left null).
 JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const uint64_t* n_primes);

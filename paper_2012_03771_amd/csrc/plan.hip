@@ -301,6 +301,24 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   return CS_OK;
 }
 
+void walk_classes(const Plan& pl, uint32_t* step, uint32_t* classes) {
+  // Only m coprime to d are rows.  Walking one class mod s costs one first solve per item and
+  // class, and visits 1/s of the m: with one solve per hit every visited m costs a solve, so the
+  // classes mod 6 pay when 6 | d (1/3 of the m for two first solves); three-gap stepping takes a
+  // few operations per visited m and keeps the single class mod 2.
+  const uint64_t d = pl.job.d;
+  if (pl.large_mode == CS_LARGE_G && d % 6 == 0) {
+    *step = 6;
+    *classes = (1u << 1) | (1u << 5);
+  } else if (d % 2 == 0) {
+    *step = 2;
+    *classes = 1u << 1;
+  } else {
+    *step = 1;
+    *classes = 1u;
+  }
+}
+
 void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
   const uint64_t lo = std::max<uint64_t>(pl.thr, p_lo > 0 ? p_lo - 1 : 0);
   const uint64_t hi = std::min<uint64_t>(p_hi, pl.job.limit);
@@ -309,8 +327,10 @@ void fill_tiers(const Plan& pl, uint64_t p_lo, uint64_t p_hi, JobDev* jd) {
   jd->tier_lo = lo;
   jd->n_tiers = 0;
   if (hi <= lo || pl.n_m == 0) return;
-  // positions the large branch visits per prime: every m, or every odd m when d is even
-  const double walked = (pl.job.d & 1) ? (double)pl.job.m_inc : ceil(0.5 * (double)pl.job.m_inc);
+  // positions the large branch visits per prime: the m of its residue classes
+  uint32_t step = 1, classes = 1;
+  walk_classes(pl, &step, &classes);
+  const double walked = ceil((double)pl.job.m_inc / step) * __builtin_popcount(classes);
   const double mw = walked * (double)(pl.w + 1);
   const double H = (double)pl.hits_per_item;
   uint64_t b = lo;
@@ -343,7 +363,8 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.d = j.d;
   jd.m_start = j.m_start;
   jd.m_inc = j.m_inc;
-  jd.m_step = (j.d & 1) ? 1u : 2u;
+  walk_classes(pl, &jd.m_step, &jd.m_classes);
+  jd.m0_mod_step = (uint32_t)(j.m_start % jd.m_step);
   jd.limit = j.limit;
   jd.thr = pl.thr;
   jd.p_lo = 2;
