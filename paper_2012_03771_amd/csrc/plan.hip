@@ -138,7 +138,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   pl.large_mode = mode;
 
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
-  // 5 M / M_c (half the paper's 10 M / M_c, measured faster on gfx950); with three-gap stepping
+  // 2.5 M / M_c (a quarter of the paper's 10 M / M_c: at 953#/210 the step is flat from 120,000
+  // to 437,507 = 2.5 M / M_c S, 216-218 ms, against 223 ms at 5 M / M_c S); with three-gap stepping
   // a hit costs a few operations and the small branch runs beside the large one, so twice the
   // paper's naive 10 S is used (measured at 953#/210: step 101 ms at 20 S, 99 ms at 25 S,
   // 104 ms at 30 S, 114 ms at 40 S).  Clamped so that a large prime divides at most one number of an interval
@@ -148,7 +149,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   uint64_t thr = tune && tune->thr ? tune->thr : 0;
   if (!thr) {
     double cm = mode == CS_LARGE_THREE_GAP ? 20.0
-                                           : (pl.n_m ? 5.0 * (double)j.m_inc / (double)pl.n_m : 5.0);
+                                           : (pl.n_m ? 2.5 * (double)j.m_inc / (double)pl.n_m : 2.5);
     thr = (uint64_t)(cm * (double)pl.S);
   }
   pl.thr = std::max(thr, thr_min);
