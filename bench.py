@@ -35,8 +35,8 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["g", "three_gap"], default="three_gap")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--cpu-rows", type=int, default=64)
-    ap.add_argument("--cpu-pmax", type=int, default=2**30)
+    ap.add_argument("--cpu-rows", type=int, default=2,
+                    help="rows of the job the oracle sieves with every prime up to the job's limit")
     ap.add_argument("--workload", default="paper_953")
     ap.add_argument("--phase-only", action="store_true", help="time the phases once, no steps")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-job batched leg")
@@ -44,8 +44,8 @@ def _args():
     ap.add_argument("--traffic-gb", type=float, default=None,
                     help="HBM traffic of one k_large launch from the committed FETCH_SIZE/WRITE_SIZE profile "
                          "of the same kernel (GB), reported as roofline.traffic")
-    ap.add_argument("--also-g", action="store_true",
-                    help="also time the phases once with one Eq. 5 solve per hit (the paper's enumeration)")
+    ap.add_argument("--no-g", action="store_true",
+                    help="skip timing the phases with one Eq. 5 solve per hit (the paper's enumeration, g_mode)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--serve-jobs", type=int, default=512)
     ap.add_argument("--serve-warmup", type=int, default=32)
@@ -56,6 +56,8 @@ def _args():
                     help="rows of the sieved job searched for their surrounding probable primes (0: skip)")
     ap.add_argument("--no-atomic-probe", action="store_true",
                     help="skip the random-atomics rate probe that the roofline of the byte-counter scatter uses")
+    ap.add_argument("--scatter-table", action="store_true",
+                    help="instead of the step benchmark: the scatter-rate probe over buffer sizes and modes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (a known-size reference for "
                          "HBM byte counters)")
@@ -213,58 +215,102 @@ def _mc_curve(cs, torch, W, np, args):
             "points": points, "rows_checked": check}
 
 
-def _cpu_baseline(job, n_rows, p_max):
-    """The oracle as it stands (plain per-interval sieve, bignum N mod p for every row and
-    prime) on a bounded sample: n_rows rows of the job and the primes <= p_max."""
+# Host threads of the CPU baseline: the host CPU share that the measurement box allots to one GPU
+# (16), or fewer where the process may use fewer cores.
+CPU_SHARE = 16
+
+
+def _cpu_baseline(job, n_rows, gpu_counts=None):
+    """The oracle as it stands (plain per-interval sieve, bignum N mod p for every row and prime,
+    Section 2.1) on a bounded sample of the workload itself: n_rows whole rows (the record-gap row
+    first, then the first rows), every prime up to the job's limit.  The oracle runs over rows; to
+    spread one row over the host threads its documented prime-range restriction is used: the range
+    [2, limit] is cut into windows of equal width, one oracle call per window, and the windows'
+    marks are OR-ed and their factors summed, which is the same definition restricted and
+    recombined.  Returns the oracle's factors/s on the sample and the whole job's time at that
+    rate (extrapolated, not measured)."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import workloads as W
     from oracle import coracle
     import paper_2012_03771_amd as cs
     lay = cs.plan(job)
+    ms_all = cs.rows(job)
     rec = W.RECORD_GAPS[0]
-    must = []
+    pick = []
     if (job.P, job.d) == (rec[0], rec[1]) and job.m_start <= rec[2] < job.m_start + job.m_inc:
-        ms_all = cs.rows(job)
-        must = [int(np.searchsorted(ms_all, rec[2]))]
-        rows = W.sample_rows(lay.n_m, n_rows, seed=11, must=must)
-        ms = ms_all[rows]
-    else:
-        ms_all = cs.rows(job)
-        rows = W.sample_rows(lay.n_m, n_rows, seed=11)
-        ms = ms_all[rows]
-    threads = len(os.sched_getaffinity(0))
-    threads = min(threads, 16)
+        pick.append(int(np.searchsorted(ms_all, rec[2])))
+    r = 0
+    while len(pick) < min(n_rows, lay.n_m):
+        if r not in pick:
+            pick.append(r)
+        r += 1
+    ms = ms_all[pick]
+    threads = max(1, min(len(os.sched_getaffinity(0)), CPU_SHARE))
+    n_win = 4 * threads
+    edges = [2] + [2 + (job.limit - 2) * (i + 1) // n_win for i in range(n_win)]
+    wins = [(edges[i] + (1 if i else 0), edges[i + 1]) for i in range(n_win)]
+
+    def one(w):
+        return coracle.sieve_rows(job.P, job.d, job.sl, ms, w[0], w[1], mode=coracle.DIRECT, threads=1)
+
     t0 = time.perf_counter()
-    _, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms, 2, min(p_max, job.limit),
-                                   mode=coracle.DIRECT, threads=threads)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(one, wins))
     dt = time.perf_counter() - t0
-    return {"value": float(counts.sum()) / dt, "unit": "factors/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(ms)} rows of {lay.n_m} (first, last, record-gap row, seeded), primes <= "
-                      f"{min(p_max, job.limit)}, plain per-interval sieve with bignum N mod p "
-                      f"(direct mode), {dt:.1f} s wall"}
+    bits = parts[0][0].copy()
+    counts = parts[0][1].astype(np.uint64)
+    for b, c in parts[1:]:
+        bits |= b
+        counts += c.astype(np.uint64)
+    factors = int(counts.sum())
+    out = {"value": factors / dt, "unit": "factors/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(ms)} whole rows of {lay.n_m} (m = {', '.join(str(int(m)) for m in ms)}), every prime "
+                     f"<= {job.limit}, plain per-interval sieve with bignum N mod p (direct mode), the prime "
+                     f"range in {n_win} windows over {threads} threads, {dt:.1f} s wall",
+           "sample_factors": factors, "sample_s": dt,
+           "extrapolated_job_s": dt * lay.n_m / len(ms),
+           "extrapolated_note": "the whole job at the sample's per-row time (not measured)"}
+    if gpu_counts is not None:
+        out["rows_equal_gpu"] = bool(np.array_equal(counts.astype(np.uint32), gpu_counts[pick]))
+    return out
 
 
-def _atomic_probe(torch, n_words, n_atomics, seed=7):
-    """Rate of device-scope 32-bit atomic adds at uniformly random words of an n_words buffer
-    (torch's scatter_add_ on int32, one atomic add per element): the access pattern of the
-    byte-counter scatter, measured on this GPU.  Returns atomics per second."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
+def _scatter_probe(cs, torch, n_words, n_ops, slices=1, op=0, seed=7):
+    """Rate of 32-bit operations at pseudo-random words of an n_words buffer (cs_probe_scatter: the
+    words come from a hash in registers, no index loads).  op 0 = device-scope atomic add (the
+    byte-counter scatter's operation), 1 = plain store, 2 = LDS atomic add; slices = 8 keeps each
+    XCD on its own eighth of the buffer.  Timed with HIP events on the launch stream after one
+    warm-up launch.  Returns operations per second."""
+    s = torch.cuda.current_stream()
     buf = torch.zeros(n_words, dtype=torch.int32, device="cuda")
-    idx = torch.randint(0, n_words, (n_atomics,), device="cuda", generator=g)
-    one = torch.ones(n_atomics, dtype=torch.int32, device="cuda")
-    buf.scatter_add_(0, idx, one)
+    cs.probe_scatter(buf, n_ops, slices, op, seed, s)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    buf.scatter_add_(0, idx, one)
-    e1.record()
+    e0.record(s)
+    cs.probe_scatter(buf, n_ops, slices, op, seed + 1, s)
+    e1.record(s)
     torch.cuda.synchronize()
-    assert int(buf.to(torch.int64).sum().item()) == 2 * n_atomics
-    rate = n_atomics / (e0.elapsed_time(e1) / 1e3)
-    del buf, idx, one
+    if op in (0, 2):
+        assert int(buf.to(torch.int64).sum().item()) == 2 * n_ops, "probe lost operations"
+    rate = n_ops / (e0.elapsed_time(e1) / 1e3)
+    del buf
     torch.cuda.empty_cache()
     return rate
+
+
+def _scatter_table(cs, torch):
+    """The probe over the buffer sizes and modes that bound the hit scatters."""
+    rows = []
+    for mib, slices, op in [(3 * 1024, 1, 0), (1024, 1, 0), (256, 1, 0), (64, 1, 0), (16, 8, 0), (3 * 1024, 1, 1),
+                            (256, 1, 1), (16, 8, 1), (1, 1, 2)]:
+        n_words = mib * 2**20 // 4
+        n_ops = 1 << 28
+        r = _scatter_probe(cs, torch, n_words, n_ops, slices, op)
+        rows.append({"MiB": mib, "slices": slices, "op": ["atomic_add", "store", "lds_atomic_add"][op],
+                     "ops_per_s": r})
+        print(f"# probe {mib} MiB slices {slices} op {op}: {r:.3e}/s", file=sys.stderr, flush=True)
+    return rows
 
 
 def _kernel_profile(mode):
@@ -447,6 +493,10 @@ def main():
         torch.cuda.set_device(0)
         print(json.dumps(_mc_curve(cs, torch, W, np, args)), flush=True)
         return
+    if args.scatter_table:
+        torch.cuda.set_device(0)
+        print(json.dumps({"metric": "scatter operations per second", "rows": _scatter_table(cs, torch)}), flush=True)
+        return
     if args.table_a2:
         torch.cuda.set_device(0)
         print(json.dumps(_table_a2(cs, torch, W, [int(x) for x in args.a2_rows.split(",")])), flush=True)
@@ -522,10 +572,16 @@ def main():
     roof = {"bound": "alu", "kernel": "k_large", "achieved": ops / t_large / 1e12, "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS,
             "traffic": args.traffic_gb if args.traffic_gb is not None else _kernel_traffic(args.mode),
-            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, profiles/)",
-            "ops_per_launch": ops, "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"],
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+            "traffic_source": "committed rocprofv3 counter profile of this kernel source (profiles/traffic.json), "
+                              "not measured by this run; null when the sources changed since",
+            "ops_per_launch": ops, "op_units": {"g_levels": diag_ph.g_levels, "g_calls": diag_ph.g_calls,
+                                                "raw_hits": diag_ph.large_raw_hits,
+                                                "large_primes": diag_ph.large_primes},
+            "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"],
             "valu_issue_frac": _valu_issue(args.mode),
-            "valu_issue_source": "rocprofv3 SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time), profiles/"}
+            "valu_issue_source": "committed rocprofv3 SQ_INSTS_VALU profile (profiles/traffic.json), not measured by "
+                                 "this run: x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time)"}
     if roof["traffic"] is not None:
         # the same launch against the HBM roofline: measured bytes over the launch time
         roof["hbm_achieved_gb_s"] = roof["traffic"] / t_large
@@ -534,12 +590,12 @@ def main():
         # the hits are device-scope atomic adds into byte counters: their rate against the rate of
         # the same atomics at random words of a buffer of the same size
         n_words = lay.n_m * lay.row_words * 8
-        rate = _atomic_probe(torch, n_words, 1 << 28)
+        rate = _scatter_probe(cs, torch, n_words, 1 << 28)
         hits = diag_ph.large_hits
         roof["atomics"] = {"count": hits, "achieved_per_s": hits / t_large, "probe_per_s": rate,
                            "frac": hits / t_large / rate,
-                           "probe": f"torch scatter_add_ of 2^28 int32 ones at uniformly random words of "
-                                    f"{n_words * 4 / 2**30:.2f} GiB (the byte counters' size)"}
+                           "probe": f"cs_probe_scatter: 2^28 device-scope atomic adds at hashed random words of "
+                                    f"{n_words * 4 / 2**30:.2f} GiB (the byte counters' size), indices in registers"}
         print(f"# atomics: {hits / t_large:.3e}/s in k_large, probe {rate:.3e}/s", file=sys.stderr, flush=True)
 
     out = {
@@ -560,7 +616,7 @@ def main():
         out["prp"] = _prp_leg(cs, torch, np, job, bitmap, min(args.prp_rows, lay.n_m), stream)
         print(f"# prp {out['prp']['s']:.3f} s, {out['prp']['tests_per_s']:.3e} tests/s, "
               f"frac {out['prp']['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
-    if args.also_g and args.mode != "g":
+    if not args.no_g and args.mode != "g":
         tg = cs.Tune(large_mode=cs.LARGE_G)
         ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         bitmap.zero_()
@@ -585,9 +641,13 @@ def main():
                          "roofline": {"bound": "alu", "kernel": "k_large", "achieved": og / tlg / 1e12,
                                       "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
                                       "frac": og / tlg / ALU_PEAK_OPS, "ops_per_launch": og,
+                                      "op_units": {"g_levels": dg.g_levels, "g_calls": dg.g_calls,
+                                                   "raw_hits": dg.large_raw_hits, "large_primes": dg.large_primes},
                                       "traffic": _kernel_traffic("g"), "valu_issue_frac": _valu_issue("g"),
+                                      "traffic_source": "committed profile (profiles/traffic.json), not this run",
                                       "launch_ms": tlg * 1e3, "large_phase_ms": ph["large"]}}
     mode_b = cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP
+    gpu_counts = ref_counts.cpu().numpy().view(np.uint32).copy()
     del bitmap, counts, ws, ref_bitmap, ref_counts
     torch.cuda.empty_cache()
     if not args.no_batch:
@@ -606,7 +666,9 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = _cpu_baseline(job, args.cpu_rows, args.cpu_pmax)
+        out["cpu_baseline"] = _cpu_baseline(job, args.cpu_rows, gpu_counts)
+        print(f"# cpu baseline {out['cpu_baseline']['value']:.3e} factors/s on {out['cpu_baseline']['cores']} "
+              f"threads, rows equal: {out['cpu_baseline'].get('rows_equal_gpu')}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -84,7 +84,16 @@ typedef struct cs_tune {
                               CS_SCATTER_ATOMIC, CS_SCATTER_BYTES or CS_SCATTER_LIST */
   uint32_t list_chunks;    /* CS_SCATTER_LIST: pool capacity in chunks of 4096 hits; 0 = automatic
                               (a smaller pool only moves hits to the atomic fallback) */
+  uint32_t walk;           /* which m the large branch visits: CS_WALK_CLASSES (0) only the residue
+                              classes of m that can hold rows (odd m when d is even; with one solve
+                              per hit m = 1, 5 mod 6 when 6 | d), CS_WALK_ALL every m of the range as
+                              the paper's program does (Section 3.2: its solve count then follows
+                              the estimate M S (log log limit - log log thr) + pi(limit) - pi(thr)) */
+  uint32_t reserved;       /* must be 0 */
 } cs_tune;
+
+#define CS_WALK_CLASSES 0u
+#define CS_WALK_ALL     1u
 
 /* Large-prime hit scatter.  ATOMIC: per hit, a device-scope atomic OR into the packed bitmap and
  * an atomic add into the row's count.  BYTES: per hit, one atomic add into a byte counter per
@@ -127,8 +136,14 @@ typedef struct cs_layout {
   uint32_t reserved;
 } cs_layout;
 
+/* Prime decades of the per-decade counters: decade i holds the primes 10^i <= p < 10^(i+1). */
+#define CS_DECADES 20
+
 /* Counters accumulated by the kernels of the last cs_prepare + cs_sieve_range calls on a
- * workspace (cs_sieve resets them). */
+ * workspace (cs_sieve resets them).  small_primes / large_primes count the primes of the branches
+ * each call ran (cs_tune.branches), so a SMALL call and a LARGE call over the same range count
+ * every prime once.  The dec_* arrays split the large branch's counters by prime decade; each
+ * total above equals the sum of its array. */
 typedef struct cs_diag {
   uint64_t n_primes;        /* primes <= max(limit, P) in the table */
   uint64_t small_primes;    /* primes handed to the small branch */
@@ -142,6 +157,11 @@ typedef struct cs_diag {
   uint64_t error_flags;     /* nonzero: a device-side consistency check failed */
   double large_kernel_ms;   /* duration of the last large-branch kernel launched on this workspace
                                (HIP events on its stream; 0 if none, or launched under capture) */
+  uint64_t dec_primes[CS_DECADES];    /* large primes per decade (= large_primes in total) */
+  uint64_t dec_raw_hits[CS_DECADES];  /* large_raw_hits per decade of the prime */
+  uint64_t dec_hits[CS_DECADES];      /* large_hits per decade */
+  uint64_t dec_solves[CS_DECADES];    /* g_calls per decade */
+  uint64_t dec_levels[CS_DECADES];    /* g_levels per decade */
 } cs_diag;
 
 /* Human-readable name of a status code (static string). */
@@ -226,6 +246,19 @@ cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* 
 cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out);
 cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,
                   void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* Scatter-rate probe (measurement only, not part of the sieve): n_ops 32-bit operations at
+ * pseudo-random words of d_buf (words uint32, device memory), the words drawn from a 64-bit mixing
+ * hash of the operation index and `seed` in registers, so that the probe loads no indices.
+ * op 0: atomic add of 1 at device scope (the byte-counter and atomic scatters' operation);
+ * op 1: plain 4-byte store of a nonzero value; op 2: atomic add of 1 into a 64 KB LDS table per
+ * workgroup (the LDS-tile scatters' operation; only the op count reaches d_buf[0]).
+ * slices > 1 (at most 16): the buffer is cut into `slices` equal ranges and each workgroup uses
+ * only the range of its XCD (hardware id mod slices).  After op 0 the words sum to n_ops (plus
+ * their previous contents).  Errors: CS_EINVAL (null buffer, op > 2, slices 0 or > 16, fewer
+ * words than slices).  Enqueued on `stream`; the caller times it (e.g. with events). */
+cs_status cs_probe_scatter(uint32_t* d_buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,
+                           uint64_t seed, void* stream);
 
 /* ------------------------------------------------------------------------------------------
  * Probable-prime stage (after the sieve).  Section 2 ("Larger Gaps", "Sieving"): the numbers

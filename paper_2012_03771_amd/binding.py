@@ -17,6 +17,9 @@ SCATTER_AUTO = 0
 SCATTER_ATOMIC = 1
 SCATTER_BYTES = 2
 SCATTER_LIST = 3
+WALK_CLASSES = 0
+WALK_ALL = 1
+DECADES = 20
 
 _ERRORS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ERANGE", -3: "CS_ENOMEM", -4: "CS_EDEVICE", -5: "CS_EBUSY"}
 
@@ -35,7 +38,8 @@ class cs_job(C.Structure):
 class cs_tune(C.Structure):
     _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
                 ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
-                ("branches", C.c_uint32), ("scatter", C.c_uint32), ("list_chunks", C.c_uint32)]
+                ("branches", C.c_uint32), ("scatter", C.c_uint32), ("list_chunks", C.c_uint32),
+                ("walk", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class cs_layout(C.Structure):
@@ -44,10 +48,14 @@ class cs_layout(C.Structure):
                 ("prime_cap", C.c_uint64), ("thr", C.c_uint64), ("scatter", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+_DEC_FIELDS = ("dec_primes", "dec_raw_hits", "dec_hits", "dec_solves", "dec_levels")
+
+
 class cs_diag(C.Structure):
-    _fields_ = [(n, C.c_uint64) for n in ("n_primes", "small_primes", "large_primes", "small_pairs",
-                                          "small_marks", "large_raw_hits", "large_hits", "g_calls",
-                                          "g_levels", "error_flags")] + [("large_kernel_ms", C.c_double)]
+    _fields_ = ([(n, C.c_uint64) for n in ("n_primes", "small_primes", "large_primes", "small_pairs",
+                                           "small_marks", "large_raw_hits", "large_hits", "g_calls",
+                                           "g_levels", "error_flags")] + [("large_kernel_ms", C.c_double)]
+                + [(n, C.c_uint64 * DECADES) for n in _DEC_FIELDS])
 
 
 class cs_server_config(C.Structure):
@@ -77,10 +85,11 @@ class Tune:
     branches: int = 0
     scatter: int = 0
     list_chunks: int = 0
+    walk: int = WALK_CLASSES
 
     def c(self):
         return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
-                       self.small_slices, self.branches, self.scatter, self.list_chunks)
+                       self.small_slices, self.branches, self.scatter, self.list_chunks, self.walk, 0)
 
 
 @dataclass
@@ -109,6 +118,19 @@ class Diag:
     g_levels: int
     error_flags: int
     large_kernel_ms: float = 0.0
+    dec_primes: tuple = ()      # large-branch counters per prime decade 10^i <= p < 10^(i+1)
+    dec_raw_hits: tuple = ()
+    dec_hits: tuple = ()
+    dec_solves: tuple = ()
+    dec_levels: tuple = ()
+
+
+def _diag_of(out) -> Diag:
+    vals = []
+    for f in cs_diag._fields_:
+        v = getattr(out, f[0])
+        vals.append(tuple(int(x) for x in v) if f[0] in _DEC_FIELDS else v)
+    return Diag(*vals)
 
 
 class cs_surround_stats(C.Structure):
@@ -174,6 +196,7 @@ def lib():
         "cs_prp_numbers": ([vp, u32, u64, vp, vp], i32),
         "cs_surround_ws": ([P(cs_job), u64, P(u64)], i32),
         "cs_surround": ([P(cs_job), vp, vp, u64, vp, vp, u64, P(cs_surround_stats), vp], i32),
+        "cs_probe_scatter": ([vp, u64, u64, u32, u32, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -305,7 +328,7 @@ def sieve_range(job, p_lo, p_hi, bitmap, counts, ws, tune: Tune | None = None, s
 def diag_read(ws, stream=None, check: bool = True) -> Diag:
     out = cs_diag()
     st = lib().cs_diag_read(_ptr(ws), C.byref(out), _stream(stream))
-    d = Diag(*[getattr(out, f[0]) for f in cs_diag._fields_])
+    d = _diag_of(out)
     if check:
         _check(st, f"cs_diag_read (error_flags={d.error_flags})")
     return d
@@ -384,7 +407,7 @@ class Batch:
     def diag(self, stream=None) -> Diag:
         out = cs_diag()
         st = lib().cs_batch_diag(self.h, C.byref(out), _stream(stream))
-        d = Diag(*[getattr(out, f[0]) for f in cs_diag._fields_])
+        d = _diag_of(out)
         _check(st, f"cs_batch_diag (error_flags={d.error_flags})")
         return d
 
@@ -488,3 +511,14 @@ def surround(job, bitmap, m_rows, ws=None, stream=None):
     _check(lib().cs_surround(C.byref(_cjob(job)), _ptr(bitmap), _ptr(m_rows), n, _ptr(out), _ptr(ws), ws.numel(),
                              C.byref(st), _stream(stream)), "cs_surround")
     return out[:n], SurroundStats(st.rounds, st.tests, st.limbs, st.bits, st.test_ms)
+
+
+PROBE_ATOMIC = 0
+PROBE_STORE = 1
+PROBE_LDS_ATOMIC = 2
+
+
+def probe_scatter(buf, n_ops: int, slices: int = 1, op: int = PROBE_ATOMIC, seed: int = 1, stream=None):
+    """cs_probe_scatter on a device int32 tensor (its words): n_ops random-word operations."""
+    _check(lib().cs_probe_scatter(_ptr(buf), buf.numel(), n_ops, slices, op, seed, _stream(stream)),
+           "cs_probe_scatter")

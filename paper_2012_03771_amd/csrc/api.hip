@@ -185,6 +185,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   jd.p_hi = p_hi;
   jd.bitmap = bitmap;
   jd.counts = counts;
+  jd.branches = branches;
   fill_tiers(pl, p_lo, p_hi, &jd);
   uint64_t* items_base = reinterpret_cast<uint64_t*>(ws + L.items_base);
   CS_TRY(launch_write_job(jd, jdp, s));
@@ -217,7 +218,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     LargeEvents* ev = nullptr;
     if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) ev = large_events(ws);
     if (ev) CS_TRY(hipEventRecord(ev->start, s));
-    CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, pl.large_blocks, pl.large_lds_bytes,
+    CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, &ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes,
                         pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, s));
     if (ev) {
       CS_TRY(hipEventRecord(ev->stop, s));
@@ -358,6 +359,13 @@ extern "C" cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream) 
   out->g_calls = c.diag[D_G_CALLS];
   out->g_levels = c.diag[D_G_LEVELS];
   out->error_flags = c.diag[D_ERROR] | c.error;
+  for (int i = 0; i < kDecades; ++i) {
+    out->dec_primes[i] = c.dec[DC_PRIMES][i];
+    out->dec_raw_hits[i] = c.dec[DC_RAW][i];
+    out->dec_hits[i] = c.dec[DC_HITS][i];
+    out->dec_solves[i] = c.dec[DC_SOLVES][i];
+    out->dec_levels[i] = c.dec[DC_LEVELS][i];
+  }
   out->large_kernel_ms = 0.0;
   {
     std::lock_guard<std::mutex> lk(g_ev_mu);
@@ -460,5 +468,14 @@ extern "C" cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out) 
   cs_status st = make_plan(&j, nullptr, 256, &pl);
   if (st) return st;
   if (ws_bytes_out) *ws_bytes_out = (pl.kq.size() + 1) * 8ull;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_probe_scatter(uint32_t* d_buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,
+                                      uint64_t seed, void* stream) {
+  if (!d_buf || op > 2 || slices == 0 || slices > 16) return CS_EINVAL;
+  if (words < slices || words / slices == 0) return CS_EINVAL;
+  if (n_ops == 0) return CS_OK;
+  CS_TRY(launch_probe_scatter(d_buf, words, n_ops, slices, op, seed, device_cu_count(), (hipStream_t)stream));
   return CS_OK;
 }

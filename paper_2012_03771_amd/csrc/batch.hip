@@ -192,7 +192,7 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
     CS_TRY(launch_items_scan(jd, 1, ib, ls));
     const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
     CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, ls));
-    CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
+    CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, &b.jds[i].ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
                         (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, ls));
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jd, 1, pl.n_m, b.n_cu, ls));
   }
@@ -219,6 +219,13 @@ cs_status multi_diag(const MultiJob& b, cs_diag* out) {
     err |= c.diag[D_ERROR];
     out->small_primes += c.diag[D_SMALL_PRIMES];
     out->large_primes += c.diag[D_LARGE_PRIMES];
+    for (int k = 0; k < kDecades; ++k) {
+      out->dec_primes[k] += c.dec[DC_PRIMES][k];
+      out->dec_raw_hits[k] += c.dec[DC_RAW][k];
+      out->dec_hits[k] += c.dec[DC_HITS][k];
+      out->dec_solves[k] += c.dec[DC_SOLVES][k];
+      out->dec_levels[k] += c.dec[DC_LEVELS][k];
+    }
     err |= c.error;
   }
   out->error_flags = err;

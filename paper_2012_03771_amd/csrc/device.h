@@ -15,6 +15,11 @@ constexpr uint64_t kGroupMax = 1ull << 50;   // K-prime products stay below 2^50
 constexpr uint32_t kKmodLdsGroups = 2048;     // K groups staged in LDS by the K mod p kernel (16 KB)
 constexpr uint32_t kDSmall = 4096;            // d <= kDSmall: m -> row from a residue table of d entries
 
+// Prime decades of the per-decade counters: decade i holds the primes 10^i <= p < 10^(i+1)
+// (every p < 2^64 falls in one of them).
+constexpr int kDecades = 20;
+enum DecSlot { DC_PRIMES = 0, DC_RAW, DC_HITS, DC_SOLVES, DC_LEVELS, DC_COUNT };
+
 // Counters in cs_diag order.
 enum DiagSlot {
   D_NPRIMES = 0, D_SMALL_PRIMES, D_LARGE_PRIMES, D_SMALL_PAIRS, D_SMALL_MARKS,
@@ -40,6 +45,7 @@ struct JobCtrl {
   uint32_t dq[kMaxDq];
   uint64_t mq[kMaxDq];               // m_start mod dq[i]
   unsigned long long diag[D_COUNT];
+  unsigned long long dec[DC_COUNT][kDecades];   // large-branch counters per prime decade
 };
 
 // Everything a kernel needs about one job.  Lives in device memory (written by a one-thread
@@ -66,7 +72,7 @@ struct JobDev {
   uint32_t m_step;
   uint32_t m_classes;
   uint32_t m0_mod_step;              // m_start mod m_step
-  uint32_t pad_classes;
+  uint32_t branches;                 // branches this call runs (CS_BRANCH_*): what the prime counters count
   // Marks of the primes dividing d depend only on m mod d: one packed row (and its factor
   // count) per residue class coprime to d, built once per job and OR-ed into each row's tile.
   uint32_t dpat_on;                  // pattern table built for this job

@@ -648,8 +648,9 @@ __global__ void k_prep_bounds(JobDev* jobs) {
   }
   c.tier_item_base[j.n_tiers] = items;
   c.n_items = items;
-  c.diag[D_SMALL_PRIMES] += c.small_hi - c.small_lo;
-  c.diag[D_LARGE_PRIMES] += prev - c.tier_lo_idx;
+  // each call counts the primes of the branches it runs (CS_BRANCH_ALL = 0, SMALL = 1, LARGE = 2)
+  if (j.branches != 2u) c.diag[D_SMALL_PRIMES] += c.small_hi - c.small_lo;
+  if (j.branches != 1u) c.diag[D_LARGE_PRIMES] += prev - c.tier_lo_idx;
 }
 
 // Prefix of large-branch item counts over the jobs of a launch.
@@ -1005,6 +1006,18 @@ __device__ __forceinline__ void mpos_add(MPos& s, uint32_t tq, uint32_t tr, uint
   if (s.rd >= d) { s.rd -= d; s.dq += 1; }
 }
 
+// Decade of p: i with 10^i <= p < 10^(i+1) (integer compares: exact for every p < 2^64).
+__device__ __forceinline__ uint32_t decade_of(uint64_t p) {
+  uint32_t dc = 0;
+  uint64_t t = 10;
+#pragma unroll
+  for (int i = 1; i < kDecades; ++i) {
+    dc += p >= t ? 1u : 0u;
+    t *= 10;
+  }
+  return dc;
+}
+
 // Table accessors: LDS copies for a single-job launch, global memory otherwise.
 template <bool kLds>
 struct LargeTables {
@@ -1185,16 +1198,18 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
 template <bool kLds, int kSc>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
-                                               unsigned long long* __restrict__ diag, uint32_t lds_ct_words,
+                                               unsigned long long* __restrict__ diag,
+                                               unsigned long long* __restrict__ dec, uint32_t lds_ct_words,
                                                uint32_t dpre_n) {
   extern __shared__ uint32_t lds[];
   __shared__ unsigned long long s_list[256 / kWave];   // per wavefront: latest list state (see list_sync)
-  __shared__ unsigned long long s_diag[4][256 / kWave];
+  __shared__ unsigned long long s_dec[DC_COUNT][kDecades];   // the workgroup's counters per prime decade
   const uint64_t total = job_item_base[n_jobs];
   if ((uint64_t)blockIdx.x * blockDim.x >= total) return;   // workgroups past the last item (uniform)
   unsigned long long* lkey = s_list + threadIdx.x / kWave;
   if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
-  if constexpr (!kLds) __syncthreads();
+  for (uint32_t i = threadIdx.x; i < DC_COUNT * kDecades; i += blockDim.x) (&s_dec[0][0])[i] = 0ull;
+  __syncthreads();
   LargeTables<kLds> T;
   if constexpr (kLds) {
     const JobDev& j0 = jobs[0];
@@ -1206,7 +1221,20 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
   }
-  unsigned long long raw = 0, useful = 0, calls = 0, levels = 0;
+  // a lane's counters for the decade of its current prime (items only grow, so a lane's primes
+  // change decade rarely); flushed into s_dec when the decade changes and at the end
+  unsigned long long raw = 0, useful = 0, calls = 0, levels = 0, n_pr = 0;
+  uint32_t cur_dec = kDecades;
+  auto flush_dec = [&]() {
+    if (cur_dec < (uint32_t)kDecades) {
+      if (n_pr) atomicAdd(&s_dec[DC_PRIMES][cur_dec], n_pr);
+      if (raw) atomicAdd(&s_dec[DC_RAW][cur_dec], raw);
+      if (useful) atomicAdd(&s_dec[DC_HITS][cur_dec], useful);
+      if (calls) atomicAdd(&s_dec[DC_SOLVES][cur_dec], calls);
+      if (levels) atomicAdd(&s_dec[DC_LEVELS][cur_dec], levels);
+    }
+    raw = useful = calls = levels = n_pr = 0;
+  };
   uint32_t err = 0;
   ListReg lreg = {kNoChunk, 0u};
   uint32_t t_last = 0, ji_last = 0;                  // a lane's items only grow: resume the tier search
@@ -1260,6 +1288,14 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
 
     const uint64_t p = gbl(j.primes)[pi];
     const uint64_t k1 = gbl(j.kmod)[pi];
+    {
+      const uint32_t dc = decade_of(p);
+      if (dc != cur_dec) {
+        flush_dec();
+        cur_dec = dc;
+      }
+      if (chunk == 0) ++n_pr;                        // each prime once (chunk 0 always has positions)
+    }
     uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
     k -= k >= 4 * p ? 4 * p : 0;                     // s <= 6: s K mod p < 8p before these
     k -= k >= 2 * p ? 2 * p : 0;
@@ -1380,22 +1416,19 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       if (ch < kPoolFull) jobs[0].list_fill[ch] = (uint32_t)k;
     }
   }
-  // counters: one atomic per workgroup and counter (many short workgroups share four addresses)
-  raw = wave_sum_u64(raw);
-  useful = wave_sum_u64(useful);
-  calls = wave_sum_u64(calls);
-  levels = wave_sum_u64(levels);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    const uint32_t wv = threadIdx.x / kWave;
-    s_diag[0][wv] = raw;
-    s_diag[1][wv] = useful;
-    s_diag[2][wv] = calls;
-    s_diag[3][wv] = levels;
-  }
+  // counters: one atomic per workgroup, decade and counter, and the totals over the decades
+  flush_dec();
   __syncthreads();
+  if (threadIdx.x < DC_COUNT * kDecades) {
+    const uint32_t slot = threadIdx.x / kDecades, dc = threadIdx.x % kDecades;
+    const unsigned long long v = s_dec[slot][dc];
+    if (v && dec) atomicAdd(&dec[slot * kDecades + dc], v);
+  }
   if (threadIdx.x < 4) {
+    const uint32_t slot = threadIdx.x == 0 ? DC_RAW : threadIdx.x == 1 ? DC_HITS : threadIdx.x == 2 ? DC_SOLVES
+                        : DC_LEVELS;
     unsigned long long v = 0;
-    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) v += s_diag[threadIdx.x][i];
+    for (uint32_t i = 0; i < (uint32_t)kDecades; ++i) v += s_dec[slot][i];
     const uint32_t at = threadIdx.x == 0 ? D_LARGE_RAW : threadIdx.x == 1 ? D_LARGE_HITS
                       : threadIdx.x == 2 ? D_G_CALLS : D_G_LEVELS;
     if (v) atomicAdd(&diag[at], v);
@@ -1655,6 +1688,56 @@ __global__ __launch_bounds__(256) void k_list_apply(const JobDev* __restrict__ j
 }
 
 // ------------------------------------------------------------------------------------------
+// Scatter-rate probe: the device's rate of the memory operations the hit scatters issue, at
+// pseudo-random 32-bit words generated in registers (a 64-bit mixing hash of the operation
+// index), so that no index is ever loaded.  op 0: atomic add of 1 at device scope (no return);
+// op 1: plain 4-byte store; op 2: atomic add of 1 into LDS (a 64 KB table per workgroup, the
+// rate of the LDS-tile scatters).  slices > 1: the buffer is cut into `slices` equal ranges and
+// a workgroup only touches range (XCC id mod slices), the id read from the hardware, which keeps
+// each range in the L2 of the one XCD that uses it.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 31;
+  x *= 0x7fb5d329728ea185ull;
+  x ^= x >> 27;
+  x *= 0x81dadef4bc2dd44dull;
+  x ^= x >> 33;
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_probe_scatter(uint32_t* __restrict__ buf, uint64_t words, uint64_t n_ops,
+                                                       uint32_t slices, uint32_t op, uint64_t seed) {
+  __shared__ uint32_t tab[16384];
+  uint64_t range = words, base = 0;
+  if (slices > 1) {
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;   // HW_REG_XCC_ID
+    range = words / slices;
+    base = (uint64_t)(xcc % slices) * range;
+  }
+  if (op == 2) {
+    for (uint32_t i = threadIdx.x; i < 16384; i += blockDim.x) tab[i] = 0;
+    __syncthreads();
+    range = 16384;
+    base = 0;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_ops; i += stride) {
+    const uint64_t h = mix64(i ^ seed);
+    const uint64_t w = base + __umul64hi(h, range);          // uniform in [base, base + range)
+    if (op == 0) atomicAdd(&buf[w], 1u);
+    else if (op == 1) buf[w] = (uint32_t)h | 1u;
+    else atomicAdd(&tab[w], 1u);
+  }
+  if (op == 2) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 16384; i += blockDim.x) acc += tab[i];
+    acc = wave_sum_u32(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0 && acc) atomicAdd(&buf[0], acc);   // the ops, for the caller's check
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // launch wrappers (host)
 // ------------------------------------------------------------------------------------------
 static thread_local char g_last_error[256];
@@ -1819,13 +1902,13 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 }
 
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
-                        unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
+                        unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
+                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
   if (n_jobs != 1 && scatter_kind == 2) scatter_kind = 0;   // the list serves single jobs only
   const bool lds = lds_bytes && lds_ct_words && n_jobs == 1;
 #define LARGE_CASE(L, K)                                                                                       \
   hipLaunchKernelGGL((k_large<L, K>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs, job_item_base, \
-                     diag, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
+                     diag, dec, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
   if (lds) {
     if (scatter_kind == 2) LARGE_CASE(true, 2);
     else if (scatter_kind == 1) LARGE_CASE(true, 1);
@@ -1837,6 +1920,12 @@ hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job
   }
 #undef LARGE_CASE
   return note(lds ? "k_large<lds>" : "k_large");
+}
+
+hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,
+                                uint64_t seed, int n_cu, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_scatter, dim3((uint32_t)n_cu * 32u), dim3(256), 0, s, buf, words, n_ops, slices, op, seed);
+  return note("k_probe_scatter");
 }
 
 hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,

@@ -63,12 +63,17 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 // that job are staged in LDS.  scatter_kind: 0 = atomic OR/add into the bitmaps and counts,
 // 1 = every job's byte counters (all jobs must have them), 2 = the job's list pool (single-job
 // launches only; 0 otherwise).
+// diag: D_COUNT totals; dec: DC_COUNT x kDecades counters per prime decade (or null).
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
-                        unsigned long long* diag, uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words,
-                        uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s);
+                        unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
+                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s);
 // Groups the list pool of one job by row bucket and applies it to the bitmap and counts.  The
 // caller cleared the pool cursor and the bucket counts before the k_large launch.
 hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,
                              uint32_t super_shift, uint32_t row_words, hipStream_t s);
+
+// Scatter-rate probe (see k_probe_scatter).
+hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,
+                                uint64_t seed, int n_cu, hipStream_t s);
 
 }  // namespace cs

@@ -40,6 +40,7 @@ struct Plan {
   uint32_t w;
   uint64_t thr;
   uint32_t large_mode;
+  bool walk_all = false;            // the large branch visits every m (CS_WALK_ALL)
   uint32_t tile_rows, n_windows, n_slices;
   uint32_t hits_per_item;
   uint32_t large_blocks, small_blocks;

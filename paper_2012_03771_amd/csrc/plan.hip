@@ -84,6 +84,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (mode > CS_LARGE_THREE_GAP) return CS_EINVAL;
   const uint32_t scatter = tune ? tune->scatter : CS_SCATTER_AUTO;
   if (scatter > CS_SCATTER_LIST) return CS_EINVAL;
+  if (tune && (tune->walk > CS_WALK_ALL || tune->reserved != 0)) return CS_EINVAL;
 
   Plan& pl = *out;
   pl.job = j;
@@ -136,6 +137,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   pl.ct_words = (pl.S + 31) / 32;
   pl.w = 2 * j.sl;
   pl.large_mode = mode;
+  pl.walk_all = tune && tune->walk == CS_WALK_ALL;
 
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 2.5 M / M_c (a quarter of the paper's 10 M / M_c: at 953#/210 the step is flat from 120,000
@@ -308,7 +310,10 @@ void walk_classes(const Plan& pl, uint32_t* step, uint32_t* classes) {
   // classes mod 6 pay when 6 | d (1/3 of the m for two first solves); three-gap stepping takes a
   // few operations per visited m and keeps the single class mod 2.
   const uint64_t d = pl.job.d;
-  if (pl.large_mode == CS_LARGE_G && d % 6 == 0) {
+  if (pl.walk_all) {
+    *step = 1;
+    *classes = 1u;
+  } else if (pl.large_mode == CS_LARGE_G && d % 6 == 0) {
     *step = 6;
     *classes = (1u << 1) | (1u << 5);
   } else if (d % 2 == 0) {

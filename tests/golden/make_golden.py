@@ -6,9 +6,13 @@ nothing comes from the HIP path.  Run from the repository root:
     python tests/golden/make_golden.py [medium] [paper] [batch]
 
 medium_503_rows.npz   per-row digests of the whole 503#/210 job (2,287 rows), plus 64 full rows
-paper_953_rows.npz    16 rows of the 953#/210 paper-scale job, primes up to 1e10: the first, the
-                      last, the row of m = 100054841 (the merit-38.048 record gap) and 13 seeded
+paper_953_rows.npz    64 rows of the 953#/210 paper-scale job, primes up to 1e10: the first, the
+                      last, the row of m = 100054841 (the merit-38.048 record gap) and 61 seeded
 batch_rows.npz        4 rows of each of the 64 seeded mixed-batch jobs
+
+Every file is written with the oracle's DIRECT mode: N mod p taken from the bignum N = m K for
+every row and prime, the traditional sieve of Section 2.1 written out, so that no stored value
+relies on the (m mod p)(K mod p) identity of Eq. 1 that the GPU path itself uses.
 """
 from __future__ import annotations
 
@@ -32,7 +36,7 @@ def medium():
     job = W.MEDIUM
     t = time.time()
     ms = coracle.rows(job.d, job.m_start, job.m_inc)
-    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms, 2, job.limit, mode=coracle.CACHED)
+    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms, 2, job.limit, mode=coracle.DIRECT)
     full = W.sample_rows(len(ms), 64, seed=21)
     np.savez_compressed(os.path.join(HERE, "medium_503_rows.npz"), job=np.array(job.as_tuple(), dtype=np.uint64),
                         digests=row_digests(bits, counts), rows=np.array(full), bits=bits[full],
@@ -47,8 +51,8 @@ def paper():
     rec = W.RECORD_GAPS[0][2]
     r_rec = int(np.searchsorted(ms, rec))
     assert ms[r_rec] == rec
-    rows = W.sample_rows(len(ms), 16, seed=31, must=[r_rec])
-    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.CACHED)
+    rows = W.sample_rows(len(ms), 64, seed=31, must=[r_rec])
+    bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.DIRECT)
     np.savez_compressed(os.path.join(HERE, "paper_953_rows.npz"), job=np.array(job.as_tuple(), dtype=np.uint64),
                         rows=np.array(rows), m=ms[rows], bits=bits, counts=counts, record_row=np.int64(r_rec))
     print(f"paper: {len(rows)} rows in {time.time() - t:.1f} s")
@@ -63,7 +67,7 @@ def batch():
         if len(ms) == 0:
             continue
         rows = W.sample_rows(len(ms), 4, seed=100 + i)
-        bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.CACHED)
+        bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms[rows], 2, job.limit, mode=coracle.DIRECT)
         out[f"job{i}_rows"] = np.array(rows)
         out[f"job{i}_bits"] = bits
         out[f"job{i}_counts"] = counts

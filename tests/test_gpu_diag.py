@@ -1,0 +1,122 @@
+"""Kernel counters of the large-prime branch against the paper's cost model and against each other.
+
+Section 3.2 estimates how often Eq. 3 is solved when every m of the range meets every prime in
+(10 S, P_limit]: M S (log log P_limit - log log 10 S) + pi(P_limit) - pi(10 S), and states that the
+count observed in its runs matches this to about 0.05%.  The library's per-decade counters
+(cs_diag.dec_*) are checked against that estimate, decade by decade against Mertens' sum, and
+against exact prime counts from the oracle.  Expected values come from the paper's formula, from
+the paper's printed prime counts and from oracle/; none from the HIP path."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2012_03771_amd as cs  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pi(x: int) -> int:
+    return coracle.prime_stats(2, x)[0] if x >= 2 else 0
+
+
+def _lnln(x: float) -> float:
+    return math.log(math.log(x))
+
+
+def test_split_branch_calls_count_each_prime_once():
+    """prepare, then a SMALL call and a LARGE call over [2, limit]: every prime is counted once, by
+    the branch that sieved it, and the per-decade counts are the oracle's prime counts."""
+    job = W.MEDIUM
+    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
+    lay, bitmap, counts, ws = cs.binding.alloc_outputs(job, tune)
+    _say("split", job, lay.thr)
+    bitmap.zero_()
+    counts.zero_()
+    cs.prepare(job, ws, tune)
+    cs.sieve_range(job, 2, job.limit, bitmap, counts, ws, cs.Tune(large_mode=cs.LARGE_THREE_GAP,
+                                                                    branches=cs.BRANCH_SMALL))
+    cs.sieve_range(job, 2, job.limit, bitmap, counts, ws, cs.Tune(large_mode=cs.LARGE_THREE_GAP,
+                                                                    branches=cs.BRANCH_LARGE))
+    torch.cuda.synchronize()
+    dg = cs.diag_read(ws)
+    pi_thr = _pi(lay.thr)
+    assert dg.small_primes == pi_thr
+    assert dg.large_primes == 5761455 - pi_thr
+    assert sum(dg.dec_primes) == dg.large_primes
+    assert sum(dg.dec_raw_hits) == dg.large_raw_hits
+    assert sum(dg.dec_hits) == dg.large_hits
+    assert sum(dg.dec_solves) == dg.g_calls
+    assert sum(dg.dec_levels) == dg.g_levels
+    for i in range(cs.binding.DECADES):
+        lo, hi = max(10 ** i, lay.thr + 1), min(10 ** (i + 1) - 1, job.limit)
+        want = _pi(hi) - _pi(lo - 1) if hi >= lo else 0
+        assert dg.dec_primes[i] == want, f"decade {i}: {dg.dec_primes[i]} primes, oracle {want}"
+    # the split calls reproduce the whole call
+    b2, c2, ws2 = cs.sieve(job, tune)
+    torch.cuda.synchronize()
+    assert torch.equal(bitmap, b2) and torch.equal(counts, c2)
+    assert dg.large_hits + dg.small_marks == int(c2.to(torch.int64).sum().item())
+
+
+@pytest.mark.parametrize("job", [W.MEDIUM, W.PAPER_SCALE], ids=["medium_503", "paper_953"])
+def test_solve_count_matches_section_3_2_estimate(job, paper_values):
+    """One Eq. 5 solve per hit over every m of the range (the paper's enumeration, CS_WALK_ALL), one
+    work item per prime, threshold 10 S: the solve count is Section 3.2's estimate within 0.1%, and
+    the raw solutions of each prime decade follow Mertens' sum over that decade."""
+    S = 2 * job.sl + 1
+    thr = 10 * S
+    tune = cs.Tune(large_mode=cs.LARGE_G, thr=thr, hits_per_item=2**31 - 1, walk=cs.WALK_ALL)
+    _say("solve count", job)
+    bitmap, counts, ws = cs.sieve(job, tune)
+    torch.cuda.synchronize()
+    dg = cs.diag_read(ws)
+    pi_lim = int(paper_values["prime_counts"][str(job.limit)])
+    pi_thr = _pi(thr)
+    M = job.m_inc
+    est_hits = M * S * (_lnln(job.limit) - _lnln(thr))
+    est = est_hits + pi_lim - pi_thr
+    dev = dg.g_calls / est - 1.0
+    _say(f"solves {dg.g_calls} estimate {est:.6g} deviation {dev * 100:.4f}%; raw solutions {dg.large_raw_hits} "
+         f"estimate {est_hits:.6g}")
+    assert dg.large_primes == pi_lim - pi_thr
+    assert abs(dev) < 1e-3
+    assert abs(dg.large_raw_hits / est_hits - 1.0) < 1e-3
+    for i in range(cs.binding.DECADES):
+        lo, hi = max(10 ** i, thr), min(10 ** (i + 1), job.limit)
+        if hi <= lo or dg.dec_raw_hits[i] == 0:
+            continue
+        e = M * S * (_lnln(hi) - _lnln(lo))
+        _say(f"  decade 1e{i}: raw {dg.dec_raw_hits[i]} estimate {e:.6g} ({(dg.dec_raw_hits[i] / e - 1) * 100:.3f}%)"
+             f" solves {dg.dec_solves[i]} levels/solve {dg.dec_levels[i] / max(dg.dec_solves[i], 1):.2f}")
+        assert abs(dg.dec_raw_hits[i] / e - 1.0) < 5e-3
+    # this enumeration is exact too: the factor total is that of the default path
+    b2, c2, _ = cs.sieve(job)
+    torch.cuda.synchronize()
+    assert torch.equal(bitmap, b2) and torch.equal(counts, c2)
+
+
+def test_raw_solutions_equal_mertens_sum_over_the_primes():
+    """503#/210 with every m: the raw solutions of the large primes are M S sum(1/p) over those
+    primes (each prime p > S meets a given m at most once, and m K mod p is equidistributed), to
+    0.02%; the primes come from the oracle."""
+    job = W.MEDIUM
+    S = 2 * job.sl + 1
+    thr = 10 * S
+    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP, thr=thr, walk=cs.WALK_ALL)
+    bitmap, counts, ws = cs.sieve(job, tune)
+    torch.cuda.synchronize()
+    dg = cs.diag_read(ws)
+    p = coracle.primes_range(thr + 1, job.limit).astype(np.float64)
+    want = job.m_inc * S * float((1.0 / p).sum())
+    _say(f"raw {dg.large_raw_hits} sum {want:.6g} ({(dg.large_raw_hits / want - 1) * 100:.4f}%)")
+    assert abs(dg.large_raw_hits / want - 1.0) < 2e-4

@@ -39,8 +39,10 @@ def _run(job, tune):
 MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP),
          cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_ATOMIC),
          cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST),
-         cs.Tune(large_mode=cs.LARGE_G, scatter=cs.SCATTER_LIST)]
-MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_list", "g_list"]
+         cs.Tune(large_mode=cs.LARGE_G, scatter=cs.SCATTER_LIST),
+         cs.Tune(large_mode=cs.LARGE_G, walk=cs.WALK_ALL),
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, walk=cs.WALK_ALL)]
+MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_list", "g_list", "g_walk_all", "three_gap_walk_all"]
 
 
 @pytest.mark.parametrize("tune", MODES, ids=MODE_IDS)
@@ -91,3 +93,21 @@ def test_paper_953_sampled_rows_and_invariants(tune):
     assert int(c.astype(np.int64).sum()) == diag.small_marks + diag.large_hits
     assert diag.n_primes == 455052511
     assert diag.error_flags == 0
+
+
+def test_paper_953_every_enumeration_gives_the_same_bitmap():
+    """Every row of the paper-scale job, not only the sampled ones: the paper's one-solve-per-hit
+    enumeration (Section 3.3), three-gap stepping, and the three hit scatters are independent
+    routes to the same definition, so their whole bitmaps and counts must be identical."""
+    job = W.PAPER_SCALE
+    ref_b = ref_c = None
+    for tune, name in zip(MODES, MODE_IDS):
+        _say("paper whole bitmap", name)
+        b, c, diag = _run(job, tune)
+        assert diag.error_flags == 0
+        if ref_b is None:
+            ref_b, ref_c = b, c
+            continue
+        same_c = np.array_equal(c, ref_c)
+        diff = 0 if np.array_equal(b, ref_b) else int((b != ref_b).any(axis=1).sum())
+        assert same_c and diff == 0, f"{name}: {diff} rows of the bitmap differ from {MODE_IDS[0]}, counts equal: {same_c}"

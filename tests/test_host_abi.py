@@ -187,3 +187,29 @@ def test_chunked_range_validation():
     with pytest.raises(cs.CsError) as e:
         cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42), 1 << 36)
     assert e.value.status == -2
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and field offsets."""
+    import ctypes
+    import subprocess
+    B = cs.binding
+    structs = {"cs_job": B.cs_job, "cs_tune": B.cs_tune, "cs_layout": B.cs_layout, "cs_diag": B.cs_diag,
+               "cs_server_config": B.cs_server_config, "cs_ticket_info": B.cs_ticket_info,
+               "cs_surround_stats": B.cs_surround_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "csieve.h"', "int main(void) {"]
+    for name, ct in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in ct._fields_:
+            lines.append(f'  printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    for name, ct in structs.items():
+        assert int(got[name]) == ctypes.sizeof(ct), name
+        for f in ct._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(ct, f[0]).offset, f"{name}.{f[0]}"
