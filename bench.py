@@ -35,7 +35,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["g", "three_gap"], default="three_gap")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--cpu-rows", type=int, default=2,
+    ap.add_argument("--cpu-rows", type=int, default=8,
                     help="rows of the job the oracle sieves with every prime up to the job's limit")
     ap.add_argument("--workload", default="paper_953")
     ap.add_argument("--phase-only", action="store_true", help="time the phases once, no steps")

@@ -71,8 +71,12 @@ def test_split_branch_calls_count_each_prime_once():
 @pytest.mark.parametrize("job", [W.MEDIUM, W.PAPER_SCALE], ids=["medium_503", "paper_953"])
 def test_solve_count_matches_section_3_2_estimate(job, paper_values):
     """One Eq. 5 solve per hit over every m of the range (the paper's enumeration, CS_WALK_ALL), one
-    work item per prime, threshold 10 S: the solve count is Section 3.2's estimate within 0.1%, and
-    the raw solutions of each prime decade follow Mertens' sum over that decade."""
+    work item per prime, threshold 10 S.  The paper's count is of every m its driver tests: each
+    solution, plus the one step per prime that runs past the range.  Here that is the raw solutions
+    plus the large primes, and it must match Section 3.2's estimate within 0.1%.  The solves
+    themselves are fewer: when the m after a hit is a hit again (residue + K mod p still in the
+    window) the driver marks it without a solve, about S/p of the hits of p.  The raw solutions of
+    each prime decade follow Mertens' sum over that decade."""
     S = 2 * job.sl + 1
     thr = 10 * S
     tune = cs.Tune(large_mode=cs.LARGE_G, thr=thr, hits_per_item=2**31 - 1, walk=cs.WALK_ALL)
@@ -85,11 +89,14 @@ def test_solve_count_matches_section_3_2_estimate(job, paper_values):
     M = job.m_inc
     est_hits = M * S * (_lnln(job.limit) - _lnln(thr))
     est = est_hits + pi_lim - pi_thr
-    dev = dg.g_calls / est - 1.0
-    _say(f"solves {dg.g_calls} estimate {est:.6g} deviation {dev * 100:.4f}%; raw solutions {dg.large_raw_hits} "
-         f"estimate {est_hits:.6g}")
+    tested = dg.large_raw_hits + dg.large_primes
+    dev = tested / est - 1.0
+    _say(f"tested m {tested} estimate {est:.6g} deviation {dev * 100:.4f}%; raw solutions {dg.large_raw_hits} "
+         f"estimate {est_hits:.6g}; solves {dg.g_calls} ({dg.g_calls / tested:.4f} of the tested m)")
     assert dg.large_primes == pi_lim - pi_thr
     assert abs(dev) < 1e-3
+    # solves skip only hits that follow a hit: at most S/thr of them
+    assert tested * (1.0 - S / thr) <= dg.g_calls <= tested
     assert abs(dg.large_raw_hits / est_hits - 1.0) < 1e-3
     for i in range(cs.binding.DECADES):
         lo, hi = max(10 ** i, thr), min(10 ** (i + 1), job.limit)
