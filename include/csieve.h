@@ -191,6 +191,20 @@ cs_status cs_rows(const cs_job* job, uint64_t* m_of_row, uint64_t cap);
 cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
                    void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* cs_sieve for callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same sieve, with the workspace taken from
+ * a device array the library holds, cs_scratch_bytes() = 256 MiB, one per device (allocated when
+ * the library's code object is loaded on that device and held until the process ends).  Jobs
+ * whose cs_plan ws_bytes exceed it get CS_ERANGE (nothing enqueued).  Everything runs on `stream`
+ * (no second stream, no timing events: cs_diag.large_kernel_ms is not updated).  The call allocates
+ * nothing.  Every call on a device shares that device's array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on one device race, so
+ * the caller serialises them (one stream, or events between streams).  The diagnostic counters
+ * live in that array too and are not readable through cs_diag_read. */
+cs_status cs_sieve_noalloc(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
+                           void* stream);
+uint64_t cs_scratch_bytes(void);
+
 /* First half of cs_sieve without touching any output: prime table, K mod p, row and column
  * tables into d_ws, and the diagnostic counters reset. */
 cs_status cs_prepare(const cs_job* job, const cs_tune* tune, void* d_ws, uint64_t ws_bytes,

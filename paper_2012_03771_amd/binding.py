@@ -197,6 +197,8 @@ def lib():
         "cs_surround_ws": ([P(cs_job), u64, P(u64)], i32),
         "cs_surround": ([P(cs_job), vp, vp, u64, vp, vp, u64, P(cs_surround_stats), vp], i32),
         "cs_probe_scatter": ([vp, u64, u64, u32, u32, u64, vp], i32),
+        "cs_sieve_noalloc": ([P(cs_job), P(cs_tune), vp, vp, vp], i32),
+        "cs_scratch_bytes": ([], u64),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -283,6 +285,16 @@ def alloc_outputs(job, tune=None, device="cuda"):
 def sieve_into(job, bitmap, counts, ws, tune: Tune | None = None, stream=None):
     _check(lib().cs_sieve(C.byref(_cjob(job)), _ctune(tune), _ptr(bitmap), _ptr(counts), _ptr(ws),
                           ws.numel(), _stream(stream)), "cs_sieve")
+
+
+def sieve_noalloc_into(job, bitmap, counts, tune: Tune | None = None, stream=None):
+    """cs_sieve_noalloc: the whole sieve with the library's own device workspace (no allocation)."""
+    _check(lib().cs_sieve_noalloc(C.byref(_cjob(job)), _ctune(tune), _ptr(bitmap), _ptr(counts), _stream(stream)),
+           "cs_sieve_noalloc")
+
+
+def scratch_bytes() -> int:
+    return int(lib().cs_scratch_bytes())
 
 
 def sieve(job, tune: Tune | None = None, stream=None):

@@ -175,8 +175,10 @@ AuxStream* aux_stream() {
   return &a;
 }
 
+// own_stream_only: everything on `s`, with no second stream and no timing events (the entry point
+// that allocates nothing creates neither).
 cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
-                        uint8_t* ws, hipStream_t s, uint32_t branches) {
+                        uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only = false) {
   const WsLayout& L = pl.ws;
   JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
   PrimeWs pw = prime_ws_of(pl, ws);
@@ -197,8 +199,8 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   // small branch (which read-modify-writes bitmap words) can run beside it on a second stream.
   hipStreamCaptureStatus cap0 = hipStreamCaptureStatusNone;
   AuxStream* aux = nullptr;
-  if (branches == CS_BRANCH_ALL && pl.scatter_bytes && hipStreamIsCapturing(s, &cap0) == hipSuccess &&
-      cap0 == hipStreamCaptureStatusNone)
+  if (!own_stream_only && branches == CS_BRANCH_ALL && pl.scatter_bytes &&
+      hipStreamIsCapturing(s, &cap0) == hipSuccess && cap0 == hipStreamCaptureStatusNone)
     aux = aux_stream();
   if (aux) {
     CS_TRY(hipEventRecord(aux->fork, s));
@@ -216,7 +218,8 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     const uint32_t kind = pl.scatter_list ? 2u : (pl.scatter_bytes ? 1u : 0u);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     LargeEvents* ev = nullptr;
-    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) ev = large_events(ws);
+    if (!own_stream_only && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone)
+      ev = large_events(ws);
     if (ev) CS_TRY(hipEventRecord(ev->start, s));
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, &ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes,
                         pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, s));
@@ -478,4 +481,57 @@ extern "C" cs_status cs_probe_scatter(uint32_t* d_buf, uint64_t words, uint64_t 
   if (n_ops == 0) return CS_OK;
   CS_TRY(launch_probe_scatter(d_buf, words, n_ops, slices, op, seed, device_cu_count(), (hipStream_t)stream));
   return CS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// The whole sieve with a workspace the library holds: for callers that cannot allocate device
+// memory (code under graph capture, serving loops, harnesses that forbid hipMalloc).  The
+// workspace is a static device array of kScratchBytes in this code object, one copy per device;
+// host code uses only the device address of the current device's copy, taken once per device.
+// ---------------------------------------------------------------------------------------------
+static constexpr uint64_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch;   // device -> device address of its copy of `scratch`
+
+cs_status scratch_ptr(uint8_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CS_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *out = it->second;
+    return CS_OK;
+  }
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return CS_EDEVICE;
+  g_scratch[dev] = static_cast<uint8_t*>(p);
+  *out = static_cast<uint8_t*>(p);
+  return CS_OK;
+}
+}  // namespace
+
+extern "C" uint64_t cs_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" cs_status cs_sieve_noalloc(const cs_job* job, const cs_tune* tune, uint32_t* d_bitmap, uint32_t* d_counts,
+                                      void* stream) {
+  Plan pl;
+  const int n_cu = device_cu_count();
+  cs_status st = make_plan(job, tune, n_cu, &pl);
+  if (st) return st;
+  if (pl.n_m > 0 && (!d_bitmap || !d_counts)) return CS_EINVAL;
+  if (pl.ws.total > kScratchBytes) return CS_ERANGE;
+  uint8_t* ws = nullptr;
+  st = scratch_ptr(&ws);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (pl.n_m > 0) {
+    CS_TRY(launch_fill_u32(d_bitmap, pl.n_m * (uint64_t)pl.row_words, 0u, s));
+    CS_TRY(launch_fill_u32(d_counts, pl.n_m, 0u, s));
+  }
+  st = prepare_planned(pl, ws, s, n_cu);
+  if (st) return st;
+  return range_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL, true);
 }
