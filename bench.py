@@ -34,6 +34,10 @@ def _args():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["g", "three_gap"], default="three_gap")
+    ap.add_argument("--scatter", choices=["auto", "atomic", "bytes", "list"], default="auto",
+                    help="large-prime hit scatter of the timed step (cs_tune.scatter)")
+    ap.add_argument("--thr-mult", type=float, default=0.0,
+                    help="small/large threshold of the timed step as a multiple of S = 2 sl + 1 (0: the plan's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-rows", type=int, default=8,
                     help="rows of the job the oracle sieves with every prime up to the job's limit")
@@ -377,26 +381,43 @@ def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
     jobs = W.batch_jobs(64, seed=0)
     t_tune = 0.0
     n_buckets = 0
+    opts = {"path": cs.BATCH_AUTO}
+    batch_timings = []
     if autotune:
         from paper_2012_03771_amd.autotune import Autotuner
         t0 = time.perf_counter()
         tuner = Autotuner()
-        tunes = tuner.tune_all(jobs)
+        tunes, opts, batch_timings = tuner.tune_batch(jobs)
         t_tune = time.perf_counter() - t0
         n_buckets = len(tuner.cache)
     else:
         tunes = [cs.Tune(large_mode=mode) for _ in jobs]
-    batch = cs.Batch(jobs, tunes)
-    bm, ct = batch.alloc_outputs()
-    batch.run(bm, ct, use_graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        batch.run(bm, ct, use_graph=True)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
+
+    def timed_batch(o):
+        b = cs.Batch(jobs, tunes, **o)
+        bm, ct = b.alloc_outputs()
+        b.run(bm, ct, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(bm, ct, use_graph=True)
+        torch.cuda.synchronize()
+        return b, bm, ct, (time.perf_counter() - t0) / reps
+
+    batch, bm, ct, t_batch = timed_batch(opts)
+    path = batch.path
     factors = sum(int(c.to(torch.int64).sum().item()) for c in ct)
     diag = batch.diag()
+    # the other path with the same tunings, for the comparison
+    other = cs.BATCH_LANES if path == cs.BATCH_PERSISTENT else cs.BATCH_PERSISTENT
+    t_other = None
+    try:
+        b2, bm2, ct2, t_other = timed_batch({"path": other})
+        same_paths = all(torch.equal(a, b) for a, b in zip(bm, bm2)) and all(torch.equal(a, b) for a, b in zip(ct, ct2))
+        b2.close()
+        del bm2, ct2
+    except cs.CsError:
+        same_paths = None
     # the same jobs, one plain launch sequence each, one after the other
     lays = [cs.plan(j, t) for j, t in zip(jobs, tunes)]
     ws = torch.empty((max(L.ws_bytes for L in lays),), dtype=torch.uint8, device="cuda")
@@ -417,6 +438,10 @@ def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
     torch.cuda.empty_cache()
     return {"workload": "64 seeded mixed jobs (P in primes [307,1019], d in {1,2,6,30,210}, m_inc 1e3-1e5, "
                         "limit 1e7-1e9, sl = round(40 ln N))",
+            "path": {cs.BATCH_PERSISTENT: "persistent", cs.BATCH_LANES: "lanes"}[path],
+            "items_per_task": opts.get("items_per_task") or None,
+            "ms_other_path": t_other * 1e3 if t_other is not None else None, "other_path_identical": same_paths,
+            "autotune_batch_ms": batch_timings,
             "ms_batched": t_batch * 1e3, "ms_sequential": t_seq * 1e3, "speedup": t_seq / t_batch,
             "jobs_per_s": 64 / t_batch, "factors_per_s": factors / t_batch,
             "seq_jobs_per_s": 64 / t_seq, "factors": factors, "identical_to_sequential": bool(same),
@@ -502,7 +527,10 @@ def main():
         print(json.dumps(_table_a2(cs, torch, W, [int(x) for x in args.a2_rows.split(",")])), flush=True)
         return
     job = W.SINGLE_JOBS[args.workload]
-    tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP)
+    scatter = {"auto": cs.SCATTER_AUTO, "atomic": cs.SCATTER_ATOMIC, "bytes": cs.SCATTER_BYTES,
+               "list": cs.SCATTER_LIST}[args.scatter]
+    tune = cs.Tune(large_mode=cs.LARGE_G if args.mode == "g" else cs.LARGE_THREE_GAP, scatter=scatter,
+                   thr=int(args.thr_mult * (2 * job.sl + 1)))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.copy_probe:

@@ -327,17 +327,60 @@ cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, const uint64_
 /* ------------------------------------------------------------------------------------------
  * Batches: many jobs (different P, d, m ranges, sl, limits) sieved by one sequence of fused
  * launches.  The prime table is built once up to the largest limit and shared; the per-job
- * preparation kernels each cover every job in a single launch, then each job's two sieve
- * branches run as single-job launches spread over lane streams that fork from and join the
- * caller's stream.  The sequence is captured once in a hipGraph and replayed.  Outputs are
- * bit-identical to one cs_sieve call per job.
+ * preparation kernels each cover every job in a single launch.  The sieve branches then run on
+ * one of two paths:
+ *   CS_BATCH_PERSISTENT  one launch of a persistent kernel whose workgroups pop tasks from a
+ *                        device queue until it is empty: every job's large-branch items in tasks
+ *                        of 1024, then every job's small-branch units; the byte counters of all
+ *                        jobs are folded by one fused launch after it.  Needs one large-prime
+ *                        enumeration (cs_tune.large_mode) for all jobs and every job's column
+ *                        table plus one tile row within 40 KB of LDS (sl up to about 40,000).
+ *   CS_BATCH_LANES       each job's branches as single-job launches spread over lane streams
+ *                        that fork from and join the caller's stream.
+ * A batch handle captures its sequence once in a hipGraph and replays it.  Outputs are
+ * bit-identical to one cs_sieve call per job on either path.
  * ------------------------------------------------------------------------------------------ */
 typedef struct cs_batch cs_batch;
 
+#define CS_BATCH_AUTO       0u   /* persistent when the jobs admit it, else lanes */
+#define CS_BATCH_PERSISTENT 1u
+#define CS_BATCH_LANES      2u
+
+#define CS_ORDER_AUTO        0u  /* persistent task queue order: CS_ORDER_BY_JOB */
+#define CS_ORDER_LARGE_FIRST 1u  /* every job's large tasks, then every job's small ones */
+#define CS_ORDER_SMALL_FIRST 2u
+#define CS_ORDER_BY_JOB      3u  /* job by job, each job's large tasks then its small ones */
+
+/* Batch-level knobs (outputs never depend on them).  NULL = all zero = automatic. */
+typedef struct cs_batch_opts {
+  uint32_t path;            /* CS_BATCH_AUTO, CS_BATCH_PERSISTENT or CS_BATCH_LANES */
+  uint32_t items_per_task;  /* persistent: large-branch work items (prime x m-chunk) per task, a
+                               multiple of 256 up to 8192; 0 = 1024 */
+  uint32_t blocks_per_cu;   /* persistent: workgroups per CU (1-8); 0 = 4 */
+  uint32_t order;           /* persistent: CS_ORDER_* of the task queue */
+} cs_batch_opts;
+
 /* Validates and plans every job, allocates the batch's device memory (prime table, per-job
- * tables; see cs_batch_layout's ws_bytes) on the current device.  tunes: n entries or NULL.
- * Errors: those of cs_plan for any job; CS_ENOMEM; CS_EDEVICE. */
+ * tables; see cs_batch_layout's ws_bytes) on the current device.  tunes: n entries or NULL;
+ * opts may be NULL (cs_batch_create passes NULL).  Errors: those of cs_plan for any job;
+ * CS_EINVAL for CS_BATCH_PERSISTENT when the jobs do not admit it, or knobs out of range;
+ * CS_ENOMEM; CS_EDEVICE. */
 cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tune* tunes, cs_batch** out);
+cs_status cs_batch_create_ex(const cs_job* jobs, uint32_t n, const cs_tune* tunes, const cs_batch_opts* opts,
+                             cs_batch** out);
+
+/* The path a handle runs: CS_BATCH_PERSISTENT or CS_BATCH_LANES (0 for NULL). */
+uint32_t cs_batch_path(const cs_batch* b);
+
+/* The whole batch in one call on the caller's stream and workspace (nothing allocated, no
+ * graph, no second stream): the persistent path when the jobs admit it, else each job's branch
+ * launches in turn on `stream`.  cs_batch_ws gives the workspace bytes (host only).  d_bitmaps /
+ * d_counts: n caller-owned outputs in cs_sieve's layout (NULL allowed for jobs without rows).
+ * Errors: those of cs_plan for any job; CS_ERANGE if ws_bytes is too small. */
+cs_status cs_batch_ws(const cs_job* jobs, uint32_t n, const cs_tune* tunes, uint64_t* ws_bytes);
+cs_status cs_sieve_batch(const cs_job* jobs, uint32_t n, const cs_tune* tunes, const cs_batch_opts* opts,
+                         uint32_t* const* d_bitmaps, uint32_t* const* d_counts, void* d_ws, uint64_t ws_bytes,
+                         void* stream);
 
 /* Layout of job i (n_m, n_x, row_words, bitmap and counts bytes); ws_bytes is the batch's
  * total device memory. */

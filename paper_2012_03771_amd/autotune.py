@@ -6,6 +6,10 @@ timed runs, HIP events on the launch stream) and the fastest is kept for the who
 Candidates vary the small/large threshold (a multiple of S = 2 sl + 1, Section 5's C_mult) and
 the expected hits per large-branch work item; all give identical outputs, so the choice only
 affects speed.
+
+tune_batch then tunes the whole batch: the batch path (one persistent launch over a device task
+queue, or per-job launches over lane streams) and the rows per small-branch LDS tile (the
+m-window of a tile), timing each combination on the batch itself replayed from its hipGraph.
 """
 from __future__ import annotations
 
@@ -79,3 +83,40 @@ class Autotuner:
 
     def tune_all(self, jobs):
         return [self.tune(j) for j in jobs]
+
+    # batch-level candidates: the persistent kernel with 256 or 1,024 large-branch items (primes x
+    # m-chunks) per task and 4 to 16 rows per small-branch tile, and the lane path
+    BATCH_CANDIDATES = ([{"path": B.BATCH_PERSISTENT, "items_per_task": ipt, "tile_rows": rows}
+                         for ipt in (256, 1024) for rows in (4, 8, 16)]
+                        + [{"path": B.BATCH_LANES, "items_per_task": 0, "tile_rows": rows} for rows in (8, 16)])
+
+    def tune_batch(self, jobs, reps: int = 2):
+        """Per-job tunings (tune_all), then the batch path, items per task and small-branch tile
+        rows that run the whole batch fastest.  Returns (tunes, batch options, timings)."""
+        import dataclasses
+        import time
+        import torch
+        base = self.tune_all(jobs)
+        timings = []
+        best = None
+        for cand in self.BATCH_CANDIDATES:
+            tunes = [dataclasses.replace(t, tile_rows=cand["tile_rows"]) for t in base]
+            try:
+                batch = B.Batch(jobs, tunes, path=cand["path"], items_per_task=cand["items_per_task"])
+            except B.CsError:
+                continue                                  # this path does not admit the jobs
+            bm, ct = batch.alloc_outputs()
+            batch.run(bm, ct, use_graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                batch.run(bm, ct, use_graph=True)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            batch.close()
+            del bm, ct
+            timings.append({**cand, "ms": t * 1e3})
+            if best is None or t < best[0]:
+                best = (t, cand, tunes)
+        torch.cuda.empty_cache()
+        return best[2], {"path": best[1]["path"], "items_per_task": best[1]["items_per_task"]}, timings

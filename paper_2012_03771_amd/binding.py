@@ -58,6 +58,11 @@ class cs_diag(C.Structure):
                 + [(n, C.c_uint64 * DECADES) for n in _DEC_FIELDS])
 
 
+class cs_batch_opts(C.Structure):
+    _fields_ = [("path", C.c_uint32), ("items_per_task", C.c_uint32), ("blocks_per_cu", C.c_uint32),
+                ("order", C.c_uint32)]
+
+
 class cs_server_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("max_limit", C.c_uint64), ("max_active", C.c_uint32),
                 ("chunks", C.c_uint32), ("tune", cs_tune)]
@@ -181,6 +186,10 @@ def lib():
         "cs_kmod_ws": ([u32, u64, P(u64)], i32),
         "cs_kmod": ([u32, u64, vp, u64, vp, vp, u64, vp], i32),
         "cs_batch_create": ([P(cs_job), u32, P(cs_tune), P(vp)], i32),
+        "cs_batch_create_ex": ([P(cs_job), u32, P(cs_tune), P(cs_batch_opts), P(vp)], i32),
+        "cs_batch_path": ([vp], u32),
+        "cs_batch_ws": ([P(cs_job), u32, P(cs_tune), P(u64)], i32),
+        "cs_sieve_batch": ([P(cs_job), u32, P(cs_tune), P(cs_batch_opts), P(vp), P(vp), vp, u64, vp], i32),
         "cs_batch_layout": ([vp, u32, P(cs_layout)], i32),
         "cs_batch_run": ([vp, P(vp), P(vp), i32, vp], i32),
         "cs_batch_diag": ([vp, P(cs_diag), vp], i32),
@@ -385,19 +394,61 @@ def unpack_bits(words, n_x: int):
     return out[:, :n_x]
 
 
-class Batch:
-    """Many jobs sieved by one fused launch sequence (replayed from a hipGraph)."""
+BATCH_AUTO = 0
+BATCH_PERSISTENT = 1
+BATCH_LANES = 2
 
-    def __init__(self, jobs, tunes=None):
+
+def _job_arrays(jobs, tunes):
+    arr = (cs_job * len(jobs))(*[_cjob(j) for j in jobs])
+    tarr = None
+    if tunes is not None:
+        tarr = (cs_tune * len(jobs))(*[t.c() if t is not None else Tune().c() for t in tunes])
+    return arr, tarr
+
+
+def batch_ws_bytes(jobs, tunes=None) -> int:
+    jobs = list(jobs)
+    arr, tarr = _job_arrays(jobs, tunes)
+    out = C.c_uint64()
+    _check(lib().cs_batch_ws(arr, len(jobs), tarr, C.byref(out)), "cs_batch_ws")
+    return out.value
+
+
+ORDER_AUTO = 0
+ORDER_LARGE_FIRST = 1
+ORDER_SMALL_FIRST = 2
+ORDER_BY_JOB = 3
+
+
+def _opts(path=BATCH_AUTO, items_per_task=0, blocks_per_cu=0, order=ORDER_AUTO):
+    return cs_batch_opts(path, items_per_task, blocks_per_cu, order)
+
+
+def sieve_batch(jobs, bitmaps, counts, ws, tunes=None, stream=None, **opts):
+    """cs_sieve_batch: every job in one call on the caller's stream and workspace."""
+    jobs = list(jobs)
+    arr, tarr = _job_arrays(jobs, tunes)
+    n = len(jobs)
+    bp = (C.c_void_p * n)(*[t.data_ptr() if t.numel() else None for t in bitmaps])
+    cp = (C.c_void_p * n)(*[t.data_ptr() if t.numel() else None for t in counts])
+    _check(lib().cs_sieve_batch(arr, n, tarr, C.byref(_opts(**opts)), bp, cp, _ptr(ws), ws.numel(), _stream(stream)),
+           "cs_sieve_batch")
+
+
+class Batch:
+    """Many jobs sieved by one fused launch sequence (replayed from a hipGraph).  Keyword options
+    are cs_batch_opts' fields (path, items_per_task, blocks_per_cu, order)."""
+
+    def __init__(self, jobs, tunes=None, path=BATCH_AUTO, **opts):
         jobs = list(jobs)
         self.n = len(jobs)
-        arr = (cs_job * self.n)(*[_cjob(j) for j in jobs])
-        tarr = None
-        if tunes is not None:
-            tarr = (cs_tune * self.n)(*[t.c() if t is not None else Tune().c() for t in tunes])
+        arr, tarr = _job_arrays(jobs, tunes)
         h = C.c_void_p()
-        _check(lib().cs_batch_create(arr, self.n, tarr, C.byref(h)), "cs_batch_create")
+        _check(lib().cs_batch_create_ex(arr, self.n, tarr, C.byref(_opts(path, **opts)), C.byref(h)),
+               "cs_batch_create_ex")
         self.h = h
+        self.path = int(lib().cs_batch_path(self.h))
         self.layouts = []
         for i in range(self.n):
             out = cs_layout()

@@ -189,19 +189,22 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
   jd.counts = counts;
   jd.branches = branches;
   fill_tiers(pl, p_lo, p_hi, &jd);
+  // With the byte counters or the list the large branch writes only its counters or cells until
+  // the fold or the grouping, so the small branch can run beside it on a second stream.  With the
+  // list, hits beyond a full pool are OR-ed into the bitmap by the large branch itself, so the small
+  // branch then merges its tiles with atomics.
+  hipStreamCaptureStatus cap0 = hipStreamCaptureStatusNone;
+  AuxStream* aux = nullptr;
+  if (!own_stream_only && branches == CS_BRANCH_ALL && (pl.scatter_bytes || pl.scatter_list) && pl.n_m > 0 &&
+      hipStreamIsCapturing(s, &cap0) == hipSuccess && cap0 == hipStreamCaptureStatusNone)
+    aux = aux_stream();
+  if (aux && pl.scatter_list) jd.small_atomic = 1;
   uint64_t* items_base = reinterpret_cast<uint64_t*>(ws + L.items_base);
   CS_TRY(launch_write_job(jd, jdp, s));
   CS_TRY(launch_prep_bounds(jdp, 1, s));
   CS_TRY(launch_items_scan(jdp, 1, items_base, s));
   if (pl.n_m == 0) return CS_OK;
   const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
-  // With the byte counters the large branch writes only the counters until the fold, so the
-  // small branch (which read-modify-writes bitmap words) can run beside it on a second stream.
-  hipStreamCaptureStatus cap0 = hipStreamCaptureStatusNone;
-  AuxStream* aux = nullptr;
-  if (!own_stream_only && branches == CS_BRANCH_ALL && pl.scatter_bytes &&
-      hipStreamIsCapturing(s, &cap0) == hipSuccess && cap0 == hipStreamCaptureStatusNone)
-    aux = aux_stream();
   if (aux) {
     CS_TRY(hipEventRecord(aux->fork, s));
     CS_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
@@ -214,6 +217,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     if (pl.scatter_list) {
       CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.list_cursor), 2, 0u, s));
       CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.bkt_count), pl.n_bkt + 1ull, 0u, s));
+      CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.list_super), kListSupers + 1ull, 0u, s));
     }
     const uint32_t kind = pl.scatter_list ? 2u : (pl.scatter_bytes ? 1u : 0u);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -222,7 +226,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
       ev = large_events(ws);
     if (ev) CS_TRY(hipEventRecord(ev->start, s));
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, &ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes,
-                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, s));
+                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, pl.large_mode, s));
     if (ev) {
       CS_TRY(hipEventRecord(ev->stop, s));
       ev->recorded = true;

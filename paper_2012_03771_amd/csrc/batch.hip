@@ -31,10 +31,9 @@ namespace cs {
 
 static uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
 
-// Re-derives the small-branch tiles of a plan for a shared LDS column-table size.
-void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune) {
+void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune, uint32_t lds_budget) {
   const uint32_t ct_bytes = lds_ct_words * 8u;
-  uint32_t rows = (kLdsBudget - ct_bytes) / (4u * pl.row_words + 8u);
+  uint32_t rows = lds_budget > ct_bytes ? (lds_budget - ct_bytes) / (4u * pl.row_words + 8u) : 0u;
   rows = std::max(1u, std::min(rows, kTileRowsMax));
   if (tune && tune->tile_rows) rows = std::min(rows, tune->tile_rows);
   pl.tile_rows = rows;
@@ -51,7 +50,7 @@ void retile_small(Plan& pl, uint32_t lds_ct_words, int n_cu, const cs_tune* tune
 }
 
 cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uint32_t n, int n_cu,
-                      uint64_t prime_extent) {
+                      uint64_t prime_extent, int want_persistent) {
   b.n = n;
   b.n_cu = n_cu;
   b.plans.assign(n, Plan());
@@ -79,6 +78,25 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
   if (Lp >= kMaxLimit) return CS_ERANGE;
   b.Lp = Lp;
   b.lds_ct_words = max_ct * 8u <= kLdsCtMax ? max_ct : 0u;
+  // The persistent kernel needs one enumeration for all jobs and every job's column table (and
+  // residue table of d) in LDS beside a small-branch tile of at least one row.
+  {
+    bool ok = b.lds_ct_words > 0;
+    uint32_t max_dp = 0;
+    b.large_mode = b.plans[0].large_mode;
+    for (uint32_t i = 0; i < n && ok; ++i) {
+      const Plan& pl = b.plans[i];
+      ok = pl.large_mode == b.large_mode;
+      max_dp = std::max<uint32_t>(max_dp, (uint32_t)pl.dpre.size());
+      if (ok && pl.n_m > 0)
+        ok = (uint64_t)b.lds_ct_words * 8u + 4ull * pl.row_words + 8u <= kPersistLds;
+    }
+    const uint32_t large_lds = b.lds_ct_words * 8u + ((max_dp * 2u + 3u) & ~3u);
+    ok = ok && large_lds <= kPersistLds;
+    if (want_persistent > 0 && !ok) return CS_EINVAL;
+    b.persistent = want_persistent != 0 && ok;
+    b.persist_lds = large_lds;
+  }
   b.units = 0;
   b.lds_bytes = 0;
   b.max_words = 0;
@@ -87,8 +105,8 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
   b.kmod_cap = 0;
   for (uint32_t i = 0; i < n; ++i) {
     Plan& pl = b.plans[i];
-    retile_small(pl, b.lds_ct_words, n_cu, tunes ? &tunes[i] : nullptr);
-    b.lds_bytes = std::max(b.lds_bytes, pl.lds_bytes);
+    retile_small(pl, b.lds_ct_words, n_cu, tunes ? &tunes[i] : nullptr, b.persistent ? kPersistLds : kLdsBudget);
+    if (pl.n_m > 0) b.lds_bytes = std::max(b.lds_bytes, pl.lds_bytes);   // jobs without rows launch nothing
     b.max_words = std::max<uint64_t>(b.max_words, pl.n_m * (uint64_t)pl.row_words);
     b.max_m_inc = std::max<uint64_t>(b.max_m_inc, pl.job.m_inc);
     b.max_sl = std::max(b.max_sl, pl.job.sl);
@@ -109,6 +127,10 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
   b.o_jobs = take(sizeof(JobDev) * (uint64_t)n);
   b.o_lim = take(8ull * (n + 1));
   b.o_items = take(8ull * (n + 1));
+  b.o_tbase = take(8ull * (2ull * n + 1));
+  b.o_next = take(8);
+  b.persist_lds = std::max(b.persist_lds, b.lds_bytes);
+  b.persist_blocks = (uint32_t)n_cu * kPersistBlocksPerCu;
   b.job_off.resize(n);
   for (uint32_t i = 0; i < n; ++i) b.job_off[i] = take(b.plans[i].ws.total);
   b.mem_bytes = o;
@@ -116,10 +138,13 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
 }
 
 cs_status multi_alloc(MultiJob& b, hipStream_t s) {
-  if (hipMalloc(&b.mem, b.mem_bytes) != hipSuccess) {
-    b.mem = nullptr;
-    return CS_ENOMEM;
-  }
+  uint8_t* mem = nullptr;
+  if (hipMalloc(&mem, b.mem_bytes) != hipSuccess) return CS_ENOMEM;
+  return multi_use_memory(b, mem, s);
+}
+
+cs_status multi_use_memory(MultiJob& b, uint8_t* mem, hipStream_t s) {
+  b.mem = mem;
   uint8_t* m = b.mem;
   b.pw.n_base = reinterpret_cast<uint32_t*>(m + b.o_nbase);
   b.pw.n_primes = reinterpret_cast<uint64_t*>(m + b.o_np);
@@ -132,6 +157,8 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
   b.jobs_dev = reinterpret_cast<JobDev*>(m + b.o_jobs);
   b.lim_base = reinterpret_cast<uint64_t*>(m + b.o_lim);
   b.items_base = reinterpret_cast<uint64_t*>(m + b.o_items);
+  b.tbase = reinterpret_cast<uint64_t*>(m + b.o_tbase);
+  b.task_next = reinterpret_cast<unsigned long long*>(m + b.o_next);
   b.jds.resize(b.n);
   uint64_t unit_base = 0;
   for (uint32_t i = 0; i < b.n; ++i) {
@@ -142,6 +169,9 @@ cs_status multi_alloc(MultiJob& b, hipStream_t s) {
       CS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + pl.ws.hitbytes), pl.n_m * (uint64_t)pl.row_words * 8ull, 0u, s));
     b.jds[i].small_unit_base = 0;             // each job's small branch is its own launch
     b.jds[i].prime_cap = b.cap;
+    // in the persistent kernel a job's small units run beside its large items: with the atomic
+    // scatter both OR into the bitmap, so the small tiles merge with atomics
+    if (b.persistent && !pl.scatter_bytes) b.jds[i].small_atomic = 1;
     unit_base += (uint64_t)pl.n_windows * pl.n_slices;
     if (!pl.dpre.empty()) {
       CS_TRY(launch_upload(ws + pl.ws.dpre, pl.dpre.data(), pl.dpre.size() * 2ull, s));
@@ -178,22 +208,31 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   CS_TRY(launch_rows_cols(b.jobs_dev, n, b.max_m_inc, b.max_sl, b.n_cu, s));
   CS_TRY(launch_dpattern(b.jobs_dev, n, b.max_phi, b.max_rw, s));
   CS_TRY(launch_prep_bounds(b.jobs_dev, n, s));
+  if (b.persistent) {
+    // every job's small units and large items in one launch, then the byte counters' fold
+    CS_TRY(launch_batch_persistent(b.jobs_dev, n, b.tbase, b.task_next, b.persist_blocks, b.persist_lds,
+                                   b.lds_ct_words, b.bytes ? 1u : 0u, b.large_mode, b.items_per_task, b.order, s));
+    if (b.bytes) CS_TRY(launch_fold_bytes(b.jobs_dev, n, b.max_rows, b.n_cu, s));
+    return CS_OK;
+  }
   // Each job's branches as single-job launches (LDS tables, uniform job fields, byte counters),
-  // jobs spread over the lanes so several run at once.
+  // jobs spread over the lanes so several run at once (on s in turn when there are no lanes).
   const uint32_t nl = (uint32_t)b.lanes.size();
-  CS_TRY(hipEventRecord(b.ev_fork, s));
-  for (uint32_t l = 0; l < nl; ++l) CS_TRY(hipStreamWaitEvent(b.lanes[l], b.ev_fork, 0));
+  if (nl) {
+    CS_TRY(hipEventRecord(b.ev_fork, s));
+    for (uint32_t l = 0; l < nl; ++l) CS_TRY(hipStreamWaitEvent(b.lanes[l], b.ev_fork, 0));
+  }
   for (uint32_t i = 0; i < n; ++i) {
     const Plan& pl = b.plans[i];
     if (pl.n_m == 0) continue;
-    hipStream_t ls = b.lanes[i % nl];
+    hipStream_t ls = nl ? b.lanes[i % nl] : s;
     const JobDev* jd = b.jobs_dev + i;
     uint64_t* ib = reinterpret_cast<uint64_t*>(b.mem + b.job_off[i] + pl.ws.items_base);
     CS_TRY(launch_items_scan(jd, 1, ib, ls));
     const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
     CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, ls));
     CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, &b.jds[i].ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
-                        (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, ls));
+                        (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, pl.large_mode, ls));
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jd, 1, pl.n_m, b.n_cu, ls));
   }
   for (uint32_t l = 0; l < nl; ++l) {
@@ -201,6 +240,25 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
     CS_TRY(hipStreamWaitEvent(s, b.ev_done[l], 0));
   }
   return CS_OK;
+}
+
+cs_status batch_opts_of(const cs_batch_opts* opts, int* want_persistent) {
+  const uint32_t path = opts ? opts->path : CS_BATCH_AUTO;
+  if (path > CS_BATCH_LANES) return CS_EINVAL;
+  if (opts && (opts->items_per_task % 256u || opts->items_per_task > 8192u || opts->blocks_per_cu > 8u ||
+               opts->order > CS_ORDER_BY_JOB))
+    return CS_EINVAL;
+  *want_persistent = path == CS_BATCH_PERSISTENT ? 1 : (path == CS_BATCH_LANES ? 0 : -1);
+  return CS_OK;
+}
+
+// Defaults measured on the 64-job mixed batch (three-gap, autotuned jobs): 1,024 items per task in
+// job order 249 ms, large tasks first 260 ms, 256 items per task 264-274 ms; the lane path 259 ms.
+void apply_batch_opts(MultiJob& b, const cs_batch_opts* opts) {
+  b.items_per_task = opts && opts->items_per_task ? opts->items_per_task : 1024u;
+  const uint32_t order = opts ? opts->order : CS_ORDER_AUTO;
+  b.order = order == CS_ORDER_LARGE_FIRST ? 0u : (order == CS_ORDER_SMALL_FIRST ? 1u : 2u);   // k_batch_queue's
+  if (opts && opts->blocks_per_cu) b.persist_blocks = (uint32_t)b.n_cu * opts->blocks_per_cu;
 }
 
 cs_status multi_diag(const MultiJob& b, cs_diag* out) {
@@ -276,16 +334,21 @@ static void drop_graph(cs_batch* b) {
   b->graph = nullptr;
 }
 
-extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tune* tunes, cs_batch** out) {
+extern "C" cs_status cs_batch_create_ex(const cs_job* jobs, uint32_t n, const cs_tune* tunes,
+                                        const cs_batch_opts* opts, cs_batch** out) {
   if (!jobs || !out || n == 0) return CS_EINVAL;
   *out = nullptr;
+  int want = -1;
+  cs_status st = batch_opts_of(opts, &want);
+  if (st) return st;
   cs_batch* b = new (std::nothrow) cs_batch();
   if (!b) return CS_ENOMEM;
   if (hipGetDevice(&b->device) != hipSuccess) { delete b; return CS_EDEVICE; }
-  cs_status st = multi_build(b->mj, jobs, tunes, n, device_cu_count(), 2);
+  st = multi_build(b->mj, jobs, tunes, n, device_cu_count(), 2, want);
   if (st) { delete b; return st; }
+  apply_batch_opts(b->mj, opts);
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return CS_EDEVICE; }
-  if (create_lanes(b->mj, std::min<uint32_t>(kBatchLanes, n)) != CS_OK) {
+  if (!b->mj.persistent && create_lanes(b->mj, std::min<uint32_t>(kBatchLanes, n)) != CS_OK) {
     (void)hipStreamDestroy(b->cap_stream);
     destroy_lanes(b->mj);
     delete b;
@@ -302,6 +365,15 @@ extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tu
   }
   *out = b;
   return CS_OK;
+}
+
+extern "C" cs_status cs_batch_create(const cs_job* jobs, uint32_t n, const cs_tune* tunes, cs_batch** out) {
+  return cs_batch_create_ex(jobs, n, tunes, nullptr, out);
+}
+
+extern "C" uint32_t cs_batch_path(const cs_batch* b) {
+  if (!b) return 0;
+  return b->mj.persistent ? CS_BATCH_PERSISTENT : CS_BATCH_LANES;
 }
 
 extern "C" cs_status cs_batch_layout(const cs_batch* b, uint32_t i, cs_layout* out) {
@@ -376,4 +448,38 @@ extern "C" cs_status cs_batch_destroy(cs_batch* b) {
   }
   delete b;
   return CS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// One call: the whole batch on the caller's stream with a caller-provided workspace.
+// ---------------------------------------------------------------------------------------------
+extern "C" cs_status cs_batch_ws(const cs_job* jobs, uint32_t n, const cs_tune* tunes, uint64_t* ws_bytes) {
+  if (!jobs || n == 0 || !ws_bytes) return CS_EINVAL;
+  MultiJob mj;
+  cs_status st = multi_build(mj, jobs, tunes, n, device_cu_count(), 2, -1);
+  if (st) return st;
+  *ws_bytes = mj.mem_bytes;
+  return CS_OK;
+}
+
+extern "C" cs_status cs_sieve_batch(const cs_job* jobs, uint32_t n, const cs_tune* tunes, const cs_batch_opts* opts,
+                                    uint32_t* const* d_bitmaps, uint32_t* const* d_counts, void* d_ws,
+                                    uint64_t ws_bytes, void* stream) {
+  if (!jobs || n == 0 || !d_bitmaps || !d_counts || !d_ws) return CS_EINVAL;
+  int want = -1;
+  cs_status st = batch_opts_of(opts, &want);
+  if (st) return st;
+  MultiJob mj;
+  st = multi_build(mj, jobs, tunes, n, device_cu_count(), 2, want);
+  if (st) return st;
+  apply_batch_opts(mj, opts);
+  if (ws_bytes < mj.mem_bytes) return CS_ERANGE;
+  for (uint32_t i = 0; i < n; ++i)
+    if (mj.plans[i].n_m > 0 && (!d_bitmaps[i] || !d_counts[i])) return CS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  st = multi_use_memory(mj, static_cast<uint8_t*>(d_ws), s);
+  if (st) return st;
+  st = multi_bind(mj, d_bitmaps, d_counts, s);
+  if (st) return st;
+  return multi_enqueue(mj, s);
 }

@@ -106,7 +106,9 @@ struct JobDev {
   uint32_t* list_sorted;             // cells grouped by bucket
   uint32_t* bkt_count;               // n_bkt + 1
   uint32_t* bkt_base;                // n_bkt + 1: exclusive prefix of bkt_count
-  uint32_t* bkt_cursor;              // n_bkt + 1 bucket cursors, then kListSupers group cursors
+  uint32_t* bkt_cursor;              // n_bkt + 1 bucket cursors
+  uint32_t* list_super;              // per group of buckets: cells counted by the large branch, bases, cursors
+                                     // (3 x (kListSupers + 1) words)
   uint64_t list_chunks;
   uint32_t n_bkt, bkt_rows;          // bkt_rows = 2^(bkt_shift - cell_shift)
   uint32_t bkt_per_super;            // 2^super_shift buckets per first-level group

@@ -882,6 +882,85 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
   }
 }
 
+// One small-branch unit (a window of tile_rows rows and a slice of the small primes) of job j,
+// by the whole workgroup: unit `local` of the job.  lds: [column table, lds_ct_words uint2][tile
+// rows x row_words][counts][m offsets]; ct_ready: the job's column table is already in place.
+__device__ __forceinline__ void small_unit(const JobDev& j, uint64_t local, uint32_t* lds, uint32_t lds_ct_words,
+                                           bool ct_ready, unsigned long long& n_pairs, unsigned long long& n_marks) {
+  const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const uint32_t nwaves = blockDim.x / kWave;
+  const auto& c = *gbl(j.ctrl);
+  const uint64_t window = local / j.n_slices;
+  const uint32_t slice = (uint32_t)(local % j.n_slices);
+  const uint64_t row_lo = window * j.tile_rows;
+  const uint64_t row_hi = min(row_lo + j.tile_rows, j.n_m);
+  const uint32_t R = (uint32_t)(row_hi - row_lo);
+  const uint32_t rw = j.row_words;
+  const uint32_t w = j.w;
+  // prime slice
+  const uint64_t span = c.small_hi - c.small_lo;
+  const uint64_t s_lo = c.small_lo + span * slice / j.n_slices;
+  const uint64_t s_hi = c.small_lo + span * (slice + 1) / j.n_slices;
+  // LDS: [column table][tile R x rw][counts R]
+  const uint32_t nct = (2 * j.sl + 1 + 31) / 32;
+  const bool ct_in_lds = nct <= lds_ct_words;
+  uint2* ct_l = reinterpret_cast<uint2*>(lds);
+  uint32_t* tile = lds + 2 * lds_ct_words;
+  uint32_t* cnt = tile + (uint32_t)j.tile_rows * rw;
+  uint32_t* moff = cnt + j.tile_rows;            // m - m_start of the tile's rows
+  if (ct_in_lds && !ct_ready)
+    for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = ((const uint2*)gbl(j.coltab))[i];
+  for (uint32_t i = threadIdx.x; i < R * rw; i += blockDim.x) tile[i] = 0;
+  for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) {
+    cnt[i] = 0;
+    moff[i] = gbl(j.m_off)[row_lo + i];
+  }
+  __syncthreads();
+  const bool dpat = j.dpat_apply != 0;
+  if (dpat && slice == 0) {
+    // primes dividing d: the row of this m's residue class (tile rows start cleared)
+    const double dd = (double)j.d;
+    for (uint32_t r = 0; r < R; ++r) {
+      const double x = (double)j.r0_d + (double)moff[r];
+      double rr = fma(-floor(x * j.inv_d), dd, x);
+      rr = rr < 0.0 ? rr + dd : (rr >= dd ? rr - dd : rr);
+      const uint32_t cls = gbl(j.dpre)[(uint32_t)rr] & 0x7fffu;
+      const gptr<const uint32_t> src = gbl(j.dpat) + (uint64_t)cls * rw;
+      for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) tile[r * rw + u] = src[u];
+      if (threadIdx.x == 0) {
+        const uint32_t pc = gbl(j.dpat_cnt)[cls];
+        cnt[r] = pc;
+        n_marks += pc;
+      }
+    }
+    __syncthreads();
+  }
+
+  {
+    SmallArgs a{j, c.small_dense, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
+    if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
+    else small_marks(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
+  }
+  __syncthreads();
+  // write the tile: rows of this unit belong to it alone unless the primes are sliced
+  for (uint32_t r = 0; r < R; ++r) {
+    const gptr<uint32_t> dst = gbl(j.bitmap) + (row_lo + r) * (uint64_t)rw;
+    for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) {
+      const uint32_t v = tile[r * rw + u];
+      if (!v) continue;
+      if (j.n_slices == 1 && !j.small_atomic) dst[u] |= v;
+      else atomicOr((uint32_t*)(dst + u), v);
+    }
+  }
+  for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
+    const uint32_t v = cnt[r];
+    if (!v) continue;
+    if (j.n_slices == 1 && !j.small_atomic) gbl(j.counts)[row_lo + r] += v;
+    else atomicAdd((uint32_t*)(gbl(j.counts) + row_lo + r), v);
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                uint64_t total_units, uint32_t lds_ct_words) {
   extern __shared__ uint32_t lds[];
@@ -891,78 +970,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
   uint32_t ji = 0;                                   // units only grow: resume the job search
   for (uint64_t unit = blockIdx.x; unit < total_units; unit += gridDim.x) {
     while (ji + 1 < n_jobs && jobs[ji + 1].small_unit_base <= unit) ++ji;
-    const JobDev& j = jobs[ji];
-    const auto& c = *gbl(j.ctrl);
-    const uint64_t local = unit - j.small_unit_base;
-    const uint64_t window = local / j.n_slices;
-    const uint32_t slice = (uint32_t)(local % j.n_slices);
-    const uint64_t row_lo = window * j.tile_rows;
-    const uint64_t row_hi = min(row_lo + j.tile_rows, j.n_m);
-    const uint32_t R = (uint32_t)(row_hi - row_lo);
-    const uint32_t rw = j.row_words;
-    const uint32_t w = j.w;
-    // prime slice
-    const uint64_t span = c.small_hi - c.small_lo;
-    const uint64_t s_lo = c.small_lo + span * slice / j.n_slices;
-    const uint64_t s_hi = c.small_lo + span * (slice + 1) / j.n_slices;
-    // LDS: [column table][tile R x rw][counts R]
-    const uint32_t nct = (2 * j.sl + 1 + 31) / 32;
-    const bool ct_in_lds = nct <= lds_ct_words;
-    uint2* ct_l = reinterpret_cast<uint2*>(lds);
-    uint32_t* tile = lds + 2 * lds_ct_words;
-    uint32_t* cnt = tile + (uint32_t)j.tile_rows * rw;
-    uint32_t* moff = cnt + j.tile_rows;            // m - m_start of the tile's rows
-    if (ct_in_lds)
-      for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ct_l[i] = ((const uint2*)gbl(j.coltab))[i];
-    for (uint32_t i = threadIdx.x; i < R * rw; i += blockDim.x) tile[i] = 0;
-    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) {
-      cnt[i] = 0;
-      moff[i] = gbl(j.m_off)[row_lo + i];
-    }
-    __syncthreads();
-    const bool dpat = j.dpat_apply != 0;
-    if (dpat && slice == 0) {
-      // primes dividing d: the row of this m's residue class (tile rows start cleared)
-      const double dd = (double)j.d;
-      for (uint32_t r = 0; r < R; ++r) {
-        const double x = (double)j.r0_d + (double)moff[r];
-        double rr = fma(-floor(x * j.inv_d), dd, x);
-        rr = rr < 0.0 ? rr + dd : (rr >= dd ? rr - dd : rr);
-        const uint32_t cls = gbl(j.dpre)[(uint32_t)rr] & 0x7fffu;
-        const gptr<const uint32_t> src = gbl(j.dpat) + (uint64_t)cls * rw;
-        for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) tile[r * rw + u] = src[u];
-        if (threadIdx.x == 0) {
-          const uint32_t pc = gbl(j.dpat_cnt)[cls];
-          cnt[r] = pc;
-          n_marks += pc;
-        }
-      }
-      __syncthreads();
-    }
-
-    {
-      SmallArgs a{j, c.small_dense, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
-      if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
-      else small_marks(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
-    }
-    __syncthreads();
-    // write the tile: rows of this unit belong to it alone unless the primes are sliced
-    for (uint32_t r = 0; r < R; ++r) {
-      const gptr<uint32_t> dst = gbl(j.bitmap) + (row_lo + r) * (uint64_t)rw;
-      for (uint32_t u = threadIdx.x; u < rw; u += blockDim.x) {
-        const uint32_t v = tile[r * rw + u];
-        if (!v) continue;
-        if (j.n_slices == 1 && !j.small_atomic) dst[u] |= v;
-        else atomicOr((uint32_t*)(dst + u), v);
-      }
-    }
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
-      const uint32_t v = cnt[r];
-      if (!v) continue;
-      if (j.n_slices == 1 && !j.small_atomic) gbl(j.counts)[row_lo + r] += v;
-      else atomicAdd((uint32_t*)(gbl(j.counts) + row_lo + r), v);
-    }
-    __syncthreads();
+    small_unit(jobs[ji], unit - jobs[ji].small_unit_base, lds, lds_ct_words, false, n_pairs, n_marks);
   }
   // counters: one atomic per workgroup and counter (lane 0 of each wavefront holds its sums)
   __shared__ unsigned long long s_cnt[2][256 / kWave];
@@ -1059,7 +1067,7 @@ struct HitCtx {
   gptr<uint32_t> list_fill;
   gptr<unsigned long long> list_cursor;
   uint64_t list_chunks;
-  uint32_t d_small, phi_d, pre_r0, row_words, cell_shift;
+  uint32_t d_small, phi_d, pre_r0, row_words, cell_shift, sup_shift;
 };
 
 __device__ __forceinline__ HitCtx hit_ctx(const JobDev& j) {
@@ -1077,6 +1085,7 @@ __device__ __forceinline__ HitCtx hit_ctx(const JobDev& j) {
   h.pre_r0 = j.pre_r0;
   h.row_words = j.row_words;
   h.cell_shift = j.cell_shift;
+  h.sup_shift = j.bkt_shift + j.super_shift;
   return h;
 }
 
@@ -1092,7 +1101,7 @@ struct ListReg {
 // wavefront).  A full chunk is closed (its fill recorded) and a new one taken from the pool
 // cursor; when the pool is exhausted, hits take the atomic path instead.
 __device__ __forceinline__ void list_step(const HitCtx& j, ListReg& lr, bool ok,
-                                          uint32_t cell, uint64_t row, uint32_t col) {
+                                          uint32_t cell, uint64_t row, uint32_t col, uint32_t* sup) {
   const unsigned long long act = __ballot(ok);
   if (act == 0) return;
   const uint32_t lane = __lane_id();
@@ -1116,6 +1125,7 @@ __device__ __forceinline__ void list_step(const HitCtx& j, ListReg& lr, bool ok,
   if (ok) {
     if (chunk != kPoolFull) {
       j.list_pool[(uint64_t)chunk * kListChunk + fill + rank] = cell;
+      atomicAdd(&sup[cell >> j.sup_shift], 1u);     // the workgroup's cells per group of buckets
     } else {
       atomicOr((uint32_t*)(j.bitmap + row * j.row_words + (col >> 5)), 1u << (col & 31));
       atomicAdd((uint32_t*)(j.counts + row), 1u);
@@ -1139,7 +1149,7 @@ __device__ __forceinline__ void list_sync(ListReg& lr, unsigned long long* lkey)
 
 template <bool kLds, int kSc>
 __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kLds>& T, uint64_t o, MPos mp,
-                                           uint32_t jj, unsigned long long& useful, ListReg& lr) {
+                                           uint32_t jj, unsigned long long& useful, ListReg& lr, uint32_t* sup) {
   if constexpr (kSc == 2) {
     // every lane of the loop takes the step, with or without a hit
     bool ok;
@@ -1155,7 +1165,7 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
     }
     uint32_t col = 0;
     if (ok) ok = lookup_col(T.ct, jj, &col);        // X shares a factor with K
-    list_step(j, lr, ok, ok ? ((row << j.cell_shift) | col) : 0u, row, col);
+    list_step(j, lr, ok, ok ? ((row << j.cell_shift) | col) : 0u, row, col, sup);
     if (ok) ++useful;
     return;
   }
@@ -1195,7 +1205,193 @@ __device__ __forceinline__ void record_hit(const HitCtx& j, const LargeTables<kL
 // residues step by 2K mod p, so Eq. 5 and the three-gap return times are those of 2K mod p and
 // the even m are never visited.
 // ------------------------------------------------------------------------------------------
-template <bool kLds, int kSc>
+// Per-lane counters of the large branch, for the decade of the lane's current prime (a lane's
+// items only grow, so its primes change decade rarely); flushed into the workgroup's per-decade
+// LDS counters when the decade changes and at the end.
+struct LaneCount {
+  unsigned long long raw, useful, calls, levels, n_pr;
+  uint32_t cur_dec, err;
+};
+
+__device__ __forceinline__ void lane_count_init(LaneCount& lc) {
+  lc.raw = lc.useful = lc.calls = lc.levels = lc.n_pr = 0;
+  lc.cur_dec = kDecades;
+  lc.err = 0;
+}
+
+__device__ __forceinline__ void flush_dec(LaneCount& lc, unsigned long long (*s_dec)[kDecades]) {
+  const uint32_t d = lc.cur_dec;
+  if (d < (uint32_t)kDecades) {
+    if (lc.n_pr) atomicAdd(&s_dec[DC_PRIMES][d], lc.n_pr);
+    if (lc.raw) atomicAdd(&s_dec[DC_RAW][d], lc.raw);
+    if (lc.useful) atomicAdd(&s_dec[DC_HITS][d], lc.useful);
+    if (lc.calls) atomicAdd(&s_dec[DC_SOLVES][d], lc.calls);
+    if (lc.levels) atomicAdd(&s_dec[DC_LEVELS][d], lc.levels);
+  }
+  lc.raw = lc.useful = lc.calls = lc.levels = lc.n_pr = 0;
+}
+
+// One large-branch work item (prime, chunk of the m range) of job j: item `local` of the job's
+// tiered item space.  t_last: the lane's tier of its previous item of this job (items only grow).
+template <bool kLds, int kSc, bool kG>
+__device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kLds>& T, uint64_t local,
+                                           uint32_t& t_last, LaneCount& lc, unsigned long long (*s_dec)[kDecades],
+                                           ListReg& lreg, unsigned long long* lkey, uint32_t* s_sup) {
+  const auto& c = *gbl(j.ctrl);
+  uint32_t t = t_last;
+  while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
+  t_last = t;
+  const uint64_t li = local - c.tier_item_base[t];
+  const uint32_t C = j.tier_chunks[t];
+  // Item order.  One solve per hit: prime-major, so neighbouring lanes share (p, K mod p)
+  // and walk the same sequence of moduli in Eq. 5's descent (less divergence).  Three-gap
+  // stepping: chunk-major, so lanes running at the same time share an m-chunk and their
+  // scattered marks stay within 1/C of the bitmap rows.
+  const uint64_t t0 = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]);
+  uint64_t chunk, pi;
+  if (C == 1) {
+    chunk = 0;
+    pi = t0 + li;
+  } else if (kG) {
+    const uint64_t q = div_small(li, C);
+    pi = t0 + q;
+    chunk = li - q * C;
+  } else {
+    const uint64_t npt = c.tier_idx[t] - t0;
+    chunk = div_small(li, npt);
+    pi = t0 + (li - chunk * npt);
+  }
+  // the walk's positions: for each class c of m mod s (s = m_step), m = m_start + o_c + s u with
+  // o_c = (c - m_start) mod s and u in [0, U); a chunk is a range of u, shared by the classes
+  const uint32_t s = j.m_step;
+  const uint64_t U = (j.m_inc + s - 1) / s;
+  const uint64_t L = C == 1 ? U : div_small(U + C - 1, C);
+  const uint64_t u_lo = (uint64_t)chunk * L;
+  const uint64_t u_hi = min(u_lo + L, U);
+  if (u_lo >= u_hi) return;
+
+  const uint64_t p = gbl(j.primes)[pi];
+  const uint64_t k1 = gbl(j.kmod)[pi];
+  {
+    const uint32_t dc = decade_of(p);
+    if (dc != lc.cur_dec) {
+      flush_dec(lc, s_dec);
+      lc.cur_dec = dc;
+    }
+    if (chunk == 0) ++lc.n_pr;                        // each prime once (chunk 0 always has positions)
+  }
+  uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
+  k -= k >= 4 * p ? 4 * p : 0;                     // s <= 6: s K mod p < 8p before these
+  k -= k >= 2 * p ? 2 * p : 0;
+  k -= k >= p ? p : 0;
+  const double pinv = recip((double)p);             // within an ulp: every quotient below is corrected
+  const uint64_t w = j.w;
+  const uint32_t d32 = (uint32_t)j.d;
+  const double inv_d = j.inv_d;
+  const bool d_small = j.d_small != 0;
+  const HitCtx hc = hit_ctx(j);
+  // k^-1 mod p (and, for three-gap stepping, the two return times) from one Euclid pass
+  uint64_t kinv = 0;
+  gaps3 g = {0, 0, 0, 0};
+  if (kG) {
+    kinv = modinv(k, p);
+  } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
+    lc.err |= E_SOLVE;
+    return;
+  }
+  // three-gap return times in offsets of m (a time past the chunk ends the walk, so the
+  // quotients below only matter for the times that are taken)
+  const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
+  uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
+  if (!kG && d_small) {
+    mpos_divmod(sta, d32, inv_d, &aq, &ar);
+    mpos_divmod(stb, d32, inv_d, &bq, &br);
+    mpos_divmod(tab, d32, inv_d, &abq, &abr);
+  }
+  const uint64_t mk = gbl(j.mk)[pi];
+  for (uint32_t cls = 0; cls < s; ++cls) {
+    // list scatter: lanes that left the previous class's walk early catch up on the wavefront's
+    // chunk state before the next walk appends (every lane reaches this point)
+    if constexpr (kSc == 2) {
+      if (cls > 0) list_sync(lreg, lkey);
+    }
+    const uint64_t o_par = (cls + s - j.m0_mod_step) % s;
+    const uint64_t o_lo = o_par + s * u_lo;
+    // a class that cannot hold rows, or that ends before this chunk, is skipped
+    if (!((j.m_classes >> cls) & 1u) || o_lo >= j.m_inc) continue;
+    const uint64_t o_hi = min(o_par + s * u_hi, j.m_inc);   // visited o = o_par + s u < o_hi
+    // residue of m*K + SL at m = m_start + o_lo
+    uint64_t r = mk + mulmod(o_lo, k1, p, pinv);
+    r = r >= p ? r - p : r;
+    r += j.sl;                                     // sl < w < thr < p
+    r = r >= p ? r - p : r;
+    uint64_t o = o_lo;
+    MPos mp = {0, 0};
+    if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
+
+    if (kG) {
+      // one solve of Eq. 3 per hit
+      while (true) {
+        if (r > w) {
+          int lv = 0;
+          uint64_t rn;
+          const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+          ++lc.calls;
+          lc.levels += (unsigned)lv;
+          if (tstep == 0) { lc.err |= E_SOLVE; break; }
+          o += s * tstep;
+          if (o >= o_hi) break;
+          r = rn;
+          if (d_small) {
+            uint32_t tq, tr;
+            mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
+            mpos_add(mp, tq, tr, d32);
+          }
+        }
+        ++lc.raw;
+        record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), lc.useful, lreg, s_sup);
+        if ((o += s) >= o_hi) break;
+        if (d_small) mpos_add(mp, 0, s, d32);      // s <= d: one correction suffices
+        r += k;
+        r = r >= p ? r - p : r;
+      }
+    } else {
+      // three-gap stepping: one solve for the first hit, then the return times
+      if (r > w) {
+        uint64_t rn;
+        int lv = 0;
+        const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+        ++lc.calls;
+        lc.levels += (unsigned)lv;
+        if (tstep == 0) { lc.err |= E_SOLVE; break; }
+        o += s * tstep;
+        r = rn;
+        if (d_small && o < o_hi) {
+          uint32_t tq, tr;
+          mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
+          mpos_add(mp, tq, tr, d32);
+        }
+      }
+      const bool a_first = g.ta < g.tb;
+      // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
+      // arithmetic, and the three cases by selects rather than branches
+      const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
+      uint32_t r32 = (uint32_t)r;
+      while (o < o_hi) {
+        ++lc.raw;
+        record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, lc.useful, lreg, s_sup);
+        const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
+        const bool ua = fa && (a_first || !fb);
+        const bool ub = !ua && fb;
+        o += ua ? sta : (ub ? stb : tab);
+        r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
+        mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
+      }
+    }
+  }
+}
+
+template <bool kLds, int kSc, bool kG>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
                                                unsigned long long* __restrict__ diag,
@@ -1204,11 +1400,13 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
   extern __shared__ uint32_t lds[];
   __shared__ unsigned long long s_list[256 / kWave];   // per wavefront: latest list state (see list_sync)
   __shared__ unsigned long long s_dec[DC_COUNT][kDecades];   // the workgroup's counters per prime decade
+  __shared__ uint32_t s_sup[kListSupers];                    // list scatter: cells per group of buckets
   const uint64_t total = job_item_base[n_jobs];
   if ((uint64_t)blockIdx.x * blockDim.x >= total) return;   // workgroups past the last item (uniform)
   unsigned long long* lkey = s_list + threadIdx.x / kWave;
   if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
   for (uint32_t i = threadIdx.x; i < DC_COUNT * kDecades; i += blockDim.x) (&s_dec[0][0])[i] = 0ull;
+  if (threadIdx.x < kListSupers) s_sup[threadIdx.x] = 0u;
   __syncthreads();
   LargeTables<kLds> T;
   if constexpr (kLds) {
@@ -1221,191 +1419,23 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
   }
-  // a lane's counters for the decade of its current prime (items only grow, so a lane's primes
-  // change decade rarely); flushed into s_dec when the decade changes and at the end
-  unsigned long long raw = 0, useful = 0, calls = 0, levels = 0, n_pr = 0;
-  uint32_t cur_dec = kDecades;
-  auto flush_dec = [&]() {
-    if (cur_dec < (uint32_t)kDecades) {
-      if (n_pr) atomicAdd(&s_dec[DC_PRIMES][cur_dec], n_pr);
-      if (raw) atomicAdd(&s_dec[DC_RAW][cur_dec], raw);
-      if (useful) atomicAdd(&s_dec[DC_HITS][cur_dec], useful);
-      if (calls) atomicAdd(&s_dec[DC_SOLVES][cur_dec], calls);
-      if (levels) atomicAdd(&s_dec[DC_LEVELS][cur_dec], levels);
-    }
-    raw = useful = calls = levels = n_pr = 0;
-  };
-  uint32_t err = 0;
+  LaneCount lc;
+  lane_count_init(lc);
   ListReg lreg = {kNoChunk, 0u};
   uint32_t t_last = 0, ji_last = 0;                  // a lane's items only grow: resume the tier search
   for (uint64_t item = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; item < total;
        item += (uint64_t)gridDim.x * blockDim.x) {
-    do {   // one item; every exit leads to the per-item list sync below
     uint32_t ji = 0;
     if constexpr (!kLds) {
       ji = ji_last;                                  // items only grow: resume the job search
       while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
+      T.ct = gbl(jobs[ji].coltab);
+      T.dp = gbl(jobs[ji].dpre);
     }
-    const JobDev& j = jobs[kLds ? 0 : ji];          // the LDS variant runs one job: uniform fields
-    if constexpr (!kLds) {
-      T.ct = gbl(j.coltab);
-      T.dp = gbl(j.dpre);
-    }
-    const auto& c = *gbl(j.ctrl);
-    const uint64_t local = item - job_item_base[ji];
-    uint32_t t = ji == ji_last ? t_last : 0u;
-    while (t + 1 < j.n_tiers && c.tier_item_base[t + 1] <= local) ++t;
-    t_last = t;
+    if (ji != ji_last) t_last = 0;
     ji_last = ji;
-    const uint64_t li = local - c.tier_item_base[t];
-    const uint32_t C = j.tier_chunks[t];
-    // Item order.  One solve per hit: prime-major, so neighbouring lanes share (p, K mod p)
-    // and walk the same sequence of moduli in Eq. 5's descent (less divergence).  Three-gap
-    // stepping: chunk-major, so lanes running at the same time share an m-chunk and their
-    // scattered marks stay within 1/C of the bitmap rows.
-    const uint64_t t0 = (t == 0 ? c.tier_lo_idx : c.tier_idx[t - 1]);
-    uint64_t chunk, pi;
-    if (C == 1) {
-      chunk = 0;
-      pi = t0 + li;
-    } else if (j.large_mode == 0) {
-      const uint64_t q = div_small(li, C);
-      pi = t0 + q;
-      chunk = li - q * C;
-    } else {
-      const uint64_t npt = c.tier_idx[t] - t0;
-      chunk = div_small(li, npt);
-      pi = t0 + (li - chunk * npt);
-    }
-    // the walk's positions: for each class c of m mod s (s = m_step), m = m_start + o_c + s u with
-    // o_c = (c - m_start) mod s and u in [0, U); a chunk is a range of u, shared by the classes
-    const uint32_t s = j.m_step;
-    const uint64_t U = (j.m_inc + s - 1) / s;
-    const uint64_t L = C == 1 ? U : div_small(U + C - 1, C);
-    const uint64_t u_lo = (uint64_t)chunk * L;
-    const uint64_t u_hi = min(u_lo + L, U);
-    if (u_lo >= u_hi) break;
-
-    const uint64_t p = gbl(j.primes)[pi];
-    const uint64_t k1 = gbl(j.kmod)[pi];
-    {
-      const uint32_t dc = decade_of(p);
-      if (dc != cur_dec) {
-        flush_dec();
-        cur_dec = dc;
-      }
-      if (chunk == 0) ++n_pr;                        // each prime once (chunk 0 always has positions)
-    }
-    uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
-    k -= k >= 4 * p ? 4 * p : 0;                     // s <= 6: s K mod p < 8p before these
-    k -= k >= 2 * p ? 2 * p : 0;
-    k -= k >= p ? p : 0;
-    const double pinv = 1.0 / (double)p;
-    const uint64_t w = j.w;
-    const uint32_t d32 = (uint32_t)j.d;
-    const double inv_d = j.inv_d;
-    const bool d_small = j.d_small != 0;
-    const HitCtx hc = hit_ctx(j);
-    // k^-1 mod p (and, for three-gap stepping, the two return times) from one Euclid pass
-    uint64_t kinv = 0;
-    gaps3 g = {0, 0, 0, 0};
-    if (j.large_mode == 0) {
-      kinv = modinv(k, p);
-    } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
-      err |= E_SOLVE;
-      break;
-    }
-    // three-gap return times in offsets of m (a time past the chunk ends the walk, so the
-    // quotients below only matter for the times that are taken)
-    const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
-    uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
-    if (j.large_mode != 0 && d_small) {
-      mpos_divmod(sta, d32, inv_d, &aq, &ar);
-      mpos_divmod(stb, d32, inv_d, &bq, &br);
-      mpos_divmod(tab, d32, inv_d, &abq, &abr);
-    }
-    const uint64_t mk = gbl(j.mk)[pi];
-    for (uint32_t cls = 0; cls < s; ++cls) {
-      // list scatter: lanes that left the previous class's walk early catch up on the wavefront's
-      // chunk state before the next walk appends (every lane reaches this point)
-      if constexpr (kSc == 2) {
-        if (cls > 0) list_sync(lreg, lkey);
-      }
-      const uint64_t o_par = (cls + s - j.m0_mod_step) % s;
-      const uint64_t o_lo = o_par + s * u_lo;
-      // a class that cannot hold rows, or that ends before this chunk, is skipped
-      if (!((j.m_classes >> cls) & 1u) || o_lo >= j.m_inc) continue;
-      const uint64_t o_hi = min(o_par + s * u_hi, j.m_inc);   // visited o = o_par + s u < o_hi
-      // residue of m*K + SL at m = m_start + o_lo
-      uint64_t r = mk + mulmod(o_lo, k1, p, pinv);
-      r = r >= p ? r - p : r;
-      r += j.sl;                                     // sl < w < thr < p
-      r = r >= p ? r - p : r;
-      uint64_t o = o_lo;
-      MPos mp = {0, 0};
-      if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
-
-      if (j.large_mode == 0) {
-        // one solve of Eq. 3 per hit
-        while (true) {
-          if (r > w) {
-            int lv = 0;
-            uint64_t rn;
-            const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
-            ++calls;
-            levels += (unsigned)lv;
-            if (tstep == 0) { err |= E_SOLVE; break; }
-            o += s * tstep;
-            if (o >= o_hi) break;
-            r = rn;
-            if (d_small) {
-              uint32_t tq, tr;
-              mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
-              mpos_add(mp, tq, tr, d32);
-            }
-          }
-          ++raw;
-          record_hit<kLds, kSc>(hc, T, o, mp, (uint32_t)(w - r), useful, lreg);
-          if ((o += s) >= o_hi) break;
-          if (d_small) mpos_add(mp, 0, s, d32);      // s <= d: one correction suffices
-          r += k;
-          r = r >= p ? r - p : r;
-        }
-      } else {
-        // three-gap stepping: one solve for the first hit, then the return times
-        if (r > w) {
-          uint64_t rn;
-          int lv = 0;
-          const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
-          ++calls;
-          levels += (unsigned)lv;
-          if (tstep == 0) { err |= E_SOLVE; break; }
-          o += s * tstep;
-          r = rn;
-          if (d_small && o < o_hi) {
-            uint32_t tq, tr;
-            mpos_divmod(s * tstep, d32, inv_d, &tq, &tr);
-            mpos_add(mp, tq, tr, d32);
-          }
-        }
-        const bool a_first = g.ta < g.tb;
-        // every residue from here on is a hit's, at most w < 2^18, and so are a and b: 32-bit
-        // arithmetic, and the three cases by selects rather than branches
-        const uint32_t w32 = (uint32_t)w, a32 = (uint32_t)g.a, b32 = (uint32_t)g.b;
-        uint32_t r32 = (uint32_t)r;
-        while (o < o_hi) {
-          ++raw;
-          record_hit<kLds, kSc>(hc, T, o, mp, w32 - r32, useful, lreg);
-          const bool fa = r32 + a32 <= w32, fb = r32 >= b32;
-          const bool ua = fa && (a_first || !fb);
-          const bool ub = !ua && fb;
-          o += ua ? sta : (ub ? stb : tab);
-          r32 = r32 + (ub ? 0u : a32) - (ua ? 0u : b32);
-          mpos_add(mp, ua ? aq : (ub ? bq : abq), ua ? ar : (ub ? br : abr), d32);
-        }
-      }
-    }
-    } while (0);
+    // the LDS variant runs one job: its fields are uniform
+    large_item<kLds, kSc, kG>(jobs[kLds ? 0 : ji], T, item - job_item_base[ji], t_last, lc, s_dec, lreg, lkey, s_sup);
     if constexpr (kSc == 2) list_sync(lreg, lkey);
   }
   if constexpr (kSc == 2) {
@@ -1417,8 +1447,11 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     }
   }
   // counters: one atomic per workgroup, decade and counter, and the totals over the decades
-  flush_dec();
+  flush_dec(lc, s_dec);
   __syncthreads();
+  if constexpr (kSc == 2) {
+    if (threadIdx.x < kListSupers && s_sup[threadIdx.x]) atomicAdd(&jobs[0].list_super[threadIdx.x], s_sup[threadIdx.x]);
+  }
   if (threadIdx.x < DC_COUNT * kDecades) {
     const uint32_t slot = threadIdx.x / kDecades, dc = threadIdx.x % kDecades;
     const unsigned long long v = s_dec[slot][dc];
@@ -1433,7 +1466,165 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
                       : threadIdx.x == 2 ? D_G_CALLS : D_G_LEVELS;
     if (v) atomicAdd(&diag[at], v);
   }
-  if (err) atomicOr(reinterpret_cast<unsigned long long*>(&diag[D_ERROR]), (unsigned long long)err);
+  if (lc.err) atomicOr(reinterpret_cast<unsigned long long*>(&diag[D_ERROR]), (unsigned long long)lc.err);
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent batch kernel: the small- and large-branch work of many jobs in one launch.  The
+// work is cut into tasks: every job's large-branch items in tasks of kBatchItems (four per lane),
+// then every job's small-branch units (one task each).  k_batch_queue counts them on the device
+// (the item counts come from k_prep_bounds) into a prefix table, and the workgroups of k_batch
+// pop tasks from one device counter until none is left, so uneven jobs share the GPU without a
+// launch per job.  A workgroup keeps the column table (and residue table) of its last job in LDS
+// and reloads them only when the job changes.  The task's counters go to its job's totals.
+// ------------------------------------------------------------------------------------------
+// Task ranges: 2 n_jobs ranges (a job's large tasks or its small tasks) in one of three orders.
+// Range q of order 0 (large first): q < n_jobs is job q's large tasks, then the small ones;
+// order 1 (small first): the reverse; order 2 (by job): job q/2's large (q even) or small tasks.
+__device__ __forceinline__ void batch_range(uint32_t q, uint32_t n_jobs, uint32_t order, uint32_t* job, bool* large) {
+  if (order == 2) {
+    *job = q >> 1;
+    *large = (q & 1u) == 0;
+  } else {
+    *job = q < n_jobs ? q : q - n_jobs;
+    *large = (q < n_jobs) == (order == 0);
+  }
+}
+
+// tbase: 2 n_jobs + 1 entries, the first task of each range and the number of tasks.  A job's
+// large tasks hold items_per_task items each, its small tasks one unit each.  Clears the task
+// counter.
+__global__ void k_batch_queue(const JobDev* __restrict__ jobs, uint32_t n_jobs, uint32_t items_per_task,
+                              uint32_t order, uint64_t* __restrict__ tbase, unsigned long long* __restrict__ next) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t s = 0;
+  for (uint32_t q = 0; q < 2 * n_jobs; ++q) {
+    tbase[q] = s;
+    uint32_t ji;
+    bool large;
+    batch_range(q, n_jobs, order, &ji, &large);
+    const JobDev& j = jobs[ji];
+    if (!j.n_m) continue;
+    s += large ? (j.ctrl->n_items + items_per_task - 1) / items_per_task : (uint64_t)j.n_windows * j.n_slices;
+  }
+  tbase[2 * n_jobs] = s;
+  *next = 0ull;
+}
+
+// The tier of item `local` of job j (the last tier whose first item is at or below it).
+template <class CT>
+__device__ __forceinline__ uint32_t tier_of(const CT& c, uint32_t n_tiers, uint64_t local) {
+  uint32_t lo = 0, hi = n_tiers;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (c.tier_item_base[mid] <= local) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Adds a workgroup's per-decade large-branch counters to a job's and clears them.
+__device__ __forceinline__ void flush_job_decades(const JobDev& j, unsigned long long (*s_dec)[kDecades]) {
+  unsigned long long* diag = j.ctrl->diag;
+  unsigned long long* dec = &j.ctrl->dec[0][0];
+  if (threadIdx.x < 4) {
+    const uint32_t slot = threadIdx.x == 0 ? DC_RAW : threadIdx.x == 1 ? DC_HITS : threadIdx.x == 2 ? DC_SOLVES
+                        : DC_LEVELS;
+    unsigned long long v = 0;
+    for (uint32_t i = 0; i < (uint32_t)kDecades; ++i) v += s_dec[slot][i];
+    const uint32_t at = threadIdx.x == 0 ? D_LARGE_RAW : threadIdx.x == 1 ? D_LARGE_HITS
+                      : threadIdx.x == 2 ? D_G_CALLS : D_G_LEVELS;
+    if (v) atomicAdd(&diag[at], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < DC_COUNT * kDecades) {
+    unsigned long long* sd = &s_dec[0][0];
+    const unsigned long long v = sd[threadIdx.x];
+    if (v) atomicAdd(&dec[threadIdx.x], v);
+    sd[threadIdx.x] = 0ull;
+  }
+  __syncthreads();
+}
+
+template <int kSc, bool kG>
+__global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, uint32_t n_jobs,
+                                               const uint64_t* __restrict__ tbase,
+                                               unsigned long long* __restrict__ next, uint32_t lds_ct_words,
+                                               uint32_t items_per_task, uint32_t order) {
+  extern __shared__ uint32_t lds[];
+  __shared__ unsigned long long s_dec[DC_COUNT][kDecades];
+  __shared__ unsigned long long s_list[256 / kWave];   // list state (the list scatter is not used here)
+  __shared__ uint32_t s_sup[kListSupers];
+  __shared__ unsigned long long s_task;
+  for (uint32_t i = threadIdx.x; i < DC_COUNT * kDecades; i += blockDim.x) (&s_dec[0][0])[i] = 0ull;
+  if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
+  if (threadIdx.x < kListSupers) s_sup[threadIdx.x] = 0u;
+  const uint64_t total = tbase[2 * n_jobs];
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t ct_job = 0xffffffffu, dp_job = 0xffffffffu;
+  LaneCount lc;
+  lane_count_init(lc);
+  ListReg lreg = {kNoChunk, 0u};
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(next, 1ull);
+    __syncthreads();
+    const uint64_t task = s_task;
+    __syncthreads();                                 // read before the next pop overwrites it
+    if (task >= total) break;
+    uint32_t lo = 0, hi = 2 * n_jobs;                // tbase[lo] <= task < tbase[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tbase[mid] <= task) lo = mid; else hi = mid;
+    }
+    uint32_t ji;
+    bool large;
+    batch_range(lo, n_jobs, order, &ji, &large);
+    const JobDev& j = jobs[ji];
+    const uint64_t local = task - tbase[lo];
+    if (!large) {
+      unsigned long long n_pairs = 0, n_marks = 0;
+      small_unit(j, local, lds, lds_ct_words, ct_job == ji, n_pairs, n_marks);
+      ct_job = ji;
+      dp_job = 0xffffffffu;                          // the tile overwrote the residue table
+      if (lane == 0) {
+        if (n_pairs) atomicAdd(&j.ctrl->diag[D_SMALL_PAIRS], n_pairs);
+        if (n_marks) atomicAdd(&j.ctrl->diag[D_SMALL_MARKS], n_marks);
+      }
+      continue;
+    }
+    // a large task: the job's tables in LDS (the plan guarantees they fit), then its items
+    uint2* ctl = reinterpret_cast<uint2*>(lds);
+    uint16_t* dpl = reinterpret_cast<uint16_t*>(lds + 2 * lds_ct_words);
+    if (ct_job != ji) {
+      const uint32_t nct = (2 * j.sl + 1 + 31) / 32;
+      for (uint32_t i = threadIdx.x; i < nct; i += blockDim.x) ctl[i] = ((const uint2*)gbl(j.coltab))[i];
+    }
+    if (dp_job != ji && j.d_small) {
+      const uint32_t dn = (uint32_t)j.d;
+      for (uint32_t i = threadIdx.x; i < dn; i += blockDim.x) dpl[i] = gbl(j.dpre)[i];
+    }
+    ct_job = dp_job = ji;
+    __syncthreads();
+    LargeTables<true> T;
+    T.ct = ctl;
+    T.dp = dpl;
+    const auto& c = *gbl(j.ctrl);
+    const uint64_t n_items = c.n_items;
+    const uint64_t first = local * items_per_task;
+    uint32_t t_last = tier_of(c, j.n_tiers, first);
+    for (uint32_t k = 0; k < items_per_task; k += 256u) {
+      const uint64_t item = first + k + threadIdx.x;
+      if (item < n_items)
+        large_item<true, kSc, kG>(j, T, item, t_last, lc, s_dec, lreg, s_list + threadIdx.x / kWave, s_sup);
+    }
+    flush_dec(lc, s_dec);
+    lc.cur_dec = kDecades;
+    if (lc.err) {
+      atomicOr(reinterpret_cast<unsigned long long*>(&j.ctrl->diag[D_ERROR]), (unsigned long long)lc.err);
+      lc.err = 0;
+    }
+    __syncthreads();
+    flush_job_decades(j, s_dec);
+  }
 }
 
 // Folds the byte counters of large-prime hits into the bitmap and the counts, one wavefront per
@@ -1486,37 +1677,144 @@ __global__ __launch_bounds__(256) void k_zero_bytes(const JobDev* __restrict__ j
 
 // ------------------------------------------------------------------------------------------
 // Grouping of the list scatter.  Cells are (row << cell_shift) | col, buckets are 2^k rows and
-// groups are 2^g buckets, so bucket = cell >> bkt_shift and group = bucket >> super_shift.  Count
-// the cells of each bucket, scan, move every cell to its group's range, then to its bucket's
-// range, then one block per bucket ORs its cells into an LDS tile of the bucket's rows and merges
-// the tile into the bitmap and the counts (the block owns those rows).
+// groups are 2^g buckets, so bucket = cell >> bkt_shift and group = cell >> (bkt_shift + g).  The
+// large branch counted the cells of each group (list_super); a scan gives the groups' ranges; the
+// first pass moves every cell of the pool to its group's range and counts the cells of each
+// bucket; a scan gives the buckets' ranges; the second pass moves the cells of each group to their
+// buckets; then one block per bucket ORs its cells into an LDS tile of the bucket's rows and merges
+// the tile into the bitmap and the counts (the block owns those rows).  Cells of a bucket come in
+// no particular order: OR and sums do not depend on it.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t list_n_chunks(const JobDev& j) {
   const unsigned long long c = *j.list_cursor;
   return c < j.list_chunks ? c : j.list_chunks;
 }
 
-__global__ __launch_bounds__(256) void k_list_count(const JobDev* __restrict__ jobs) {
+// list_super layout: counts [kListSupers + 1], bases [kListSupers + 1], cursors [kListSupers + 1].
+constexpr uint32_t kSupStride = kListSupers + 1;
+
+// Bases and cursors of the groups from the large branch's counts (one wavefront).
+__global__ __launch_bounds__(64) void k_list_scan1(const JobDev* __restrict__ jobs) {
   const JobDev& j = jobs[0];
-  extern __shared__ uint32_t hist[];
+  uint32_t* cnt = j.list_super;
+  uint32_t* base = cnt + kSupStride;
+  uint32_t* cur = base + kSupStride;
+  const uint32_t t = threadIdx.x;
+  const uint32_t v = t < kListSupers ? cnt[t] : 0u;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, kWave);
+    if ((int)t >= o) x += y;
+  }
+  if (t < kListSupers) {
+    base[t] = x - v;
+    cur[t] = x - v;
+  }
+  if (t == kWave - 1) base[kListSupers] = x;
+}
+
+constexpr uint32_t kPartBatch = 4096;   // cells per batch of the partition passes (16 per thread)
+
+// One batch of a partition pass: up to kPartBatch cells src[0, nf) are ranked per key in LDS,
+// each key with cells in the batch reserves a run of its output range with one atomic on its
+// global cursor, the cells are placed by key in an LDS stage, and consecutive threads write each
+// key's run (contiguous stores).  cnt (n_keys <= 256 words) is zero on entry and on exit.  With
+// hist2, each cell also adds one to the LDS counter of its bucket (cell >> bsh).
+template <class KeyOf>
+__device__ __forceinline__ void part_batch(const uint32_t* __restrict__ src, uint32_t nf, uint32_t n_keys,
+                                           KeyOf key_of, uint32_t* cnt, uint32_t* start, uint32_t* gofs,
+                                           uint32_t* stg, uint32_t* __restrict__ gcur, uint32_t* __restrict__ dst,
+                                           uint32_t* hist2, uint32_t bsh) {
+  constexpr uint32_t kPer = kPartBatch / 256;
+  uint32_t cell[kPer], rk[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = threadIdx.x + 256u * k;
+    cell[k] = i < nf ? src[i] : 0u;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = threadIdx.x + 256u * k;
+    if (i < nf) {
+      rk[k] = atomicAdd(&cnt[key_of(cell[k])], 1u);
+      if (hist2) atomicAdd(&hist2[cell[k] >> bsh], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    // the first wavefront scans the counts (up to 4 consecutive keys per lane) and reserves the runs
+    const uint32_t lane = threadIdx.x;
+    const uint32_t per = (n_keys + kWave - 1) / kWave;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t key = lane * per + q;
+      v[q] = (q < per && key < n_keys) ? cnt[key] : 0u;
+      sum += v[q];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, kWave);
+      if ((int)lane >= o) x += y;
+    }
+    uint32_t ex = x - sum;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t key = lane * per + q;
+      if (q < per && key < n_keys) {
+        start[key] = ex;
+        if (v[q]) gofs[key] = atomicAdd(&gcur[key], v[q]);
+        ex += v[q];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = threadIdx.x + 256u * k;
+    if (i < nf) stg[start[key_of(cell[k])] + rk[k]] = cell[k];
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nf; i += 256u) {
+    const uint32_t c = stg[i];
+    const uint32_t key = key_of(c);
+    dst[gofs[key] + (i - start[key])] = c;
+  }
+  for (uint32_t q = threadIdx.x; q < n_keys; q += 256u) cnt[q] = 0u;
+  __syncthreads();
+}
+
+// First pass: the pool's chunks -> their groups' ranges of list_sorted, and the bucket counts.
+// Each block takes kListChunksPerBlock chunks; its bucket counts (n_bkt words of dynamic LDS)
+// reach bkt_count with one atomic per bucket at its end.
+__global__ __launch_bounds__(256) void k_list_part1(const JobDev* __restrict__ jobs) {
+  const JobDev& j = jobs[0];
+  extern __shared__ uint32_t hist2[];
+  __shared__ uint32_t cnt[kListSupers], start[kListSupers], gofs[kListSupers], fills[kListChunksPerBlock];
+  __shared__ uint32_t stg[kPartBatch];
   const uint64_t n_chunks = list_n_chunks(j);
   const uint64_t c0 = blockIdx.x * (uint64_t)kListChunksPerBlock;
   if (c0 >= n_chunks) return;
-  const uint64_t c1 = min(c0 + kListChunksPerBlock, n_chunks);
-  const uint32_t bsh = j.bkt_shift;
-  for (uint32_t i = threadIdx.x; i < j.n_bkt; i += blockDim.x) hist[i] = 0;
+  const uint32_t nc = (uint32_t)min<uint64_t>(kListChunksPerBlock, n_chunks - c0);
+  const uint32_t n_bkt = j.n_bkt;
+  for (uint32_t i = threadIdx.x; i < n_bkt; i += blockDim.x) hist2[i] = 0u;
+  if (threadIdx.x < kListSupers) cnt[threadIdx.x] = 0u;
+  for (uint32_t i = threadIdx.x; i < nc; i += blockDim.x) fills[i] = min(j.list_fill[c0 + i], kListChunk);
   __syncthreads();
-  for (uint64_t c = c0; c < c1; ++c) {
-    const uint32_t nf = min(j.list_fill[c], kListChunk);
-    const uint32_t* __restrict__ src = j.list_pool + c * kListChunk;
-    for (uint32_t e = threadIdx.x; e < nf; e += blockDim.x) atomicAdd(&hist[src[e] >> bsh], 1u);
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < j.n_bkt; i += blockDim.x)
-    if (hist[i]) atomicAdd(&j.bkt_count[i], hist[i]);
+  const uint32_t ssh = j.bkt_shift + j.super_shift, bsh = j.bkt_shift;
+  uint32_t* cur = j.list_super + 2 * kSupStride;
+  auto key_of = [ssh](uint32_t cell) { return cell >> ssh; };
+  for (uint32_t c = 0; c < nc; ++c)
+    part_batch(j.list_pool + (c0 + c) * kListChunk, fills[c], kListSupers, key_of, cnt, start, gofs, stg, cur,
+               j.list_sorted, hist2, bsh);
+  for (uint32_t i = threadIdx.x; i < n_bkt; i += blockDim.x)
+    if (hist2[i]) atomicAdd(&j.bkt_count[i], hist2[i]);
 }
 
-// Exclusive scan of n_bkt <= kMaxBuckets counts by one block of 1024 threads.
+// Exclusive scan of n_bkt <= kMaxBuckets bucket counts by one block of 1024 threads: the buckets'
+// bases and cursors.
 __global__ __launch_bounds__(1024) void k_list_scan(const JobDev* __restrict__ jobs) {
   const JobDev& j = jobs[0];
   __shared__ uint32_t part[1024];
@@ -1548,109 +1846,30 @@ __global__ __launch_bounds__(1024) void k_list_scan(const JobDev* __restrict__ j
     run += v[k];
   }
   if (threadIdx.x == 1023) j.bkt_base[j.n_bkt] = part[1023];
-  __syncthreads();
-  // super-bucket cursors: the base of each group's first bucket
-  const uint32_t g = j.bkt_per_super;
-  for (uint32_t q = threadIdx.x; q * g < j.n_bkt; q += blockDim.x) j.bkt_cursor[j.n_bkt + 1 + q] = j.bkt_base[q * g];
 }
 
-// Counting sort of up to 4096 cells (16 per thread of a 256-thread block) by key in LDS, then
-// each key's segment is written to dst at run[key] onwards by consecutive threads (contiguous
-// stores), and run[key] advances.  hist/start/run: n_keys LDS words each; stg: 4096 LDS words.
-template <typename KeyOf>
-__device__ __forceinline__ void sort_write_batch(const uint32_t* __restrict__ src, uint32_t nf, uint32_t n_keys,
-                                                 KeyOf key_of, uint32_t* hist, uint32_t* start, uint32_t* run,
-                                                 uint32_t* stg, uint32_t* __restrict__ dst) {
-  for (uint32_t i = threadIdx.x; i < n_keys; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  uint32_t cell[16], rk[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t i = threadIdx.x + 256u * k;
-    cell[k] = i < nf ? src[i] : 0u;
-    rk[k] = i < nf ? atomicAdd(&hist[key_of(cell[k])], 1u) : 0u;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t q = 0; q < n_keys; ++q) {
-      start[q] = acc;
-      acc += hist[q];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t i = threadIdx.x + 256u * k;
-    if (i < nf) stg[start[key_of(cell[k])] + rk[k]] = cell[k];
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) {
-    const uint32_t c = stg[i];
-    const uint32_t q = key_of(c);
-    dst[run[q] + (i - start[q])] = c;
-  }
-  __syncthreads();
-  for (uint32_t q = threadIdx.x; q < n_keys; q += blockDim.x) run[q] += hist[q];
-  __syncthreads();
-}
-
-// First level: cells of the pool -> their super-bucket (kListSupers groups of buckets) in
-// list_sorted.  Each block takes kListChunksPerBlock chunks, counts them per super-bucket,
-// reserves its ranges with one atomic per super-bucket, then writes chunk by chunk.
-__global__ __launch_bounds__(256) void k_list_part1(const JobDev* __restrict__ jobs) {
-  const JobDev& j = jobs[0];
-  __shared__ uint32_t hist[kListSupers], start[kListSupers], run[kListSupers], tot[kListSupers];
-  __shared__ uint32_t stg[kListChunk];
-  const uint64_t n_chunks = list_n_chunks(j);
-  const uint64_t c0 = blockIdx.x * (uint64_t)kListChunksPerBlock;
-  if (c0 >= n_chunks) return;
-  const uint64_t c1 = min(c0 + kListChunksPerBlock, n_chunks);
-  const uint32_t g = j.bkt_per_super;
-  const uint32_t n_sup = (j.n_bkt + g - 1) / g;
-  const uint32_t ssh = j.bkt_shift + j.super_shift;
-  auto key_of = [&](uint32_t cell) { return cell >> ssh; };
-  for (uint32_t i = threadIdx.x; i < n_sup; i += blockDim.x) tot[i] = 0;
-  __syncthreads();
-  for (uint64_t c = c0; c < c1; ++c) {
-    const uint32_t nf = min(j.list_fill[c], kListChunk);
-    const uint32_t* __restrict__ src = j.list_pool + c * kListChunk;
-    for (uint32_t e = threadIdx.x; e < nf; e += blockDim.x) atomicAdd(&tot[key_of(src[e])], 1u);
-  }
-  __syncthreads();
-  uint32_t* super_cursor = j.bkt_cursor + j.n_bkt + 1;
-  for (uint32_t i = threadIdx.x; i < n_sup; i += blockDim.x) run[i] = tot[i] ? atomicAdd(&super_cursor[i], tot[i]) : 0u;
-  __syncthreads();
-  for (uint64_t c = c0; c < c1; ++c)
-    sort_write_batch(j.list_pool + c * kListChunk, min(j.list_fill[c], kListChunk), n_sup, key_of, hist, start, run,
-                     stg, j.list_sorted);
-}
-
-// Second level: each super-bucket's range of list_sorted -> its buckets, into list_pool (free by
-// now).  Block (x, s) takes pieces x, x + gridDim.x, ... of kListPiece cells of super-bucket s.
+// Second pass: each group's range of list_sorted -> its buckets' ranges, into list_pool (free by
+// now).  Block (x, g) takes pieces x, x + gridDim.x, ... of kListPiece cells of group g.
 __global__ __launch_bounds__(256) void k_list_part2(const JobDev* __restrict__ jobs) {
   const JobDev& j = jobs[0];
-  __shared__ uint32_t hist[kListMaxPerSuper], start[kListMaxPerSuper], run[kListMaxPerSuper], tot[kListMaxPerSuper];
-  __shared__ uint32_t stg[kListChunk];
+  __shared__ uint32_t cnt[kListMaxPerSuper], start[kListMaxPerSuper], gofs[kListMaxPerSuper];
+  __shared__ uint32_t stg[kPartBatch];
   const uint32_t g = j.bkt_per_super;
   const uint32_t sup = blockIdx.y;
   const uint32_t b0 = sup * g;
   if (b0 >= j.n_bkt) return;
-  const uint32_t b1 = min(b0 + g, j.n_bkt);
-  const uint32_t nk = b1 - b0;
-  const uint32_t lo = j.bkt_base[b0], hi = j.bkt_base[b1];
+  const uint32_t nk = min(b0 + g, j.n_bkt) - b0;
+  const uint32_t* sbase = j.list_super + kSupStride;
+  const uint32_t lo = sbase[sup], hi = sbase[sup + 1];
   const uint32_t bsh = j.bkt_shift;
-  auto key_of = [&](uint32_t cell) { return (cell >> bsh) - b0; };
+  for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) cnt[i] = 0u;
+  __syncthreads();
+  auto key_of = [bsh, b0](uint32_t cell) { return (cell >> bsh) - b0; };
   for (uint64_t p0 = lo + (uint64_t)blockIdx.x * kListPiece; p0 < hi; p0 += (uint64_t)gridDim.x * kListPiece) {
     const uint32_t p1 = (uint32_t)min<uint64_t>(p0 + kListPiece, hi);
-    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) tot[i] = 0;
-    __syncthreads();
-    for (uint32_t e = (uint32_t)p0 + threadIdx.x; e < p1; e += blockDim.x) atomicAdd(&tot[key_of(j.list_sorted[e])], 1u);
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) run[i] = tot[i] ? atomicAdd(&j.bkt_cursor[b0 + i], tot[i]) : 0u;
-    __syncthreads();
-    for (uint32_t e = (uint32_t)p0; e < p1; e += kListChunk)
-      sort_write_batch(j.list_sorted + e, min(kListChunk, p1 - e), nk, key_of, hist, start, run, stg, j.list_pool);
+    for (uint32_t e = (uint32_t)p0; e < p1; e += kPartBatch)
+      part_batch(j.list_sorted + e, min(kPartBatch, p1 - e), nk, key_of, cnt, start, gofs, stg, j.bkt_cursor + b0,
+                 j.list_pool, nullptr, 0u);
   }
 }
 
@@ -1903,21 +2122,28 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
-                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s) {
+                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, uint32_t large_mode,
+                        hipStream_t s) {
   if (n_jobs != 1 && scatter_kind == 2) scatter_kind = 0;   // the list serves single jobs only
   const bool lds = lds_bytes && lds_ct_words && n_jobs == 1;
-#define LARGE_CASE(L, K)                                                                                       \
-  hipLaunchKernelGGL((k_large<L, K>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs, job_item_base, \
-                     diag, dec, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
+#define LARGE_CASE(L, K, G)                                                                                    \
+  hipLaunchKernelGGL((k_large<L, K, G>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs,          \
+                     job_item_base, diag, dec, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
+#define LARGE_MODES(L, K)                     \
+  do {                                        \
+    if (large_mode == 0) LARGE_CASE(L, K, true); \
+    else LARGE_CASE(L, K, false);             \
+  } while (0)
   if (lds) {
-    if (scatter_kind == 2) LARGE_CASE(true, 2);
-    else if (scatter_kind == 1) LARGE_CASE(true, 1);
-    else LARGE_CASE(true, 0);
+    if (scatter_kind == 2) LARGE_MODES(true, 2);
+    else if (scatter_kind == 1) LARGE_MODES(true, 1);
+    else LARGE_MODES(true, 0);
   } else {
-    if (scatter_kind == 2) LARGE_CASE(false, 2);
-    else if (scatter_kind == 1) LARGE_CASE(false, 1);
-    else LARGE_CASE(false, 0);
+    if (scatter_kind == 2) LARGE_MODES(false, 2);
+    else if (scatter_kind == 1) LARGE_MODES(false, 1);
+    else LARGE_MODES(false, 0);
   }
+#undef LARGE_MODES
 #undef LARGE_CASE
   return note(lds ? "k_large<lds>" : "k_large");
 }
@@ -1928,19 +2154,36 @@ hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, u
   return note("k_probe_scatter");
 }
 
+hipError_t launch_batch_persistent(const JobDev* jobs, uint32_t n_jobs, uint64_t* tbase, unsigned long long* next,
+                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t scatter_kind,
+                                   uint32_t large_mode, uint32_t items_per_task, uint32_t order, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_queue, dim3(1), dim3(64), 0, s, jobs, n_jobs, items_per_task, order, tbase, next);
+  { hipError_t e_ = note("k_batch_queue"); if (e_ != hipSuccess) return e_; }
+#define BATCH_CASE(K, G) \
+  hipLaunchKernelGGL((k_batch<K, G>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, (const uint64_t*)tbase, next, \
+                     lds_ct_words, items_per_task, order)
+  if (scatter_kind == 1) {
+    if (large_mode == 0) BATCH_CASE(1, true); else BATCH_CASE(1, false);
+  } else {
+    if (large_mode == 0) BATCH_CASE(0, true); else BATCH_CASE(0, false);
+  }
+#undef BATCH_CASE
+  return note("k_batch");
+}
+
 hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,
                              uint32_t super_shift, uint32_t row_words, hipStream_t s) {
   if (n_bkt == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)((list_chunks + kListChunksPerBlock - 1) / kListChunksPerBlock);
+  hipLaunchKernelGGL(k_list_scan1, dim3(1), dim3(kWave), 0, s, job);
+  { hipError_t e_ = note("k_list_scan1"); if (e_ != hipSuccess) return e_; }
   if (blocks) {
-    hipLaunchKernelGGL(k_list_count, dim3(blocks), dim3(256), n_bkt * 4u, s, job);
-    { hipError_t e_ = note("k_list_count"); if (e_ != hipSuccess) return e_; }
+    hipLaunchKernelGGL(k_list_part1, dim3(blocks), dim3(256), n_bkt * 4u, s, job);
+    { hipError_t e_ = note("k_list_part1"); if (e_ != hipSuccess) return e_; }
   }
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, job);
   { hipError_t e_ = note("k_list_scan"); if (e_ != hipSuccess) return e_; }
   if (blocks) {
-    hipLaunchKernelGGL(k_list_part1, dim3(blocks), dim3(256), 0, s, job);
-    { hipError_t e_ = note("k_list_part1"); if (e_ != hipSuccess) return e_; }
     const uint32_t n_sup = (n_bkt + (1u << super_shift) - 1) >> super_shift;
     hipLaunchKernelGGL(k_list_part2, dim3(kListPart2X, n_sup), dim3(256), 0, s, job);
     { hipError_t e_ = note("k_list_part2"); if (e_ != hipSuccess) return e_; }

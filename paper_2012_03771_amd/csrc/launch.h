@@ -64,13 +64,23 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 // 1 = every job's byte counters (all jobs must have them), 2 = the job's list pool (single-job
 // launches only; 0 otherwise).
 // diag: D_COUNT totals; dec: DC_COUNT x kDecades counters per prime decade (or null).
+// large_mode: CS_LARGE_G (0) or CS_LARGE_THREE_GAP (1), the same for every job of the launch.
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
-                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, hipStream_t s);
+                        uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, uint32_t large_mode,
+                        hipStream_t s);
 // Groups the list pool of one job by row bucket and applies it to the bitmap and counts.  The
 // caller cleared the pool cursor and the bucket counts before the k_large launch.
 hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,
                              uint32_t super_shift, uint32_t row_words, hipStream_t s);
+
+// The persistent batch kernel over n_jobs jobs (see k_batch): tbase holds 2 n_jobs + 1 device words
+// and next one; every job's column table fits lds_ct_words (and its residue table after it);
+// scatter_kind 0 (atomic) or 1 (byte counters) and large_mode are common to the jobs.
+// items_per_task: a multiple of 256; order: 0 large tasks first, 1 small tasks first, 2 by job.
+hipError_t launch_batch_persistent(const JobDev* jobs, uint32_t n_jobs, uint64_t* tbase, unsigned long long* next,
+                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t scatter_kind,
+                                   uint32_t large_mode, uint32_t items_per_task, uint32_t order, hipStream_t s);
 
 // Scatter-rate probe (see k_probe_scatter).
 hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,

@@ -26,7 +26,7 @@ constexpr uint32_t kBaseCap = 155700;           // odd primes below 2^21 (155,61
 struct WsLayout {
   uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
       kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, hitbytes, list_pool,
-      list_fill, list_cursor, list_sorted, bkt_count, bkt_base, bkt_cursor, total;
+      list_fill, list_cursor, list_sorted, bkt_count, bkt_base, bkt_cursor, list_super, total;
 };
 
 struct Plan {

@@ -299,7 +299,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.list_sorted = take(pl.list_chunks * kListChunk * 4ull);
   L.bkt_count = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
   L.bkt_base = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
-  L.bkt_cursor = take(pl.scatter_list ? (pl.n_bkt + 1ull + kListSupers) * 4ull : 0);
+  L.bkt_cursor = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
+  L.list_super = take(pl.scatter_list ? 3ull * (kListSupers + 1) * 4ull : 0);
   L.total = o;
   return CS_OK;
 }
@@ -419,6 +420,7 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.bkt_count = reinterpret_cast<uint32_t*>(ws + L.bkt_count);
   jd.bkt_base = reinterpret_cast<uint32_t*>(ws + L.bkt_base);
   jd.bkt_cursor = reinterpret_cast<uint32_t*>(ws + L.bkt_cursor);
+  jd.list_super = reinterpret_cast<uint32_t*>(ws + L.list_super);
   jd.list_chunks = pl.list_chunks;
   jd.n_bkt = pl.n_bkt;
   jd.bkt_rows = pl.bkt_rows;

@@ -340,7 +340,8 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
       return false;
     if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, s->aux) != hipSuccess) return false;
   }
-  if (launch_large(s->run_dev, n, s->items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u, st) !=
+  if (launch_large(s->run_dev, n, s->items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u,
+                   s->cfg.tune.large_mode, st) !=
       hipSuccess)
     return false;
   if (units && (hipEventRecord(s->ev_join, s->aux) != hipSuccess || hipStreamWaitEvent(st, s->ev_join, 0) != hipSuccess))

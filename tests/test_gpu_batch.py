@@ -37,10 +37,18 @@ SMALL_MIX = [W.Job(61, 6, 1000, 3000, 500, 10**6), W.Job(131, 1, 7, 5000, 900, 2
              W.Job(401, 210, 99, 30000, 3000, 10**7), W.Job(211, 210, 1, 1000, 4000, 10**6)]
 
 
-@pytest.mark.parametrize("mode", [cs.LARGE_G, cs.LARGE_THREE_GAP], ids=["g", "three_gap"])
-def test_small_batch_equals_alone_and_oracle(mode):
-    tunes = [cs.Tune(large_mode=mode) for _ in SMALL_MIX]
-    batch = cs.Batch(SMALL_MIX, tunes)
+PATHS = [cs.BATCH_PERSISTENT, cs.BATCH_LANES]
+PATH_IDS = ["persistent", "lanes"]
+
+
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
+@pytest.mark.parametrize("mode,scatter", [(cs.LARGE_G, cs.SCATTER_AUTO), (cs.LARGE_THREE_GAP, cs.SCATTER_AUTO),
+                                          (cs.LARGE_THREE_GAP, cs.SCATTER_ATOMIC)],
+                         ids=["g", "three_gap", "three_gap_atomic"])
+def test_small_batch_equals_alone_and_oracle(mode, scatter, path):
+    tunes = [cs.Tune(large_mode=mode, scatter=scatter) for _ in SMALL_MIX]
+    batch = cs.Batch(SMALL_MIX, tunes, path=path)
+    assert batch.path == path
     bm, ct = batch.alloc_outputs()
     batch.run(bm, ct, use_graph=False)
     torch.cuda.synchronize()
@@ -65,11 +73,13 @@ def test_small_batch_equals_alone_and_oracle(mode):
     batch.close()
 
 
-def test_mixed_64_job_batch_against_oracle_rows():
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
+def test_mixed_64_job_batch_against_oracle_rows(path):
     g = load("batch_rows.npz")
     jobs = W.batch_jobs(64, seed=0)
     tunes = [cs.Tune(large_mode=cs.LARGE_THREE_GAP) for _ in jobs]
-    batch = cs.Batch(jobs, tunes)
+    batch = cs.Batch(jobs, tunes, path=path)
+    assert batch.path == path
     bm, ct = batch.alloc_outputs()
     for rep in range(2):
         batch.run(bm, ct, use_graph=True)
@@ -109,4 +119,50 @@ def test_autotuned_batch_equals_alone():
     for i, job in enumerate(jobs):
         a_b, a_c = _alone(job)                    # default tuning: outputs do not depend on it
         assert np.array_equal(_np(bm[i]), a_b) and np.array_equal(_np(ct[i]), a_c), job
+    batch.close()
+
+
+@pytest.mark.parametrize("mode", [cs.LARGE_G, cs.LARGE_THREE_GAP], ids=["g", "three_gap"])
+def test_one_call_batch_equals_handle(mode):
+    """cs_sieve_batch (caller's workspace and stream, no graph) gives the handle's outputs."""
+    jobs = SMALL_MIX + W.batch_jobs(64, seed=0)[:6]
+    tunes = [cs.Tune(large_mode=mode) for _ in jobs]
+    batch = cs.Batch(jobs, tunes)
+    bm, ct = batch.alloc_outputs()
+    batch.run(bm, ct, use_graph=True)
+    ws = torch.empty((cs.batch_ws_bytes(jobs, tunes),), dtype=torch.uint8, device="cuda")
+    bm2, ct2 = batch.alloc_outputs()
+    for t in bm2 + ct2:
+        t.fill_(-1)
+    cs.sieve_batch(jobs, bm2, ct2, ws, tunes)
+    torch.cuda.synchronize()
+    for i, job in enumerate(jobs):
+        assert torch.equal(bm[i], bm2[i]) and torch.equal(ct[i], ct2[i]), job
+    batch.close()
+
+
+def test_persistent_refuses_mixed_enumerations():
+    tunes = [cs.Tune(large_mode=cs.LARGE_G), cs.Tune(large_mode=cs.LARGE_THREE_GAP)]
+    with pytest.raises(cs.CsError):
+        cs.Batch(SMALL_MIX[:2], tunes, path=cs.BATCH_PERSISTENT)
+    b = cs.Batch(SMALL_MIX[:2], tunes)
+    assert b.path == cs.BATCH_LANES
+    b.close()
+
+
+@pytest.mark.parametrize("order", [cs.ORDER_LARGE_FIRST, cs.ORDER_SMALL_FIRST, cs.ORDER_BY_JOB],
+                         ids=["large_first", "small_first", "by_job"])
+@pytest.mark.parametrize("ipt", [256, 2048])
+def test_persistent_task_shapes_equal_alone(order, ipt):
+    """The persistent kernel's queue order and items per task change only the schedule."""
+    tunes = [cs.Tune(large_mode=cs.LARGE_THREE_GAP) for _ in SMALL_MIX]
+    batch = cs.Batch(SMALL_MIX, tunes, path=cs.BATCH_PERSISTENT, items_per_task=ipt, order=order, blocks_per_cu=2)
+    bm, ct = batch.alloc_outputs()
+    batch.run(bm, ct, use_graph=True)
+    torch.cuda.synchronize()
+    for i, job in enumerate(SMALL_MIX):
+        a_b, a_c = _alone(job, tunes[i])
+        assert np.array_equal(_np(bm[i]), a_b) and np.array_equal(_np(ct[i]), a_c), job
+    d = batch.diag()
+    assert d.error_flags == 0 and sum(d.dec_primes) == d.large_primes
     batch.close()

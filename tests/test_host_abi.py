@@ -196,6 +196,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     B = cs.binding
     structs = {"cs_job": B.cs_job, "cs_tune": B.cs_tune, "cs_layout": B.cs_layout, "cs_diag": B.cs_diag,
                "cs_server_config": B.cs_server_config, "cs_ticket_info": B.cs_ticket_info,
+               "cs_batch_opts": B.cs_batch_opts,
                "cs_surround_stats": B.cs_surround_stats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "csieve.h"', "int main(void) {"]
     for name, ct in structs.items():
