@@ -52,7 +52,9 @@ typedef int32_t cs_status;
  *   2 <= P < 2^24;  d >= 1 squarefree with every prime factor <= P (d | P#);
  *   m_start >= 1;  1 <= m_inc < 2^32;  m_start + m_inc < 2^63;
  *   1 <= sl < 2^17 (a packed row fits an LDS tile) and sl < m_start*K (every N + X > 0);
- *   2 <= limit and max(limit, P) < 2^42 (CS_ERANGE otherwise).
+ *   2 <= limit and max(limit, P) < 2^63 (CS_ERANGE otherwise); primes from 2^42 take the exact
+ *   64-bit residue path (Section 3.3: p < 2^64), and limits whose tables exceed device memory go
+ *   through the chunked sieve.  Batches, the server and cs_primes take limits below 2^42.
  * A job whose range holds no m coprime to d is valid and has no rows. */
 typedef struct cs_job {
   uint32_t P;
@@ -89,7 +91,9 @@ typedef struct cs_tune {
                               per hit m = 1, 5 mod 6 when 6 | d), CS_WALK_ALL every m of the range as
                               the paper's program does (Section 3.2: its solve count then follows
                               the estimate M S (log log limit - log log thr) + pi(limit) - pi(thr)) */
-  uint32_t reserved;       /* must be 0 */
+  uint32_t wide_log2;      /* primes p >= 2^wide_log2 take the exact 64-bit residue arithmetic
+                              (Montgomery products, integer quotients); 0 = 42, the bound of the
+                              fp64 arithmetic; 20..42 move smaller primes onto it (e.g. to check it) */
 } cs_tune;
 
 #define CS_WALK_CLASSES 0u
@@ -255,7 +259,8 @@ cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* 
                     void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* K mod p for n primes (Eq. 1: the cached residue, K = P#/d): d_out[i] = K mod d_primes[i].
- * Every d_primes[i] must be a prime below 2^42.  d_ws: cs_kmod_ws bytes (it receives the
+ * Every d_primes[i] must be a prime below 2^63 (from 2^42 on the products are exact 64-bit
+ * Montgomery products).  d_ws: cs_kmod_ws bytes (it receives the
  * products of the primes dividing K, grouped below 2^50). */
 cs_status cs_kmod_ws(uint32_t P, uint64_t d, uint64_t* ws_bytes_out);
 cs_status cs_kmod(uint32_t P, uint64_t d, const uint64_t* d_primes, uint64_t n, uint64_t* d_out,

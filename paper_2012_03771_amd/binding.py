@@ -39,7 +39,7 @@ class cs_tune(C.Structure):
     _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
                 ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
                 ("branches", C.c_uint32), ("scatter", C.c_uint32), ("list_chunks", C.c_uint32),
-                ("walk", C.c_uint32), ("reserved", C.c_uint32)]
+                ("walk", C.c_uint32), ("wide_log2", C.c_uint32)]
 
 
 class cs_layout(C.Structure):
@@ -91,10 +91,11 @@ class Tune:
     scatter: int = 0
     list_chunks: int = 0
     walk: int = WALK_CLASSES
+    wide_log2: int = 0
 
     def c(self):
         return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
-                       self.small_slices, self.branches, self.scatter, self.list_chunks, self.walk, 0)
+                       self.small_slices, self.branches, self.scatter, self.list_chunks, self.walk, self.wide_log2)
 
 
 @dataclass

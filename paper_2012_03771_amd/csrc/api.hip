@@ -111,6 +111,15 @@ PrimeWs prime_ws_of(const Plan& pl, uint8_t* ws) {
   pw.primes = reinterpret_cast<uint64_t*>(ws + L.primes);
   pw.n_primes = reinterpret_cast<uint64_t*>(ws + L.n_primes);
   pw.cap = pl.cap;
+  if (pl.isq) {
+    pw.base2 = reinterpret_cast<uint64_t*>(ws + L.base2);
+    pw.n_base2 = reinterpret_cast<uint64_t*>(ws + L.n_base2);
+    pw.flags2 = reinterpret_cast<uint32_t*>(ws + L.flags2);
+    pw.seg_count2 = reinterpret_cast<uint32_t*>(ws + L.seg_count2);
+    pw.seg_off2 = reinterpret_cast<uint64_t*>(ws + L.seg_off2);
+    pw.cap2 = pl.cap2;
+    pw.isq = pl.isq;
+  }
   return pw;
 }
 
@@ -177,8 +186,9 @@ AuxStream* aux_stream() {
 
 // own_stream_only: everything on `s`, with no second stream and no timing events (the entry point
 // that allocates nothing creates neither).
-cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
-                        uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only = false) {
+// wide: the range lies at or above the plan's wide_lo; its large primes take the 64-bit path.
+cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
+                     uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only, bool wide) {
   const WsLayout& L = pl.ws;
   JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
   PrimeWs pw = prime_ws_of(pl, ws);
@@ -226,7 +236,7 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
       ev = large_events(ws);
     if (ev) CS_TRY(hipEventRecord(ev->start, s));
     CS_TRY(launch_large(jdp, 1, items_base, ctrl->diag, &ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes,
-                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, pl.large_mode, s));
+                        pl.large_lds_ct_words, (uint32_t)pl.dpre.size(), kind, pl.large_mode, s, wide));
     if (ev) {
       CS_TRY(hipEventRecord(ev->stop, s));
       ev->recorded = true;
@@ -240,6 +250,21 @@ cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* 
     if (pl.scatter_list) CS_TRY(launch_list_group(jdp, pl.list_chunks, pl.n_bkt, pl.bkt_rows, pl.super_shift, pl.row_words, s));
   }
   return CS_OK;
+}
+
+// The primes of [p_lo, p_hi]: below wide_lo with the fp64 arithmetic, from wide_lo on (large
+// primes only, since the threshold stays below it) with the 64-bit arithmetic.
+cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
+                        uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only = false) {
+  const uint64_t wl = pl.wide_lo;
+  if (p_hi < wl || pl.job.limit < wl)
+    return range_core(pl, p_lo, p_hi, bitmap, counts, ws, s, branches, own_stream_only, false);
+  if (p_lo < wl) {
+    cs_status st = range_core(pl, p_lo, wl - 1, bitmap, counts, ws, s, branches, own_stream_only, false);
+    if (st) return st;
+  }
+  if (branches == CS_BRANCH_SMALL) return CS_OK;
+  return range_core(pl, std::max(p_lo, wl), p_hi, bitmap, counts, ws, s, CS_BRANCH_LARGE, own_stream_only, true);
 }
 
 }  // namespace
@@ -300,9 +325,9 @@ cs_status chunked_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t
   const uint64_t limit = pl.job.limit;
   const uint64_t lo = std::max<uint64_t>(p_lo, 2), hi_all = std::min(p_hi, limit);
   const uint64_t step = pl.span ? pl.span : limit + 1;
-  for (uint64_t a = 0; a <= hi_all; a += step) {
+  // from the chunk that holds p_lo (chunks below it hold no prime of the range)
+  for (uint64_t a = lo / step * step; a <= hi_all; a += step) {
     const uint64_t hi = std::min<uint64_t>(a + step - 1, limit);
-    if (hi < lo) continue;                          // no prime of [p_lo, p_hi] in this chunk
     if (a > 0) {
       PrimeWs pw = prime_ws_of(pl, ws);
       JobDev* jdp = reinterpret_cast<JobDev*>(ws + pl.ws.jobdev);
@@ -352,6 +377,7 @@ extern "C" cs_status cs_sieve_chunked(const cs_job* job, const cs_tune* tune, ui
 
 extern "C" cs_status cs_diag_read(const void* d_ws, cs_diag* out, void* stream) {
   if (!d_ws || !out) return CS_EINVAL;
+  // every workspace layout puts the control block first (WsLayout::ctrl == 0)
   hipStream_t s = (hipStream_t)stream;
   if (hipStreamSynchronize(s) != hipSuccess) return CS_EDEVICE;
   JobCtrl c;
@@ -410,7 +436,7 @@ PrimeOnlyLayout prime_only_layout(uint64_t limit) {
 
 extern "C" cs_status cs_primes_ws(uint64_t limit, uint64_t* cap_out, uint64_t* ws_bytes_out) {
   if (limit < 2) return CS_EINVAL;
-  if (limit >= kMaxLimit) return CS_ERANGE;
+  if (limit >= kWideLo) return CS_ERANGE;
   PrimeOnlyLayout L = prime_only_layout(limit);
   if (cap_out) *cap_out = L.cap;
   if (ws_bytes_out) *ws_bytes_out = L.total;
@@ -420,7 +446,7 @@ extern "C" cs_status cs_primes_ws(uint64_t limit, uint64_t* cap_out, uint64_t* w
 extern "C" cs_status cs_primes(uint64_t limit, uint64_t* d_primes, uint64_t cap, uint64_t* d_count, void* d_ws,
                                uint64_t ws_bytes, void* stream) {
   if (limit < 2 || !d_primes || !d_count || !d_ws) return CS_EINVAL;
-  if (limit >= kMaxLimit) return CS_ERANGE;
+  if (limit >= kWideLo) return CS_ERANGE;
   PrimeOnlyLayout L = prime_only_layout(limit);
   if (cap < L.cap || ws_bytes < L.total) return CS_ERANGE;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);

@@ -75,7 +75,7 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
   }
   b.max_rows = 0;
   for (uint32_t i = 0; i < n; ++i) b.max_rows = std::max<uint64_t>(b.max_rows, b.plans[i].n_m);
-  if (Lp >= kMaxLimit) return CS_ERANGE;
+  if (Lp >= kWideLo) return CS_ERANGE;
   b.Lp = Lp;
   b.lds_ct_words = max_ct * 8u <= kLdsCtMax ? max_ct : 0u;
   // The persistent kernel needs one enumeration for all jobs and every job's column table (and

@@ -66,6 +66,7 @@ struct JobDev {
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
   uint32_t kmod_cached;              // 1: kmod already holds K mod p (a shared table); only mk is built
+  uint64_t wide_lo;                  // primes >= wide_lo take the exact 64-bit residue arithmetic
   // The large branch walks m of the residue classes mod m_step that can hold rows (bit c of
   // m_classes: m = c mod m_step coprime to it; m_step divides d), one class after the other:
   // 2 (odd m) when d is even, 6 (m = 1, 5 mod 6) with one solve per hit when 6 divides d, else 1.

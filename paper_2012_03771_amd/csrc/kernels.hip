@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include "arith.h"
+#include "arith_wide.h"
 #include "device.h"
 #include "launch.h"
 
@@ -223,14 +224,33 @@ __device__ __forceinline__ uint32_t pattern_word(uint32_t u, uint32_t b0) {
   return every_qth(Q) << ph;
 }
 
+// The first odd multiple of q at or above max(lo, q^2).  kWide: lo up to 2^64 (exact 64-bit
+// remainder); otherwise lo < 2^42, where the fp64 quotient is exact.
+template <bool kWide>
+__device__ __forceinline__ uint64_t first_odd_multiple(uint64_t lo, uint64_t q) {
+  uint64_t st;
+  if constexpr (kWide) {
+    const uint64_t r = mod64(lo, q, 1.0 / (double)q);
+    st = r ? lo + (q - r) : lo;
+  } else {
+    st = (uint64_t)(ceil((double)lo / (double)q)) * q;
+  }
+  if (st < q * q) st = q * q;
+  if ((st & 1) == 0) st += q;
+  return st;
+}
+
+// BT, NT: types of the base-prime table and of its length (uint32_t for the LDS-sieved base below
+// 2^21; uint64_t for the level-2 table of limits from 2^42, which starts with the prime 2).
+template <bool kWide, class BT, class NT>
 __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t seg0, uint64_t n_seg,
-                                                        const uint32_t* __restrict__ base,
-                                                        const uint32_t* __restrict__ n_base_p,
+                                                        const BT* __restrict__ base,
+                                                        const NT* __restrict__ n_base_p,
                                                         uint32_t* __restrict__ flags,
                                                         uint32_t* __restrict__ seg_count) {
   __shared__ uint32_t bits[kSegWords];
   __shared__ uint32_t sh[32];
-  const uint32_t n_base = *n_base_p;
+  const uint64_t n_base = *n_base_p;
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const uint64_t gs = seg0 + s;                                  // segment of the whole range
     const uint64_t lo = gs << kSegLog;
@@ -254,28 +274,23 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t s
     }
     __syncthreads();
     const uint32_t nbits = (uint32_t)((hi - lo + 1) / 2);          // bits standing for n <= hi
-    const double dlo = (double)lo;
     // dense base primes above 13: the whole workgroup strides over the multiples of each
-    uint32_t i = 0;
+    uint64_t i = 0;
     while (i < n_base && base[i] <= 13) ++i;
     for (; i < n_base; ++i) {
       const uint64_t q = base[i];
       if (q * q > hi || q >= 4096) break;
-      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;         // exact: lo < 2^42
-      if (st < q * q) st = q * q;
-      if ((st & 1) == 0) st += q;
+      const uint64_t st = first_odd_multiple<kWide>(lo, q);
       if (st > hi) continue;
       const uint32_t b0 = (uint32_t)((st - lo) >> 1);
       for (uint32_t b = b0 + threadIdx.x * (uint32_t)q; b < nbits; b += blockDim.x * (uint32_t)q)
         atomicOr(&bits[b >> 5], 1u << (b & 31));
     }
     // sparse base primes: one thread per prime
-    for (uint32_t j = i + threadIdx.x; j < n_base; j += blockDim.x) {
+    for (uint64_t j = i + threadIdx.x; j < n_base; j += blockDim.x) {
       const uint64_t q = base[j];
       if (q * q > hi) continue;
-      uint64_t st = (uint64_t)(ceil(dlo / (double)q)) * q;
-      if (st < q * q) st = q * q;
-      if ((st & 1) == 0) st += q;
+      const uint64_t st = first_odd_multiple<kWide>(lo, q);
       for (uint64_t b = (st - lo) >> 1; b < nbits; b += q)
         atomicOr(&bits[b >> 5], 1u << (b & 31));
     }
@@ -420,6 +435,19 @@ __device__ __forceinline__ const JobDev& job_of_index(const JobDev* __restrict__
   return jobs[lo];
 }
 
+// K mod p and m_start*K mod p of one prime p >= 2^20 (odd) with the exact 64-bit arithmetic.
+__device__ __noinline__ void kmod_wide_one(const JobDev& j, uint64_t i, uint64_t p) {
+  const Mont64 m = mont_setup(p);
+  uint64_t k;
+  if (j.kmod_cached) {
+    k = gbl(j.kmod)[i];
+  } else {
+    k = kmod64(m, gbl(j.kgroups), gbl(j.ctrl)->n_kgroups);
+    gbl(j.kmod)[i] = k;
+  }
+  gbl(j.mk)[i] = mulmod_m(m, umod64(j.m_start, p), k);
+}
+
 // K mod p and m_start*K mod p for every prime index < n_lim of every job (Eq. 1's cached
 // residue); the index space of all jobs is flattened so one launch covers a whole batch.  Each
 // thread takes two indices and interleaves their multiplication chains.
@@ -443,6 +471,12 @@ __global__ __launch_bounds__(256) void k_kmod(const JobDev* __restrict__ jobs, u
     const JobDev& j1 = two ? job_of_index(jobs, n_jobs, lim_base, g1, &i1) : j0;
     if (!two) i1 = i0;
     const uint64_t p0 = gbl(j0.primes)[i0], p1 = gbl(j1.primes)[i1];
+    if (p0 >= j0.wide_lo || p1 >= j1.wide_lo) {
+      // 64-bit primes: Montgomery products of K's groups (the rare top of a wide range)
+      kmod_wide_one(j0, i0, p0);
+      if (two) kmod_wide_one(j1, i1, p1);
+      continue;
+    }
     const double v0 = 1.0 / (double)p0, v1 = 1.0 / (double)p1;
     uint64_t r0, r1;
     if (&j0 == &j1 && !j0.kmod_cached) {
@@ -509,6 +543,10 @@ __global__ __launch_bounds__(256) void k_kmod_list(const uint64_t* __restrict__ 
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t p = primes[i];
+    if (p >= (1ull << 42)) {                       // exact 64-bit products for the widest primes
+      out[i] = kmod64(mont_setup(p), G, ng);
+      continue;
+    }
     const double pinv = 1.0 / (double)p;
     uint64_t r = 1 % p;
     for (uint32_t g = 0; g < ng; ++g) r = mulmod(r, G[g], p, pinv);
@@ -1233,7 +1271,8 @@ __device__ __forceinline__ void flush_dec(LaneCount& lc, unsigned long long (*s_
 
 // One large-branch work item (prime, chunk of the m range) of job j: item `local` of the job's
 // tiered item space.  t_last: the lane's tier of its previous item of this job (items only grow).
-template <bool kLds, int kSc, bool kG>
+// kWide: the prime is at least 2^42 and its residues take the exact 64-bit arithmetic.
+template <bool kLds, int kSc, bool kG, bool kWide = false>
 __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kLds>& T, uint64_t local,
                                            uint32_t& t_last, LaneCount& lc, unsigned long long (*s_dec)[kDecades],
                                            ListReg& lreg, unsigned long long* lkey, uint32_t* s_sup) {
@@ -1280,11 +1319,19 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     }
     if (chunk == 0) ++lc.n_pr;                        // each prime once (chunk 0 always has positions)
   }
-  uint64_t k = s * k1;                             // residue step of one walk position: s K mod p
-  k -= k >= 4 * p ? 4 * p : 0;                     // s <= 6: s K mod p < 8p before these
-  k -= k >= 2 * p ? 2 * p : 0;
-  k -= k >= p ? p : 0;
+  uint64_t k;                                      // residue step of one walk position: s K mod p
+  if constexpr (kWide) {
+    k = k1;
+    for (uint32_t i = 1; i < s; ++i) k = addmod64(k, k1, p);
+  } else {
+    k = s * k1;
+    k -= k >= 4 * p ? 4 * p : 0;                   // s <= 6: s K mod p < 8p before these
+    k -= k >= 2 * p ? 2 * p : 0;
+    k -= k >= p ? p : 0;
+  }
   const double pinv = recip((double)p);             // within an ulp: every quotient below is corrected
+  Mont64 mt = {0, 0, 0};
+  if constexpr (kWide) mt = mont_setup(p);
   const uint64_t w = j.w;
   const uint32_t d32 = (uint32_t)j.d;
   const double inv_d = j.inv_d;
@@ -1293,15 +1340,28 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
   // k^-1 mod p (and, for three-gap stepping, the two return times) from one Euclid pass
   uint64_t kinv = 0;
   gaps3 g = {0, 0, 0, 0};
-  if (kG) {
-    kinv = modinv(k, p);
-  } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
-    lc.err |= E_SOLVE;
-    return;
+  if constexpr (kWide) {
+    if (kG) {
+      kinv = modinv64(k, p);
+    } else if (!three_gap_euclid64(p, k, w, &g, &kinv)) {
+      lc.err |= E_SOLVE;
+      return;
+    }
+  } else {
+    if (kG) {
+      kinv = modinv(k, p);
+    } else if (!three_gap_euclid(p, k, w, &g, &kinv, nullptr)) {
+      lc.err |= E_SOLVE;
+      return;
+    }
   }
   // three-gap return times in offsets of m (a time past the chunk ends the walk, so the
-  // quotients below only matter for the times that are taken)
-  const uint64_t sta = s * g.ta, stb = s * g.tb, tab = sta + stb;
+  // quotients below only matter for the times that are taken); with 64-bit primes they are
+  // capped at 2^33, beyond any range of m, so that they stay exact in fp64 and never overflow
+  constexpr uint64_t kCap = 1ull << 33;
+  const uint64_t sta = kWide ? (g.ta >= kCap / s ? kCap : s * g.ta) : s * g.ta;
+  const uint64_t stb = kWide ? (g.tb >= kCap / s ? kCap : s * g.tb) : s * g.tb;
+  const uint64_t tab = kWide ? min(sta + stb, kCap) : sta + stb;
   uint32_t aq = 0, ar = 0, bq = 0, br = 0, abq = 0, abr = 0;
   if (!kG && d_small) {
     mpos_divmod(sta, d32, inv_d, &aq, &ar);
@@ -1321,8 +1381,13 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     if (!((j.m_classes >> cls) & 1u) || o_lo >= j.m_inc) continue;
     const uint64_t o_hi = min(o_par + s * u_hi, j.m_inc);   // visited o = o_par + s u < o_hi
     // residue of m*K + SL at m = m_start + o_lo
-    uint64_t r = mk + mulmod(o_lo, k1, p, pinv);
-    r = r >= p ? r - p : r;
+    uint64_t r;
+    if constexpr (kWide) {
+      r = addmod64(mk, mulmod_m(mt, o_lo, k1), p);      // o_lo < 2^32 < p
+    } else {
+      r = mk + mulmod(o_lo, k1, p, pinv);
+      r = r >= p ? r - p : r;
+    }
     r += j.sl;                                     // sl < w < thr < p
     r = r >= p ? r - p : r;
     uint64_t o = o_lo;
@@ -1335,10 +1400,13 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
         if (r > w) {
           int lv = 0;
           uint64_t rn;
-          const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+          uint64_t tstep;
+          if constexpr (kWide) tstep = next_hit64(mt, k, kinv, r, w, &rn, &lv);
+          else tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
           ++lc.calls;
           lc.levels += (unsigned)lv;
           if (tstep == 0) { lc.err |= E_SOLVE; break; }
+          if (kWide && tstep > (o_hi - o) / s) break;   // past the range (and no overflow below)
           o += s * tstep;
           if (o >= o_hi) break;
           r = rn;
@@ -1360,10 +1428,13 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
       if (r > w) {
         uint64_t rn;
         int lv = 0;
-        const uint64_t tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+        uint64_t tstep;
+        if constexpr (kWide) tstep = next_hit64(mt, k, kinv, r, w, &rn, &lv);
+        else tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
         ++lc.calls;
         lc.levels += (unsigned)lv;
         if (tstep == 0) { lc.err |= E_SOLVE; break; }
+        if (kWide && tstep > (o_hi - o) / s) continue;  // the class's first hit lies past the range
         o += s * tstep;
         r = rn;
         if (d_small && o < o_hi) {
@@ -1391,7 +1462,7 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
   }
 }
 
-template <bool kLds, int kSc, bool kG>
+template <bool kLds, int kSc, bool kG, bool kWide>
 __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ job_item_base,
                                                unsigned long long* __restrict__ diag,
@@ -1435,7 +1506,8 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     if (ji != ji_last) t_last = 0;
     ji_last = ji;
     // the LDS variant runs one job: its fields are uniform
-    large_item<kLds, kSc, kG>(jobs[kLds ? 0 : ji], T, item - job_item_base[ji], t_last, lc, s_dec, lreg, lkey, s_sup);
+    large_item<kLds, kSc, kG, kWide>(jobs[kLds ? 0 : ji], T, item - job_item_base[ji], t_last, lc, s_dec, lreg, lkey,
+                                     s_sup);
     if constexpr (kSc == 2) list_sync(lreg, lkey);
   }
   if constexpr (kSc == 2) {
@@ -2007,12 +2079,31 @@ hipError_t launch_primes(uint64_t lim, const PrimeWs& pw, hipStream_t s) {
 }
 
 hipError_t launch_primes_range(uint64_t seg0, uint64_t lim, const PrimeWs& pw, hipStream_t s) {
-  hipLaunchKernelGGL(k_base_primes, dim3(1), dim3(1024), 0, s, lim, pw.base, pw.n_base); { hipError_t e_ = note("k_base_primes"); if (e_ != hipSuccess) return e_; }
   const uint64_t n_seg = (lim >> kSegLog) + 1 - seg0;
   uint32_t blocks = (uint32_t)(n_seg < 8192 ? n_seg : 8192);
   const uint32_t seg_blocks = (uint32_t)(n_seg < (1ull << 31) ? n_seg : (1ull << 31));   // one per segment
-  hipLaunchKernelGGL(k_sieve_segments, dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg, pw.base, pw.n_base,
-                     pw.flags, pw.seg_count); { hipError_t e_ = note("k_sieve_segments"); if (e_ != hipSuccess) return e_; }
+  if (pw.isq && lim >= (1ull << 42)) {
+    // level 2: the primes up to sqrt(lim) with the LDS-sieved base, then the segments with them
+    PrimeWs p2;
+    p2.base = pw.base;
+    p2.n_base = pw.n_base;
+    p2.flags = pw.flags2;
+    p2.seg_count = pw.seg_count2;
+    p2.seg_off = pw.seg_off2;
+    p2.primes = pw.base2;
+    p2.n_primes = pw.n_base2;
+    p2.cap = pw.cap2;
+    hipError_t e = launch_primes_range(0, pw.isq, p2, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sieve_segments<true, uint64_t, uint64_t>), dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg,
+                       (const uint64_t*)pw.base2, (const uint64_t*)pw.n_base2, pw.flags, pw.seg_count);
+    { hipError_t e_ = note("k_sieve_segments<wide>"); if (e_ != hipSuccess) return e_; }
+  } else {
+    hipLaunchKernelGGL(k_base_primes, dim3(1), dim3(1024), 0, s, lim, pw.base, pw.n_base); { hipError_t e_ = note("k_base_primes"); if (e_ != hipSuccess) return e_; }
+    hipLaunchKernelGGL((k_sieve_segments<false, uint32_t, uint32_t>), dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg,
+                       (const uint32_t*)pw.base, (const uint32_t*)pw.n_base, pw.flags, pw.seg_count);
+    { hipError_t e_ = note("k_sieve_segments"); if (e_ != hipSuccess) return e_; }
+  }
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pw.seg_count, n_seg, pw.seg_off, pw.n_primes); { hipError_t e_ = note("k_scan_counts"); if (e_ != hipSuccess) return e_; }
   hipLaunchKernelGGL(k_compact_primes, dim3(blocks), dim3(256), 0, s, seg0, n_seg, pw.flags, pw.seg_off,
                      pw.primes, pw.cap); { hipError_t e_ = note("k_compact_primes"); if (e_ != hipSuccess) return e_; }
@@ -2123,16 +2214,22 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
                         uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, uint32_t large_mode,
-                        hipStream_t s) {
+                        hipStream_t s, bool wide) {
   if (n_jobs != 1 && scatter_kind == 2) scatter_kind = 0;   // the list serves single jobs only
+  if (n_jobs != 1) wide = false;                            // (the 64-bit path serves single jobs)
   const bool lds = lds_bytes && lds_ct_words && n_jobs == 1;
-#define LARGE_CASE(L, K, G)                                                                                    \
-  hipLaunchKernelGGL((k_large<L, K, G>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs,          \
+#define LARGE_CASE(L, K, G, W)                                                                                 \
+  hipLaunchKernelGGL((k_large<L, K, G, W>), dim3(blocks), dim3(256), L ? lds_bytes : 0u, s, jobs, n_jobs,       \
                      job_item_base, diag, dec, L ? lds_ct_words : 0u, L ? dpre_n : 0u)
-#define LARGE_MODES(L, K)                     \
-  do {                                        \
-    if (large_mode == 0) LARGE_CASE(L, K, true); \
-    else LARGE_CASE(L, K, false);             \
+#define LARGE_MODES(L, K)                                  \
+  do {                                                     \
+    if (wide) {                                            \
+      if (large_mode == 0) LARGE_CASE(L, K, true, true);   \
+      else LARGE_CASE(L, K, false, true);                  \
+    } else {                                               \
+      if (large_mode == 0) LARGE_CASE(L, K, true, false);  \
+      else LARGE_CASE(L, K, false, false);                 \
+    }                                                      \
   } while (0)
   if (lds) {
     if (scatter_kind == 2) LARGE_MODES(true, 2);

@@ -17,6 +17,14 @@ struct PrimeWs {
   uint64_t* primes;     // output table
   uint64_t* n_primes;   // device scalar
   uint64_t cap;
+  // level-2 base primes for limits from 2^42 (null otherwise): the primes up to isq, sieved with
+  // their own segment scratch, then the base of the limit's segments
+  uint64_t* base2 = nullptr;
+  uint64_t* n_base2 = nullptr;
+  uint32_t* flags2 = nullptr;
+  uint32_t* seg_count2 = nullptr;
+  uint64_t* seg_off2 = nullptr;
+  uint64_t cap2 = 0, isq = 0;
 };
 
 // Name and message of the last failed launch in this thread (empty if none).
@@ -65,10 +73,11 @@ hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_unit
 // launches only; 0 otherwise).
 // diag: D_COUNT totals; dec: DC_COUNT x kDecades counters per prime decade (or null).
 // large_mode: CS_LARGE_G (0) or CS_LARGE_THREE_GAP (1), the same for every job of the launch.
+// wide: the primes of the launch are at least 2^42 (single-job launches): exact 64-bit residues.
 hipError_t launch_large(const JobDev* jobs, uint32_t n_jobs, const uint64_t* job_item_base,
                         unsigned long long* diag, unsigned long long* dec, uint32_t blocks, uint32_t lds_bytes,
                         uint32_t lds_ct_words, uint32_t dpre_n, uint32_t scatter_kind, uint32_t large_mode,
-                        hipStream_t s);
+                        hipStream_t s, bool wide = false);
 // Groups the list pool of one job by row bucket and applies it to the bitmap and counts.  The
 // caller cleared the pool cursor and the bucket counts before the k_large launch.
 hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n_bkt, uint32_t bkt_rows,

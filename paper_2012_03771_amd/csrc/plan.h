@@ -9,7 +9,9 @@
 namespace cs {
 
 constexpr uint32_t kMaxSl = (1u << 17) - 1;     // a packed row (<= 2^18 bits) fits an LDS tile
-constexpr uint64_t kMaxLimit = 1ull << 42;
+constexpr uint64_t kMaxLimit = 1ull << 63;    // sieve limits of single jobs (chunked beyond memory)
+constexpr uint64_t kWideLo = 1ull << 42;      // primes from here take the exact 64-bit residue path;
+                                              // batches, the server and cs_primes stay below it
 constexpr uint32_t kMaxP = 1u << 24;
 constexpr uint64_t kMaxMInc = 1ull << 32;
 constexpr uint32_t kSmallBlock = 512;
@@ -24,7 +26,9 @@ constexpr uint32_t kTileRowsMax = 16;          // rows per small-branch tile (mo
 constexpr uint32_t kBaseCap = 155700;           // odd primes below 2^21 (155,610) plus slack
 
 struct WsLayout {
-  uint64_t ctrl, jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
+  uint64_t ctrl;                     // always 0: cs_diag_read reads the control block there
+  uint64_t base2, n_base2, flags2, seg_count2, seg_off2;   // level-2 base primes (limits >= 2^42)
+  uint64_t jobdev, items_base, lim_base, base, n_base, n_primes, flags, seg_count, seg_off, primes,
       kmod, mk, row_of, m_off, row_blk, coltab, kgroups, kq, dpre, dres, dpat, dpat_cnt, hitbytes, list_pool,
       list_fill, list_cursor, list_sorted, bkt_count, bkt_base, bkt_cursor, list_super, total;
 };
@@ -41,6 +45,8 @@ struct Plan {
   uint64_t thr;
   uint32_t large_mode;
   bool walk_all = false;            // the large branch visits every m (CS_WALK_ALL)
+  uint64_t wide_lo = kWideLo;       // primes >= wide_lo take the 64-bit residue path
+  uint64_t isq = 0, cap2 = 0, n_seg2 = 0;   // level-2 base primes: up to isq (0: not needed)
   uint32_t tile_rows, n_windows, n_slices;
   uint32_t hits_per_item;
   uint32_t large_blocks, small_blocks;

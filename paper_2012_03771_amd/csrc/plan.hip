@@ -84,7 +84,8 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (mode > CS_LARGE_THREE_GAP) return CS_EINVAL;
   const uint32_t scatter = tune ? tune->scatter : CS_SCATTER_AUTO;
   if (scatter > CS_SCATTER_LIST) return CS_EINVAL;
-  if (tune && (tune->walk > CS_WALK_ALL || tune->reserved != 0)) return CS_EINVAL;
+  if (tune && tune->walk > CS_WALK_ALL) return CS_EINVAL;
+  if (tune && tune->wide_log2 && (tune->wide_log2 < 20 || tune->wide_log2 > 42)) return CS_EINVAL;
 
   Plan& pl = *out;
   pl.job = j;
@@ -138,6 +139,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   pl.w = 2 * j.sl;
   pl.large_mode = mode;
   pl.walk_all = tune && tune->walk == CS_WALK_ALL;
+  pl.wide_lo = tune && tune->wide_log2 ? (1ull << tune->wide_log2) : kWideLo;
 
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 2.5 M / M_c (a quarter of the paper's 10 M / M_c: at 953#/210 the step is flat from 120,000
@@ -155,6 +157,9 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     thr = (uint64_t)(cm * (double)pl.S);
   }
   pl.thr = std::max(thr, thr_min);
+  // the small branch and the fp64 large branch stop below wide_lo
+  if (thr_min >= pl.wide_lo) return CS_EINVAL;
+  pl.thr = std::min<uint64_t>(pl.thr, pl.wide_lo - 1);
 
   // small branch tiles
   const bool ct_lds = pl.ct_words * 8u <= kLdsCtMax;
@@ -217,6 +222,19 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t at = o; o = align256(o + std::max<uint64_t>(bytes, 8)); return at; };
   const uint64_t cap_lim = pl.span ? pl.cap : pi_upper(j.limit);
+  // Limits from 2^42 on need base primes beyond the two LDS windows of k_base_primes (2^21): the
+  // primes up to the square root of the limit are sieved first into their own table.
+  pl.isq = 0;
+  const uint64_t top = std::max<uint64_t>(j.limit, j.P);
+  if (own_primes && top >= kWideLo) {
+    uint64_t r = (uint64_t)sqrtl((long double)top);
+    while (r * r > top) --r;
+    while ((r + 1) * (r + 1) <= top) ++r;
+    pl.isq = r;
+    pl.n_seg2 = (r >> kSegLog) + 1;
+    pl.cap2 = pi_upper(r);
+  }
+
   L.ctrl = take(sizeof(JobCtrl));
   L.jobdev = take(sizeof(JobDev));
   L.items_base = take(2 * sizeof(uint64_t));
@@ -301,6 +319,12 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.bkt_base = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
   L.bkt_cursor = take(pl.scatter_list ? (pl.n_bkt + 1ull) * 4ull : 0);
   L.list_super = take(pl.scatter_list ? 3ull * (kListSupers + 1) * 4ull : 0);
+  // (the control block stays at offset 0: cs_diag_read reads it there)
+  L.base2 = take(pl.isq ? pl.cap2 * 8ull : 0);
+  L.n_base2 = take(8);
+  L.flags2 = take(pl.isq ? pl.n_seg2 * kSegWords * 4ull : 0);
+  L.seg_count2 = take(pl.isq ? pl.n_seg2 * 4ull : 0);
+  L.seg_off2 = take(pl.isq ? pl.n_seg2 * 8ull : 0);
   L.total = o;
   return CS_OK;
 }
@@ -390,6 +414,7 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.small_unit_base = 0;
   jd.dense_max = pl.dense_max;
   jd.prime_cap = pl.cap;
+  jd.wide_lo = pl.wide_lo;
   jd.primes = primes;
   jd.n_primes = n_primes;
   const WsLayout& L = pl.ws;

@@ -401,7 +401,7 @@ void fill_info(const cs_server* s, const SJob& J, cs_ticket_info* out) {
 
 extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** out) {
   if (!cfg || !out || cfg->budget_bytes == 0 || cfg->max_active == 0 || cfg->max_limit < 2) return CS_EINVAL;
-  if (cfg->max_limit >= kMaxLimit) return CS_ERANGE;
+  if (cfg->max_limit >= kWideLo) return CS_ERANGE;
   *out = nullptr;
   cs_server* s = new (std::nothrow) cs_server();
   if (!s) return CS_ENOMEM;

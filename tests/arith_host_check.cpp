@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../paper_2012_03771_amd/csrc/arith.h"
+#include "../paper_2012_03771_amd/csrc/arith_wide.h"
 
 typedef unsigned __int128 u128;
 
@@ -266,6 +267,98 @@ int main(int argc, char** argv) {
     cs::euclid_tail_f32(&x, &y, &s0, &s1);
     if ((uint64_t)x != g || y != 0.0) { bad = fail("tail_gcd_rand", a, b, (uint64_t)x, g); break; }
     if ((int64_t)s0 != u0 * ca + v0 * cb) { bad = fail("tail_bezout", a, b, (uint64_t)s0, 0); break; }
+  }
+  // ---- the 64-bit residue arithmetic (primes up to 2^63) ----
+  // division: random dividends and divisors of every magnitude, and divisors near 2^62 and 2^63
+  for (int i = 0; i < 400000 && !bad; ++i) {
+    const uint64_t a = i % 7 == 0 ? ~0ull - rng() % 1000 : rng() >> (rng() % 64);
+    uint64_t b = (rng() >> (1 + rng() % 63)) | 1;
+    if (i % 11 == 0) b = (1ull << 62) + (rng() % 1000) - 500;
+    if (i % 13 == 0) b = (1ull << 63) - 1 - rng() % 100000;
+    if (b >= (1ull << 63)) b = (1ull << 63) - 1;
+    uint64_t q, r;
+    cs::udivmod64(a, b, &q, &r);
+    if (q != a / b || r != a % b) bad = fail("udivmod64", a, b, q, r);
+  }
+  // Montgomery products, inverses and K mod p against 128-bit integers, odd p up to 2^63
+  for (int i = 0; i < 200000 && !bad; ++i) {
+    uint64_t p = ((rng() >> (1 + rng() % 60)) | 1) | 3;
+    if (i % 9 == 0) p = (1ull << 63) - 1 - 2 * (rng() % 1000);
+    const cs::Mont64 m = cs::mont_setup(p);
+    const uint64_t a = rng() % p, b = rng() % p;
+    if (cs::mulmod_m(m, a, b) != (uint64_t)((u128)a * b % p)) { bad = fail("mulmod_m", a, b, p, 0); break; }
+  }
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t p;
+    do { p = (rng() >> (1 + rng() % 40)) | 1; } while (p < 5 || !is_prime_mr(p));
+    const uint64_t k = 1 + rng() % (p - 1);
+    const uint64_t inv = cs::modinv64(k, p);
+    if ((uint64_t)((u128)inv * k % p) != 1) { bad = fail("modinv64", p, k, inv, 0); break; }
+    const uint64_t gr[4] = {rng() >> 14, rng() >> 14, rng() >> 20, 3};
+    uint64_t want = 1 % p;
+    for (int t = 0; t < 4; ++t) want = (uint64_t)((u128)want * (gr[t] % p) % p);
+    const cs::Mont64 m = cs::mont_setup(p);
+    if (cs::kmod64(m, gr, 4) != want) { bad = fail("kmod64", p, gr[0], gr[1], 0); break; }
+  }
+  // Eq. 5 in 64-bit integers against brute force (small p) and against the fp64 form (p < 2^42)
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    uint64_t p;
+    do { p = 3 + rng() % 4000; } while (!is_prime(p));
+    const uint64_t K = 1 + rng() % (p - 1), width = rng() % (p / 2), L = 1 + rng() % (p - width - 1);
+    int lv;
+    const uint64_t off = cs::g_offset64(p, K, L, width, &lv);
+    const uint64_t t = brute_G(p, K, L, L + width);
+    const uint64_t v = (uint64_t)((u128)t * K % p);
+    if (off == ~0ull || L + off != v) { bad = fail("g_offset64", p, K, L, width); break; }
+  }
+  for (int i = 0; i < 50000 && !bad; ++i) {
+    uint64_t p;
+    do { p = (rng() >> (22 + rng() % 20)) | 1; } while (p < (1ull << 20) || !is_prime_mr(p));
+    if (p >= (1ull << 42)) continue;
+    const uint64_t K = 1 + rng() % (p - 1), width = 1 + rng() % (1u << 17), L = 1 + rng() % (p - width - 1);
+    int l1, l2;
+    const uint64_t o1 = cs::g_offset64(p, K, L, width, &l1);
+    const double o2 = cs::g_offset((double)p, (double)K, (double)L, (double)width, &l2);
+    if (o2 < 0.0 || o1 != (uint64_t)o2) { bad = fail("g_offset64_vs_fp64", p, K, L, width); break; }
+  }
+  // three-gap constants in 64-bit integers: against the fp64 pass below 2^42, and at 2^50..2^63
+  // the rule's next hit from a hit against an Eq. 5 solve from the following residue
+  for (int i = 0; i < 40000 && !bad; ++i) {
+    uint64_t p;
+    const int top = i % 2 ? 42 : 63;
+    do { p = (rng() >> (64 - top + rng() % 20)) | 1; } while (p < (1ull << 22) || !is_prime_mr(p));
+    if (p >= (1ull << 63)) continue;
+    const uint64_t w = 1 + rng() % (1u << 18);
+    const uint64_t k = 1 + rng() % (p - 1);
+    cs::gaps3 g;
+    uint64_t kinv = 0;
+    if (!cs::three_gap_euclid64(p, k, w, &g, &kinv)) { bad = fail("euclid64", p, k, w, 0); break; }
+    if ((uint64_t)((u128)kinv * k % p) != 1) { bad = fail("euclid64_inv", p, k, kinv, 0); break; }
+    if ((uint64_t)((u128)g.ta * k % p) != g.a || g.a < 1 || g.a > w) { bad = fail("euclid64_ta", p, k, w, g.ta); break; }
+    if (p - (uint64_t)((u128)g.tb * k % p) != g.b || g.b < 1 || g.b > w) { bad = fail("euclid64_tb", p, k, w, g.tb); break; }
+    if (p < (1ull << 42)) {
+      cs::gaps3 g2;
+      uint64_t kinv2 = 0;
+      if (!cs::three_gap_euclid(p, k, w, &g2, &kinv2, nullptr) || g2.ta != g.ta || g2.tb != g.tb || g2.a != g.a ||
+          g2.b != g.b || kinv2 != kinv) {
+        bad = fail("euclid64_vs_fp64", p, k, w, 0);
+        break;
+      }
+    }
+    const cs::Mont64 m = cs::mont_setup(p);
+    for (int j = 0; j < 4 && !bad; ++j) {
+      const uint64_t r = rng() % (w + 1);                     // a hit's residue
+      const bool a_first = g.ta < g.tb;
+      const bool fa = r + g.a <= w, fb = r >= g.b;
+      const uint64_t t_rule = (fa && (a_first || !fb)) ? g.ta : (fb ? g.tb : g.ta + g.tb);
+      uint64_t r1 = r + k;                                     // residue after one step
+      r1 = r1 >= p ? r1 - p : r1;
+      uint64_t t_g = 1, rn = r1;
+      int lv;
+      if (r1 > w) t_g = 1 + cs::next_hit64(m, k, kinv, r1, w, &rn, &lv);
+      if (t_g != t_rule) { bad = fail("three_gap64_vs_G", p, k, r, t_rule); break; }
+      if ((uint64_t)(((u128)r + (u128)t_g * k) % p) != rn || rn > w) { bad = fail("next_hit64", p, k, r, t_g); break; }
+    }
   }
   if (!bad) std::printf("OK\n");
   return bad;

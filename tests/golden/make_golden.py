@@ -3,12 +3,13 @@
 Every value written here comes from oracle/ (the plain CPU sieve) on jobs from workloads/;
 nothing comes from the HIP path.  Run from the repository root:
 
-    python tests/golden/make_golden.py [medium] [paper] [batch]
+    python tests/golden/make_golden.py [medium] [paper] [batch] [wide]
 
 medium_503_rows.npz   per-row digests of the whole 503#/210 job (2,287 rows), plus 64 full rows
 paper_953_rows.npz    64 rows of the 953#/210 paper-scale job, primes up to 1e10: the first, the
                       last, the row of m = 100054841 (the merit-38.048 record gap) and 61 seeded
 batch_rows.npz        4 rows of each of the 64 seeded mixed-batch jobs
+wide_windows.npz      every row of two jobs placed on windows of primes near 2^50 and 2^63
 
 Every file is written with the oracle's DIRECT mode: N mod p taken from the bignum N = m K for
 every row and prime, the traditional sieve of Section 2.1 written out, so that no stored value
@@ -77,7 +78,36 @@ def batch():
     print(f"batch: 64 jobs in {time.time() - t:.1f} s")
 
 
+def wide():
+    """Windows of the prime range near 2^50 and just below 2^63, where the GPU takes its exact
+    64-bit residue path.  Large primes hit an interval of a feasible job there with probability
+    about rows * S / p, so each job is placed where a chosen prime q of its window does divide:
+    K = 7# (P = 7, d = 1), q the first prime at or above the window's centre (from the oracle's
+    sieve), and m0 = -K^-1 mod q, so that q divides m K + X for X = 1 + 210 j at m = m0 - j: 39
+    rows of the 1,000 hold a factor q at a column (|X| <= 4000, X = 1 mod 210 is coprime to K).
+    Expected bitmaps and counts: the oracle's direct sieve of every row with every prime of the
+    window.  Only the job's placement uses Python integers; no expected value does."""
+    out = {}
+    for name, centre in (("w50", 1 << 50), ("w63", (1 << 63) - (1 << 23))):
+        t = time.time()
+        q = int(coracle.primes_range(centre, centre + 10**5)[0])
+        K = 210
+        m0 = (-pow(K, -1, q)) % q
+        job = W.Job(7, 1, m0 - 500, 1000, 4000, q + (1 << 22))
+        p_lo, p_hi = q - (1 << 22), q + (1 << 22)
+        ms = coracle.rows(job.d, job.m_start, job.m_inc)
+        bits, counts = coracle.sieve_rows(job.P, job.d, job.sl, ms, p_lo, p_hi, mode=coracle.DIRECT)
+        n_pr = len(coracle.primes_range(p_lo, p_hi))
+        out[f"{name}_job"] = np.array(job.as_tuple(), dtype=np.uint64)
+        out[f"{name}_window"] = np.array([p_lo, p_hi, q, n_pr], dtype=np.uint64)
+        out[f"{name}_bits"] = bits
+        out[f"{name}_counts"] = counts
+        print(f"wide {name}: q={q} m0={m0} primes in window {n_pr} factors {int(counts.sum())} "
+              f"({time.time() - t:.1f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "wide_windows.npz"), **out)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["medium", "paper", "batch"]
+    which = sys.argv[1:] or ["medium", "paper", "batch", "wide"]
     for w in which:
-        {"medium": medium, "paper": paper, "batch": batch}[w]()
+        {"medium": medium, "paper": paper, "batch": batch, "wide": wide}[w]()

@@ -81,7 +81,7 @@ def test_coprime_m_count_13_primorial(paper_values):
     (W.Job(11, 1, 1, 10, 0, 100), -1),               # sl = 0
     (W.Job(11, 1, 1, 10, 2**17, 100), -1),           # sl too large
     (W.Job(11, 1, 1, 10, 10, 1), -1),                # limit < 2
-    (W.Job(11, 1, 1, 10, 10, 2**42), -2),            # limit too large
+    (W.Job(11, 1, 1, 10, 10, 2**63), -2),            # limit too large (primes below 2^63)
     (W.Job(5, 30, 1, 10, 1, 100), -1),               # K = 1, sl >= m_start*K
     (W.Job(7, 6, 1, 10, 35, 100), -1),               # K = 35, sl = 35 >= 1*35
 ])
@@ -176,7 +176,7 @@ def test_chunked_plan():
 
 def test_chunked_range_validation():
     """cs_sieve_chunked_range rejects a zero span and a missing workspace before any device work;
-    chunked plans take limits below 2^42 and reject 2^42."""
+    chunked plans take limits below 2^63 and reject 2^63."""
     import ctypes as C
     L = cs.binding.lib()
     job = cs.binding._cjob(W.Job(61, 6, 1000, 100, 500, 10**8))
@@ -184,8 +184,9 @@ def test_chunked_range_validation():
     assert L.cs_sieve_chunked_range(C.byref(job), None, 1 << 25, 2, 100, None, None, None, 0, None) == -1
     lay = cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42 - 1), 1 << 36)
     assert lay.prime_cap < 3 * 10**9                         # one chunk's table, not pi(2^42)
+    assert cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42), 1 << 36).prime_cap < 3 * 10**9
     with pytest.raises(cs.CsError) as e:
-        cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**42), 1 << 36)
+        cs.plan_chunked(W.Job(61, 6, 1000, 100, 500, 2**63), 1 << 36)
     assert e.value.status == -2
 
 
@@ -214,3 +215,14 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(ct), name
         for f in ct._fields_:
             assert int(got[f"{name}.{f[0]}"]) == getattr(ct, f[0]).offset, f"{name}.{f[0]}"
+
+
+def test_limits_up_to_2_63_are_planned():
+    """Limits from 2^42 to 2^63 - 1 take the 64-bit residue path; planning accepts them, with the
+    level-2 base primes (up to the square root of the limit) in the chunked workspace."""
+    job = W.Job(7, 1, 10**12, 1000, 4000, 2**63 - 1)
+    lay = cs.plan_chunked(job, 1 << 25)
+    assert lay.n_m == 1000 and lay.ws_bytes > 8 * 140_000_000      # base primes up to 3.04e9
+    assert cs.plan(W.Job(7, 1, 10**12, 1000, 4000, 2**42)).n_m == 1000
+    with pytest.raises(cs.CsError):
+        cs.plan(W.SMALL, cs.Tune(wide_log2=19))
