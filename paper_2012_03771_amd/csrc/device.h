@@ -36,6 +36,7 @@ struct JobCtrl {
   uint64_t n_lim;                    // primes <= limit
   uint64_t n_pP;                     // primes <= P
   uint64_t small_lo, small_dense, small_hi;   // prime indices of the small branch
+  uint64_t small_single;             // first small prime above w (at most one mark per row)
   uint64_t tier_lo_idx;              // first prime index of tier 0
   uint64_t tier_idx[kMaxTiers];      // one past the last prime index of tier t
   uint64_t tier_item_base[kMaxTiers + 1];

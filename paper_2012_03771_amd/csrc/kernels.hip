@@ -674,6 +674,9 @@ __global__ void k_prep_bounds(JobDev* jobs) {
   c.small_dense = (dm >= lo) ? upper_index(pr, n, dm) : c.small_lo;
   if (c.small_dense > c.small_hi) c.small_dense = c.small_hi;
   if (c.small_dense < c.small_lo) c.small_dense = c.small_lo;
+  c.small_single = upper_index(pr, n, j.w);
+  if (c.small_single > c.small_hi) c.small_single = c.small_hi;
+  if (c.small_single < c.small_dense) c.small_single = c.small_dense;
   c.tier_lo_idx = upper_index(pr, n, j.tier_lo);
   uint64_t prev = c.tier_lo_idx, items = 0;
   for (uint32_t t = 0; t < j.n_tiers; ++t) {
@@ -764,7 +767,7 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t p) 
 // each copy reads it through its own address space.
 struct SmallArgs {
   const JobDev& j;
-  uint64_t small_dense;
+  uint64_t small_dense, small_single;
   uint32_t* tile;
   uint32_t* cnt;
   const uint32_t* moff;
@@ -773,6 +776,91 @@ struct SmallArgs {
   bool dpat;
   uint32_t lane, wid, nwaves;
 };
+
+// Small primes above w (at most one mark per row), residues below 2^31: prime indices
+// [i_lo, i_hi), one lane per prime.  Between rows the offset s (the X + sl with p | m K + X)
+// steps by -dm k (mod p) for the row gap dm, which is the same for every lane: the multiples
+// g k mod p for g < 16 sit in registers and the gap indexes them (a scalar index), and a gap of
+// 16 or more takes one modular product.  The column lookup runs for every lane without a branch,
+// two rows at a time so that their LDS reads overlap, and row r's marks by the wave accumulate
+// in lane r of one register (rows <= 64), added to the tile's row counts once at the end.
+template <class CT>
+__device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, uint64_t i_lo, uint64_t i_hi,
+                                                   unsigned long long& n_pairs, unsigned long long& n_marks) {
+  const JobDev& j = a.j;
+  uint32_t* tile = a.tile;
+  const uint32_t R = a.R, rw = a.rw, w = a.w, lane = a.lane;
+  const bool dpat = a.dpat;
+  const uint64_t sl = j.sl;
+  const uint32_t P = j.P;
+  const gptr<const uint64_t> primes = gbl(j.primes);
+  const gptr<const uint64_t> kmod = gbl(j.kmod);
+  const gptr<const uint64_t> mkp = gbl(j.mk);
+  const uint32_t moffv = lane < R ? a.moff[lane] : 0u;         // lane r: m offset of row r
+  uint32_t cntv = 0;                                           // lane r: this wave's marks in row r
+  for (uint64_t ib = i_lo; ib < i_hi; ib += blockDim.x) {
+    const uint64_t i = ib + threadIdx.x;
+    bool act = i < i_hi;
+    uint64_t p = 3, k = 0, mk = 0;
+    if (act) { p = primes[i]; k = kmod[i]; mk = mkp[i]; }
+    act = act && k != 0 && !(dpat && p <= P);
+    const double pinv = 1.0 / (double)p;
+    const uint32_t p32 = (uint32_t)p;
+    uint32_t km[16];                                           // g k mod p
+    km[0] = 0;
+#pragma unroll
+    for (int g = 1; g < 16; ++g) {
+      const uint32_t t = km[g - 1] + (uint32_t)k;              // < 2p < 2^32
+      km[g] = t >= p32 ? t - p32 : t;
+    }
+    uint32_t s0;
+    {
+      const uint32_t o0 = __builtin_amdgcn_readfirstlane(moffv);
+      uint64_t rn = mk + mulmod(o0, k, p, pinv);
+      rn = rn >= p ? rn - p : rn;
+      s0 = (uint32_t)sub_mod(mod64(sl, p, pinv), rn, p);
+    }
+    auto advance = [&](uint32_t s, uint32_t dm) -> uint32_t {
+      const uint32_t kd = dm < 16u ? km[dm] : (uint32_t)mulmod(dm, k, p, pinv);
+      const uint32_t t = s - kd;
+      return s >= kd ? t : t + p32;
+    };
+    const uint32_t na = (uint32_t)__popcll(__ballot(act));
+    for (uint32_t r = 0; r < R; r += 2) {
+      const bool two = r + 1 < R;                              // the same for every lane
+      const uint32_t o_r = __builtin_amdgcn_readlane(moffv, r);
+      const uint32_t o_r1 = two ? __builtin_amdgcn_readlane(moffv, r + 1) : o_r;
+      const uint32_t s1 = two ? advance(s0, o_r1 - o_r) : s0;
+      const bool h0 = act && s0 <= w;
+      const bool h1 = two && act && s1 <= w;
+      const uint32_t j0 = h0 ? s0 : 0u, j1 = h1 ? s1 : 0u;
+      const uint64_t e0 = ct_entry(ct, j0 >> 5);
+      const uint64_t e1 = ct_entry(ct, j1 >> 5);
+      const uint32_t b0 = j0 & 31u, b1 = j1 & 31u;
+      const bool ok0 = h0 && (((uint32_t)e0 >> b0) & 1u);
+      const bool ok1 = h1 && (((uint32_t)e1 >> b1) & 1u);
+      if (ok0) {
+        const uint32_t col = (uint32_t)(e0 >> 32) + __popc((uint32_t)e0 & ((1u << b0) - 1u));
+        atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+      }
+      if (ok1) {
+        const uint32_t col = (uint32_t)(e1 >> 32) + __popc((uint32_t)e1 & ((1u << b1) - 1u));
+        atomicOr(&tile[(r + 1) * rw + (col >> 5)], 1u << (col & 31));
+      }
+      const uint32_t t0 = (uint32_t)__popcll(__ballot(ok0));
+      const uint32_t t1 = (uint32_t)__popcll(__ballot(ok1));
+      cntv += lane == r ? t0 : (lane == r + 1 ? t1 : 0u);
+      if (r + 2 < R) {
+        const uint32_t o_r2 = __builtin_amdgcn_readlane(moffv, r + 2);
+        s0 = advance(s1, o_r2 - o_r1);
+      }
+    }
+    if (lane == 0) n_pairs += (unsigned long long)na * R;
+  }
+  if (lane < R && cntv) atomicAdd(&a.cnt[lane], cntv);
+  const uint32_t tot = wave_sum_u32(cntv);
+  if (lane == 0) n_marks += tot;
+}
 
 __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __restrict__ ct,
                                             unsigned long long& n_pairs, unsigned long long& n_marks) {
@@ -821,12 +909,17 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
   // sparse primes: one lane per prime, rows in order, residues stepped by the m gaps
   const uint64_t sp_lo = max(s_lo, min(a.small_dense, s_hi));
   if (j.thr < (1ull << 31)) {
-    // every small prime (<= thr) is below 2^31: residues in 32-bit registers (s + p - k < 2^32,
-    // jj + p < 2^32), and the marks of a row counted by ballots (a lane marks a row at most
-    // once when p > w; the full reduction runs only for a row where some lane marked twice)
-    for (uint64_t ib = sp_lo; ib < s_hi; ib += blockDim.x) {
+    // primes above w: at most one mark per row
+    const uint64_t sg_lo = max(sp_lo, min(a.small_single, s_hi));
+    if (R <= kWave && sg_lo < s_hi) small_single_marks(a, ct, sg_lo, s_hi, n_pairs, n_marks);
+    const uint64_t sp_hi = R <= kWave ? sg_lo : s_hi;
+    // the others: every small prime (<= thr) is below 2^31, so residues sit in 32-bit registers
+    // (s + p - k < 2^32, jj + p < 2^32), and the marks of a row are counted by ballots (a lane
+    // marks a row at most once when p > w; the full reduction runs only for a row where some
+    // lane marked twice)
+    for (uint64_t ib = sp_lo; ib < sp_hi; ib += blockDim.x) {
       const uint64_t i = ib + threadIdx.x;
-      bool act = i < s_hi;
+      bool act = i < sp_hi;
       uint64_t p = 3, k = 0, mk = 0;
       if (act) { p = primes[i]; k = kmod[i]; mk = mkp[i]; }
       act = act && k != 0 && !(dpat && p <= P);
@@ -975,7 +1068,7 @@ __device__ __forceinline__ void small_unit(const JobDev& j, uint64_t local, uint
   }
 
   {
-    SmallArgs a{j, c.small_dense, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
+    SmallArgs a{j, c.small_dense, c.small_single, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
     if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
     else small_marks(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
   }
