@@ -94,7 +94,15 @@ typedef struct cs_tune {
   uint32_t wide_log2;      /* primes p >= 2^wide_log2 take the exact 64-bit residue arithmetic
                               (Montgomery products, integer quotients); 0 = 42, the bound of the
                               fp64 arithmetic; 20..42 move smaller primes onto it (e.g. to check it) */
+  uint32_t kmod;           /* where the large branch takes K mod p and m_start K mod p (Eq. 1) from:
+                              CS_KMOD_AUTO (0) forms them in the large-branch kernel itself for a
+                              single job whose primes all stay below 2^42 (the table then covers only
+                              the primes <= thr, for the small branch), else a table built during
+                              preparation; CS_KMOD_TABLE (1) always the table.  Outputs are identical. */
 } cs_tune;
+
+#define CS_KMOD_AUTO  0u
+#define CS_KMOD_TABLE 1u
 
 #define CS_WALK_CLASSES 0u
 #define CS_WALK_ALL     1u

@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     prp_numbers, surround, surround_ws_bytes, SurroundStats, plan_chunked, sieve_chunked, sieve_chunked_into, sieve_chunked_range,
     WALK_CLASSES, WALK_ALL, DECADES, probe_scatter, PROBE_ATOMIC, PROBE_STORE, PROBE_LDS_ATOMIC,
     sieve_noalloc_into, scratch_bytes, BATCH_AUTO, BATCH_PERSISTENT, BATCH_LANES, batch_ws_bytes, sieve_batch,
-    ORDER_AUTO, ORDER_LARGE_FIRST, ORDER_SMALL_FIRST, ORDER_BY_JOB,
+    ORDER_AUTO, ORDER_LARGE_FIRST, ORDER_SMALL_FIRST, ORDER_BY_JOB, KMOD_AUTO, KMOD_TABLE,
 )

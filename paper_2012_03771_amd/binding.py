@@ -19,6 +19,7 @@ SCATTER_BYTES = 2
 SCATTER_LIST = 3
 WALK_CLASSES = 0
 WALK_ALL = 1
+KMOD_AUTO, KMOD_TABLE = 0, 1
 DECADES = 20
 
 _ERRORS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ERANGE", -3: "CS_ENOMEM", -4: "CS_EDEVICE", -5: "CS_EBUSY"}
@@ -39,7 +40,7 @@ class cs_tune(C.Structure):
     _fields_ = [("thr", C.c_uint64), ("tile_rows", C.c_uint32), ("hits_per_item", C.c_uint32),
                 ("large_mode", C.c_uint32), ("large_blocks", C.c_uint32), ("small_slices", C.c_uint32),
                 ("branches", C.c_uint32), ("scatter", C.c_uint32), ("list_chunks", C.c_uint32),
-                ("walk", C.c_uint32), ("wide_log2", C.c_uint32)]
+                ("walk", C.c_uint32), ("wide_log2", C.c_uint32), ("kmod", C.c_uint32)]
 
 
 class cs_layout(C.Structure):
@@ -92,10 +93,12 @@ class Tune:
     list_chunks: int = 0
     walk: int = WALK_CLASSES
     wide_log2: int = 0
+    kmod: int = KMOD_AUTO
 
     def c(self):
         return cs_tune(self.thr, self.tile_rows, self.hits_per_item, self.large_mode, self.large_blocks,
-                       self.small_slices, self.branches, self.scatter, self.list_chunks, self.walk, self.wide_log2)
+                       self.small_slices, self.branches, self.scatter, self.list_chunks, self.walk, self.wide_log2,
+                       self.kmod)
 
 
 @dataclass

@@ -13,6 +13,7 @@ constexpr uint32_t kSegWords = kSegBits / 32;
 constexpr int kWave = 64;
 constexpr uint64_t kGroupMax = 1ull << 50;   // K-prime products stay below 2^50 (mulmod bound)
 constexpr uint32_t kKmodLdsGroups = 2048;     // K groups staged in LDS by the K mod p kernel (16 KB)
+constexpr uint32_t kFusedGroupsMax = 512;     // primes dividing K for K mod p formed in the large branch
 constexpr uint32_t kDSmall = 4096;            // d <= kDSmall: m -> row from a residue table of d entries
 
 // Prime decades of the per-decade counters: decade i holds the primes 10^i <= p < 10^(i+1)
@@ -67,6 +68,8 @@ struct JobDev {
   uint32_t pre_r0;                   // coprime residues below r0_d
   double inv_d;                      // 1/d, correctly rounded
   uint32_t kmod_cached;              // 1: kmod already holds K mod p (a shared table); only mk is built
+  uint32_t kmod_fused;               // 1: kmod and mk cover only the primes <= thr; the large branch
+                                     // forms K mod p and m_start K mod p of its primes itself
   uint64_t wide_lo;                  // primes >= wide_lo take the exact 64-bit residue arithmetic
   // The large branch walks m of the residue classes mod m_step that can hold rows (bit c of
   // m_classes: m = c mod m_step coprime to it; m_step divides d), one class after the other:

@@ -416,7 +416,9 @@ __global__ void k_lim_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base) 
   uint64_t s = 0;
   for (uint32_t i = 0; i < n_jobs; ++i) {
     base[i] = s;
-    s += jobs[i].ctrl->n_lim;
+    const JobDev& j = jobs[i];
+    const uint64_t n = j.ctrl->n_lim;
+    s += j.kmod_fused ? upper_index(j.primes, n, j.thr) : n;   // fused: the small branch's primes only
   }
   base[n_jobs] = s;
 }
@@ -1162,11 +1164,13 @@ template <bool kLds>
 struct LargeTables {
   const uint2* ct;
   const uint16_t* dp;
+  const double* kg;              // K's prime groups as doubles (K mod p formed in the kernel)
 };
 template <>
 struct LargeTables<false> {
   gptr<const uint2> ct;
   gptr<const uint16_t> dp;
+  gptr<const uint64_t> kg;
 };
 
 // Large-hit scatter variants (template argument kSc): 0 = atomic OR into the bitmap and atomic add
@@ -1403,7 +1407,20 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
   if (u_lo >= u_hi) return;
 
   const uint64_t p = gbl(j.primes)[pi];
-  const uint64_t k1 = gbl(j.kmod)[pi];
+  // K mod p (Eq. 1) and m_start K mod p: from the tables, or formed here as the product of K's
+  // prime groups (each below 2^50) modulo p, lazily reduced, in fp64 with 1/p correctly rounded
+  uint64_t k1, mk;
+  if (!kWide && j.kmod_fused) {
+    const double pd = (double)p, pcr = 1.0 / pd;
+    const uint32_t ng = gbl(j.ctrl)->n_kgroups;
+    double x = 1.0;
+    for (uint32_t t = 0; t < ng; ++t) x = mulmod_f64_lazy(x, (double)T.kg[t], pd, pcr);
+    k1 = (uint64_t)reduce_f64(x, pd, pcr);
+    mk = (uint64_t)mulmod_f64((double)mod64(j.m_start, p, pcr), (double)k1, pd, pcr);
+  } else {
+    k1 = gbl(j.kmod)[pi];
+    mk = gbl(j.mk)[pi];
+  }
   {
     const uint32_t dc = decade_of(p);
     if (dc != lc.cur_dec) {
@@ -1461,7 +1478,6 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     mpos_divmod(stb, d32, inv_d, &bq, &br);
     mpos_divmod(tab, d32, inv_d, &abq, &abr);
   }
-  const uint64_t mk = gbl(j.mk)[pi];
   for (uint32_t cls = 0; cls < s; ++cls) {
     // list scatter: lanes that left the previous class's walk early catch up on the wavefront's
     // chunk state before the next walk appends (every lane reaches this point)
@@ -1579,9 +1595,18 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
     uint16_t* dpl = reinterpret_cast<uint16_t*>(lds + 2 * lds_ct_words);
     for (uint32_t i = threadIdx.x; i < lds_ct_words; i += blockDim.x) ctl[i] = ((const uint2*)gbl(j0.coltab))[i];
     for (uint32_t i = threadIdx.x; i < dpre_n; i += blockDim.x) dpl[i] = gbl(j0.dpre)[i];
-    __syncthreads();
     T.ct = ctl;                                      // this variant runs only when the table fits
     T.dp = dpl;
+    T.kg = nullptr;
+    if (j0.kmod_fused && !kWide) {
+      // after the column and residue tables, 8-byte aligned (the plan sized the region)
+      const uint32_t off = ((2 * lds_ct_words + (dpre_n + 1) / 2) + 1) & ~1u;
+      double* kgl = reinterpret_cast<double*>(lds + off);
+      const uint32_t ng = gbl(j0.ctrl)->n_kgroups;
+      for (uint32_t i = threadIdx.x; i < ng; i += blockDim.x) kgl[i] = (double)gbl(j0.kgroups)[i];
+      T.kg = kgl;
+    }
+    __syncthreads();
   }
   LaneCount lc;
   lane_count_init(lc);
@@ -1595,6 +1620,7 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
       while (ji + 1 < n_jobs && job_item_base[ji + 1] <= item) ++ji;
       T.ct = gbl(jobs[ji].coltab);
       T.dp = gbl(jobs[ji].dpre);
+      T.kg = gbl((const uint64_t*)jobs[ji].kgroups);
     }
     if (ji != ji_last) t_last = 0;
     ji_last = ji;
@@ -1772,6 +1798,7 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
     LargeTables<true> T;
     T.ct = ctl;
     T.dp = dpl;
+    T.kg = nullptr;                                  // batch jobs read K mod p from their tables
     const auto& c = *gbl(j.ctrl);
     const uint64_t n_items = c.n_items;
     const uint64_t first = local * items_per_task;

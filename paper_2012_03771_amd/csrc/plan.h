@@ -60,6 +60,8 @@ struct Plan {
   bool scatter_bytes = false;       // large hits via byte counters (see CS_SCATTER_BYTES)
   double cell_max = 0;              // bound on large-prime hits of one (row, column)
   bool scatter_list = false;        // large hits via the list scatter (see CS_SCATTER_LIST)
+  bool kmod_fused = false;          // the large branch forms K mod p itself; the table stops at thr
+  uint32_t kg_lds_off = 0;          // large-branch LDS: byte offset of the K groups (fused, LDS tables)
   uint64_t list_chunks = 0;         // pool capacity in chunks
   uint32_t n_bkt = 0, bkt_rows = 0; // row buckets of the list scatter (bkt_rows a power of two)
   uint32_t cell_shift = 0, super_shift = 0;

@@ -86,6 +86,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (scatter > CS_SCATTER_LIST) return CS_EINVAL;
   if (tune && tune->walk > CS_WALK_ALL) return CS_EINVAL;
   if (tune && tune->wide_log2 && (tune->wide_log2 < 20 || tune->wide_log2 > 42)) return CS_EINVAL;
+  if (tune && tune->kmod > CS_KMOD_TABLE) return CS_EINVAL;
 
   Plan& pl = *out;
   pl.job = j;
@@ -152,7 +153,7 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
   uint64_t thr = tune && tune->thr ? tune->thr : 0;
   if (!thr) {
-    double cm = mode == CS_LARGE_THREE_GAP ? 20.0
+    double cm = mode == CS_LARGE_THREE_GAP ? 30.0
                                            : (pl.n_m ? 2.5 * (double)j.m_inc / (double)pl.n_m : 2.5);
     thr = (uint64_t)(cm * (double)pl.S);
   }
@@ -212,6 +213,16 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     const uint32_t dp_b = (uint32_t)pl.dpre.size() * 2u;
     pl.large_lds_ct_words = ct_b <= 16384u ? pl.ct_words : 0u;
     pl.large_lds_bytes = (pl.large_lds_ct_words ? ct_b : 0u) + ((dp_b + 3u) & ~3u);
+    // K mod p formed in the large branch: a single job with its own tables, no chunks and no prime
+    // on the 64-bit path; K's groups (at most one per prime dividing K) as doubles in its LDS
+    pl.kmod_fused = own_primes && own_kmod && bytes_ok && span == 0 &&
+                    (!tune || tune->kmod == CS_KMOD_AUTO) && std::max<uint64_t>(j.limit, j.P) < pl.wide_lo &&
+                    pl.kq.size() <= kFusedGroupsMax;
+    pl.kg_lds_off = 0;
+    if (pl.kmod_fused && pl.large_lds_ct_words) {
+      pl.kg_lds_off = (pl.large_lds_bytes + 7u) & ~7u;
+      pl.large_lds_bytes = pl.kg_lds_off + 8u * (uint32_t)std::max<size_t>(pl.kq.size(), 1);
+    }
   }
 
   pl.hits_per_item = tune && tune->hits_per_item ? tune->hits_per_item
@@ -247,8 +258,10 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   L.seg_count = take(ns * 4ull);
   L.seg_off = take(ns * 8ull);
   L.primes = take(own_primes ? pl.cap * 8ull : 0);
-  L.kmod = take(own_kmod ? cap_lim * 8ull : 0);
-  L.mk = take(cap_lim * 8ull);
+  // with K mod p formed in the large branch the tables hold the primes <= thr only
+  const uint64_t cap_km = pl.kmod_fused ? std::min<uint64_t>(cap_lim, pi_upper(pl.thr)) : cap_lim;
+  L.kmod = take(own_kmod ? cap_km * 8ull : 0);
+  L.mk = take(cap_km * 8ull);
   L.row_of = take(j.m_inc * 4ull);
   L.m_off = take(std::max<uint64_t>(pl.n_m, 1) * 4ull);
   L.row_blk = take(((j.m_inc + 1023) / 1024) * 4ull);
@@ -415,6 +428,7 @@ JobDev make_jobdev(const Plan& pl, uint8_t* ws, const uint64_t* primes, const ui
   jd.dense_max = pl.dense_max;
   jd.prime_cap = pl.cap;
   jd.wide_lo = pl.wide_lo;
+  jd.kmod_fused = pl.kmod_fused ? 1u : 0u;
   jd.primes = primes;
   jd.n_primes = n_primes;
   const WsLayout& L = pl.ws;

@@ -41,12 +41,13 @@ def test_chunked_equals_whole(job, mode):
 
 def test_chunked_paper_scale():
     """953#/210, primes to 1e10, in five chunks of 2^31 integers (a workspace of 5.3 GiB instead
-    of 13.6 GiB): the same bitmap and counts as the whole sieve."""
+    of the 13.6 GiB of the whole sieve with K mod p tables for every prime): the same bitmap and
+    counts as the whole sieve."""
     job = W.PAPER_SCALE
     tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
     _say("chunked paper scale")
     lay = cs.plan_chunked(job, 1 << 31, tune)
-    assert lay.ws_bytes < cs.plan(job, tune).ws_bytes / 2
+    assert lay.ws_bytes < cs.plan(job, cs.Tune(large_mode=cs.LARGE_THREE_GAP, kmod=cs.KMOD_TABLE)).ws_bytes / 2
     b0, c0, ws0 = cs.sieve(job, tune)
     h0, k0 = b0.cpu(), c0.cpu()
     n0 = cs.diag_read(ws0).n_primes

@@ -41,8 +41,11 @@ MODES = [cs.Tune(), cs.Tune(large_mode=cs.LARGE_THREE_GAP),
          cs.Tune(large_mode=cs.LARGE_THREE_GAP, scatter=cs.SCATTER_LIST),
          cs.Tune(large_mode=cs.LARGE_G, scatter=cs.SCATTER_LIST),
          cs.Tune(large_mode=cs.LARGE_G, walk=cs.WALK_ALL),
-         cs.Tune(large_mode=cs.LARGE_THREE_GAP, walk=cs.WALK_ALL)]
-MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_list", "g_list", "g_walk_all", "three_gap_walk_all"]
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, walk=cs.WALK_ALL),
+         cs.Tune(large_mode=cs.LARGE_G, kmod=cs.KMOD_TABLE),
+         cs.Tune(large_mode=cs.LARGE_THREE_GAP, kmod=cs.KMOD_TABLE)]
+MODE_IDS = ["g", "three_gap", "three_gap_atomic", "three_gap_list", "g_list", "g_walk_all", "three_gap_walk_all",
+            "g_kmod_table", "three_gap_kmod_table"]
 
 
 @pytest.mark.parametrize("tune", MODES, ids=MODE_IDS)

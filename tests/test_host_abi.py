@@ -163,7 +163,7 @@ def test_chunked_plan():
     """cs_plan_chunked: spans must be segment-aligned, at least 2^25 and above P; a span above
     the limit is the whole sieve; smaller spans hold one chunk's tables."""
     job = W.PAPER_SCALE
-    whole = cs.plan(job)
+    whole = cs.plan(job, cs.Tune(kmod=cs.KMOD_TABLE))     # chunks always read K mod p from tables
     for bad in (0, (1 << 25) + 1, 1 << 24, 3 << 19):
         with pytest.raises(cs.CsError):
             cs.plan_chunked(job, bad)
@@ -226,3 +226,15 @@ def test_limits_up_to_2_63_are_planned():
     assert cs.plan(W.Job(7, 1, 10**12, 1000, 4000, 2**42)).n_m == 1000
     with pytest.raises(cs.CsError):
         cs.plan(W.SMALL, cs.Tune(wide_log2=19))
+
+
+def test_kmod_formed_in_the_large_branch_by_default():
+    """A single job below 2^42 forms K mod p in the large-branch kernel, so its K mod p tables stop
+    at the threshold; CS_KMOD_TABLE keeps them for every prime, and other values are rejected."""
+    job = W.PAPER_SCALE
+    fused = cs.plan(job, cs.Tune(large_mode=cs.LARGE_THREE_GAP))
+    table = cs.plan(job, cs.Tune(large_mode=cs.LARGE_THREE_GAP, kmod=cs.KMOD_TABLE))
+    # two tables of 8 bytes per prime up to the limit, against up to thr
+    assert 2 * 8 * 454_000_000 < table.ws_bytes - fused.ws_bytes < 2 * 8 * 456_000_000
+    with pytest.raises(cs.CsError):
+        cs.plan(job, cs.Tune(kmod=2))
