@@ -42,6 +42,24 @@ CS_HD double recip(double x) {
 #endif
 }
 
+// 1/x for 1 <= x < 2^52 with one Newton step: a relative error below 2^-47 (the seed's error
+// squared, about 2^-48.8, plus the rounding of the step), three instructions.  For integers
+// y, x < 2^42 the product y * recip1(x) is then within (y / x) 2^-47 < 1/x of y/x, whose
+// fractional part is 0 or at least 1/x: its floor is exact unless x divides y, when it may be
+// one low.  The host build, which only serves tests, moves the correctly rounded quotient by
+// 2^-48 of its value in either direction, the size of the device's error.
+CS_HD double recip1(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  const double r = 1.0 / x;
+  const uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull;   // direction by a hash of the argument
+  return (h >> 63) ? r * (1.0 - 0x1p-48) : r * (1.0 + 0x1p-48);
+#endif
+}
+
 // 1/x in fp32 to within one unit in the last place (the device's hardware reciprocal).  The host
 // build, which only serves tests, perturbs the correctly rounded quotient by one unit in either
 // direction so that callers are checked against the worst error they allow.
@@ -147,7 +165,7 @@ CS_HD uint64_t modinv(uint64_t k, uint64_t p) {
   double a = (double)p, b = (double)k;
   double s0 = 0.0, s1 = 1.0;          // s_i * k == r_i (mod p)
   for (int it = 0; it < 128 && b != 0.0 && a >= 1048576.0; ++it) {
-    double inv = recip(b);
+    double inv = recip1(b);
     double q = floor(a * inv);                 // a < 2^42: exact or one low (as in g_offset)
     double r = fma(-q, b, a);
     if (r >= b) { r -= b; q += 1.0; }
@@ -182,25 +200,24 @@ CS_HD double g_offset(double p, double K, double L, double width, int* levels_ou
   int par = 0, lv = 0;
   double off = -1.0;
   for (; lv < max_levels; ++lv) {
-    if (L == 0.0) { off = 0.0; break; }                       // (a)
-    const bool mir = K + K >= p;                               // (d)
+    // (a) needs no test of its own: with L = 0 the mirror is skipped (it needs 0 outside
+    // [L, R]) and (c) finds the multiple 0 of K, offset 0
+    const bool mir = K + K >= p && L != 0.0;                   // (d)
     L = mir ? p - L - width : L;
     K = mir ? p - K : K;
     par ^= mir ? 1 : 0;
-    // L, p < 2^42 and inv within 1.5 units in the last place: L*inv is within (L/K) 2^-51 < 1/K
-    // of L/K, whose fractional part is 0 or at least 1/K, so its floor is exact unless K divides
-    // L, when it may be one low.  The remainders below are therefore in [0, K], K standing for 0:
-    // both give up = 0, and p mod K is never 0 or K (gcd(p, K) = 1, K > 1 here since K = 1
-    // always ends in (c)).
-    const double inv = recip(K);
+    // L, p < 2^42 and inv = recip1(K): floor(L*inv) is exact unless K divides L, when it may be
+    // one low, so rem lies in [0, K], K standing for 0 (both give up = 0).  gcd(p, K) = 1 at
+    // every level ((d) and (e) keep it) and K > 1 here (K = 1 always ends in (c)), so K never
+    // divides p: p mod K is exact and in [1, K - 1], and the new K is in [1, K - 1].
+    const double inv = recip1(K);
     const double rem = fma(-floor(L * inv), K, L);             // L mod K, or K for 0
     const double up = rem == 0.0 ? 0.0 : K - rem;              // ceil(L/K)*K - L
     if (up <= width) { off = up; break; }                      // (c)
-    const double pm = fma(-floor(p * inv), K, p);              // p mod K, in (0, K)
+    const double pm = fma(-floor(p * inv), K, p);              // p mod K
     p = K;                                                      // (e)
-    K = (pm == 0.0) ? 0.0 : K - pm;
+    K = K - pm;
     L = rem;
-    if (K == 0.0) { off = -1.0; break; }                       // only if gcd(p, K) > 1
   }
   if (levels_out) *levels_out = lv + 1;
   if (off < 0.0) return -1.0;
@@ -275,10 +292,10 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
   int it = 0;
   if (b > wd) {
     for (; it < 160; ++it) {
-      inv = recip(b);
-      double q = floor(a * inv);
-      r = fma(-q, b, a);                      // a < 2^42: exact or one low
-      if (r >= b) { r -= b; q += 1.0; }
+      // b > w >= 1 and gcd(a, b) = 1, so b does not divide a and the floor is exact (recip1)
+      inv = recip1(b);
+      const double q = floor(a * inv);
+      r = fma(-q, b, a);
       sn = fma(-q, sb, sa);                   // s_{i+1}, same side as s_{i-1}
       if (r <= wd) break;                     // the first remainder at or below w
       a = b; b = r; sa = sb; sb = sn;
@@ -291,7 +308,7 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
     t1 = 1.0;
     v1 = b;
     pos1 = true;
-    inv = recip(b);
+    inv = recip1(b);                          // (b may be 1 here: the correction stays)
     double q = floor(a * inv);
     r = fma(-q, b, a);
     if (r >= b) { r -= b; q += 1.0; }
@@ -302,7 +319,7 @@ CS_HD int three_gap_euclid(uint64_t p, uint64_t k, uint64_t w, gaps3* g, uint64_
     tg_side(a, b, inv, sa, sb, wd, &t1, &v1);
     // one more exact step: (r_i, r_{i+1}) gives the other side
     a = b; b = r; sa = sb; sb = sn;
-    inv = recip(b);
+    inv = recip1(b);
     double q = floor(a * inv);
     r = fma(-q, b, a);
     if (r >= b) { r -= b; q += 1.0; }

@@ -1413,9 +1413,15 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
   if (!kWide && j.kmod_fused) {
     const double pd = (double)p, pcr = 1.0 / pd;
     const uint32_t ng = gbl(j.ctrl)->n_kgroups;
-    double x = 1.0;
-    for (uint32_t t = 0; t < ng; ++t) x = mulmod_f64_lazy(x, (double)T.kg[t], pd, pcr);
-    k1 = (uint64_t)reduce_f64(x, pd, pcr);
+    // two interleaved chains (even and odd groups), joined by one more product
+    double x0 = 1.0, x1 = 1.0;
+    uint32_t t = 0;
+    for (; t + 2 <= ng; t += 2) {
+      x0 = mulmod_f64_lazy(x0, (double)T.kg[t], pd, pcr);
+      x1 = mulmod_f64_lazy(x1, (double)T.kg[t + 1], pd, pcr);
+    }
+    if (t < ng) x0 = mulmod_f64_lazy(x0, (double)T.kg[t], pd, pcr);
+    k1 = (uint64_t)reduce_f64(mulmod_f64_lazy(x0, reduce_f64(x1, pd, pcr), pd, pcr), pd, pcr);
     mk = (uint64_t)mulmod_f64((double)mod64(j.m_start, p, pcr), (double)k1, pd, pcr);
   } else {
     k1 = gbl(j.kmod)[pi];
