@@ -237,6 +237,19 @@ CS_HD uint64_t next_hit(uint64_t p, uint64_t k, uint64_t kinv, double pinv, uint
   return mulmod(v, kinv, p, pinv);
 }
 
+// next_hit with every value held as a double (all are integers below 2^42): returns t (0.0 on an
+// internal failure) and writes the residue reached.  The multiplier is v * k^-1 mod p by
+// mulmod_f64, which a reciprocal of p within an ulp serves here: the product v k^-1 < 2^84 over p
+// is below 2^42, so h * pinv is within 2^-9 of h / p.
+CS_HD double next_hit_d(double p, double k, double kinv, double pinv, double r, double w, double* r_new,
+                        int* levels) {
+  const double L = p - r;                   // t*k mod p must lie in [p - r, p - r + w]
+  const double off = g_offset(p, k, L, w, levels);
+  if (off < 0.0) return 0.0;
+  *r_new = off;                             // (r + v) - p
+  return mulmod_f64(L + off, kinv, p, pinv);
+}
+
 // Return-time constants of the rotation by k mod p to the window [0, w] (three-gap theorem):
 // ta = least t >= 1 with t*k mod p in [1, w], a = that value;
 // tb = least t >= 1 with t*k mod p in [p - w, p - 1], b = p - that value.

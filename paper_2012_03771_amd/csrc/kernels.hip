@@ -1141,6 +1141,17 @@ __device__ __forceinline__ void mpos_divmod(uint64_t x, uint32_t d, double inv_d
   *r = (uint32_t)rr;
 }
 
+// The same for a double holding an integer below 2^52.
+__device__ __forceinline__ void mpos_divmod_d(double xd, uint32_t d, double inv_d, uint32_t* q, uint32_t* r) {
+  const double dd = (double)d;
+  double qq = floor(xd * inv_d);
+  double rr = fma(-qq, dd, xd);
+  if (rr < 0.0) { rr += dd; qq -= 1.0; }
+  if (rr >= dd) { rr -= dd; qq += 1.0; }
+  *q = (uint32_t)qq;
+  *r = (uint32_t)rr;
+}
+
 __device__ __forceinline__ void mpos_add(MPos& s, uint32_t tq, uint32_t tr, uint32_t d) {
   s.rd += tr;
   s.dq += tq;
@@ -1509,8 +1520,38 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     MPos mp = {0, 0};
     if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
 
-    if (kG) {
-      // one solve of Eq. 3 per hit
+    if (kG && !kWide) {
+      // one solve of Eq. 3 per hit; every value an integer below 2^45 held as a double
+      const double pd = (double)p, kd = (double)k, kinvd = (double)kinv, wd = (double)w, sd = (double)s;
+      const double ohd = (double)o_hi;
+      double rd = (double)r, od = (double)o;
+      while (true) {
+        if (rd > wd) {
+          int lv = 0;
+          double rn = 0.0;
+          const double t = next_hit_d(pd, kd, kinvd, pinv, rd, wd, &rn, &lv);
+          ++lc.calls;
+          lc.levels += (unsigned)lv;
+          if (t == 0.0) { lc.err |= E_SOLVE; break; }
+          od = fma(sd, t, od);
+          if (od >= ohd) break;
+          rd = rn;
+          if (d_small) {
+            uint32_t tq, tr;
+            mpos_divmod_d(sd * t, d32, inv_d, &tq, &tr);
+            mpos_add(mp, tq, tr, d32);
+          }
+        }
+        ++lc.raw;
+        record_hit<kLds, kSc>(hc, T, (uint64_t)(uint32_t)od, mp, (uint32_t)(wd - rd), lc.useful, lreg, s_sup);
+        od += sd;
+        if (od >= ohd) break;
+        if (d_small) mpos_add(mp, 0, s, d32);      // s <= d: one correction suffices
+        rd += kd;
+        rd = rd >= pd ? rd - pd : rd;
+      }
+    } else if (kG) {
+      // one solve of Eq. 3 per hit (64-bit primes)
       while (true) {
         if (r > w) {
           int lv = 0;

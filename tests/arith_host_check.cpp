@@ -176,6 +176,26 @@ int main(int argc, char** argv) {
       o += 1; r += k; if (r >= p) r -= p;
     }
     if (!bad && got != want) bad = fail("driver", p, k, w, m_inc);
+    // G per hit with every value a double (the one-solve-per-hit walk of the kernels), the
+    // reciprocal of p within an ulp as on the device
+    {
+      std::vector<uint64_t> gotd;
+      const double pd = (double)p, kd = (double)k, kinvd = (double)kinv, wd = (double)w;
+      const double pr = cs::recip(pd);
+      double od = 0.0, rd = (double)r0;
+      while (od < (double)m_inc) {
+        if (rd > wd) {
+          double rn; int lv;
+          const double t = cs::next_hit_d(pd, kd, kinvd, pr, rd, wd, &rn, &lv);
+          if (t == 0.0) { bad = fail("next_hit_d0", p, k, (uint64_t)rd, w); break; }
+          od += t; if (od >= (double)m_inc) break;
+          rd = rn;
+        }
+        gotd.push_back((uint64_t)od);
+        od += 1.0; rd += kd; if (rd >= pd) rd -= pd;
+      }
+      if (!bad && gotd != want) bad = fail("driver_d", p, k, w, m_inc);
+    }
     // three-gap
     cs::gaps3 g; int lv3;
     if (!cs::three_gap_setup(p, k, kinv, pinv, w, &g, &lv3)) { bad = fail("3gap_setup", p, k, w, 0); break; }
@@ -193,6 +213,21 @@ int main(int argc, char** argv) {
       else { o += g.ta + g.tb; r = r + g.a - g.b; }
     }
     if (!bad && got3 != want) bad = fail("three_gap", p, k, w, m_inc);
+  }
+  // next_hit_d against next_hit for primes up to 2^42
+  for (int i = 0; i < 200000 && !bad; ++i) {
+    const uint64_t w = 1 + rng() % 200000;
+    uint64_t p;
+    do { p = (rng() >> (22 + rng() % 20)) | 1; } while (p <= 2 * w + 1 || p >= (1ull << 42) || !is_prime_mr(p));
+    const uint64_t k = 1 + rng() % (p - 1);
+    const uint64_t kinv = cs::modinv(k, p);
+    const uint64_t r = w + 1 + rng() % (p - w - 1);
+    uint64_t rn; int lv;
+    const uint64_t t = cs::next_hit(p, k, kinv, 1.0 / (double)p, r, w, &rn, &lv);
+    double rnd; int lvd;
+    const double td = cs::next_hit_d((double)p, (double)k, (double)kinv, cs::recip((double)p), (double)r, (double)w,
+                                     &rnd, &lvd);
+    if (t == 0 || (uint64_t)td != t || (uint64_t)rnd != rn) bad = fail("next_hit_d", p, k, r, w);
   }
   // one-pass Euclid: inverse and three-gap constants against brute force and the G-based setup
   for (int i = 0; i < 20000 && !bad; ++i) {
