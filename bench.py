@@ -326,7 +326,7 @@ def _kernel_profile(mode):
         return None
     rec = json.load(open(path)).get(mode)
     m = hashlib.sha256()
-    for f in ("kernels.hip", "arith.h", "device.h"):
+    for f in ("kernels.hip", "arith.h", "arith_wide.h", "device.h"):
         m.update(open(os.path.join(ROOT, "paper_2012_03771_amd", "csrc", f), "rb").read())
     if not rec or rec.get("hash") != m.hexdigest()[:16]:
         return None

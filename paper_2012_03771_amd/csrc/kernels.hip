@@ -1585,8 +1585,13 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
         uint64_t rn;
         int lv = 0;
         uint64_t tstep;
-        if constexpr (kWide) tstep = next_hit64(mt, k, kinv, r, w, &rn, &lv);
-        else tstep = next_hit(p, k, kinv, pinv, r, w, &rn, &lv);
+        if constexpr (kWide) {
+          tstep = next_hit64(mt, k, kinv, r, w, &rn, &lv);
+        } else {
+          double rnd = 0.0;
+          tstep = (uint64_t)next_hit_d((double)p, (double)k, (double)kinv, pinv, (double)r, (double)w, &rnd, &lv);
+          rn = (uint64_t)rnd;
+        }
         ++lc.calls;
         lc.levels += (unsigned)lv;
         if (tstep == 0) { lc.err |= E_SOLVE; break; }
