@@ -53,9 +53,12 @@ def _args():
     ap.add_argument("--no-serve", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--serve-jobs", type=int, default=512)
     ap.add_argument("--serve-warmup", type=int, default=32)
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
+                    help="loads (fractions of the saturated throughput) of the served legs; 0.8 is the headline")
     ap.add_argument("--serve-chunks", type=int, default=1,
-                    help="large-prime chunks per served job (1 measured best on this mix: capacity 184 jobs/s, "
-                         "p50 35 ms, p99 142 ms at 0.8x; 4 chunks: 156 jobs/s, 48 ms, 193 ms)")
+                    help="large-prime chunks per served job (cs_server_config.chunks; 1 measured best on this "
+                         "mix: p50 24 / p99 141 ms at 0.8 load, against 28 / 271 ms with about 2 ms of estimated "
+                         "device time per chunk)")
     ap.add_argument("--prp-rows", type=int, default=16384,
                     help="rows of the sieved job searched for their surrounding probable primes (0: skip)")
     ap.add_argument("--no-atomic-probe", action="store_true",
@@ -465,6 +468,30 @@ def _server_capacity(cs, W, mode, n_jobs=128, chunks=1):
     return n_jobs / span
 
 
+def _alone_times(cs, torch, W, mode, n_jobs):
+    """Device time of each of the first n_jobs jobs of the served stream run alone (cs_sieve on the
+    current stream, HIP events around it): the service times queueing adds to."""
+    import numpy as np
+    _, jobs = W.poisson_arrivals(n_jobs, 1.0, seed=1)
+    s = torch.cuda.current_stream()
+    out = []
+    for job in jobs:
+        tune = cs.Tune(large_mode=mode)
+        lay, bm, ct, ws = cs.binding.alloc_outputs(job, tune)
+        cs.sieve_into(job, bm, ct, ws, tune, s)                       # warm-up (first use of the sizes)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        cs.sieve_into(job, bm, ct, ws, tune, s)
+        e1.record(s)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+        del bm, ct, ws
+    torch.cuda.empty_cache()
+    a = np.array(out)
+    return {"jobs": n_jobs, "p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean()), "max_ms": float(a.max())}
+
+
 def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm, chunks=1):
     """Poisson arrivals of jobs from the mixed-batch distribution into the continuous-batching
     server (64 GB budget); latency = completion - arrival."""
@@ -496,7 +523,7 @@ def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm, chunks=1):
     span = t_end - t_first
     lat = np.array(lat)
     return {"workload": f"{n_jobs} jobs (+{n_warm} warm-up) from the mixed-batch distribution, Poisson arrivals "
-                        "at 0.8x the server's saturated throughput, 64 GB admission budget, 32 slots, "
+                        f"at {rate:.1f} jobs/s, 64 GB admission budget, 32 slots, "
                         f"{chunks} large-prime chunk(s) per job",
             "arrival_rate_per_s": rate, "jobs_per_s": n_jobs / span, "factors_per_s": factors / span,
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
@@ -686,12 +713,24 @@ def main():
     if not args.no_serve:
         print("# serve capacity ...", file=sys.stderr, flush=True)
         cap = _server_capacity(cs, W, mode_b, chunks=args.serve_chunks)
-        rate = 0.8 * cap
-        print(f"# serve leg at {rate:.1f} jobs/s (capacity {cap:.1f}) ...", file=sys.stderr, flush=True)
-        out["serve"] = _serve_leg(cs, torch, W, mode_b, rate, args.serve_jobs, args.serve_warmup, args.serve_chunks)
-        out["serve"]["capacity_jobs_per_s"] = cap
-        print(f"# serve p50 {out['serve']['p50_latency_ms']:.1f} ms p99 {out['serve']['p99_latency_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
+        loads = sorted({float(x) for x in args.serve_loads.split(",")} | {0.8})
+        curve = []
+        for load in loads:
+            rate = load * cap
+            print(f"# serve leg at {rate:.1f} jobs/s ({load} of capacity {cap:.1f}) ...", file=sys.stderr, flush=True)
+            leg = _serve_leg(cs, torch, W, mode_b, rate, args.serve_jobs, args.serve_warmup, args.serve_chunks)
+            leg["load"] = load
+            leg["capacity_jobs_per_s"] = cap
+            print(f"# serve {load}: p50 {leg['p50_latency_ms']:.1f} ms p99 {leg['p99_latency_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
+            if load == 0.8:
+                out["serve"] = leg
+            curve.append({k: leg[k] for k in ("load", "arrival_rate_per_s", "jobs_per_s", "p50_latency_ms",
+                                             "p99_latency_ms", "mean_latency_ms", "iterations")})
+        out["serve"]["curve"] = curve
+        out["serve"]["alone"] = _alone_times(cs, torch, W, mode_b, 256)
+        print(f"# served jobs alone: p50 {out['serve']['alone']['p50_ms']:.2f} ms p99 "
+              f"{out['serve']['alone']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = _cpu_baseline(job, args.cpu_rows, gpu_counts)

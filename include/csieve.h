@@ -418,8 +418,9 @@ cs_status cs_batch_destroy(cs_batch* b);
  * max_limit) and K mod p tables (per (P, d), reused by any later job whose limit they cover)
  * resident, admits queued jobs in arrival order as slots and budget allow, and runs
  * iterations on its own stream: one iteration is one fused launch sequence that advances every
- * active job by one prime-range chunk (small primes first, then `chunks` ranges of large
- * primes).  Jobs that arrive while others run join the next iteration.  Each job's result is
+ * active job by one prime-range chunk (`chunks` ranges of large primes of about equal prime
+ * count, the first of them together with the small primes, whose branch runs on a second stream
+ * beside the large one).  Jobs that arrive while others run join the next iteration.  Each job's result is
  * bit-identical to cs_sieve of that job alone.  Outputs live in the server's memory until
  * released.  A server handle may be used from several host threads.
  * ------------------------------------------------------------------------------------------ */
@@ -429,7 +430,8 @@ typedef struct cs_server_config {
   uint64_t budget_bytes;   /* device bytes for per-job tables, K mod p tables and outputs */
   uint64_t max_limit;      /* largest max(limit, P) accepted; the resident prime table reaches it */
   uint32_t max_active;     /* jobs in flight at once (slots) */
-  uint32_t chunks;         /* large-prime chunks per job (0 = 4) */
+  uint32_t chunks;         /* large-prime chunks per job, one per iteration (0 = 1: every job in one
+                              iteration, measured best for latency on mixed jobs) */
   cs_tune tune;            /* applied to every job */
 } cs_server_config;
 

@@ -493,7 +493,7 @@ class Batch:
 class Server:
     """Continuous-batching sieve server (native loop in libcsieve; this class only marshals)."""
 
-    def __init__(self, budget_bytes: int, max_limit: int, max_active: int = 16, chunks: int = 4,
+    def __init__(self, budget_bytes: int, max_limit: int, max_active: int = 16, chunks: int = 1,
                  tune: Tune | None = None):
         cfg = cs_server_config(budget_bytes, max_limit, max_active, chunks, (tune or Tune()).c())
         h = C.c_void_p()

@@ -1,8 +1,9 @@
 // Serving: a request loop that admits sieve jobs by device memory, keeps the prime table and
 // per-(P, d) K mod p tables resident, and runs continuous batching.
 //
-// Each job is split into prime-range chunks: chunk 0 holds the small primes (p <= thr) and
-// chunks 1..C split the large primes into ranges of about equal prime count.  One iteration
+// Each job is split into prime-range chunks: the large primes in C ranges of about equal prime
+// count, the first of which also takes the small primes (p <= thr), whose branch runs on a second
+// stream beside the large one.  One iteration
 // of the server is one fused launch sequence that advances every active job by one chunk
 // (OR-ing and adding into its outputs; Section 3's marks are order independent).  Jobs that
 // arrive while others run are admitted at the next iteration when a slot and memory are free,
@@ -232,19 +233,18 @@ bool admit(cs_server* s, uint64_t ticket) {
   J.jd.kmod_cached = E.ready ? 1u : 0u;
   J.jd.bitmap = reinterpret_cast<uint32_t*>(s->arena_mem + off_o);
   J.jd.counts = reinterpret_cast<uint32_t*>(s->arena_mem + off_o + a256(pl.n_m * (uint64_t)pl.row_words * 4ull));
-  // chunks: small primes first, then the large primes in ranges of about equal prime count
+  // chunks: the large primes in ranges of about equal prime count, the small primes with the first
   J.bounds.clear();
   J.bounds.push_back(1);
   const uint64_t thr = std::min<uint64_t>(pl.thr, J.job.limit);
-  J.bounds.push_back(thr);
   if (J.job.limit > thr) {
     const uint32_t C = std::max<uint32_t>(1, s->cfg.chunks);
     for (uint32_t c = 1; c < C; ++c) {
       const uint64_t v = prime_quantile(thr, J.job.limit, (double)c / C);
-      if (v > J.bounds.back() && v < J.job.limit) J.bounds.push_back(v);
+      if (v > J.bounds.back() && v > thr && v < J.job.limit) J.bounds.push_back(v);
     }
-    J.bounds.push_back(J.job.limit);
   }
+  J.bounds.push_back(J.job.limit);
   J.chunk = 0;
   J.state = S_ACTIVE;
   J.prepped = false;
@@ -406,7 +406,6 @@ extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** o
   cs_server* s = new (std::nothrow) cs_server();
   if (!s) return CS_ENOMEM;
   s->cfg = *cfg;
-  if (s->cfg.chunks == 0) s->cfg.chunks = 4;
   if (hipGetDevice(&s->device) != hipSuccess) { delete s; return CS_EDEVICE; }
   s->n_cu = device_cu_count();
   // fixed memory: prime table up to max_limit, descriptors, prefix arrays, counters
