@@ -623,7 +623,9 @@ def main():
     # over the kernel's own duration (HIP events around the launch, on its stream)
     from paper_2012_03771_amd import roofline as RL
     t_large = (diag_ph.large_kernel_ms or phases["large"]) / 1e3
-    ops = RL.large_branch_ops(diag_ph, args.mode == "three_gap")
+    # a single job below 2^42 forms K mod p of its large primes in the kernel (cs_tune.kmod AUTO)
+    groups = RL.kmod_groups(job.P, job.d) if max(job.limit, job.P) < 2**42 else 0
+    ops = RL.large_branch_ops(diag_ph, args.mode == "three_gap", groups)
     roof = {"bound": "alu", "kernel": "k_large", "achieved": ops / t_large / 1e12, "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (VALU lane-ops)", "frac": ops / t_large / ALU_PEAK_OPS,
             "traffic": args.traffic_gb if args.traffic_gb is not None else _kernel_traffic(args.mode),
@@ -632,7 +634,8 @@ def main():
                               "not measured by this run; null when the sources changed since",
             "ops_per_launch": ops, "op_units": {"g_levels": diag_ph.g_levels, "g_calls": diag_ph.g_calls,
                                                 "raw_hits": diag_ph.large_raw_hits,
-                                                "large_primes": diag_ph.large_primes},
+                                                "large_primes": diag_ph.large_primes,
+                                                "kmod_groups_formed": groups},
             "launch_ms": t_large * 1e3, "large_phase_ms": phases["large"],
             "valu_issue_frac": _valu_issue(args.mode),
             "valu_issue_source": "committed rocprofv3 SQ_INSTS_VALU profile (profiles/traffic.json), not measured by "
@@ -687,7 +690,7 @@ def main():
         dg = cs.diag_read(ws, stream)
         ph = {"prepare": ev2[0].elapsed_time(ev2[1]), "small": ev2[1].elapsed_time(ev2[2]),
               "large": ev2[2].elapsed_time(ev2[3])}
-        og = RL.large_branch_ops(dg, False)
+        og = RL.large_branch_ops(dg, False, groups)
         tlg = (dg.large_kernel_ms or ph["large"]) / 1e3
         out["g_mode"] = {"phases_ms": ph, "ms_per_step": sum(ph.values()), "thr": cs.plan(job, tg).thr,
                          "factors_per_s": factors / (sum(ph.values()) / 1e3),
