@@ -24,9 +24,9 @@ namespace cs {
 namespace {
 
 constexpr int kPrpBlock = 256;
-// Candidates per open side and round: at least kSurroundB0, and enough for one wavefront per SIMD
-// (the test kernel holds one wavefront per SIMD, so a round of fewer candidates costs as much),
-// at most kSurroundBMax.  Small rounds waste few tests past each side's first probable prime.
+// Candidates per open side and round: at least kSurroundB0, and enough to fill the device once
+// (the test kernel's resident candidates: a round of fewer costs as much), at most kSurroundBMax.
+// Small rounds waste few tests past each side's first probable prime.
 constexpr uint32_t kSurroundB0 = 2;
 constexpr uint32_t kSurroundBMax = 1024;
 constexpr uint64_t kSurroundSlotsMin = 1u << 18;
@@ -199,6 +199,267 @@ __device__ bool sprp2(const uint32_t (&n)[NL], uint32_t* __restrict__ b) {
   return false;
 }
 
+// ---------------------------------------------------------------------------------------------
+// The same test with a candidate spread over a quad of lanes, for NL = 4L limbs (L >= 3).  Lane r
+// of a quad holds limbs [rL, rL + L) of each number, so a lane keeps three L-limb arrays (the
+// value, the modulus and the accumulator) instead of three NL-limb ones: about a quarter of the
+// registers, and four times the wavefronts per SIMD.  Limbs cross lanes by DPP quad permutations
+// (a VALU operation, no LDS round trip).  Carries out of a lane's top limb are kept pending and
+// enter the next lane at the next step, so no step waits for a carry to ripple through the quad;
+// they are resolved once per squaring.  Every lane of a quad computes the same control values, so
+// the quad stays converged.
+// ---------------------------------------------------------------------------------------------
+// DPP quad permutations: lane r of each quad reads lane SRC[r].
+template <int SRC>
+__device__ __forceinline__ uint32_t q_bcast(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, SRC * 0x55, 0xf, 0xf, false);          // (S, S, S, S)
+}
+__device__ __forceinline__ uint32_t q_from_prev(uint32_t v, uint32_t r) {    // lane r - 1 (lane 0: 0)
+  const uint32_t x = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x90, 0xf, 0xf, false);   // (0, 0, 1, 2)
+  return r ? x : 0u;
+}
+__device__ __forceinline__ uint32_t q_from_next(uint32_t v) {                 // lane r + 1 (lane 3: itself)
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xf9, 0xf, 0xf, false);               // (1, 2, 3, 3)
+}
+__device__ __forceinline__ uint32_t q_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xb1, 0xf, 0xf, false));          // (1, 0, 3, 2)
+  return max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4e, 0xf, 0xf, false));       // (2, 3, 0, 1)
+}
+__device__ __forceinline__ uint32_t q_min(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xb1, 0xf, 0xf, false));
+  return min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4e, 0xf, 0xf, false));
+}
+// every lane of the quad has the predicate (the quads of a wavefront are aligned to 4 lanes)
+__device__ __forceinline__ bool q_all(bool p) {
+  const unsigned long long b = __ballot(p);
+  return ((b >> (__lane_id() & ~3u)) & 0xfull) == 0xfull;
+}
+
+// Carries pending out of each lane's top limb (pc, into the next lane's limb 0; lane 3's go to the
+// word above the number, `top`) are added in; three rounds carry them across the quad.
+template <int L>
+__device__ __forceinline__ void q_resolve(uint32_t (&t)[L], uint32_t pc, uint32_t& top, uint32_t r) {
+#pragma unroll
+  for (int round = 0; round < 3; ++round) {
+    uint32_t c = q_from_prev(pc, r);
+    if (r == 3) top += pc;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint64_t s = (uint64_t)t[j] + c;
+      t[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    pc = c;
+  }
+  if (r == 3) top += pc;
+}
+
+// t = t - n if (top != 0 or t >= n), for a resolved t < 2n (top: the word above the number).
+template <int L>
+__device__ __forceinline__ void q_sub_if_ge(uint32_t (&t)[L], uint32_t top, const uint32_t (&n)[L], uint32_t r) {
+  // this lane's borrow out of t - n for a borrow in of 0 (b0) and of 1 (b1 = b0 or t == n here)
+  uint32_t br = 0, diff = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t d = (uint64_t)t[j] - n[j] - br;
+    br = (uint32_t)(d >> 32) & 1u;
+    diff |= (uint32_t)d;
+  }
+  const uint32_t b0 = br, b1 = br | (diff == 0 ? 1u : 0u);
+  uint32_t bin = 0;                                   // borrow into this lane, across the quad
+#pragma unroll
+  for (int round = 0; round < 3; ++round) bin = q_from_prev(bin ? b1 : b0, r);
+  const uint32_t bout = bin ? b1 : b0;               // lane 3: borrow out of the whole t - n
+  const bool sub = q_bcast<3>((top != 0 || bout == 0) ? 1u : 0u) != 0;
+  if (!sub) return;
+  br = bin;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t d = (uint64_t)t[j] - n[j] - br;
+    t[j] = (uint32_t)d;
+    br = (uint32_t)(d >> 32) & 1u;
+  }
+}
+
+// a = a*a/R mod n (R = 2^(32 NL)), a < n; col: this quad's LDS columns (lane o's limb l at
+// col[l * kPrpBlock + o]), where a is written first so every lane can read the multiplier limbs.
+template <int L>
+__device__ __forceinline__ void q_mont_sqr(uint32_t (&a)[L], const uint32_t (&n)[L], uint32_t ninv, uint32_t r,
+                                           uint32_t* own, const uint32_t* col) {
+  // (own and col overlap: the writes must stay before the reads)
+#pragma unroll
+  for (int j = 0; j < L; ++j) own[j * kPrpBlock] = a[j];
+  uint32_t t[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) t[j] = 0;
+  uint32_t pc = 0, top = 0;
+#pragma unroll 1
+  for (int i = 0; i < 4 * L; ++i) {
+    const int o = i / L, l = i - o * L;
+    const uint32_t bi = col[l * kPrpBlock + o];      // limb i of the multiplier (owner lane o)
+    uint32_t c = q_from_prev(pc, r);                  // pending carry into this lane's limb 0
+#pragma unroll
+    for (int j = 0; j < L; ++j) {                     // t += a * b_i
+      const uint64_t s = (uint64_t)a[j] * bi + t[j] + c;
+      t[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    const uint32_t ca = c;
+    const uint32_t q = q_bcast<0>(t[0] * ninv);      // lane 0's limb 0 is exact: t + q n = 0 mod 2^32
+    c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {                     // t += q * n
+      const uint64_t s = (uint64_t)q * n[j] + t[j] + c;
+      t[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    // t /= 2^32: lane r + 1's limb 0 (lane 3: the word above) and this lane's pending carries
+    // become this lane's top limb
+    const uint32_t up = q_from_next(t[0]);
+#pragma unroll
+    for (int j = 0; j < L - 1; ++j) t[j] = t[j + 1];
+    const uint64_t h = (uint64_t)(r == 3 ? top : up) + ca + c;
+    t[L - 1] = (uint32_t)h;
+    pc = (uint32_t)(h >> 32);
+    if (r == 3) top = pc;
+  }
+  if (r == 3) pc = 0;                                 // lane 3's carry is `top` already
+  q_resolve<L>(t, pc, top, r);
+  q_sub_if_ge<L>(t, top, n, r);
+#pragma unroll
+  for (int j = 0; j < L; ++j) a[j] = t[j];
+}
+
+// a = 2a mod n for a < n.
+template <int L>
+__device__ __forceinline__ void q_mod_dbl(uint32_t (&a)[L], const uint32_t (&n)[L], uint32_t r) {
+  const uint32_t hib = a[L - 1] >> 31;
+  const uint32_t cin = q_from_prev(hib, r);
+#pragma unroll
+  for (int j = L - 1; j > 0; --j) a[j] = (a[j] << 1) | (a[j - 1] >> 31);
+  a[0] = (a[0] << 1) | cin;
+  q_sub_if_ge<L>(a, q_bcast<3>(hib), n, r);
+}
+
+// y = x R^-1 mod n (Montgomery reduction) for x < n.
+template <int L>
+__device__ __forceinline__ void q_mont_redc(const uint32_t (&x)[L], const uint32_t (&n)[L], uint32_t ninv,
+                                            uint32_t r, uint32_t (&y)[L]) {
+  uint32_t t[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) t[j] = x[j];
+  uint32_t pc = 0, top = 0;
+#pragma unroll 1
+  for (int i = 0; i < 4 * L; ++i) {
+    uint32_t c = q_from_prev(pc, r);
+    const uint32_t q = q_bcast<0>((t[0] + c) * ninv);   // lane 0: c = 0
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint64_t s = (uint64_t)q * n[j] + t[j] + c;
+      t[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    const uint32_t up = q_from_next(t[0]);
+#pragma unroll
+    for (int j = 0; j < L - 1; ++j) t[j] = t[j + 1];
+    const uint64_t h = (uint64_t)(r == 3 ? top : up) + c;
+    t[L - 1] = (uint32_t)h;
+    pc = (uint32_t)(h >> 32);
+    if (r == 3) top = pc;
+  }
+  if (r == 3) pc = 0;
+  q_resolve<L>(t, pc, top, r);
+  q_sub_if_ge<L>(t, top, n, r);
+#pragma unroll
+  for (int j = 0; j < L; ++j) y[j] = t[j];
+}
+
+// Strong probable-prime test to base 2 of n (NL = 4L limbs spread over the quad); own/col: this
+// lane's LDS column and the quad's (2L words per lane: the multiplier, then n).
+template <int L>
+__device__ bool q_sprp2(const uint32_t (&n)[L], uint32_t r, uint32_t* own, const uint32_t* col) {
+  // the quad's n in LDS for the exponent bits
+#pragma unroll
+  for (int j = 0; j < L; ++j) own[(L + j) * kPrpBlock] = n[j];
+  uint32_t hi_local = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) hi_local |= (r == 0 && j == 0) ? 0u : n[j];
+  const bool hi_zero = q_all(hi_local == 0);
+  const uint32_t n0 = q_bcast<0>(n[0]);
+  if (!(n0 & 1u)) return hi_zero && n0 == 2u;
+  if (hi_zero && n0 < 3u) return false;             // 1
+  uint32_t inv = n0;                                 // n0^-1 mod 2^32 by Newton (3 -> 48 bits)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) inv *= 2u - n0 * inv;
+  const uint32_t ninv = 0u - inv;
+  // bit length of n, and s with n - 1 = 2^s t, t odd
+  uint32_t bl = 0, tz = 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint32_t g = r * L + j;
+    if (n[j]) bl = 32 * g + 32 - __clz(n[j]);
+    const uint32_t e = (r == 0 && j == 0) ? n[j] - 1u : n[j];
+    if (e && tz == 0xffffffffu) tz = 32 * g + __ffs(e) - 1;
+  }
+  const int bits = (int)q_max(bl);
+  const int s = (int)q_min(tz);
+  auto nm1_limb = [&](int g) -> uint32_t {           // limb g of n - 1, from the quad's LDS copy
+    const int o = g / L, l = g - o * L;
+    const uint32_t v = col[(L + l) * kPrpBlock + o];
+    return g == 0 ? v - 1u : v;
+  };
+  // x = 2R mod n: 2^(bits-1) < n doubled up to 2^(32 NL + 1)
+  uint32_t x[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) x[j] = ((int)(r * L + j) == ((bits - 1) >> 5)) ? (1u << ((bits - 1) & 31)) : 0u;
+  for (int k = 0; k < 32 * 4 * L - bits + 2; ++k) q_mod_dbl<L>(x, n, r);
+  uint32_t e = nm1_limb((bits - 2) >> 5);
+  for (int bit = bits - 2; bit >= s; --bit) {
+    if ((bit & 31) == 31) e = nm1_limb(bit >> 5);
+    q_mont_sqr<L>(x, n, ninv, r, own, col);
+    if ((e >> (bit & 31)) & 1u) q_mod_dbl<L>(x, n, r);
+  }
+  uint32_t y[L];
+  q_mont_redc<L>(x, n, ninv, r, y);
+  auto is_one = [&]() {
+    uint32_t d = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) d |= y[j] ^ ((r == 0 && j == 0) ? 1u : 0u);
+    return q_all(d == 0);
+  };
+  auto is_minus_one = [&]() {
+    uint32_t d = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) d |= y[j] ^ ((r == 0 && j == 0) ? n[j] - 1u : n[j]);
+    return q_all(d == 0);
+  };
+  if (is_one() || is_minus_one()) return true;
+  for (int k = 1; k < s; ++k) {
+    q_mont_sqr<L>(x, n, ninv, r, own, col);
+    q_mont_redc<L>(x, n, ninv, r, y);
+    if (is_minus_one()) return true;
+    if (is_one()) return false;
+  }
+  return false;
+}
+
+template <int L>
+__global__ __launch_bounds__(kPrpBlock) void k_prp_numbers_q(const uint32_t* __restrict__ limbs, uint32_t n_limbs,
+                                                             uint64_t count, uint8_t* __restrict__ out) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t i = (blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x) / 4;
+  if (i >= count) return;                            // whole quads leave together
+  const uint32_t r = threadIdx.x & 3u;
+  uint32_t v[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint32_t g = r * L + j;
+    v[j] = g < n_limbs ? limbs[i * n_limbs + g] : 0u;
+  }
+  const bool pp = q_sprp2<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u));
+  if (r == 0) out[i] = pp ? 1 : 0;
+}
+
 template <int NL>
 __global__ __launch_bounds__(kPrpBlock) void k_prp_numbers(const uint32_t* __restrict__ limbs, uint32_t n_limbs,
                                                            uint64_t count, uint8_t* __restrict__ out) {
@@ -349,6 +610,71 @@ __global__ __launch_bounds__(kPrpBlock) void k_sv_test(SurroundDev sv, uint32_t 
   sv.slot_res[sidx] = sprp2<NL>(v, lds + threadIdx.x) ? 1 : 0;
 }
 
+// The same on a quad of lanes per candidate (NL = 4L limbs).
+template <int L>
+__global__ __launch_bounds__(kPrpBlock) void k_sv_test_q(SurroundDev sv, uint32_t in, uint64_t n_slots, uint32_t B) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t sidx = (blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x) / 4;
+  if (sidx >= n_slots) return;                       // whole quads leave together
+  const uint32_t r = threadIdx.x & 3u;
+  const int32_t col = sv.slot_col[sidx];
+  const unsigned long long live = __ballot(col >= 0 && r == 0);
+  if ((threadIdx.x & (kWave - 1)) == 0 && live) atomicAdd(sv.tests, (unsigned long long)__popcll(live));
+  if (col < 0) {
+    if (r == 0) sv.slot_res[sidx] = 0;
+    return;
+  }
+  const uint32_t task = sv.act[in][sidx / B];
+  const uint64_t m = sv.m[task >> 1];
+  if (m < sv.m_lo || m >= sv.m_hi) {                // outside the job's range: no result
+    if (r == 0) {
+      atomicOr(&sv.n_act[2], 1u);
+      sv.slot_res[sidx] = 0;
+    }
+    return;
+  }
+  const int32_t X = sv.x_of_col[col];
+  // N = m K + X: each lane forms its limbs, the carries out of its top limb resolved across the
+  // quad after each pass (N < 2^(32 NL), so nothing leaves the quad)
+  uint32_t v[L];
+  uint32_t dummy = 0;
+  const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t s = (uint64_t)sv.klimbs[r * L + j] * mlo + c;
+    v[j] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  q_resolve<L>(v, c, dummy, r);
+  if (mhi) {                                          // the same quad-uniform branch in every lane
+    c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint32_t g = r * L + j;
+      const uint64_t s = (uint64_t)(g ? sv.klimbs[g - 1] : 0u) * mhi + v[j] + c;
+      v[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    q_resolve<L>(v, c, dummy, r);
+  }
+  // + X, or + (2^(32 NL) - |X|) with the carry out of the number dropped
+  const bool neg = X < 0;
+  const uint32_t ax = (uint32_t)(neg ? -X : X);
+  c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const bool low = r == 0 && j == 0;
+    const uint32_t add = neg ? (low ? 0u - ax : 0xffffffffu) : (low ? ax : 0u);
+    const uint64_t s = (uint64_t)v[j] + add + c;
+    v[j] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  q_resolve<L>(v, c, dummy, r);
+  const bool pp = q_sprp2<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u));
+  if (r == 0) sv.slot_res[sidx] = pp ? 1 : 0;
+}
+
 __global__ void k_sv_resolve(SurroundDev sv, uint32_t in, uint32_t n_open, uint32_t B) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_open) return;
@@ -388,8 +714,27 @@ uint32_t pick_nl(uint32_t limbs) {
   return 0;
 }
 
+// From 12 limbs a candidate takes a quad of lanes (L = NL / 4 limbs each, 2L LDS words per lane);
+// below that one lane (NL LDS words per lane).
+#define PRP_QUAD_INSTANCES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+constexpr uint32_t kQuadMinNl = 12;
+
 hipError_t launch_prp_numbers(uint32_t nl, const uint32_t* limbs, uint32_t n_limbs, uint64_t count, uint8_t* out,
                               hipStream_t s) {
+  if (nl >= kQuadMinNl) {
+    const uint32_t blocks = (uint32_t)((count * 4 + kPrpBlock - 1) / kPrpBlock);
+    const size_t lds = (size_t)(nl / 2) * kPrpBlock * 4;
+    switch (nl / 4) {
+#define QCASE(L)                                                                                               \
+  case L:                                                                                                      \
+    hipLaunchKernelGGL(k_prp_numbers_q<L>, dim3(blocks), dim3(kPrpBlock), lds, s, limbs, n_limbs, count, out); \
+    break;
+      PRP_QUAD_INSTANCES(QCASE)
+#undef QCASE
+      default: return hipErrorInvalidValue;
+    }
+    return record_launch("k_prp_numbers_q");
+  }
   const uint32_t blocks = (uint32_t)((count + kPrpBlock - 1) / kPrpBlock);
   const size_t lds = (size_t)nl * kPrpBlock * 4;
   switch (nl) {
@@ -406,6 +751,20 @@ hipError_t launch_prp_numbers(uint32_t nl, const uint32_t* limbs, uint32_t n_lim
 
 hipError_t launch_sv_test(uint32_t nl, const SurroundDev& sv, uint32_t in, uint64_t n_slots, uint32_t B,
                           hipStream_t s) {
+  if (nl >= kQuadMinNl) {
+    const uint32_t blocks = (uint32_t)((n_slots * 4 + kPrpBlock - 1) / kPrpBlock);
+    const size_t lds = (size_t)(nl / 2) * kPrpBlock * 4;
+    switch (nl / 4) {
+#define QCASE(L)                                                                                     \
+  case L:                                                                                            \
+    hipLaunchKernelGGL(k_sv_test_q<L>, dim3(blocks), dim3(kPrpBlock), lds, s, sv, in, n_slots, B);   \
+    break;
+      PRP_QUAD_INSTANCES(QCASE)
+#undef QCASE
+      default: return hipErrorInvalidValue;
+    }
+    return record_launch("k_sv_test_q");
+  }
   const uint32_t blocks = (uint32_t)((n_slots + kPrpBlock - 1) / kPrpBlock);
   const size_t lds = (size_t)nl * kPrpBlock * 4;
   switch (nl) {
@@ -418,6 +777,35 @@ hipError_t launch_sv_test(uint32_t nl, const SurroundDev& sv, uint32_t in, uint6
     default: return hipErrorInvalidValue;
   }
   return record_launch("k_sv_test");
+}
+
+// Candidates the test kernel of this limb count holds at once on the device (its occupancy by
+// registers and LDS): a round of fewer candidates costs as much as a round of this many.
+uint64_t sv_resident(uint32_t nl) {
+  int per_cu = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (nl >= kQuadMinNl) {
+    const size_t lds = (size_t)(nl / 2) * kPrpBlock * 4;
+    switch (nl / 4) {
+#define QOCC(L) \
+  case L: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sv_test_q<L>, kPrpBlock, lds); break;
+      PRP_QUAD_INSTANCES(QOCC)
+#undef QOCC
+      default: break;
+    }
+  } else {
+    const size_t lds = (size_t)nl * kPrpBlock * 4;
+    switch (nl) {
+#define OCC(N) \
+  case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sv_test<N>, kPrpBlock, lds); break;
+      PRP_INSTANCES(OCC)
+#undef OCC
+      default: break;
+    }
+  }
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const uint64_t per_block = nl >= kQuadMinNl ? kPrpBlock / 4 : kPrpBlock;
+  return (uint64_t)device_cu_count() * (uint64_t)per_cu * per_block;
 }
 
 // K = product of the primes dividing K, as 32-bit limbs (little endian).
@@ -570,7 +958,7 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
   double test_ms = 0.0;
   cs_status result = CS_OK;
   uint32_t n_open = (uint32_t)tasks;
-  const uint64_t round_target = std::min<uint64_t>(L.slots, (uint64_t)device_cu_count() * 4u * 64u);
+  const uint64_t round_target = std::min<uint64_t>(L.slots, sv_resident(nl));
   uint32_t in = 0;
   uint64_t rounds = 0;
   unsigned long long run = 0;
