@@ -224,6 +224,84 @@ CS_HD double g_offset(double p, double K, double L, double width, int* levels_ou
   return par ? width - off : off;
 }
 
+// The moduli of Eq. 5's descent, and whether the mirror (d) applies at each level, depend on
+// (p, K) alone, not on L: a prime's walk solves Eq. 3 many times with one (p, K) and different L.
+// GCache holds the first kGCache levels of that descent, computed once: the level's K after the
+// mirror, its reciprocal and the mirror flags; a solve then spends at each cached level only the
+// remainder of L and the test of (c).  The descent of every L ends at the first level whose K
+// (after the mirror) is at most width + 1, since a multiple of such a K lies in every window of
+// width + 1 integers; the cache stops there.
+constexpr int kGCache = 8;
+struct GCache {
+  double p0;                 // p
+  double km[kGCache];        // K of level i after the mirror (the modulus of level i + 1)
+  double inv[kGCache];       // recip1(km[i])
+  double p_next, K_next;     // (p, K) of level kGCache, when the cache is full
+  uint32_t mir;              // bit i: 2K >= p at level i
+  int depth;                 // cached levels
+};
+
+CS_HD void g_cache_build(double p, double K, double width, GCache* c) {
+  c->p0 = p;
+  c->mir = 0;
+  int i = 0;
+  for (; i < kGCache; ++i) {
+    const bool mir = K + K >= p;
+    const double km = mir ? p - K : K;
+    c->km[i] = km;
+    c->inv[i] = recip1(km);
+    if (mir) c->mir |= 1u << i;
+    if (km <= width + 1.0) { ++i; break; }                      // every L ends at this level
+    const double pm = fma(-floor(p * c->inv[i]), km, p);        // p mod km, in [1, km - 1]
+    p = km;
+    K = km - pm;
+  }
+  c->depth = i;
+  c->p_next = p;
+  c->K_next = K;
+}
+
+// g_offset(p, K, L, width) from the cached levels (the same cases, in the same order), then the
+// descent itself below them.
+CS_HD double g_offset_cached(const GCache& c, double L, double width, int* levels_out) {
+  int par = 0;
+  double p = c.p0;
+#pragma unroll
+  for (int i = 0; i < kGCache; ++i) {
+    if (i < c.depth) {
+      const double km = c.km[i];
+      const bool mir = ((c.mir >> i) & 1u) != 0 && L != 0.0;   // (d); L = 0 ends in (c) with 0
+      L = mir ? p - L - width : L;
+      par ^= mir ? 1 : 0;
+      const double rem = fma(-floor(L * c.inv[i]), km, L);      // L mod km, or km for 0
+      const double up = rem == 0.0 ? 0.0 : km - rem;
+      if (up <= width) {                                        // (c)
+        if (levels_out) *levels_out = i + 1;
+        return par ? width - up : up;
+      }
+      L = rem;                                                  // (e)
+      p = km;
+    }
+  }
+  if (c.depth < kGCache) return -1.0;                           // (never: the cache ended at km <= width + 1)
+  int lv = 0;
+  const double off = g_offset(c.p_next, c.K_next, L, width, &lv);
+  if (levels_out) *levels_out = kGCache + lv;
+  if (off < 0.0) return -1.0;
+  return par ? width - off : off;
+}
+
+// next_hit_d through the cached descent of (p, k).
+CS_HD double next_hit_cached(const GCache& c, double kinv, double pinv, double r, double w, double* r_new,
+                             int* levels) {
+  const double p = c.p0;
+  const double L = p - r;
+  const double off = g_offset_cached(c, L, w, levels);
+  if (off < 0.0) return 0.0;
+  *r_new = off;
+  return mulmod_f64(L + off, kinv, p, pinv);
+}
+
 // Smallest t >= 1 such that (r + t*k) mod p <= w, given r > w (Eq. 3 in shifted form:
 // r is the residue of m*K + SL).  Returns t and writes the residue reached (<= w).
 // Returns 0 on an internal failure (never for valid input).

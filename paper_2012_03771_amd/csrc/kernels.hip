@@ -1495,6 +1495,8 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     mpos_divmod(stb, d32, inv_d, &bq, &br);
     mpos_divmod(tab, d32, inv_d, &abq, &abr);
   }
+  GCache gc;
+  if constexpr (kG && !kWide) g_cache_build((double)p, (double)k, (double)w, &gc);
   for (uint32_t cls = 0; cls < s; ++cls) {
     // list scatter: lanes that left the previous class's walk early catch up on the wavefront's
     // chunk state before the next walk appends (every lane reaches this point)
@@ -1521,7 +1523,8 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
     if (d_small) mpos_divmod(j.r0_d + o_lo, d32, inv_d, &mp.dq, &mp.rd);
 
     if (kG && !kWide) {
-      // one solve of Eq. 3 per hit; every value an integer below 2^45 held as a double
+      // one solve of Eq. 3 per hit; every value an integer below 2^45 held as a double, and the
+      // first levels of Eq. 5's descent for (p, k) taken from the item's cache
       const double pd = (double)p, kd = (double)k, kinvd = (double)kinv, wd = (double)w, sd = (double)s;
       const double ohd = (double)o_hi;
       double rd = (double)r, od = (double)o;
@@ -1529,7 +1532,7 @@ __device__ __forceinline__ void large_item(const JobDev& j, const LargeTables<kL
         if (rd > wd) {
           int lv = 0;
           double rn = 0.0;
-          const double t = next_hit_d(pd, kd, kinvd, pinv, rd, wd, &rn, &lv);
+          const double t = next_hit_cached(gc, kinvd, pinv, rd, wd, &rn, &lv);
           ++lc.calls;
           lc.levels += (unsigned)lv;
           if (t == 0.0) { lc.err |= E_SOLVE; break; }

@@ -214,6 +214,36 @@ int main(int argc, char** argv) {
     }
     if (!bad && got3 != want) bad = fail("three_gap", p, k, w, m_inc);
   }
+  // the cached descent of Eq. 5 against the plain one: one cache per (p, K), many L
+  for (int i = 0; i < 100000 && !bad; ++i) {
+    const uint64_t w = 1 + rng() % (i % 4 == 0 ? 8 : 200000);
+    uint64_t p;
+    do { p = (rng() >> (22 + rng() % 30)) | 1; } while (p <= 2 * w + 1 || p >= (1ull << 42) || !is_prime_mr(p));
+    const uint64_t K = 1 + rng() % (p - 1);
+    cs::GCache gc;
+    cs::g_cache_build((double)p, (double)K, (double)w, &gc);
+    for (int q = 0; q < 8 && !bad; ++q) {
+      const uint64_t L = (q == 0) ? 0 : rng() % (p - w);
+      int l1 = 0, l2 = 0;
+      const double a = cs::g_offset((double)p, (double)K, (double)L, (double)w, &l1);
+      const double b = cs::g_offset_cached(gc, (double)L, (double)w, &l2);
+      if (a != b || l1 != l2) bad = fail("g_cached", p, K, L, w);
+    }
+  }
+  // and against brute force on small primes
+  for (int i = 0; i < 20000 && !bad; ++i) {
+    const uint64_t w = rng() % 40;
+    uint64_t p;
+    do { p = 2 * w + 3 + rng() % 3000; } while (!is_prime(p));
+    const uint64_t K = 1 + rng() % (p - 1);
+    cs::GCache gc;
+    cs::g_cache_build((double)p, (double)K, (double)w, &gc);
+    const uint64_t L = rng() % (p - w);
+    int lv = 0;
+    const double off = cs::g_offset_cached(gc, (double)L, (double)w, &lv);
+    const uint64_t t = brute_G(p, K, L, L + w);
+    if (off < 0.0 || (uint64_t)((u128)t * K % p) != L + (uint64_t)off) bad = fail("g_cached_brute", p, K, L, w);
+  }
   // next_hit_d against next_hit for primes up to 2^42
   for (int i = 0; i < 200000 && !bad; ++i) {
     const uint64_t w = 1 + rng() % 200000;
