@@ -21,7 +21,7 @@ from . import binding as B
 
 DEFAULT_CANDIDATES = [
     {"thr_mult": m, "hits_per_item": h, "large_mode": B.LARGE_THREE_GAP}
-    for m in (4, 10, 25) for h in (512, 2048)
+    for m in (8, 20, 40) for h in (512, 2048)
 ]
 
 
@@ -84,10 +84,10 @@ class Autotuner:
     def tune_all(self, jobs):
         return [self.tune(j) for j in jobs]
 
-    # batch-level candidates: the persistent kernel with 256 or 1,024 large-branch items (primes x
-    # m-chunks) per task and 4 to 16 rows per small-branch tile, and the lane path
+    # batch-level candidates: the persistent kernel with 256 to 4,096 large-branch items (primes x
+    # m-chunks) per task and 8 or 16 rows per small-branch tile, and the lane path
     BATCH_CANDIDATES = ([{"path": B.BATCH_PERSISTENT, "items_per_task": ipt, "tile_rows": rows}
-                         for ipt in (256, 1024) for rows in (4, 8, 16)]
+                         for ipt, rows in ((256, 16), (1024, 8), (1024, 16), (4096, 16))]
                         + [{"path": B.BATCH_LANES, "items_per_task": 0, "tile_rows": rows} for rows in (8, 16)])
 
     def tune_batch(self, jobs, reps: int = 2):
