@@ -240,6 +240,12 @@ __device__ __forceinline__ uint64_t first_odd_multiple(uint64_t lo, uint64_t q) 
   return st;
 }
 
+// Base primes per chunk of the segment sieve, and the prime below which whole waves mark one
+// prime (a prime from there on has at most 2^18 / 1024 = 256 odd multiples in a segment and is
+// marked by one thread).
+constexpr uint32_t kSieveChunk = 512;
+constexpr uint32_t kSieveWaveMax = 1024;
+
 // BT, NT: types of the base-prime table and of its length (uint32_t for the LDS-sieved base below
 // 2^21; uint64_t for the level-2 table of limits from 2^42, which starts with the prime 2).
 template <bool kWide, class BT, class NT>
@@ -249,8 +255,12 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t s
                                                         uint32_t* __restrict__ flags,
                                                         uint32_t* __restrict__ seg_count) {
   __shared__ uint32_t bits[kSegWords];
+  __shared__ uint32_t cq[kSieveChunk];     // a chunk of base primes
+  __shared__ uint32_t cb[kSieveChunk];     // the first bit each marks in the segment, ~0u for none
   __shared__ uint32_t sh[32];
   const uint64_t n_base = *n_base_p;
+  uint64_t i_first = 0;                    // the first base prime above 13
+  while (i_first < n_base && base[i_first] <= 13) ++i_first;
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const uint64_t gs = seg0 + s;                                  // segment of the whole range
     const uint64_t lo = gs << kSegLog;
@@ -272,27 +282,45 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t s
         bits[u] = w;
       }
     }
-    __syncthreads();
     const uint32_t nbits = (uint32_t)((hi - lo + 1) / 2);          // bits standing for n <= hi
-    // dense base primes above 13: the whole workgroup strides over the multiples of each
-    uint64_t i = 0;
-    while (i < n_base && base[i] <= 13) ++i;
-    for (; i < n_base; ++i) {
-      const uint64_t q = base[i];
-      if (q * q > hi || q >= 4096) break;
-      const uint64_t st = first_odd_multiple<kWide>(lo, q);
-      if (st > hi) continue;
-      const uint32_t b0 = (uint32_t)((st - lo) >> 1);
-      for (uint32_t b = b0 + threadIdx.x * (uint32_t)q; b < nbits; b += blockDim.x * (uint32_t)q)
-        atomicOr(&bits[b >> 5], 1u << (b & 31));
-    }
-    // sparse base primes: one thread per prime
-    for (uint64_t j = i + threadIdx.x; j < n_base; j += blockDim.x) {
-      const uint64_t q = base[j];
-      if (q * q > hi) continue;
-      const uint64_t st = first_odd_multiple<kWide>(lo, q);
-      for (uint64_t b = (st - lo) >> 1; b < nbits; b += q)
-        atomicOr(&bits[b >> 5], 1u << (b & 31));
+    // The base primes above 13, a chunk at a time: first every thread finds the first marked bit
+    // of its primes of the chunk (one division per prime and segment), then the primes below
+    // kSieveWaveMax are marked by whole waves, one prime per wave at a time with lanes q apart,
+    // and the larger ones (fewer marks each) one prime per thread.
+    for (uint64_t c0 = i_first; c0 < n_base; c0 += kSieveChunk) {
+      const uint64_t q_lead = base[c0];
+      if (q_lead * q_lead > hi) break;                             // uniform: the primes are sorted
+      const uint32_t nc = (uint32_t)min<uint64_t>(kSieveChunk, n_base - c0);
+      __syncthreads();                                             // patterns / last chunk done
+      for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
+        const uint64_t q = base[c0 + k];
+        uint32_t b0 = ~0u;
+        if (q * q <= hi) {
+          const uint64_t st = first_odd_multiple<kWide>(lo, q);
+          if (st <= hi) b0 = (uint32_t)((st - lo) >> 1);
+        }
+        cq[k] = (uint32_t)q;
+        cb[k] = b0;
+      }
+      __syncthreads();
+      const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nwav = blockDim.x / kWave;
+      for (uint32_t k = wid; k < nc; k += nwav) {
+        const uint32_t q = cq[k];
+        if (q >= kSieveWaveMax) break;
+        const uint32_t b0 = cb[k];
+        if (b0 == ~0u) continue;
+        for (uint32_t b = b0 + lane * q; b < nbits; b += kWave * q) atomicOr(&bits[b >> 5], 1u << (b & 31));
+      }
+      for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
+        const uint32_t q = cq[k];
+        const uint32_t b0 = cb[k];
+        if (q < kSieveWaveMax || b0 == ~0u) continue;
+        if (q >= nbits) {                                          // one multiple (and b + q could wrap)
+          atomicOr(&bits[b0 >> 5], 1u << (b0 & 31));
+          continue;
+        }
+        for (uint32_t b = b0; b < nbits; b += q) atomicOr(&bits[b >> 5], 1u << (b & 31));
+      }
     }
     __syncthreads();
     uint32_t c = 0;
@@ -329,11 +357,14 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 }
 
 // Ordered compaction of the prime flags: 256 consecutive words per step, so reads are
-// coalesced and each step's primes land in one contiguous run of the table.
+// coalesced and each step's primes land in one contiguous run of the table.  The bit positions
+// of a step's primes are gathered in LDS first, so the table is written with consecutive lanes
+// at consecutive addresses.
 __global__ __launch_bounds__(256) void k_compact_primes(uint64_t seg0, uint64_t n_seg, const uint32_t* __restrict__ flags,
                                                         const uint64_t* __restrict__ off,
                                                         uint64_t* __restrict__ primes, uint64_t cap) {
   __shared__ uint32_t sh[32];
+  __shared__ uint16_t pos_bits[256 * 32];   // a step's primes: bit index within the step
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     uint64_t base = off[s];
     if (seg0 + s == 0) {
@@ -342,17 +373,22 @@ __global__ __launch_bounds__(256) void k_compact_primes(uint64_t seg0, uint64_t 
     }
     const uint64_t lo = (seg0 + s) << kSegLog;
     for (uint32_t step = 0; step < kSegWords / 256; ++step) {
-      const uint32_t word = step * 256 + threadIdx.x;
-      uint32_t m = flags[s * kSegWords + word];
+      uint32_t m = flags[s * kSegWords + step * 256 + threadIdx.x];
       uint32_t tot;
-      uint64_t pos = base + block_exclusive_scan(__popc(m), sh, &tot);
+      uint32_t k = block_exclusive_scan(__popc(m), sh, &tot);     // ends with a barrier
       while (m) {
         const uint32_t b = __ffs(m) - 1;
         m &= m - 1;
-        if (pos < cap) primes[pos] = lo + 2ull * (word * 32 + b) + 1;
-        ++pos;
+        pos_bits[k++] = (uint16_t)(threadIdx.x * 32 + b);
+      }
+      __syncthreads();
+      const uint64_t step_lo = lo + 2ull * step * 256 * 32 + 1;
+      for (uint32_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        const uint64_t g = base + t;
+        if (g < cap) primes[g] = step_lo + 2ull * pos_bits[t];
       }
       base += tot;
+      __syncthreads();                                             // pos_bits reusable
     }
   }
 }

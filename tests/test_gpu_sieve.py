@@ -47,7 +47,7 @@ def _assert_same(job, got_b, got_c, want_b, want_c, rows=None):
 # prime table and K mod p
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("limit", [2, 3, 10, 100, 1000, 2**19 - 1, 2**19, 2**19 + 1, 3 * 2**19 + 7, 10**6,
-                                   10**7])
+                                   10**7, 2 * 10**8 + 7])
 def test_prime_table_matches_oracle(limit):
     _say("primes", limit)
     got, n = cs.primes(limit)
