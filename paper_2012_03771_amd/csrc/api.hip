@@ -123,7 +123,15 @@ PrimeWs prime_ws_of(const Plan& pl, uint8_t* ws) {
   return pw;
 }
 
-cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) {
+struct AuxStream;
+cs_status aux_clear(const Plan& pl, JobDev* jdp, uint32_t* bitmap, uint32_t* counts, hipStream_t s, int n_cu,
+                    AuxStream* aux);
+cs_status aux_join(AuxStream* aux, hipStream_t s);
+
+// aux (optional): a second stream that clears the outputs and the byte counters beside the prime
+// sieve (pure stores against the sieve's LDS work); `s` waits for it before returning.
+cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu, AuxStream* aux = nullptr,
+                          uint32_t* bitmap = nullptr, uint32_t* counts = nullptr) {
   const WsLayout& L = pl.ws;
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
   JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
@@ -131,6 +139,7 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
   JobDev jd = make_jobdev(pl, ws, pw.primes, pw.n_primes);
   CS_TRY(launch_zero_ctrl(ctrl, s));
   CS_TRY(launch_write_job(jd, jdp, s));
+  if (aux) CS_TRY(aux_clear(pl, jdp, bitmap, counts, s, n_cu, aux));
   CS_TRY(launch_primes(pl.Lp, pw, s));
   CS_TRY(launch_prep_tables(jdp, 1, s));
   CS_TRY(launch_kmod(jdp, 1, reinterpret_cast<uint64_t*>(ws + L.lim_base), pi_upper(pl.job.limit), n_cu, s));
@@ -140,6 +149,7 @@ cs_status prepare_planned(const Plan& pl, uint8_t* ws, hipStream_t s, int n_cu) 
     CS_TRY(launch_upload(ws + L.dres, pl.dres.data(), pl.dres.size() * 2ull, s));
   }
   if (pl.dpat_on) CS_TRY(launch_dpattern(jdp, 1, pl.phi_d, pl.row_words, s));
+  if (aux) return aux_join(aux, s);
   if (pl.scatter_bytes) CS_TRY(launch_zero_bytes(jdp, 1, pl.n_m * (uint64_t)pl.row_words, n_cu, s));
   return CS_OK;
 }
@@ -184,11 +194,34 @@ AuxStream* aux_stream() {
   return &a;
 }
 
+// The clears of prepare_planned on the second stream: the outputs (when given) and the byte
+// counters, after the job descriptor is written on `s`.
+cs_status aux_clear(const Plan& pl, JobDev* jdp, uint32_t* bitmap, uint32_t* counts, hipStream_t s, int n_cu,
+                    AuxStream* aux) {
+  CS_TRY(hipEventRecord(aux->fork, s));
+  CS_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
+  if (bitmap && pl.n_m > 0) {
+    CS_TRY(launch_fill_u32(bitmap, pl.n_m * (uint64_t)pl.row_words, 0u, aux->s));
+    CS_TRY(launch_fill_u32(counts, pl.n_m, 0u, aux->s));
+  }
+  if (pl.scatter_bytes) CS_TRY(launch_zero_bytes(jdp, 1, pl.n_m * (uint64_t)pl.row_words, n_cu, aux->s));
+  CS_TRY(hipEventRecord(aux->join, aux->s));
+  return CS_OK;
+}
+
+cs_status aux_join(AuxStream* aux, hipStream_t s) {
+  CS_TRY(hipStreamWaitEvent(s, aux->join, 0));
+  return CS_OK;
+}
+
 // own_stream_only: everything on `s`, with no second stream and no timing events (the entry point
 // that allocates nothing creates neither).
 // wide: the range lies at or above the plan's wide_lo; its large primes take the 64-bit path.
+// fold_keep: no later call adds to the byte counters before the next preparation clears them, so
+// the fold need not clear them back.
 cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
-                     uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only, bool wide) {
+                     uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only, bool wide,
+                     bool fold_keep = false) {
   const WsLayout& L = pl.ws;
   JobDev* jdp = reinterpret_cast<JobDev*>(ws + L.jobdev);
   PrimeWs pw = prime_ws_of(pl, ws);
@@ -198,6 +231,7 @@ cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bit
   jd.bitmap = bitmap;
   jd.counts = counts;
   jd.branches = branches;
+  jd.fold_keep = fold_keep ? 1u : 0u;
   fill_tiers(pl, p_lo, p_hi, &jd);
   // With the byte counters or the list the large branch writes only its counters or cells until
   // the fold or the grouping, so the small branch can run beside it on a second stream.  With the
@@ -255,10 +289,11 @@ cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bit
 // The primes of [p_lo, p_hi]: below wide_lo with the fp64 arithmetic, from wide_lo on (large
 // primes only, since the threshold stays below it) with the 64-bit arithmetic.
 cs_status range_planned(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bitmap, uint32_t* counts,
-                        uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only = false) {
+                        uint8_t* ws, hipStream_t s, uint32_t branches, bool own_stream_only = false,
+                        bool fold_keep = false) {
   const uint64_t wl = pl.wide_lo;
   if (p_hi < wl || pl.job.limit < wl)
-    return range_core(pl, p_lo, p_hi, bitmap, counts, ws, s, branches, own_stream_only, false);
+    return range_core(pl, p_lo, p_hi, bitmap, counts, ws, s, branches, own_stream_only, false, fold_keep);
   if (p_lo < wl) {
     cs_status st = range_core(pl, p_lo, wl - 1, bitmap, counts, ws, s, branches, own_stream_only, false);
     if (st) return st;
@@ -306,13 +341,21 @@ extern "C" cs_status cs_sieve(const cs_job* job, const cs_tune* tune, uint32_t* 
   if (ws_bytes < pl.ws.total) return CS_ERANGE;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
-  if (pl.n_m > 0) {
+  // the outputs and the byte counters are cleared on a second stream beside the prime sieve
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  AuxStream* aux = nullptr;
+  if (pl.n_m > 0 && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone)
+    aux = aux_stream();
+  if (pl.n_m > 0 && !aux) {
     CS_TRY(launch_fill_u32(d_bitmap, pl.n_m * (uint64_t)pl.row_words, 0u, s));
     CS_TRY(launch_fill_u32(d_counts, pl.n_m, 0u, s));
   }
-  st = prepare_planned(pl, ws, s, n_cu);
+  st = prepare_planned(pl, ws, s, n_cu, aux, d_bitmap, d_counts);
   if (st) return st;
-  return range_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL);
+  // one range call over the whole prime range: its fold is the counters' last use in this call
+  // (the wide part, when there is one, adds to them after the first part's fold)
+  const bool keep = pl.job.limit < pl.wide_lo;
+  return range_planned(pl, 2, pl.job.limit, d_bitmap, d_counts, ws, s, CS_BRANCH_ALL, false, keep);
 }
 
 namespace {

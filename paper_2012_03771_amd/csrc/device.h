@@ -102,6 +102,8 @@ struct JobDev {
   uint32_t* bitmap;
   uint32_t* counts;
   uint8_t* hitbytes;                 // one byte per (row, column slot) or null: large hits by store
+  uint32_t fold_keep;                // 1: the fold leaves the byte counters as they are (no later call
+                                     // of this preparation adds to them; the next one clears them)
   // List scatter: large hits appended as cells (row << cell_shift) | col into chunks of kListChunk cells
   // (one chunk open per wavefront), then grouped by buckets of bkt_rows rows and OR-ed / counted
   // into the outputs through LDS tiles.

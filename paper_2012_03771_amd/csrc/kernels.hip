@@ -1937,8 +1937,10 @@ __global__ __launch_bounds__(256) void k_fold_bytes(const JobDev* __restrict__ j
         s += (h & 0xffffu) + (h >> 16);
       }
       if (bits) {
-        src[2 * wi] = make_uint4(0, 0, 0, 0);
-        src[2 * wi + 1] = make_uint4(0, 0, 0, 0);
+        if (!j.fold_keep) {
+          src[2 * wi] = make_uint4(0, 0, 0, 0);
+          src[2 * wi + 1] = make_uint4(0, 0, 0, 0);
+        }
         dst[wi] |= bits;
       }
       sum += s;
