@@ -216,12 +216,23 @@ __host__ __device__ constexpr uint32_t every_qth(uint32_t Q) {
   return m;
 }
 
-// The marks of the odd multiples of Q in word u of a segment whose first marked bit is b0 (bit b
-// stands for n = lo + 2b + 1): the bits b = 32u + ph + kQ with ph = (b0 - 32u) mod Q.
+// Periodic marks of the odd multiples of a small prime Q (below 32, so every word holds one
+// or more): bit b stands for n = lo + 2b + 1, and Q | n iff b = b0 (mod Q) with
+// b0 = (Q - (lo + 1) mod Q) (Q + 1)/2 mod Q.  A thread fills words u0, u0 + kStride, ...; the
+// marks of word u are bits ph, ph + Q, ... with ph = (b0 - 32u) mod Q, which moves by
+// (32 kStride) mod Q from one of its words to the next.
 template <uint32_t Q>
-__device__ __forceinline__ uint32_t pattern_word(uint32_t u, uint32_t b0) {
-  const uint32_t ph = (b0 + Q * 32u - (u % Q) * (32u % Q)) % Q;
-  return every_qth(Q) << ph;
+__device__ __forceinline__ uint32_t pat_phase(uint64_t lo, uint32_t u0) {
+  const uint32_t b0 = (uint32_t)(((Q - (lo + 1) % Q) * ((Q + 1) / 2)) % Q);
+  return (b0 + Q * 32u - (u0 % Q) * (32u % Q)) % Q;
+}
+
+template <uint32_t Q, uint32_t kStride>
+__device__ __forceinline__ uint32_t pat_next(uint32_t& ph) {
+  const uint32_t w = every_qth(Q) << ph;
+  constexpr uint32_t D = (kStride * 32u) % Q;
+  ph = ph >= D ? ph - D : ph + Q - D;
+  return w;
 }
 
 // The first odd multiple of q at or above max(lo, q^2).  kWide: lo up to 2^64 (exact 64-bit
@@ -245,11 +256,15 @@ __device__ __forceinline__ uint64_t first_odd_multiple(uint64_t lo, uint64_t q) 
 // marked by one thread).
 constexpr uint32_t kSieveChunk = 512;
 constexpr uint32_t kSieveWaveMax = 1024;
+constexpr uint32_t kSieveThreads = 512;   // workgroup size of the segment sieve
+// bits of 3, 5, ..., 31 themselves in word 0 of segment 0 (n = 2b + 1)
+constexpr uint32_t kPatPrimeBits = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 5) | (1u << 6) | (1u << 8) |
+                                   (1u << 9) | (1u << 11) | (1u << 14) | (1u << 15);
 
 // BT, NT: types of the base-prime table and of its length (uint32_t for the LDS-sieved base below
 // 2^21; uint64_t for the level-2 table of limits from 2^42, which starts with the prime 2).
 template <bool kWide, class BT, class NT>
-__global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t seg0, uint64_t n_seg,
+__global__ __launch_bounds__(kSieveThreads) void k_sieve_segments(uint64_t lim, uint64_t seg0, uint64_t n_seg,
                                                         const BT* __restrict__ base,
                                                         const NT* __restrict__ n_base_p,
                                                         uint32_t* __restrict__ flags,
@@ -259,26 +274,28 @@ __global__ __launch_bounds__(512) void k_sieve_segments(uint64_t lim, uint64_t s
   __shared__ uint32_t cb[kSieveChunk];     // the first bit each marks in the segment, ~0u for none
   __shared__ uint32_t sh[32];
   const uint64_t n_base = *n_base_p;
-  uint64_t i_first = 0;                    // the first base prime above 13
-  while (i_first < n_base && base[i_first] <= 13) ++i_first;
+  uint64_t i_first = 0;                    // the first base prime above 31
+  while (i_first < n_base && base[i_first] <= 31) ++i_first;
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const uint64_t gs = seg0 + s;                                  // segment of the whole range
     const uint64_t lo = gs << kSegLog;
     const uint64_t hi = min(lo + (1ull << kSegLog) - 1, lim);     // inclusive
-    // The odd multiples of 3, 5, 7, 11 and 13 (over 40% of all marks, and the ones whose
-    // atomics collide most) come from periodic word patterns; q | lo + 2b + 1 iff
-    // b = (q - (lo + 1) mod q) (q + 1)/2 (mod q).  A multiple below q^2 is composite too, so the
-    // patterns need no q^2 start; only the primes themselves (segment 0) are taken back.
+    // The odd multiples of the primes 3 to 31 (over half of all marks, and the ones whose atomics
+    // would collide most) come from periodic word patterns.  A multiple below q^2 is composite
+    // too, so the patterns need no q^2 start; only the primes themselves (segment 0) are taken
+    // back.
     {
-      const uint32_t b3 = (uint32_t)(((3 - (lo + 1) % 3) * 2) % 3);
-      const uint32_t b5 = (uint32_t)(((5 - (lo + 1) % 5) * 3) % 5);
-      const uint32_t b7 = (uint32_t)(((7 - (lo + 1) % 7) * 4) % 7);
-      const uint32_t b11 = (uint32_t)(((11 - (lo + 1) % 11) * 6) % 11);
-      const uint32_t b13 = (uint32_t)(((13 - (lo + 1) % 13) * 7) % 13);
-      for (uint32_t u = threadIdx.x; u < kSegWords; u += blockDim.x) {
-        uint32_t w = pattern_word<3>(u, b3) | pattern_word<5>(u, b5) | pattern_word<7>(u, b7) |
-                     pattern_word<11>(u, b11) | pattern_word<13>(u, b13);
-        if (gs == 0 && u == 0) w &= ~0x6Eu;                         // 3, 5, 7, 11, 13 are prime
+      const uint32_t u0 = threadIdx.x;
+      uint32_t p3 = pat_phase<3>(lo, u0), p5 = pat_phase<5>(lo, u0), p7 = pat_phase<7>(lo, u0);
+      uint32_t p11 = pat_phase<11>(lo, u0), p13 = pat_phase<13>(lo, u0), p17 = pat_phase<17>(lo, u0);
+      uint32_t p19 = pat_phase<19>(lo, u0), p23 = pat_phase<23>(lo, u0), p29 = pat_phase<29>(lo, u0);
+      uint32_t p31 = pat_phase<31>(lo, u0);
+      constexpr uint32_t T = kSieveThreads;
+      for (uint32_t u = u0; u < kSegWords; u += T) {
+        uint32_t w = pat_next<3, T>(p3) | pat_next<5, T>(p5) | pat_next<7, T>(p7) | pat_next<11, T>(p11) |
+                     pat_next<13, T>(p13) | pat_next<17, T>(p17) | pat_next<19, T>(p19) | pat_next<23, T>(p23) |
+                     pat_next<29, T>(p29) | pat_next<31, T>(p31);
+        if (gs == 0 && u == 0) w &= ~kPatPrimeBits;
         bits[u] = w;
       }
     }
@@ -357,14 +374,18 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 }
 
 // Ordered compaction of the prime flags: 256 consecutive words per step, so reads are
-// coalesced and each step's primes land in one contiguous run of the table.  The bit positions
-// of a step's primes are gathered in LDS first, so the table is written with consecutive lanes
-// at consecutive addresses.
+// coalesced and each step's primes land in one contiguous run of the table.  Each wavefront
+// scans its 64 words with cross-lane operations, gathers the bit positions of their primes in its
+// own LDS region and writes them with consecutive lanes at consecutive addresses; the only
+// workgroup barrier per step publishes the wavefronts' totals (double-buffered by step parity).
 __global__ __launch_bounds__(256) void k_compact_primes(uint64_t seg0, uint64_t n_seg, const uint32_t* __restrict__ flags,
                                                         const uint64_t* __restrict__ off,
                                                         uint64_t* __restrict__ primes, uint64_t cap) {
-  __shared__ uint32_t sh[32];
-  __shared__ uint16_t pos_bits[256 * 32];   // a step's primes: bit index within the step
+  constexpr uint32_t kWaves = 256 / kWave;
+  __shared__ uint32_t wtot[2][kWaves];
+  __shared__ uint16_t pos_bits[kWaves][kWave * 32];   // a wavefront's primes: bit index in its words
+  const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t parity = 0;
   for (uint64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
     uint64_t base = off[s];
     if (seg0 + s == 0) {
@@ -372,23 +393,47 @@ __global__ __launch_bounds__(256) void k_compact_primes(uint64_t seg0, uint64_t 
       base += 1;
     }
     const uint64_t lo = (seg0 + s) << kSegLog;
-    for (uint32_t step = 0; step < kSegWords / 256; ++step) {
-      uint32_t m = flags[s * kSegWords + step * 256 + threadIdx.x];
-      uint32_t tot;
-      uint32_t k = block_exclusive_scan(__popc(m), sh, &tot);     // ends with a barrier
-      while (m) {
-        const uint32_t b = __ffs(m) - 1;
-        m &= m - 1;
-        pos_bits[k++] = (uint16_t)(threadIdx.x * 32 + b);
+    constexpr uint32_t kAhead = 4;                               // steps whose words are loaded together
+    static_assert((kSegWords / 256) % kAhead == 0, "whole batches of steps");
+    for (uint32_t step0 = 0; step0 < kSegWords / 256; step0 += kAhead) {
+      uint32_t mw[kAhead];
+#pragma unroll
+      for (uint32_t i = 0; i < kAhead; ++i) mw[i] = flags[s * kSegWords + (step0 + i) * 256 + threadIdx.x];
+#pragma unroll
+      for (uint32_t i = 0; i < kAhead; ++i, parity ^= 1) {
+        const uint32_t step = step0 + i;
+        uint32_t m = mw[i];
+        const uint32_t c = __popc(m);
+        uint32_t x = c;                                          // inclusive scan over the wavefront
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o, kWave);
+          if (lane >= (uint32_t)o) x += y;
+        }
+        const uint32_t wave_total = __shfl(x, kWave - 1, kWave);
+        uint32_t k = x - c;
+        while (m) {
+          const uint32_t b = __ffs(m) - 1;
+          m &= m - 1;
+          pos_bits[wid][k++] = (uint16_t)(lane * 32 + b);
+        }
+        if (lane == 0) wtot[parity][wid] = wave_total;
+        __syncthreads();
+        uint64_t wbase = base;
+        uint32_t step_total = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kWaves; ++w) {
+          const uint32_t t = wtot[parity][w];
+          if (w < wid) wbase += t;
+          step_total += t;
+        }
+        const uint64_t wave_lo = lo + 2ull * (step * 256 + wid * kWave) * 32 + 1;
+        for (uint32_t t = lane; t < wave_total; t += kWave) {
+          const uint64_t g = wbase + t;
+          if (g < cap) primes[g] = wave_lo + 2ull * pos_bits[wid][t];
+        }
+        base += step_total;
       }
-      __syncthreads();
-      const uint64_t step_lo = lo + 2ull * step * 256 * 32 + 1;
-      for (uint32_t t = threadIdx.x; t < tot; t += blockDim.x) {
-        const uint64_t g = base + t;
-        if (g < cap) primes[g] = step_lo + 2ull * pos_bits[t];
-      }
-      base += tot;
-      __syncthreads();                                             // pos_bits reusable
     }
   }
 }
@@ -1914,39 +1959,64 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
 // row (each lane takes 32 columns = one bitmap word at a time), and clears them for the next call.
 // Every counter is below 256 (the plan admits the counters only when no number of the interval
 // can have more distinct prime factors above the threshold), so the byte sums never carry.
+// One 32-byte group of counters (32 column slots): its bitmap word and the sum of its counts.
+__device__ __forceinline__ uint32_t fold_group(const uint4 a, const uint4 b, uint32_t* sum) {
+  const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t bits = 0, s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t x = v[q];
+    bits |= (((x & 0xffu) ? 1u : 0u) | ((x & 0xff00u) ? 2u : 0u) | ((x & 0xff0000u) ? 4u : 0u) |
+             ((x & 0xff000000u) ? 8u : 0u)) << (4 * q);
+    const uint32_t h = (x & 0x00ff00ffu) + ((x >> 8) & 0x00ff00ffu);   // two 16-bit pair sums
+    s += (h & 0xffffu) + (h >> 16);
+  }
+  *sum += s;
+  return bits;
+}
+
+// One wavefront per row; each lane loads two 32-byte groups before folding either, so twice
+// the bytes are in flight per wavefront.
 __global__ __launch_bounds__(256) void k_fold_bytes(const JobDev* __restrict__ jobs) {
   const JobDev& j = jobs[blockIdx.y];
   if (!j.hitbytes) return;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t waves = blockDim.x / kWave;
+  const bool clear = !j.fold_keep;
+  const uint32_t rw = j.row_words;
   for (uint64_t row = blockIdx.x * (uint64_t)waves + threadIdx.x / kWave; row < j.n_m;
        row += (uint64_t)gridDim.x * waves) {
-    uint4* __restrict__ src = (uint4*)(gbl(j.hitbytes) + row * j.row_words * 32ull);
-    const gptr<uint32_t> dst = gbl(j.bitmap) + row * j.row_words;
-    unsigned long long sum = 0;
-    for (uint32_t wi = lane; wi < j.row_words; wi += kWave) {
-      const uint4 a = src[2 * wi], b = src[2 * wi + 1];
-      const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-      uint32_t bits = 0, s = 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const uint32_t x = v[q];
-        bits |= (((x & 0xffu) ? 1u : 0u) | ((x & 0xff00u) ? 2u : 0u) | ((x & 0xff0000u) ? 4u : 0u) |
-                 ((x & 0xff000000u) ? 8u : 0u)) << (4 * q);
-        const uint32_t h = (x & 0x00ff00ffu) + ((x >> 8) & 0x00ff00ffu);   // two 16-bit pair sums
-        s += (h & 0xffffu) + (h >> 16);
+    uint4* __restrict__ src = (uint4*)(gbl(j.hitbytes) + row * rw * 32ull);
+    const gptr<uint32_t> dst = gbl(j.bitmap) + row * rw;
+    uint32_t sum = 0;                       // at most 255 x 32 per group a lane folds
+    for (uint32_t w0 = lane; w0 < rw; w0 += 2 * kWave) {
+      const uint32_t w1 = w0 + kWave;
+      const bool has1 = w1 < rw;
+      const uint4 a0 = src[2 * w0], b0 = src[2 * w0 + 1];
+      uint4 a1 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+      if (has1) {
+        a1 = src[2 * w1];
+        b1 = src[2 * w1 + 1];
       }
-      if (bits) {
-        if (!j.fold_keep) {
-          src[2 * wi] = make_uint4(0, 0, 0, 0);
-          src[2 * wi + 1] = make_uint4(0, 0, 0, 0);
+      const uint32_t bits0 = fold_group(a0, b0, &sum);
+      const uint32_t bits1 = fold_group(a1, b1, &sum);
+      if (bits0) {
+        if (clear) {
+          src[2 * w0] = make_uint4(0, 0, 0, 0);
+          src[2 * w0 + 1] = make_uint4(0, 0, 0, 0);
         }
-        dst[wi] |= bits;
+        dst[w0] |= bits0;
       }
-      sum += s;
+      if (bits1) {
+        if (clear) {
+          src[2 * w1] = make_uint4(0, 0, 0, 0);
+          src[2 * w1 + 1] = make_uint4(0, 0, 0, 0);
+        }
+        dst[w1] |= bits1;
+      }
     }
-    sum = wave_sum_u64(sum);
-    if (lane == 0 && sum) gbl(j.counts)[row] += (uint32_t)sum;
+    const unsigned long long tot = wave_sum_u64(sum);
+    if (lane == 0 && tot) gbl(j.counts)[row] += (uint32_t)tot;
   }
 }
 
@@ -2308,12 +2378,12 @@ hipError_t launch_primes_range(uint64_t seg0, uint64_t lim, const PrimeWs& pw, h
     p2.cap = pw.cap2;
     hipError_t e = launch_primes_range(0, pw.isq, p2, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sieve_segments<true, uint64_t, uint64_t>), dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg,
+    hipLaunchKernelGGL((k_sieve_segments<true, uint64_t, uint64_t>), dim3(seg_blocks), dim3(kSieveThreads), 0, s, lim, seg0, n_seg,
                        (const uint64_t*)pw.base2, (const uint64_t*)pw.n_base2, pw.flags, pw.seg_count);
     { hipError_t e_ = note("k_sieve_segments<wide>"); if (e_ != hipSuccess) return e_; }
   } else {
     hipLaunchKernelGGL(k_base_primes, dim3(1), dim3(1024), 0, s, lim, pw.base, pw.n_base); { hipError_t e_ = note("k_base_primes"); if (e_ != hipSuccess) return e_; }
-    hipLaunchKernelGGL((k_sieve_segments<false, uint32_t, uint32_t>), dim3(seg_blocks), dim3(512), 0, s, lim, seg0, n_seg,
+    hipLaunchKernelGGL((k_sieve_segments<false, uint32_t, uint32_t>), dim3(seg_blocks), dim3(kSieveThreads), 0, s, lim, seg0, n_seg,
                        (const uint32_t*)pw.base, (const uint32_t*)pw.n_base, pw.flags, pw.seg_count);
     { hipError_t e_ = note("k_sieve_segments"); if (e_ != hipSuccess) return e_; }
   }
