@@ -244,19 +244,29 @@ struct GCache {
 CS_HD void g_cache_build(double p, double K, double width, GCache* c) {
   c->p0 = p;
   c->mir = 0;
-  int i = 0;
-  for (; i < kGCache; ++i) {
+  int depth = 0;
+  bool done = false;
+  // every level index is a constant after unrolling, so the cache can live in registers
+#pragma unroll
+  for (int i = 0; i < kGCache; ++i) {
     const bool mir = K + K >= p;
     const double km = mir ? p - K : K;
+    const double inv = recip1(km);
     c->km[i] = km;
-    c->inv[i] = recip1(km);
-    if (mir) c->mir |= 1u << i;
-    if (km <= width + 1.0) { ++i; break; }                      // every L ends at this level
-    const double pm = fma(-floor(p * c->inv[i]), km, p);        // p mod km, in [1, km - 1]
-    p = km;
-    K = km - pm;
+    c->inv[i] = inv;
+    if (!done) {
+      if (mir) c->mir |= 1u << i;
+      depth = i + 1;
+      if (km <= width + 1.0) {
+        done = true;                                            // every L ends at this level
+      } else {
+        const double pm = fma(-floor(p * inv), km, p);          // p mod km, in [1, km - 1]
+        p = km;
+        K = km - pm;
+      }
+    }
   }
-  c->depth = i;
+  c->depth = depth;
   c->p_next = p;
   c->K_next = K;
 }
