@@ -281,6 +281,34 @@ __device__ __forceinline__ void q_sub_if_ge(uint32_t (&t)[L], uint32_t top, cons
   }
 }
 
+// One row of the Montgomery product, t = t + x * y (y one limb), over this lane's limbs, with
+// c_in entering limb 0; returns the carry out of the top limb.  Each limb of t sits in the low
+// half of a 64-bit word whose high half stays 0, so x_j * y + t_j is one v_mad_u64_u32 that
+// cannot overflow; the high halves of the products then go up one limb in a single
+// add-with-carry chain.  SHIFT: the result is written one limb down (limb j + 1 into word j;
+// limb 0 is returned through low0), which is the division by 2^32 of the reduction step.
+template <int L, bool SHIFT>
+__device__ __forceinline__ uint32_t q_row(uint64_t (&T)[L], const uint32_t (&x)[L], uint32_t y, uint32_t c_in,
+                                          uint32_t* low0) {
+  uint32_t prev = c_in, cy = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t D = (uint64_t)x[j] * y + T[j];
+    uint32_t co;
+    const uint32_t v = __builtin_addc((uint32_t)D, prev, cy, &co);
+    cy = co;
+    prev = (uint32_t)(D >> 32);
+    // (the high halves keep their zero register: only the low half is replaced)
+    if (SHIFT) {
+      if (j == 0) *low0 = v;
+      else T[j - 1] = (T[j - 1] & 0xffffffff00000000ull) | v;
+    } else {
+      T[j] = (T[j] & 0xffffffff00000000ull) | v;
+    }
+  }
+  return prev + cy;          // the lane's part of the sum fits in L + 1 limbs
+}
+
 // a = a*a/R mod n (R = 2^(32 NL)), a < n; col: this quad's LDS columns (lane o's limb l at
 // col[l * kPrpBlock + o]), where a is written first so every lane can read the multiplier limbs.
 template <int L>
@@ -289,41 +317,31 @@ __device__ __forceinline__ void q_mont_sqr(uint32_t (&a)[L], const uint32_t (&n)
   // (own and col overlap: the writes must stay before the reads)
 #pragma unroll
   for (int j = 0; j < L; ++j) own[j * kPrpBlock] = a[j];
-  uint32_t t[L];
+  uint64_t T[L];
 #pragma unroll
-  for (int j = 0; j < L; ++j) t[j] = 0;
+  for (int j = 0; j < L; ++j) T[j] = 0;
   uint32_t pc = 0, top = 0;
 #pragma unroll 1
   for (int i = 0; i < 4 * L; ++i) {
     const int o = i / L, l = i - o * L;
     const uint32_t bi = col[l * kPrpBlock + o];      // limb i of the multiplier (owner lane o)
-    uint32_t c = q_from_prev(pc, r);                  // pending carry into this lane's limb 0
-#pragma unroll
-    for (int j = 0; j < L; ++j) {                     // t += a * b_i
-      const uint64_t s = (uint64_t)a[j] * bi + t[j] + c;
-      t[j] = (uint32_t)s;
-      c = (uint32_t)(s >> 32);
-    }
-    const uint32_t ca = c;
-    const uint32_t q = q_bcast<0>(t[0] * ninv);      // lane 0's limb 0 is exact: t + q n = 0 mod 2^32
-    c = 0;
-#pragma unroll
-    for (int j = 0; j < L; ++j) {                     // t += q * n
-      const uint64_t s = (uint64_t)q * n[j] + t[j] + c;
-      t[j] = (uint32_t)s;
-      c = (uint32_t)(s >> 32);
-    }
-    // t /= 2^32: lane r + 1's limb 0 (lane 3: the word above) and this lane's pending carries
-    // become this lane's top limb
-    const uint32_t up = q_from_next(t[0]);
-#pragma unroll
-    for (int j = 0; j < L - 1; ++j) t[j] = t[j + 1];
+    // t += a * b_i, with the pending carry into this lane's limb 0
+    const uint32_t ca = q_row<L, false>(T, a, bi, q_from_prev(pc, r), nullptr);
+    const uint32_t q = q_bcast<0>((uint32_t)T[0] * ninv);   // lane 0's limb 0 is exact: t + q n = 0 mod 2^32
+    // t = (t + q n) / 2^32: this lane's limbs move down one; lane r + 1's limb 0 (lane 3: the word
+    // above) and this lane's pending carries become this lane's top limb
+    uint32_t low0;
+    const uint32_t c = q_row<L, true>(T, n, q, 0u, &low0);
+    const uint32_t up = q_from_next(low0);
     const uint64_t h = (uint64_t)(r == 3 ? top : up) + ca + c;
-    t[L - 1] = (uint32_t)h;
+    T[L - 1] = (T[L - 1] & 0xffffffff00000000ull) | (uint32_t)h;
     pc = (uint32_t)(h >> 32);
     if (r == 3) top = pc;
   }
   if (r == 3) pc = 0;                                 // lane 3's carry is `top` already
+  uint32_t t[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) t[j] = (uint32_t)T[j];
   q_resolve<L>(t, pc, top, r);
   q_sub_if_ge<L>(t, top, n, r);
 #pragma unroll
