@@ -629,8 +629,16 @@ __global__ __launch_bounds__(kPrpBlock) void k_sv_test(SurroundDev sv, uint32_t 
 }
 
 // The same on a quad of lanes per candidate (NL = 4L limbs).
+// Wavefronts per SIMD the register allocation of k_sv_test_q aims for: at 10 to 12 limbs per
+// lane (numbers of 1,280 to 1,536 bits) the squaring loop fits in 96 VGPRs without spills (only a
+// few values of the per-squaring carry resolution go to scratch), for five wavefronts instead of
+// four; elsewhere the compiler's own choice.
 template <int L>
-__global__ __launch_bounds__(kPrpBlock) void k_sv_test_q(SurroundDev sv, uint32_t in, uint64_t n_slots, uint32_t B) {
+constexpr int sv_min_waves() { return (L >= 10 && L <= 12) ? 5 : 1; }
+
+template <int L>
+__global__ __launch_bounds__(kPrpBlock) __attribute__((amdgpu_waves_per_eu(sv_min_waves<L>())))
+void k_sv_test_q(SurroundDev sv, uint32_t in, uint64_t n_slots, uint32_t B) {
   extern __shared__ uint32_t lds[];
   const uint64_t sidx = (blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x) / 4;
   if (sidx >= n_slots) return;                       // whole quads leave together
