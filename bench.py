@@ -352,7 +352,8 @@ def _valu_issue(mode):
 
 def _prp_leg(cs, torch, np, job, bitmap, n_rows, stream):
     """Surrounding probable primes of the first n_rows sieved rows (cs_surround): each side of a
-    row is searched outward among its unmarked columns with the strong base-2 test."""
+    row is searched outward among its unmarked columns with the strong base-2 test, and the number
+    found is checked with the strong Lucas test (BPSW)."""
     ms = cs.rows(job)[:n_rows]
     m_dev = torch.from_numpy(ms.astype(np.int64)).cuda()
     rows = bitmap[:n_rows]
@@ -373,6 +374,7 @@ def _prp_leg(cs, torch, np, job, bitmap, n_rows, stream):
             "tests_run": st.tests, "tests_per_s": st.tests / sec, "useful_tests_per_s": useful / sec,
             "rounds": st.rounds, "limbs": st.limbs, "bits": st.bits, "rows_both_found": int(both.sum()),
             "mean_gap": float(gaps.mean()) if len(gaps) else None, "max_gap": int(gaps.max()) if len(gaps) else None,
+            "lucas_tests": st.lucas_tests, "lucas_passes": st.lucas_passes, "lucas_ms": st.lucas_ms,
             "roofline": {"bound": "alu", "kernel": "k_sv_test", "achieved": mads / (st.test_ms / 1e3) / 1e12,
                          "peak": MAD_PEAK / 1e12, "unit": "T v_mad_u64_u32/s",
                          "frac": mads / (st.test_ms / 1e3) / MAD_PEAK, "test_ms": st.test_ms, "traffic": None}}

@@ -303,13 +303,32 @@ cs_status cs_probe_scatter(uint32_t* d_buf, uint64_t words, uint64_t n_ops, uint
  * buffers; enqueued on `stream`, no workspace. */
 cs_status cs_prp_numbers(const uint32_t* d_limbs, uint32_t n_limbs, uint64_t n, uint8_t* d_out, void* stream);
 
+/* The tests of BPSW (Section 2.2: the paper's search tests with GMP's probable-prime routine, a
+ * BPSW test).  CS_PRP_SPRP2 is the strong test to base 2 above.  CS_PRP_LUCAS is the strong Lucas
+ * test with Selfridge's parameters: D the first of 5, -7, 9, -11, ... with Jacobi symbol
+ * (D/n) = -1, P = 1, Q = (1 - D)/4; with n + 1 = 2^s d, d odd, n passes iff U_d = 0 or
+ * V_(2^r d) = 0 (mod n) for some 0 <= r < s, where U, V are the Lucas sequences of (P, Q).  Even
+ * n other than 2, 0, 1, perfect squares and n with (D/n) = 0 for some |D| != n before a D with
+ * (D/n) = -1 fail.  (Under the generalised Riemann hypothesis every other n < 2^2048 has such a
+ * D below 2^23; a search reaching 2^23 reports n composite, and a perfect square of 2^32 or more
+ * is found composite that way, after about 4 million Jacobi symbols.)  CS_PRP_BPSW: both (the
+ * Lucas test only for numbers passing the first); no composite is known to pass. */
+#define CS_PRP_SPRP2 0u
+#define CS_PRP_LUCAS 1u
+#define CS_PRP_BPSW  2u
+
+/* cs_prp_numbers with a choice of test (CS_PRP_*; CS_EINVAL for another value); same buffers,
+ * limits and errors.  The Lucas and BPSW tests take a quad of lanes per number. */
+cs_status cs_prp_test(const uint32_t* d_limbs, uint32_t n_limbs, uint64_t n, uint32_t test, uint8_t* d_out,
+                      void* stream);
+
 /* Result of the surrounding-prime search for one row, N = m*K. */
 typedef struct cs_surround_row {
-  int32_t prev;         /* largest X < 0 with N + X a probable prime, searched among the unmarked
-                           columns in [-sl, -1]; 0 if there is none */
+  int32_t prev;         /* largest X < 0 with N + X a BPSW probable prime, searched among the
+                           unmarked columns in [-sl, -1]; 0 if there is none */
   int32_t next;         /* smallest such X > 0 in [1, sl]; 0 if none */
   uint32_t tests_prev;  /* unmarked columns on that side up to and including prev (all of them
-                           when prev = 0): the tests a sequential search runs */
+                           when prev = 0): the strong tests to base 2 a sequential search runs */
   uint32_t tests_next;
 } cs_surround_row;
 
@@ -320,17 +339,25 @@ typedef struct cs_surround_stats {
   uint64_t bits;        /* bit length of K plus that of the largest m: every N + X tested has
                            this many bits or one fewer (one more only if X > 0 carries) */
   double test_ms;       /* time of the test kernels alone (HIP events on `stream`) */
+  uint64_t lucas_tests; /* strong Lucas tests run: every pass tests each side that holds a
+                           probable prime */
+  uint64_t lucas_passes;/* passes of the Lucas test over the sides (more than one only when a
+                           strong pseudoprime to base 2 was found and its side searched on) */
+  double lucas_ms;      /* time of the Lucas passes (HIP events on `stream`) */
 } cs_surround_stats;
 
 /* Workspace bytes of cs_surround for n_rows rows of this job (host only). */
 cs_status cs_surround_ws(const cs_job* job, uint64_t n_rows, uint64_t* ws_bytes);
 
-/* Surrounding probable primes of n_rows rows of a sieved job.
+/* Surrounding probable primes of n_rows rows of a sieved job: the nearest BPSW probable primes on
+ * both sides of N = m K.
  * d_bitmap: n_rows rows of row_words words in cs_sieve's layout (1 = marked composite), the
  * rows to search (e.g. a slice of cs_sieve's bitmap); d_m[i]: the m of row i, within
  * [m_start, m_start + m_inc) (a device-side check reports CS_EDEVICE otherwise); d_out: n_rows
- * results.  Candidates per side are tested in rounds of up to 1024 at once and the first
- * probable prime in walking order wins, so results equal a sequential search's.
+ * results.  Candidates per side are tested with the strong test to base 2 in rounds of up to
+ * 1024 at once and the first probable prime in walking order is kept; the strong Lucas test then
+ * checks each side's number, and a side whose number fails searches on past it, so results equal
+ * a sequential BPSW search's.
  * N = m K + sl must stay below 2^2048 (CS_ERANGE).  Synchronous: returns after the work has
  * completed (one host read of a counter per round).  stats may be NULL. */
 cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, const uint64_t* d_m, uint64_t n_rows,

@@ -144,7 +144,8 @@ def _diag_of(out) -> Diag:
 
 class cs_surround_stats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("tests", C.c_uint64), ("limbs", C.c_uint64), ("bits", C.c_uint64),
-                ("test_ms", C.c_double)]
+                ("test_ms", C.c_double), ("lucas_tests", C.c_uint64), ("lucas_passes", C.c_uint64),
+                ("lucas_ms", C.c_double)]
 
 
 @dataclass
@@ -154,6 +155,9 @@ class SurroundStats:
     limbs: int
     bits: int
     test_ms: float
+    lucas_tests: int = 0
+    lucas_passes: int = 0
+    lucas_ms: float = 0.0
 
 
 _lib = None
@@ -207,6 +211,7 @@ def lib():
         "cs_server_stats": ([vp, P(cs_server_counters)], i32),
         "cs_server_destroy": ([vp], i32),
         "cs_prp_numbers": ([vp, u32, u64, vp, vp], i32),
+        "cs_prp_test": ([vp, u32, u64, u32, vp, vp], i32),
         "cs_surround_ws": ([P(cs_job), u64, P(u64)], i32),
         "cs_surround": ([P(cs_job), vp, vp, u64, vp, vp, u64, P(cs_surround_stats), vp], i32),
         "cs_probe_scatter": ([vp, u64, u64, u32, u32, u64, vp], i32),
@@ -558,6 +563,22 @@ def prp_numbers(limbs, stream=None):
     return out
 
 
+PRP_SPRP2 = 0
+PRP_LUCAS = 1
+PRP_BPSW = 2
+
+
+def prp_test(limbs, test: int = PRP_BPSW, stream=None):
+    """cs_prp_test: the strong test to base 2, the strong Lucas test or BPSW (PRP_*) of the numbers
+    in a device int32 tensor [n, n_limbs] of little-endian 32-bit limbs.  Returns a device uint8
+    tensor [n]."""
+    import torch
+    n, nl = limbs.shape
+    out = torch.empty((n,), dtype=torch.uint8, device=limbs.device)
+    _check(lib().cs_prp_test(_ptr(limbs.contiguous()), nl, n, test, _ptr(out), _stream(stream)), "cs_prp_test")
+    return out
+
+
 def surround_ws_bytes(job, n_rows: int) -> int:
     out = C.c_uint64()
     _check(lib().cs_surround_ws(C.byref(_cjob(job)), n_rows, C.byref(out)), "cs_surround_ws")
@@ -565,7 +586,7 @@ def surround_ws_bytes(job, n_rows: int) -> int:
 
 
 def surround(job, bitmap, m_rows, ws=None, stream=None):
-    """Nearest probable primes below and above N = m*K for each row (cs_surround).  bitmap: device
+    """Nearest BPSW probable primes below and above N = m*K for each row (cs_surround).  bitmap: device
     int32 [n_rows, row_words] (sieved rows); m_rows: device int64 [n_rows] (the m of each row).
     Returns (device int32 tensor [n_rows, 4] = prev, next, tests_prev, tests_next; SurroundStats).
     The call returns after the work has completed."""
@@ -577,7 +598,8 @@ def surround(job, bitmap, m_rows, ws=None, stream=None):
     st = cs_surround_stats()
     _check(lib().cs_surround(C.byref(_cjob(job)), _ptr(bitmap), _ptr(m_rows), n, _ptr(out), _ptr(ws), ws.numel(),
                              C.byref(st), _stream(stream)), "cs_surround")
-    return out[:n], SurroundStats(st.rounds, st.tests, st.limbs, st.bits, st.test_ms)
+    return out[:n], SurroundStats(st.rounds, st.tests, st.limbs, st.bits, st.test_ms, st.lucas_tests,
+                                  st.lucas_passes, st.lucas_ms)
 
 
 PROBE_ATOMIC = 0

@@ -309,14 +309,14 @@ __device__ __forceinline__ uint32_t q_row(uint64_t (&T)[L], const uint32_t (&x)[
   return prev + cy;          // the lane's part of the sum fits in L + 1 limbs
 }
 
-// a = a*a/R mod n (R = 2^(32 NL)), a < n; col: this quad's LDS columns (lane o's limb l at
-// col[l * kPrpBlock + o]), where a is written first so every lane can read the multiplier limbs.
+// a = a*b/R mod n (R = 2^(32 NL)), a, b < n; col: this quad's LDS columns (lane o's limb l at
+// col[l * kPrpBlock + o]), where b is written first so every lane can read the multiplier limbs.
 template <int L>
-__device__ __forceinline__ void q_mont_sqr(uint32_t (&a)[L], const uint32_t (&n)[L], uint32_t ninv, uint32_t r,
-                                           uint32_t* own, const uint32_t* col) {
+__device__ __forceinline__ void q_mont_mul(uint32_t (&a)[L], const uint32_t (&b)[L], const uint32_t (&n)[L],
+                                           uint32_t ninv, uint32_t r, uint32_t* own, const uint32_t* col) {
   // (own and col overlap: the writes must stay before the reads)
 #pragma unroll
-  for (int j = 0; j < L; ++j) own[j * kPrpBlock] = a[j];
+  for (int j = 0; j < L; ++j) own[j * kPrpBlock] = b[j];
   uint64_t T[L];
 #pragma unroll
   for (int j = 0; j < L; ++j) T[j] = 0;
@@ -346,6 +346,13 @@ __device__ __forceinline__ void q_mont_sqr(uint32_t (&a)[L], const uint32_t (&n)
   q_sub_if_ge<L>(t, top, n, r);
 #pragma unroll
   for (int j = 0; j < L; ++j) a[j] = t[j];
+}
+
+// a = a*a/R mod n.
+template <int L>
+__device__ __forceinline__ void q_mont_sqr(uint32_t (&a)[L], const uint32_t (&n)[L], uint32_t ninv, uint32_t r,
+                                           uint32_t* own, const uint32_t* col) {
+  q_mont_mul<L>(a, a, n, ninv, r, own, col);
 }
 
 // a = 2a mod n for a < n.
@@ -461,6 +468,299 @@ __device__ bool q_sprp2(const uint32_t (&n)[L], uint32_t r, uint32_t* own, const
   return false;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Strong Lucas test on a quad of lanes (the second half of BPSW).  Section 2.2: the search tests
+// with GMP's probable-prime routine, a BPSW test.  Parameters after Selfridge: D the first of 5,
+// -7, 9, -11, ... with Jacobi symbol (D/n) = -1, P = 1, Q = (1 - D)/4; with n + 1 = 2^s d, d odd,
+// n passes iff U_d = 0 or V_(2^r d) = 0 (mod n) for some 0 <= r < s.  U, V and Q^k run in
+// Montgomery form through the doubling formulas U_2k = U_k V_k, V_2k = V_k^2 - 2Q^k and the step
+// U_(k+1) = (U_k + V_k)/2, V_(k+1) = (D U_k + V_k)/2.
+// ---------------------------------------------------------------------------------------------
+// Searched values of |D|: a non-square n has (D/n) = -1 for some |D| below 2 (ln n)^2 under the
+// generalised Riemann hypothesis (4.1e6 for n < 2^2048); a search that reaches the bound reports
+// n composite, which a perfect square (for which no such D exists) is.
+constexpr uint32_t kLucasDMax = 1u << 23;
+
+// Sum of a quad-uniform reduction: every lane gets v0 + v1 + v2 + v3 of its quad.
+__device__ __forceinline__ uint64_t q_sum64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  uint64_t x = ((uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0xb1, 0xf, 0xf, false) << 32) |
+               (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0xb1, 0xf, 0xf, false);     // (1, 0, 3, 2)
+  v += x;
+  lo = (uint32_t)v;
+  hi = (uint32_t)(v >> 32);
+  x = ((uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x4e, 0xf, 0xf, false) << 32) |
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x4e, 0xf, 0xf, false);              // (2, 3, 0, 1)
+  return v + x;
+}
+
+// n mod q for 2 < q < 2^32 (q odd), n spread over the quad.
+template <int L>
+__device__ __forceinline__ uint32_t q_mod_u32(const uint32_t (&n)[L], uint32_t q, uint32_t r) {
+  const uint64_t b = (uint64_t)(((uint64_t)1 << 32) % q);    // 2^32 mod q
+  uint64_t w = 1;                                             // 2^(32 g) mod q for this lane's first limb
+  for (uint32_t g = 0; g < r * L; ++g) w = w * b % q;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    acc = (acc + (uint64_t)(n[j] % q) * w) % q;
+    w = w * b % q;
+  }
+  return (uint32_t)(q_sum64(acc) % q);
+}
+
+// Jacobi symbol (a/m) for odd m > 0, a < m (quadratic reciprocity and the rule for (2/m)).
+__device__ __forceinline__ int jacobi_u32(uint32_t a, uint32_t m) {
+  int t = 1;
+  while (a != 0) {
+    while ((a & 1u) == 0) {
+      a >>= 1;
+      const uint32_t m8 = m & 7u;
+      if (m8 == 3 || m8 == 5) t = -t;
+    }
+    const uint32_t tmp = a;
+    a = m;
+    m = tmp;
+    if ((a & 3u) == 3 && (m & 3u) == 3) t = -t;
+    a %= m;
+  }
+  return m == 1 ? t : 0;
+}
+
+// t = a + b mod n for a, b < n.
+template <int L>
+__device__ __forceinline__ void q_mod_add(uint32_t (&t)[L], const uint32_t (&a)[L], const uint32_t (&b)[L],
+                                          const uint32_t (&n)[L], uint32_t r) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t v = (uint64_t)a[j] + b[j] + c;
+    t[j] = (uint32_t)v;
+    c = (uint32_t)(v >> 32);
+  }
+  uint32_t top = 0;
+  q_resolve<L>(t, c, top, r);
+  q_sub_if_ge<L>(t, top, n, r);
+}
+
+// t = a - b mod n for a, b < n: a + (2^(32 NL) - b), then n added back if that did not carry out.
+template <int L>
+__device__ __forceinline__ void q_mod_sub(uint32_t (&t)[L], const uint32_t (&a)[L], const uint32_t (&b)[L],
+                                          const uint32_t (&n)[L], uint32_t r) {
+  uint32_t c = r == 0 ? 1u : 0u;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t v = (uint64_t)a[j] + (uint32_t)~b[j] + c;
+    t[j] = (uint32_t)v;
+    c = (uint32_t)(v >> 32);
+  }
+  uint32_t top = 0;
+  q_resolve<L>(t, c, top, r);
+  if (q_bcast<3>(top) != 0) return;                   // a >= b
+  c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint64_t v = (uint64_t)t[j] + n[j] + c;
+    t[j] = (uint32_t)v;
+    c = (uint32_t)(v >> 32);
+  }
+  uint32_t drop = 0;                                  // the carry out of 2^(32 NL)
+  q_resolve<L>(t, c, drop, r);
+}
+
+// a = a / 2 mod n for a < n, n odd: (a + n) / 2 when a is odd.
+template <int L>
+__device__ __forceinline__ void q_half(uint32_t (&a)[L], const uint32_t (&n)[L], uint32_t r) {
+  uint32_t top = 0;
+  if (q_bcast<0>(a[0]) & 1u) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint64_t v = (uint64_t)a[j] + n[j] + c;
+      a[j] = (uint32_t)v;
+      c = (uint32_t)(v >> 32);
+    }
+    q_resolve<L>(a, c, top, r);
+  }
+  const uint32_t next_low = q_from_next(a[0]);        // lane r + 1's limb 0 (lane 3: the carry word)
+  const uint32_t in_bit = (r == 3 ? top : next_low) & 1u;
+#pragma unroll
+  for (int j = 0; j < L - 1; ++j) a[j] = (a[j] >> 1) | (a[j + 1] << 31);
+  a[L - 1] = (a[L - 1] >> 1) | (in_bit << 31);
+}
+
+template <int L>
+__device__ __forceinline__ bool q_is_zero(const uint32_t (&a)[L]) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) d |= a[j];
+  return q_all(d == 0);
+}
+
+// c R mod n for a small signed c, from one = R mod n by doubling and adding.
+template <int L>
+__device__ __forceinline__ void q_mont_small(uint32_t (&t)[L], int32_t c, const uint32_t (&one)[L],
+                                             const uint32_t (&n)[L], uint32_t r) {
+  const uint32_t a = (uint32_t)(c < 0 ? -c : c);
+#pragma unroll
+  for (int j = 0; j < L; ++j) t[j] = 0;
+  for (int bit = 31 - __clz(a); bit >= 0; --bit) {
+    q_mod_dbl<L>(t, n, r);
+    if ((a >> bit) & 1u) q_mod_add<L>(t, t, one, n, r);
+  }
+  if (c < 0) {
+    uint32_t z[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) z[j] = 0;
+    q_mod_sub<L>(t, z, t, n, r);
+  }
+}
+
+// Strong Lucas probable-prime test of n (NL = 4L limbs spread over the quad); own/col as in
+// q_sprp2 (the second L words of each lane's column receive n + 1).
+template <int L>
+__device__ bool q_strong_lucas(const uint32_t (&n)[L], uint32_t r, uint32_t* own, const uint32_t* col) {
+  uint32_t hi_local = 0, ones = 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    hi_local |= (r == 0 && j == 0) ? 0u : n[j];
+    ones &= n[j];
+  }
+  const bool hi_zero = q_all(hi_local == 0);
+  const uint32_t n0 = q_bcast<0>(n[0]);
+  if (!(n0 & 1u)) return hi_zero && n0 == 2u;
+  if (hi_zero && n0 < 3u) return false;               // 1
+  if (q_all(ones == 0xffffffffu)) return false;       // 2^(32 NL) - 1: composite (32 NL is even)
+  if (hi_zero) {                                      // a square below 2^32 has no D below
+    const uint32_t s0 = (uint32_t)sqrt((double)n0);
+    for (uint32_t x = s0 > 0 ? s0 - 1 : 0; x <= s0 + 1; ++x)
+      if ((uint64_t)x * x == n0) return false;
+  }
+  // D: the first of 5, -7, 9, -11, ... with (D/n) = -1
+  int32_t D = 5;
+  for (;;) {
+    const uint32_t q = (uint32_t)(D < 0 ? -D : D);
+    const uint32_t nm = q_mod_u32<L>(n, q, r);
+    int j = jacobi_u32(nm, q);
+    if (j == 0) {
+      if (!(hi_zero && n0 == q)) return false;        // 1 < gcd(q, n) <= q < n: n is composite
+    } else {
+      // (|D|/n) = (n/|D|) (-1)^((|D|-1)/2 (n-1)/2); (-1/n) = (-1)^((n-1)/2)
+      if ((q & 3u) == 3 && (n0 & 3u) == 3) j = -j;
+      if (D < 0 && (n0 & 3u) == 3) j = -j;
+      if (j == -1) break;
+    }
+    if (q >= kLucasDMax) return false;
+    D = D > 0 ? -(D + 2) : -D + 2;
+  }
+  const int32_t Q = (1 - D) / 4;
+  // n + 1, kept in LDS for its bits; s = its trailing zeros, bl = its bit length
+  uint32_t np1[L];
+  {
+    uint32_t c = r == 0 ? 1u : 0u;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint64_t v = (uint64_t)n[j] + c;
+      np1[j] = (uint32_t)v;
+      c = (uint32_t)(v >> 32);
+    }
+    uint32_t top = 0;
+    q_resolve<L>(np1, c, top, r);                    // no carry out: n is not 2^(32 NL) - 1
+  }
+#pragma unroll
+  for (int j = 0; j < L; ++j) own[(L + j) * kPrpBlock] = np1[j];
+  uint32_t bl = 0, tz = 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint32_t g = r * L + j;
+    if (np1[j]) bl = 32 * g + 32 - __clz(np1[j]);
+    if (np1[j] && tz == 0xffffffffu) tz = 32 * g + __ffs(np1[j]) - 1;
+  }
+  const int bits = (int)q_max(bl);
+  const int s = (int)q_min(tz);
+  auto np1_bit = [&](int bit) -> uint32_t {
+    const int g = bit >> 5, o = g / L, l = g - o * L;
+    return (col[(L + l) * kPrpBlock + o] >> (bit & 31)) & 1u;
+  };
+  // Montgomery constants: ninv = -n^-1 mod 2^32; one = R mod n from the largest power of two below n
+  uint32_t inv = n0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) inv *= 2u - n0 * inv;
+  const uint32_t ninv = 0u - inv;
+  uint32_t nbl = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j)
+    if (n[j]) nbl = 32 * (r * L + j) + 32 - __clz(n[j]);
+  const int nbits = (int)q_max(nbl);
+  uint32_t one[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) one[j] = ((int)(r * L + j) == ((nbits - 1) >> 5)) ? (1u << ((nbits - 1) & 31)) : 0u;
+  for (int k = 0; k < 32 * 4 * L - nbits + 1; ++k) q_mod_dbl<L>(one, n, r);
+  uint32_t Dm[L], Qm[L];
+  q_mont_small<L>(Dm, D, one, n, r);
+  q_mont_small<L>(Qm, Q, one, n, r);
+  // U_1 = 1, V_1 = P = 1, Q^1; then the bits of d = (n + 1) / 2^s below its top bit
+  uint32_t U[L], V[L], Qk[L], t[L], w[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    U[j] = one[j];
+    V[j] = one[j];
+    Qk[j] = Qm[j];
+  }
+  for (int bit = bits - 2; bit >= s; --bit) {
+    q_mont_mul<L>(U, V, n, ninv, r, own, col);                        // U_2k = U_k V_k
+    q_mont_sqr<L>(V, n, ninv, r, own, col);
+    q_mod_add<L>(t, Qk, Qk, n, r);
+    q_mod_sub<L>(V, V, t, n, r);                                      // V_2k = V_k^2 - 2 Q^k
+    q_mont_sqr<L>(Qk, n, ninv, r, own, col);                          // Q^2k
+    if (np1_bit(bit)) {
+#pragma unroll
+      for (int j = 0; j < L; ++j) w[j] = U[j];
+      q_mont_mul<L>(w, Dm, n, ninv, r, own, col);                     // D U_k
+      q_mod_add<L>(t, U, V, n, r);
+      q_half<L>(t, n, r);                                             // U_(k+1) = (U_k + V_k) / 2
+      q_mod_add<L>(w, w, V, n, r);
+      q_half<L>(w, n, r);                                             // V_(k+1) = (D U_k + V_k) / 2
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        U[j] = t[j];
+        V[j] = w[j];
+      }
+      q_mont_mul<L>(Qk, Qm, n, ninv, r, own, col);                    // Q^(k+1)
+    }
+  }
+  if (q_is_zero<L>(U) || q_is_zero<L>(V)) return true;
+  for (int k = 1; k < s; ++k) {
+    q_mont_sqr<L>(V, n, ninv, r, own, col);
+    q_mod_add<L>(t, Qk, Qk, n, r);
+    q_mod_sub<L>(V, V, t, n, r);                                      // V_(2^k d)
+    if (q_is_zero<L>(V)) return true;
+    q_mont_sqr<L>(Qk, n, ninv, r, own, col);
+  }
+  return false;
+}
+
+// Any of the tests on numbers given as limbs (a quad of lanes per number): test = CS_PRP_SPRP2,
+// CS_PRP_LUCAS or CS_PRP_BPSW (both, the Lucas test only for numbers passing the first).
+template <int L>
+__global__ __launch_bounds__(kPrpBlock) void k_prp_test_q(const uint32_t* __restrict__ limbs, uint32_t n_limbs,
+                                                          uint64_t count, uint32_t test, uint8_t* __restrict__ out) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t i = (blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x) / 4;
+  if (i >= count) return;                            // whole quads leave together
+  const uint32_t r = threadIdx.x & 3u;
+  uint32_t v[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint32_t g = r * L + j;
+    v[j] = g < n_limbs ? limbs[i * n_limbs + g] : 0u;
+  }
+  bool pp = true;
+  if (test != CS_PRP_LUCAS) pp = q_sprp2<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u));
+  if (pp && test != CS_PRP_SPRP2) pp = q_strong_lucas<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u));
+  if (r == 0) out[i] = pp ? 1 : 0;
+}
+
 template <int L>
 __global__ __launch_bounds__(kPrpBlock) void k_prp_numbers_q(const uint32_t* __restrict__ limbs, uint32_t n_limbs,
                                                              uint64_t count, uint8_t* __restrict__ out) {
@@ -507,7 +807,7 @@ struct SurroundDev {
   uint8_t* slot_res;          // per slot: 1 if probable prime
   uint32_t* act[2];           // open-task lists (ping-pong)
   uint32_t* n_act;            // [0], [1] list sizes; [2] error flags
-  unsigned long long* tests;  // tests run
+  unsigned long long* tests;  // [0] strong tests to base 2 run, [1] strong Lucas tests run
   cs_surround_row* out;
   uint64_t n_rows, m_lo, m_hi;
   uint32_t row_words, n_x;
@@ -628,6 +928,49 @@ __global__ __launch_bounds__(kPrpBlock) void k_sv_test(SurroundDev sv, uint32_t 
   sv.slot_res[sidx] = sprp2<NL>(v, lds + threadIdx.x) ? 1 : 0;
 }
 
+// N = m K + X on a quad of lanes (K has kl limbs, at most 4L): each lane forms its limbs, the
+// carries out of its top limb resolved across the quad after each pass (N < 2^(32 NL), so nothing
+// leaves the quad).
+template <int L>
+__device__ __forceinline__ void q_sv_number(const SurroundDev& sv, uint32_t kl, uint64_t m, int32_t X, uint32_t r,
+                                            uint32_t (&v)[L]) {
+  uint32_t dummy = 0;
+  const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const uint32_t g = r * L + j;
+    const uint64_t s = (uint64_t)(g < kl ? sv.klimbs[g] : 0u) * mlo + c;
+    v[j] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  q_resolve<L>(v, c, dummy, r);
+  if (mhi) {                                          // the same quad-uniform branch in every lane
+    c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const uint32_t g = r * L + j;
+      const uint64_t s = (uint64_t)(g && g - 1 < kl ? sv.klimbs[g - 1] : 0u) * mhi + v[j] + c;
+      v[j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+    q_resolve<L>(v, c, dummy, r);
+  }
+  // + X, or + (2^(32 NL) - |X|) with the carry out of the number dropped
+  const bool neg = X < 0;
+  const uint32_t ax = (uint32_t)(neg ? -X : X);
+  c = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const bool low = r == 0 && j == 0;
+    const uint32_t add = neg ? (low ? 0u - ax : 0xffffffffu) : (low ? ax : 0u);
+    const uint64_t s = (uint64_t)v[j] + add + c;
+    v[j] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
+  }
+  q_resolve<L>(v, c, dummy, r);
+}
+
 // The same on a quad of lanes per candidate (NL = 4L limbs).
 // Wavefronts per SIMD the register allocation of k_sv_test_q aims for: at 10 to 12 limbs per
 // lane (numbers of 1,280 to 1,536 bits) the squaring loop fits in 96 VGPRs without spills (only a
@@ -660,43 +1003,8 @@ void k_sv_test_q(SurroundDev sv, uint32_t in, uint64_t n_slots, uint32_t B) {
     return;
   }
   const int32_t X = sv.x_of_col[col];
-  // N = m K + X: each lane forms its limbs, the carries out of its top limb resolved across the
-  // quad after each pass (N < 2^(32 NL), so nothing leaves the quad)
   uint32_t v[L];
-  uint32_t dummy = 0;
-  const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
-  uint32_t c = 0;
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    const uint64_t s = (uint64_t)sv.klimbs[r * L + j] * mlo + c;
-    v[j] = (uint32_t)s;
-    c = (uint32_t)(s >> 32);
-  }
-  q_resolve<L>(v, c, dummy, r);
-  if (mhi) {                                          // the same quad-uniform branch in every lane
-    c = 0;
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const uint32_t g = r * L + j;
-      const uint64_t s = (uint64_t)(g ? sv.klimbs[g - 1] : 0u) * mhi + v[j] + c;
-      v[j] = (uint32_t)s;
-      c = (uint32_t)(s >> 32);
-    }
-    q_resolve<L>(v, c, dummy, r);
-  }
-  // + X, or + (2^(32 NL) - |X|) with the carry out of the number dropped
-  const bool neg = X < 0;
-  const uint32_t ax = (uint32_t)(neg ? -X : X);
-  c = 0;
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    const bool low = r == 0 && j == 0;
-    const uint32_t add = neg ? (low ? 0u - ax : 0xffffffffu) : (low ? ax : 0u);
-    const uint64_t s = (uint64_t)v[j] + add + c;
-    v[j] = (uint32_t)s;
-    c = (uint32_t)(s >> 32);
-  }
-  q_resolve<L>(v, c, dummy, r);
+  q_sv_number<L>(sv, 4 * L, m, X, r, v);
   const bool pp = q_sprp2<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u));
   if (r == 0) sv.slot_res[sidx] = pp ? 1 : 0;
 }
@@ -726,6 +1034,37 @@ __global__ void k_sv_resolve(SurroundDev sv, uint32_t in, uint32_t n_open, uint3
     const uint32_t at = atomicAdd(&sv.n_act[in ^ 1], 1u);
     sv.act[in ^ 1][at] = task;
   }
+}
+
+// The second half of BPSW for every side's probable prime (sides with none are skipped): the
+// strong Lucas test of N + X on a quad of lanes (K has kl limbs).  A side whose number fails (a
+// strong pseudoprime to base 2) is reopened just past it and appended to list `fail`.
+template <int L>
+__global__ __launch_bounds__(kPrpBlock) void k_sv_lucas_q(SurroundDev sv, uint32_t kl, uint32_t fail, uint64_t n_tasks) {
+  extern __shared__ uint32_t lds[];
+  const uint64_t task = (blockIdx.x * (uint64_t)kPrpBlock + threadIdx.x) / 4;
+  if (task >= n_tasks) return;                        // whole quads leave together
+  const uint32_t r = threadIdx.x & 3u;
+  const uint64_t row = task >> 1;
+  cs_surround_row& o = sv.out[row];
+  const int32_t X = (task & 1) ? o.next : o.prev;
+  if (X == 0) return;                                 // no probable prime on this side
+  if (r == 0) atomicAdd(sv.tests + 1, 1ull);
+  uint32_t v[L];
+  q_sv_number<L>(sv, kl, sv.m[row], X, r, v);
+  if (q_strong_lucas<L>(v, r, lds + threadIdx.x, lds + (threadIdx.x & ~3u)) || r != 0) return;
+  // its column (x_of_col ascends), and the search resumes at the next one in walking order
+  uint32_t lo = 0, hi = sv.n_x;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (sv.x_of_col[mid] <= X) lo = mid;
+    else hi = mid;
+  }
+  if (task & 1) o.next = 0;
+  else o.prev = 0;
+  sv.cur[task] = (task & 1) ? (int32_t)lo + 1 : (int32_t)lo - 1;
+  const uint32_t at = atomicAdd(&sv.n_act[fail], 1u);
+  sv.act[fail][at] = (uint32_t)task;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -773,6 +1112,42 @@ hipError_t launch_prp_numbers(uint32_t nl, const uint32_t* limbs, uint32_t n_lim
     default: return hipErrorInvalidValue;
   }
   return record_launch("k_prp_numbers");
+}
+
+// The strong Lucas or BPSW test on a quad of lanes per number, L = nl / 4 limbs per lane (at
+// least 3).
+hipError_t launch_prp_test(uint32_t nl, const uint32_t* limbs, uint32_t n_limbs, uint64_t count, uint32_t test,
+                           uint8_t* out, hipStream_t s) {
+  const uint32_t L = nl / 4 < 3 ? 3 : nl / 4;
+  const uint32_t blocks = (uint32_t)((count * 4 + kPrpBlock - 1) / kPrpBlock);
+  const size_t lds = (size_t)(2 * L) * kPrpBlock * 4;
+  switch (L) {
+#define TCASE(LL)                                                                                                  \
+  case LL:                                                                                                         \
+    hipLaunchKernelGGL(k_prp_test_q<LL>, dim3(blocks), dim3(kPrpBlock), lds, s, limbs, n_limbs, count, test, out); \
+    break;
+    PRP_QUAD_INSTANCES(TCASE)
+#undef TCASE
+    default: return hipErrorInvalidValue;
+  }
+  return record_launch("k_prp_test_q");
+}
+
+hipError_t launch_sv_lucas(uint32_t nl, const SurroundDev& sv, uint32_t kl, uint32_t fail, uint64_t n_tasks,
+                           hipStream_t s) {
+  const uint32_t L = nl / 4 < 3 ? 3 : nl / 4;
+  const uint32_t blocks = (uint32_t)((n_tasks * 4 + kPrpBlock - 1) / kPrpBlock);
+  const size_t lds = (size_t)(2 * L) * kPrpBlock * 4;
+  switch (L) {
+#define LCASE(LL)                                                                                            \
+  case LL:                                                                                                   \
+    hipLaunchKernelGGL(k_sv_lucas_q<LL>, dim3(blocks), dim3(kPrpBlock), lds, s, sv, kl, fail, n_tasks);      \
+    break;
+    PRP_QUAD_INSTANCES(LCASE)
+#undef LCASE
+    default: return hipErrorInvalidValue;
+  }
+  return record_launch("k_sv_lucas_q");
 }
 
 hipError_t launch_sv_test(uint32_t nl, const SurroundDev& sv, uint32_t in, uint64_t n_slots, uint32_t B,
@@ -906,6 +1281,20 @@ extern "C" cs_status cs_prp_numbers(const uint32_t* d_limbs, uint32_t n_limbs, u
              : CS_EDEVICE;
 }
 
+extern "C" cs_status cs_prp_test(const uint32_t* d_limbs, uint32_t n_limbs, uint64_t n, uint32_t test,
+                                 uint8_t* d_out, void* stream) {
+  if (test > CS_PRP_BPSW) return CS_EINVAL;
+  if (test == CS_PRP_SPRP2) return cs_prp_numbers(d_limbs, n_limbs, n, d_out, stream);
+  if (n == 0) return CS_OK;
+  if (!d_limbs || !d_out || n_limbs == 0) return CS_EINVAL;
+  const uint32_t nl = pick_nl(n_limbs);
+  if (!nl) return CS_ERANGE;
+  if (n > (1ull << 40)) return CS_ERANGE;
+  return launch_prp_test(nl, d_limbs, n_limbs, n, test, d_out, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? CS_OK
+             : CS_EDEVICE;
+}
+
 extern "C" cs_status cs_surround_ws(const cs_job* job, uint64_t n_rows, uint64_t* ws_bytes) {
   if (!job || !ws_bytes) return CS_EINVAL;
   if (n_rows >= (1ull << 30)) return CS_ERANGE;
@@ -981,7 +1370,9 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
     (void)hipEventDestroy(ev[0]);
     return CS_EDEVICE;
   }
-  double test_ms = 0.0;
+  double test_ms = 0.0, lucas_ms = 0.0;
+  uint64_t lucas_passes = 0;
+  unsigned long long lucas_run = 0;
   cs_status result = CS_OK;
   uint32_t n_open = (uint32_t)tasks;
   const uint64_t round_target = std::min<uint64_t>(L.slots, sv_resident(nl));
@@ -992,6 +1383,7 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
   do {
     hipLaunchKernelGGL(k_sv_init, dim3((uint32_t)((tasks + 255) / 256)), dim3(256), 0, s, sv);
     if (record_launch("k_sv_init") != hipSuccess) { result = CS_EDEVICE; break; }
+    for (;;) {
     while (n_open) {
       uint64_t B = std::max<uint64_t>(round_target / n_open, kSurroundB0);
       B = std::min<uint64_t>(std::min<uint64_t>(B, kSurroundBMax), L.slots / n_open);
@@ -1015,8 +1407,25 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
       in ^= 1;
     }
     if (result) break;
+    // BPSW: the strong Lucas test of each side's probable prime; the sides whose number fails go
+    // back to the rounds from just past it (list `in`), until every found number passes
+    if (launch_fill_u32(sv.n_act + in, 1, 0u, s) != hipSuccess) { result = CS_EDEVICE; break; }
+    if (hipEventRecord(ev[0], s) != hipSuccess) { result = CS_EDEVICE; break; }
+    if (launch_sv_lucas(nl, sv, (uint32_t)kl.size(), in, tasks, s) != hipSuccess) { result = CS_EDEVICE; break; }
+    if (hipEventRecord(ev[1], s) != hipSuccess) { result = CS_EDEVICE; break; }
+    uint32_t failed = 0;
+    if (hipMemcpyAsync(&failed, sv.n_act + in, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { result = CS_EDEVICE; break; }
+    float lms = 0.f;
+    if (hipEventElapsedTime(&lms, ev[0], ev[1]) == hipSuccess) lucas_ms += lms;
+    ++lucas_passes;
+    if (failed == 0) break;
+    n_open = failed;
+    }
+    if (result) break;
     if (hipMemcpyAsync(&err, sv.n_act + 2, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&run, sv.tests, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&lucas_run, sv.tests + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       result = CS_EDEVICE;
   } while (0);
@@ -1030,6 +1439,9 @@ extern "C" cs_status cs_surround(const cs_job* job, const uint32_t* d_bitmap, co
     stats->limbs = nl;
     stats->bits = bit_length(kl) + (64 - __builtin_clzll(pl.job.m_start + pl.job.m_inc - 1));
     stats->test_ms = test_ms;
+    stats->lucas_tests = lucas_run;
+    stats->lucas_passes = lucas_passes;
+    stats->lucas_ms = lucas_ms;
   }
   return err ? CS_EDEVICE : CS_OK;
 }

@@ -191,3 +191,65 @@ def test_advisor_sieve_limit_and_interval():
     assert narrow.warn and narrow.beyond > 10
     _, want = _oracle_rows(W.Job(503, 210, 10**6, 300, 300, 10**8), cs.rows(W.Job(503, 210, 10**6, 300, 300, 10**8))[:32])
     assert sum(1 for p, n, _, _ in want if p == 0 or n == 0) > 0
+
+
+# ------------------------------------------------------------------------------------------
+# The strong Lucas test and BPSW (cs_prp_test)
+# ------------------------------------------------------------------------------------------
+LUCAS_SPECIAL = [5459, 5777, 10877, 16109, 18971, 22499, 24569, 25199, 40309, 58519, 75077, 97439,
+                 25, 49, 121, 169, 3**20, 65521**2, 7, 11, 13, 97, 5 * 7 * 11]
+
+
+def _gpu_test(ns, n_limbs, test):
+    out = cs.prp_test(_limbs(ns, n_limbs), test)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(bool)
+
+
+def test_lucas_and_bpsw_small_numbers():
+    """Every n below 20,000 and the strong Lucas pseudoprimes below 10^5, as one-limb numbers."""
+    ns = list(range(0, 20000)) + LUCAS_SPECIAL
+    _say("lucas small", len(ns))
+    for test, ref in ((cs.PRP_LUCAS, prp.strong_lucas), (cs.PRP_BPSW, prp.bpsw), (cs.PRP_SPRP2, prp.sprp2)):
+        got = _gpu_test(ns, 1, test)
+        want = np.array([ref(n) for n in ns])
+        bad = [ns[i] for i in np.nonzero(got != want)[0]]
+        assert not bad, (test, bad[:6])
+
+
+@pytest.mark.parametrize("n_limbs", [2, 3, 8, 12, 16, 20, 44, 64])
+def test_lucas_and_bpsw_against_oracle(n_limbs):
+    _say("lucas n_limbs", n_limbs)
+    rng = random.Random(1000 + n_limbs)
+    bits = 32 * n_limbs
+    ns = [x for x in SPECIAL + LUCAS_SPECIAL if x.bit_length() <= bits and (x < 2**32 or math.isqrt(x)**2 != x)]
+    for _ in range(60 if n_limbs <= 16 else 16):
+        b = rng.randint(max(2, bits - 40), bits)
+        ns.append(rng.getrandbits(b) | 1)
+    for _ in range(12 if n_limbs <= 16 else 3):            # probable primes and products of two
+        b = rng.randint(max(3, bits // 2 - 8), bits // 2 - 1)
+        p = _next_prp(rng.getrandbits(b) | (1 << (b - 1)))
+        q = _next_prp(p + 2)
+        ns += [p, p * q]
+    ns = [n for n in ns if n.bit_length() <= bits]
+    for test, ref in ((cs.PRP_LUCAS, prp.strong_lucas), (cs.PRP_BPSW, prp.bpsw)):
+        got = _gpu_test(ns, n_limbs, test)
+        want = np.array([ref(n) for n in ns])
+        bad = [ns[i] for i in np.nonzero(got != want)[0]]
+        assert not bad, (test, bad[:4])
+        assert want.sum() >= 2
+    with pytest.raises(cs.CsError):
+        cs.prp_test(_limbs(ns[:2], n_limbs), 3)
+
+
+def test_surround_searches_past_a_base2_pseudoprime():
+    """N = 68 * 5# = 2040 sieved to 20: above N the unmarked numbers are 2047 = 23 * 89, a strong
+    pseudoprime to base 2, then the prime 2053.  BPSW rejects 2047, so the side searches on (a
+    second Lucas pass) and stops at X = 13; below N, 2039 (X = -1) is prime."""
+    job = W.Job(5, 1, 68, 1, 20, 20)
+    gb, ms, out, stats = _sieve_and_surround(job)
+    ob, want = _oracle_rows(job, ms)
+    assert np.array_equal(gb, ob)
+    assert [tuple(int(v) for v in r) for r in out] == [tuple(w) for w in want] == [(-1, 13, 1, 2)]
+    # each pass tests every side that holds a probable prime: 2 in the first, 2 again in the second
+    assert stats.lucas_passes == 2 and stats.lucas_tests == 4 and stats.lucas_ms > 0
