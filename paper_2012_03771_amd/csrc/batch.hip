@@ -91,7 +91,17 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
       if (ok && pl.n_m > 0)
         ok = (uint64_t)b.lds_ct_words * 8u + 4ull * pl.row_words + 8u <= kPersistLds;
     }
-    const uint32_t large_lds = b.lds_ct_words * 8u + ((max_dp * 2u + 3u) & ~3u);
+    uint32_t large_lds = b.lds_ct_words * 8u + ((max_dp * 2u + 3u) & ~3u);
+    // K's groups of the jobs that form K mod p in the large branch, after the tables, 8-aligned
+    size_t max_kg = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      if (b.plans[i].kmod_fused) max_kg = std::max(max_kg, std::max<size_t>(b.plans[i].kq.size(), 1));
+    b.kg_off_words = 0;
+    if (max_kg) {
+      const uint32_t off = (large_lds + 7u) & ~7u;
+      b.kg_off_words = off / 4u;
+      large_lds = off + 8u * (uint32_t)max_kg;
+    }
     ok = ok && large_lds <= kPersistLds;
     if (want_persistent > 0 && !ok) return CS_EINVAL;
     b.persistent = want_persistent != 0 && ok;
@@ -110,7 +120,7 @@ cs_status multi_build(MultiJob& b, const cs_job* jobs, const cs_tune* tunes, uin
     b.max_words = std::max<uint64_t>(b.max_words, pl.n_m * (uint64_t)pl.row_words);
     b.max_m_inc = std::max<uint64_t>(b.max_m_inc, pl.job.m_inc);
     b.max_sl = std::max(b.max_sl, pl.job.sl);
-    b.kmod_cap += pi_upper(pl.job.limit);
+    b.kmod_cap += pl.kmod_fused ? std::min(pi_upper(pl.job.limit), pi_upper(pl.thr)) : pi_upper(pl.job.limit);
   }
   // device memory: shared prime table, job descriptors, prefix arrays, per-job tables
   b.n_seg = (Lp >> kSegLog) + 1;
@@ -211,7 +221,8 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
   if (b.persistent) {
     // every job's small units and large items in one launch, then the byte counters' fold
     CS_TRY(launch_batch_persistent(b.jobs_dev, n, b.tbase, b.task_next, b.persist_blocks, b.persist_lds,
-                                   b.lds_ct_words, b.bytes ? 1u : 0u, b.large_mode, b.items_per_task, b.order, s));
+                                   b.lds_ct_words, b.kg_off_words, b.bytes ? 1u : 0u, b.large_mode, b.items_per_task,
+                                   b.order, s));
     if (b.bytes) CS_TRY(launch_fold_bytes(b.jobs_dev, n, b.max_rows, b.n_cu, s));
     return CS_OK;
   }

@@ -42,6 +42,7 @@ struct MultiJob {
   uint32_t large_mode = 0;
   uint32_t items_per_task = 256, order = 0;
   uint32_t persist_lds = 0, persist_blocks = 0;
+  uint32_t kg_off_words = 0;        // LDS word offset of K's groups in k_batch (0: no job forms K mod p)
   uint64_t o_tbase = 0, o_next = 0;
   uint64_t* tbase = nullptr;
   unsigned long long* task_next = nullptr;

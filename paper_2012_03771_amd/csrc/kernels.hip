@@ -1876,7 +1876,7 @@ template <int kSc, bool kG>
 __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                const uint64_t* __restrict__ tbase,
                                                unsigned long long* __restrict__ next, uint32_t lds_ct_words,
-                                               uint32_t items_per_task, uint32_t order) {
+                                               uint32_t kg_off_words, uint32_t items_per_task, uint32_t order) {
   extern __shared__ uint32_t lds[];
   __shared__ unsigned long long s_dec[DC_COUNT][kDecades];
   __shared__ unsigned long long s_list[256 / kWave];   // list state (the list scatter is not used here)
@@ -1887,7 +1887,7 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
   if (threadIdx.x < kListSupers) s_sup[threadIdx.x] = 0u;
   const uint64_t total = tbase[2 * n_jobs];
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  uint32_t ct_job = 0xffffffffu, dp_job = 0xffffffffu;
+  uint32_t ct_job = 0xffffffffu, dp_job = 0xffffffffu, kg_job = 0xffffffffu;
   LaneCount lc;
   lane_count_init(lc);
   ListReg lreg = {kNoChunk, 0u};
@@ -1911,7 +1911,7 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
       unsigned long long n_pairs = 0, n_marks = 0;
       small_unit(j, local, lds, lds_ct_words, ct_job == ji, n_pairs, n_marks);
       ct_job = ji;
-      dp_job = 0xffffffffu;                          // the tile overwrote the residue table
+      dp_job = kg_job = 0xffffffffu;                 // the tile overwrote the residue table and K's groups
       if (lane == 0) {
         if (n_pairs) atomicAdd(&j.ctrl->diag[D_SMALL_PAIRS], n_pairs);
         if (n_marks) atomicAdd(&j.ctrl->diag[D_SMALL_MARKS], n_marks);
@@ -1929,12 +1929,18 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
       const uint32_t dn = (uint32_t)j.d;
       for (uint32_t i = threadIdx.x; i < dn; i += blockDim.x) dpl[i] = gbl(j.dpre)[i];
     }
+    double* kgl = reinterpret_cast<double*>(lds + kg_off_words);
+    if (j.kmod_fused && kg_job != ji) {              // K's groups, for K mod p formed per prime
+      const uint32_t ng = gbl(j.ctrl)->n_kgroups;
+      for (uint32_t i = threadIdx.x; i < ng; i += blockDim.x) kgl[i] = (double)gbl(j.kgroups)[i];
+      kg_job = ji;
+    }
     ct_job = dp_job = ji;
     __syncthreads();
     LargeTables<true> T;
     T.ct = ctl;
     T.dp = dpl;
-    T.kg = nullptr;                                  // batch jobs read K mod p from their tables
+    T.kg = j.kmod_fused ? kgl : nullptr;             // else the job reads K mod p from its tables
     const auto& c = *gbl(j.ctrl);
     const uint64_t n_items = c.n_items;
     const uint64_t first = local * items_per_task;
@@ -2535,13 +2541,14 @@ hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, u
 }
 
 hipError_t launch_batch_persistent(const JobDev* jobs, uint32_t n_jobs, uint64_t* tbase, unsigned long long* next,
-                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t scatter_kind,
-                                   uint32_t large_mode, uint32_t items_per_task, uint32_t order, hipStream_t s) {
+                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t kg_off_words,
+                                   uint32_t scatter_kind, uint32_t large_mode, uint32_t items_per_task, uint32_t order,
+                                   hipStream_t s) {
   hipLaunchKernelGGL(k_batch_queue, dim3(1), dim3(64), 0, s, jobs, n_jobs, items_per_task, order, tbase, next);
   { hipError_t e_ = note("k_batch_queue"); if (e_ != hipSuccess) return e_; }
 #define BATCH_CASE(K, G) \
   hipLaunchKernelGGL((k_batch<K, G>), dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, (const uint64_t*)tbase, next, \
-                     lds_ct_words, items_per_task, order)
+                     lds_ct_words, kg_off_words, items_per_task, order)
   if (scatter_kind == 1) {
     if (large_mode == 0) BATCH_CASE(1, true); else BATCH_CASE(1, false);
   } else {

@@ -87,9 +87,12 @@ hipError_t launch_list_group(const JobDev* job, uint64_t list_chunks, uint32_t n
 // and next one; every job's column table fits lds_ct_words (and its residue table after it);
 // scatter_kind 0 (atomic) or 1 (byte counters) and large_mode are common to the jobs.
 // items_per_task: a multiple of 256; order: 0 large tasks first, 1 small tasks first, 2 by job.
+// kg_off_words: LDS word offset (8-byte aligned) where a large task of a job that forms K mod p
+// itself stages K's groups; 0 when no job does.
 hipError_t launch_batch_persistent(const JobDev* jobs, uint32_t n_jobs, uint64_t* tbase, unsigned long long* next,
-                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t scatter_kind,
-                                   uint32_t large_mode, uint32_t items_per_task, uint32_t order, hipStream_t s);
+                                   uint32_t blocks, uint32_t lds_bytes, uint32_t lds_ct_words, uint32_t kg_off_words,
+                                   uint32_t scatter_kind, uint32_t large_mode, uint32_t items_per_task, uint32_t order,
+                                   hipStream_t s);
 
 // Scatter-rate probe (see k_probe_scatter).
 hipError_t launch_probe_scatter(uint32_t* buf, uint64_t words, uint64_t n_ops, uint32_t slices, uint32_t op,
