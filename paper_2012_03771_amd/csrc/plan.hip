@@ -213,10 +213,10 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
     const uint32_t dp_b = (uint32_t)pl.dpre.size() * 2u;
     pl.large_lds_ct_words = ct_b <= 16384u ? pl.ct_words : 0u;
     pl.large_lds_bytes = (pl.large_lds_ct_words ? ct_b : 0u) + ((dp_b + 3u) & ~3u);
-    // K mod p formed in the large branch: a job with its own K mod p table (a single job or one of
-    // a batch), no chunks and no prime on the 64-bit path; K's groups (at most one per prime
-    // dividing K) as doubles in its LDS
-    pl.kmod_fused = own_kmod && bytes_ok && span == 0 &&
+    // K mod p formed in the large branch: a job with its own K mod p table (a single job, or one of
+    // a batch or a server), no chunks and no prime on the 64-bit path; K's groups (at most one per
+    // prime dividing K) as doubles in its LDS
+    pl.kmod_fused = own_kmod && span == 0 &&
                     (!tune || tune->kmod == CS_KMOD_AUTO) && std::max<uint64_t>(j.limit, j.P) < pl.wide_lo &&
                     pl.kq.size() <= kFusedGroupsMax;
     pl.kg_lds_off = 0;

@@ -156,9 +156,15 @@ struct cs_server {
 
 namespace {
 
+// A job whose large branch forms K mod p itself keeps a table for its small primes in its own
+// tables; any other job shares one K mod p table per (P, d) across jobs.
 cs_status plan_for_server(const cs_server* s, const cs_job* job, Plan* pl) {
-  cs_status st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, false, false);
+  cs_status st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, true, false);
   if (st) return st;
+  if (!pl->kmod_fused) {
+    st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, false, false);
+    if (st) return st;
+  }
   if (pl->Lp > s->cfg.max_limit) return CS_ERANGE;
   return CS_OK;
 }
@@ -188,12 +194,41 @@ bool make_room(cs_server* s, uint64_t need) {
   }
 }
 
+void set_chunks(cs_server* s, SJob& J);
+
+// Admits a job whose tables hold its own (small-prime) K mod p: memory and descriptor only.
+bool admit_own(cs_server* s, SJob& J) {
+  const Plan& pl = J.plan;
+  const uint64_t need = job_bytes(pl);
+  if (!make_room(s, need + 256)) return false;
+  uint64_t off_t = 0, off_o = 0;
+  const uint64_t bt = a256(pl.ws.total);
+  const uint64_t bo = need - bt;
+  if (!s->arena.alloc(bt, &off_t)) return false;
+  if (!s->arena.alloc(bo, &off_o)) { s->arena.release(off_t, bt); return false; }
+  J.kentry = 0;
+  J.off_tab = off_t;
+  J.bytes_tab = bt;
+  J.off_out = off_o;
+  J.bytes_out = bo;
+  uint8_t* ws = s->arena_mem + off_t;
+  J.jd = make_jobdev(pl, ws, s->pw.primes, s->pw.n_primes);
+  J.jd.prime_cap = s->pw.cap;
+  J.jd.kmod_cached = 0;
+  J.jd.bitmap = reinterpret_cast<uint32_t*>(s->arena_mem + off_o);
+  J.jd.counts = reinterpret_cast<uint32_t*>(s->arena_mem + off_o + a256(pl.n_m * (uint64_t)pl.row_words * 4ull));
+  set_chunks(s, J);
+  return true;
+}
+
 // Tries to admit the job (memory, K mod p table, descriptor).  Called with the mutex held.
 bool admit(cs_server* s, uint64_t ticket) {
   SJob& J = s->jobs[ticket];
   const Plan& pl = J.plan;
-  // K mod p table for (P, d): reuse one whose limit covers this job's (prime indices agree)
+  // K mod p table for (P, d): reuse one whose limit covers this job's (prime indices agree); a job
+  // that forms K mod p itself needs none
   uint64_t kid = 0;
+  if (pl.kmod_fused) return admit_own(s, J);
   for (auto& kv : s->kcache) {
     const KEntry& e = kv.second;
     if (e.P == J.job.P && e.d == J.job.d && e.limit >= J.job.limit) { kid = kv.first; break; }
@@ -233,7 +268,14 @@ bool admit(cs_server* s, uint64_t ticket) {
   J.jd.kmod_cached = E.ready ? 1u : 0u;
   J.jd.bitmap = reinterpret_cast<uint32_t*>(s->arena_mem + off_o);
   J.jd.counts = reinterpret_cast<uint32_t*>(s->arena_mem + off_o + a256(pl.n_m * (uint64_t)pl.row_words * 4ull));
-  // chunks: the large primes in ranges of about equal prime count, the small primes with the first
+  set_chunks(s, J);
+  return true;
+}
+
+// The job's chunks (the large primes in ranges of about equal prime count, the small primes with
+// the first), and the job marked active.
+void set_chunks(cs_server* s, SJob& J) {
+  const Plan& pl = J.plan;
   J.bounds.clear();
   J.bounds.push_back(1);
   const uint64_t thr = std::min<uint64_t>(pl.thr, J.job.limit);
@@ -250,7 +292,6 @@ bool admit(cs_server* s, uint64_t ticket) {
   J.prepped = false;
   J.t_admit = now_s();
   s->st.admitted++;
-  return true;
 }
 
 void retire(cs_server* s, SJob& J, int state) {
@@ -292,7 +333,7 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
         max_phi = std::max(max_phi, J.plan.phi_d);
         max_rw = std::max(max_rw, J.plan.row_words);
       }
-      kcap += pi_upper(J.job.limit);
+      kcap += J.plan.kmod_fused ? std::min(pi_upper(J.job.limit), pi_upper(J.plan.thr)) : pi_upper(J.job.limit);
       max_words = std::max<uint64_t>(max_words, J.plan.n_m * (uint64_t)J.plan.row_words);
       max_m = std::max<uint64_t>(max_m, J.job.m_inc);
       max_sl = std::max(max_sl, J.job.sl);
@@ -466,7 +507,7 @@ extern "C" cs_status cs_server_submit(cs_server* s, const cs_job* job, uint64_t*
   Plan pl;
   cs_status st = plan_for_server(s, job, &pl);
   if (st) return st;
-  if (job_bytes(pl) + kmod_bytes(job->limit) + 512 > s->cfg.budget_bytes) return CS_ERANGE;
+  if (job_bytes(pl) + (pl.kmod_fused ? 0 : kmod_bytes(job->limit)) + 512 > s->cfg.budget_bytes) return CS_ERANGE;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->failed) return CS_EDEVICE;
   const uint64_t t = s->next_ticket++;

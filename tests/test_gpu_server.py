@@ -34,9 +34,11 @@ JOBS = [W.Job(61, 6, 1000, 3000, 500, 10**6), W.Job(131, 1, 7, 5000, 900, 2 * 10
         W.Job(503, 210, 10**6, 4000, 7000, 3 * 10**7), W.Job(97, 30, 10**6, 20000, 1200, 5 * 10**6)]
 
 
-@pytest.mark.parametrize("mode", [cs.LARGE_G, cs.LARGE_THREE_GAP], ids=["g", "three_gap"])
-def test_served_equals_alone(mode):
-    tune = cs.Tune(large_mode=mode)
+@pytest.mark.parametrize("mode,kmod", [(cs.LARGE_G, cs.KMOD_AUTO), (cs.LARGE_THREE_GAP, cs.KMOD_AUTO),
+                                       (cs.LARGE_THREE_GAP, cs.KMOD_TABLE)], ids=["g", "three_gap", "three_gap_table"])
+def test_served_equals_alone(mode, kmod):
+    """Jobs forming K mod p in their large branch (the default), or sharing one table per (P, d)."""
+    tune = cs.Tune(large_mode=mode, kmod=kmod)
     srv = cs.Server(budget_bytes=2 << 30, max_limit=10**8, max_active=4, chunks=3, tune=tune)
     tickets = []
     for i, job in enumerate(JOBS):
@@ -57,7 +59,10 @@ def test_served_equals_alone(mode):
         srv.release(t)
     st = srv.stats()
     assert st["completed"] == len(JOBS) and st["failed"] == 0
-    assert st["kmod_hits"] >= 1
+    if kmod == cs.KMOD_TABLE:
+        assert st["kmod_hits"] >= 1                    # (401, 210) twice
+    else:
+        assert st["kmod_builds"] == 0 and st["kmod_hits"] == 0
     assert st["iterations"] >= 4
     srv.close()
 
