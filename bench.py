@@ -59,6 +59,10 @@ def _args():
                     help="large-prime chunks per served job (cs_server_config.chunks; 1 measured best on this "
                          "mix: p50 24 / p99 141 ms at 0.8 load, against 28 / 271 ms with about 2 ms of estimated "
                          "device time per chunk)")
+    ap.add_argument("--serve-long-ms", type=float, default=3.0,
+                    help="cs_server_config.long_ms: jobs estimated to take longer alone run in a second lane "
+                         "(0: one lane; 3 measured best on this mix: p50/p99 23.6/103 ms at 0.8 load and "
+                         "68/173 ms at 0.95, against 22.3/117 and 120/214 ms with one lane)")
     ap.add_argument("--prp-rows", type=int, default=16384,
                     help="rows of the sieved job searched for their surrounding probable primes (0: skip)")
     ap.add_argument("--no-atomic-probe", action="store_true",
@@ -454,12 +458,12 @@ def _batch_leg(cs, torch, W, mode, reps=3, autotune=True):
             "autotune_s": t_tune}
 
 
-def _server_capacity(cs, W, mode, n_jobs=128, chunks=1):
+def _server_capacity(cs, W, mode, n_jobs=128, chunks=1, long_ms=0.0):
     """Saturated throughput of the server: n_jobs from the mixed-batch distribution (seed 2)
     submitted at once, completed jobs per second."""
     _, jobs = W.poisson_arrivals(n_jobs, 1.0, seed=2)
     srv = cs.Server(budget_bytes=64 << 30, max_limit=max(j.limit for j in jobs), max_active=32, chunks=chunks,
-                    tune=cs.Tune(large_mode=mode))
+                    tune=cs.Tune(large_mode=mode), long_ms=long_ms)
     t0 = time.perf_counter()
     tickets = [srv.submit(j) for j in jobs]
     for t in tickets:
@@ -494,13 +498,13 @@ def _alone_times(cs, torch, W, mode, n_jobs):
             "mean_ms": float(a.mean()), "max_ms": float(a.max())}
 
 
-def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm, chunks=1):
+def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm, chunks=1, long_ms=0.0):
     """Poisson arrivals of jobs from the mixed-batch distribution into the continuous-batching
     server (64 GB budget); latency = completion - arrival."""
     import numpy as np
     times, jobs = W.poisson_arrivals(n_warm + n_jobs, rate, seed=1)
     srv = cs.Server(budget_bytes=64 << 30, max_limit=max(j.limit for j in jobs), max_active=32, chunks=chunks,
-                    tune=cs.Tune(large_mode=mode))
+                    tune=cs.Tune(large_mode=mode), long_ms=long_ms)
     tickets = []
     t0 = time.perf_counter()
     for t_arr, job in zip(times, jobs):
@@ -526,7 +530,8 @@ def _serve_leg(cs, torch, W, mode, rate, n_jobs, n_warm, chunks=1):
     lat = np.array(lat)
     return {"workload": f"{n_jobs} jobs (+{n_warm} warm-up) from the mixed-batch distribution, Poisson arrivals "
                         f"at {rate:.1f} jobs/s, 64 GB admission budget, 32 slots, "
-                        f"{chunks} large-prime chunk(s) per job",
+                        f"{chunks} large-prime chunk(s) per job, "
+                        + (f"jobs estimated above {long_ms:g} ms alone in a second lane" if long_ms > 0 else "one lane"),
             "arrival_rate_per_s": rate, "jobs_per_s": n_jobs / span, "factors_per_s": factors / span,
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_latency_ms": float(lat.mean() * 1e3), "iterations": st["iterations"],
@@ -717,13 +722,14 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_serve:
         print("# serve capacity ...", file=sys.stderr, flush=True)
-        cap = _server_capacity(cs, W, mode_b, chunks=args.serve_chunks)
+        cap = _server_capacity(cs, W, mode_b, chunks=args.serve_chunks, long_ms=args.serve_long_ms)
         loads = sorted({float(x) for x in args.serve_loads.split(",")} | {0.8})
         curve = []
         for load in loads:
             rate = load * cap
             print(f"# serve leg at {rate:.1f} jobs/s ({load} of capacity {cap:.1f}) ...", file=sys.stderr, flush=True)
-            leg = _serve_leg(cs, torch, W, mode_b, rate, args.serve_jobs, args.serve_warmup, args.serve_chunks)
+            leg = _serve_leg(cs, torch, W, mode_b, rate, args.serve_jobs, args.serve_warmup, args.serve_chunks,
+                             args.serve_long_ms)
             leg["load"] = load
             leg["capacity_jobs_per_s"] = cap
             print(f"# serve {load}: p50 {leg['p50_latency_ms']:.1f} ms p99 {leg['p99_latency_ms']:.1f} ms",

@@ -460,6 +460,12 @@ typedef struct cs_server_config {
   uint32_t chunks;         /* large-prime chunks per job, one per iteration (0 = 1: every job in one
                               iteration, measured best for latency on mixed jobs) */
   cs_tune tune;            /* applied to every job */
+  double long_ms;          /* > 0: jobs whose estimated device time alone exceeds this many ms run
+                              in a second lane (its own loop, streams and iterations) beside the
+                              others, so that their iterations do not wait for the long jobs;
+                              0: one lane.  The estimate (from the plan: the large branch's hits
+                              by Mertens' theorem and its per-prime setup, and the small branch's
+                              pairs) changes no result. */
 } cs_server_config;
 
 typedef struct cs_ticket_info {

@@ -66,7 +66,7 @@ class cs_batch_opts(C.Structure):
 
 class cs_server_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("max_limit", C.c_uint64), ("max_active", C.c_uint32),
-                ("chunks", C.c_uint32), ("tune", cs_tune)]
+                ("chunks", C.c_uint32), ("tune", cs_tune), ("long_ms", C.c_double)]
 
 
 class cs_ticket_info(C.Structure):
@@ -499,8 +499,9 @@ class Server:
     """Continuous-batching sieve server (native loop in libcsieve; this class only marshals)."""
 
     def __init__(self, budget_bytes: int, max_limit: int, max_active: int = 16, chunks: int = 1,
-                 tune: Tune | None = None):
-        cfg = cs_server_config(budget_bytes, max_limit, max_active, chunks, (tune or Tune()).c())
+                 tune: Tune | None = None, long_ms: float = 0.0):
+        """long_ms > 0: jobs estimated to take longer than that alone run in a second lane."""
+        cfg = cs_server_config(budget_bytes, max_limit, max_active, chunks, (tune or Tune()).c(), long_ms)
         h = C.c_void_p()
         _check(lib().cs_server_create(C.byref(cfg), C.byref(h)), "cs_server_create")
         self.h = h

@@ -106,8 +106,25 @@ struct SJob {
   uint64_t off_tab = 0, bytes_tab = 0, off_out = 0, bytes_out = 0;
   uint64_t kentry = 0;              // id of the K mod p table (0: none)
   uint32_t chunk = 0;
+  uint32_t lane = 0;                // 0: the short lane, 1: the long lane
   std::vector<uint64_t> bounds;   // chunk c covers primes in (bounds[c], bounds[c+1]]
   JobDev jd;
+};
+
+// One lane of the server: its own loop thread, streams, descriptor arrays, queue and active set.
+// With two lanes the jobs estimated to take long run in the second one, so that the iterations of
+// the others (which complete a job per iteration) do not wait for them.
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;           // the small branch beside the large one (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  JobDev* run_dev = nullptr;
+  JobDev* prep_dev = nullptr;
+  uint64_t* lim_base = nullptr;
+  uint64_t* items_base = nullptr;
+  std::deque<uint64_t> pending;
+  std::vector<uint64_t> active;
+  std::thread th;
 };
 
 // Prime value below which about `frac` of the primes up to `hi` (and above lo) lie.
@@ -128,27 +145,19 @@ struct cs_server {
   cs_server_config cfg;
   int device = 0;
   int n_cu = 256;
-  hipStream_t stream = nullptr;
-  hipStream_t aux = nullptr;           // the small branch beside the large one (default priority)
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  Lane lane[2];
+  uint32_t n_lanes = 1;
   uint8_t* arena_mem = nullptr;
   uint8_t* fixed_mem = nullptr;
   Arena arena;
   PrimeWs pw{};
-  JobDev* run_dev = nullptr;
-  JobDev* prep_dev = nullptr;
-  uint64_t* lim_base = nullptr;
-  uint64_t* items_base = nullptr;
   unsigned long long* diag = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::thread th;
   bool stop = false;
   bool failed = false;
   uint64_t next_ticket = 1;
   std::unordered_map<uint64_t, SJob> jobs;
-  std::deque<uint64_t> pending;
-  std::vector<uint64_t> active;
   std::map<uint64_t, KEntry> kcache;
   uint64_t next_kid = 1;
   cs_server_counters st{};
@@ -311,8 +320,8 @@ void retire(cs_server* s, SJob& J, int state) {
 }
 
 // One iteration: prepare the newly admitted jobs and advance every active job by one chunk.
-bool iterate(cs_server* s, std::vector<SJob*>& act) {
-  hipStream_t st = s->stream;
+bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act) {
+  hipStream_t st = L.stream;
   const uint32_t n = (uint32_t)act.size();
   std::vector<SJob*> fresh;
   for (SJob* J : act)
@@ -322,7 +331,7 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
     uint32_t max_sl = 0, max_phi = 0, max_rw = 0;
     for (uint32_t i = 0; i < fresh.size(); ++i) {
       SJob& J = *fresh[i];
-      if (launch_write_job(J.jd, s->prep_dev + i, st) != hipSuccess) return false;
+      if (launch_write_job(J.jd, L.prep_dev + i, st) != hipSuccess) return false;
       if (!J.plan.dpre.empty() &&
           (launch_upload(s->arena_mem + J.off_tab + J.plan.ws.dpre, J.plan.dpre.data(), J.plan.dpre.size() * 2ull,
                          st) != hipSuccess ||
@@ -339,12 +348,12 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
       max_sl = std::max(max_sl, J.job.sl);
     }
     const uint32_t nf = (uint32_t)fresh.size();
-    if (launch_zero_ctrls(s->prep_dev, nf, st) != hipSuccess) return false;
-    if (launch_fill_jobs(s->prep_dev, nf, max_words, st) != hipSuccess) return false;
-    if (launch_prep_tables(s->prep_dev, nf, st) != hipSuccess) return false;
-    if (launch_kmod(s->prep_dev, nf, s->lim_base, kcap, s->n_cu, st) != hipSuccess) return false;
-    if (launch_rows_cols(s->prep_dev, nf, max_m, max_sl, s->n_cu, st) != hipSuccess) return false;
-    if (launch_dpattern(s->prep_dev, nf, max_phi, max_rw, st) != hipSuccess) return false;
+    if (launch_zero_ctrls(L.prep_dev, nf, st) != hipSuccess) return false;
+    if (launch_fill_jobs(L.prep_dev, nf, max_words, st) != hipSuccess) return false;
+    if (launch_prep_tables(L.prep_dev, nf, st) != hipSuccess) return false;
+    if (launch_kmod(L.prep_dev, nf, L.lim_base, kcap, s->n_cu, st) != hipSuccess) return false;
+    if (launch_rows_cols(L.prep_dev, nf, max_m, max_sl, s->n_cu, st) != hipSuccess) return false;
+    if (launch_dpattern(L.prep_dev, nf, max_phi, max_rw, st) != hipSuccess) return false;
     for (SJob* J : fresh) J->prepped = true;
   }
   // the sieve: every active job's current chunk, fused
@@ -369,61 +378,79 @@ bool iterate(cs_server* s, std::vector<SJob*>& act) {
       units += (uint64_t)J.plan.n_windows * J.plan.n_slices;
       lds = std::max(lds, J.plan.lds_bytes);
     }
-    if (launch_write_job(jd, s->run_dev + i, st) != hipSuccess) return false;
+    if (launch_write_job(jd, L.run_dev + i, st) != hipSuccess) return false;
   }
-  if (launch_prep_bounds(s->run_dev, n, st) != hipSuccess) return false;
-  if (launch_items_scan(s->run_dev, n, s->items_base, st) != hipSuccess) return false;
+  if (launch_prep_bounds(L.run_dev, n, st) != hipSuccess) return false;
+  if (launch_items_scan(L.run_dev, n, L.items_base, st) != hipSuccess) return false;
   // the small branch on the second stream beside the large one: both merge into the bitmap and
   // counts with atomics (small_atomic), so the order of their updates does not matter
   if (units) {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, 1ull << 31);   // one workgroup per unit
-    if (hipEventRecord(s->ev_fork, st) != hipSuccess || hipStreamWaitEvent(s->aux, s->ev_fork, 0) != hipSuccess)
+    if (hipEventRecord(L.ev_fork, st) != hipSuccess || hipStreamWaitEvent(L.aux, L.ev_fork, 0) != hipSuccess)
       return false;
-    if (launch_small(s->run_dev, n, units, lds, lds_ct, blocks, s->aux) != hipSuccess) return false;
+    if (launch_small(L.run_dev, n, units, lds, lds_ct, blocks, L.aux) != hipSuccess) return false;
   }
-  if (launch_large(s->run_dev, n, s->items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u,
+  if (launch_large(L.run_dev, n, L.items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u,
                    s->cfg.tune.large_mode, st) !=
       hipSuccess)
     return false;
-  if (units && (hipEventRecord(s->ev_join, s->aux) != hipSuccess || hipStreamWaitEvent(st, s->ev_join, 0) != hipSuccess))
+  if (units && (hipEventRecord(L.ev_join, L.aux) != hipSuccess || hipStreamWaitEvent(st, L.ev_join, 0) != hipSuccess))
     return false;
   if (hipStreamSynchronize(st) != hipSuccess) return false;
   return true;
 }
 
-void server_loop(cs_server* s) {
+void server_loop(cs_server* s, uint32_t li) {
   (void)hipSetDevice(s->device);
+  Lane& L = s->lane[li];
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     // admission: queue order, as slots and memory allow
-    while (!s->pending.empty() && s->active.size() < s->cfg.max_active) {
-      const uint64_t t = s->pending.front();
+    while (!L.pending.empty() && L.active.size() < s->cfg.max_active) {
+      const uint64_t t = L.pending.front();
       if (!admit(s, t)) break;
-      s->pending.pop_front();
-      s->active.push_back(t);
+      L.pending.pop_front();
+      L.active.push_back(t);
     }
-    if (s->active.empty()) {
+    if (L.active.empty()) {
       s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
       continue;
     }
     std::vector<SJob*> act;
-    for (uint64_t t : s->active) act.push_back(&s->jobs[t]);
+    for (uint64_t t : L.active) act.push_back(&s->jobs[t]);
     lk.unlock();
-    const bool ok = iterate(s, act);
+    const bool ok = iterate(s, L, act);
     lk.lock();
     s->st.iterations++;
     std::vector<uint64_t> keep;
-    for (uint64_t t : s->active) {
+    for (uint64_t t : L.active) {
       SJob& J = s->jobs[t];
       if (!ok) { retire(s, J, S_ERROR); continue; }
       J.chunk++;
       if (J.chunk + 1 >= J.bounds.size()) retire(s, J, S_DONE);
       else keep.push_back(t);
     }
-    s->active.swap(keep);
+    L.active.swap(keep);
     if (!ok) s->failed = true;
     s->cv_done.notify_all();
+    s->cv_work.notify_all();          // memory freed here may admit the other lane's jobs
   }
+}
+
+// Estimated device time of a job alone (ms), from its plan: the large branch's hit atomics
+// (n_m n_x (log log limit - log log thr) by Mertens' theorem, at about 1.8e10 per second) or its
+// per-prime setup (about 45 ps per large prime), whichever is larger, plus part of the small
+// branch (about 1.25 ps per (row, small prime) pair, largely hidden beside the large one).
+double est_ms(const Plan& pl) {
+  const cs_job& j = pl.job;
+  if (pl.n_m == 0) return 0.0;
+  const double thr = std::max<double>((double)std::min<uint64_t>(pl.thr, j.limit), 3.0);
+  const double lim = std::max<double>((double)j.limit, thr);
+  auto pc = [](double x) { return x < 3 ? 0.0 : x / log(x); };
+  const double hits = (double)pl.n_m * pl.n_x * std::max(0.0, log(log(lim)) - log(log(thr)));
+  const double large = std::max(hits / 1.8e10, (pc(lim) - pc(thr)) * 4.5e-11);
+  const double small = (double)pl.n_m * pc(thr) * 1.25e-12;
+  return 1e3 * (large + 0.3 * small);
 }
 
 void fill_info(const cs_server* s, const SJob& J, cs_ticket_info* out) {
@@ -442,6 +469,7 @@ void fill_info(const cs_server* s, const SJob& J, cs_ticket_info* out) {
 
 extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** out) {
   if (!cfg || !out || cfg->budget_bytes == 0 || cfg->max_active == 0 || cfg->max_limit < 2) return CS_EINVAL;
+  if (!(cfg->long_ms >= 0.0)) return CS_EINVAL;
   if (cfg->max_limit >= kWideLo) return CS_ERANGE;
   *out = nullptr;
   cs_server* s = new (std::nothrow) cs_server();
@@ -449,15 +477,22 @@ extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** o
   s->cfg = *cfg;
   if (hipGetDevice(&s->device) != hipSuccess) { delete s; return CS_EDEVICE; }
   s->n_cu = device_cu_count();
-  // fixed memory: prime table up to max_limit, descriptors, prefix arrays, counters
+  s->n_lanes = cfg->long_ms > 0.0 ? 2u : 1u;
+  // fixed memory: prime table up to max_limit, descriptors and prefix arrays per lane, counters
   const uint64_t n_seg = (cfg->max_limit >> kSegLog) + 1, cap = pi_upper(cfg->max_limit);
   const uint32_t na = cfg->max_active;
   uint64_t o = 0;
   auto take = [&](uint64_t b) { uint64_t at = o; o = a256(o + std::max<uint64_t>(b, 8)); return at; };
   const uint64_t o_nb = take(8), o_np = take(8), o_base = take(kBaseCap * 4ull), o_fl = take(n_seg * kSegWords * 4ull);
   const uint64_t o_sc = take(n_seg * 4ull), o_so = take(n_seg * 8ull), o_pr = take(cap * 8ull);
-  const uint64_t o_run = take(sizeof(JobDev) * (uint64_t)na), o_prep = take(sizeof(JobDev) * (uint64_t)na);
-  const uint64_t o_lim = take(8ull * (na + 1)), o_it = take(8ull * (na + 1)), o_dg = take(8ull * D_COUNT);
+  uint64_t o_run[2], o_prep[2], o_lim[2], o_it[2];
+  for (uint32_t li = 0; li < s->n_lanes; ++li) {
+    o_run[li] = take(sizeof(JobDev) * (uint64_t)na);
+    o_prep[li] = take(sizeof(JobDev) * (uint64_t)na);
+    o_lim[li] = take(8ull * (na + 1));
+    o_it[li] = take(8ull * (na + 1));
+  }
+  const uint64_t o_dg = take(8ull * D_COUNT);
   if (hipMalloc(&s->fixed_mem, o) != hipSuccess) { delete s; return CS_ENOMEM; }
   if (hipMalloc(&s->arena_mem, cfg->budget_bytes) != hipSuccess) {
     (void)hipFree(s->fixed_mem);
@@ -474,30 +509,38 @@ extern "C" cs_status cs_server_create(const cs_server_config* cfg, cs_server** o
   s->pw.seg_off = reinterpret_cast<uint64_t*>(m + o_so);
   s->pw.primes = reinterpret_cast<uint64_t*>(m + o_pr);
   s->pw.cap = cap;
-  s->run_dev = reinterpret_cast<JobDev*>(m + o_run);
-  s->prep_dev = reinterpret_cast<JobDev*>(m + o_prep);
-  s->lim_base = reinterpret_cast<uint64_t*>(m + o_lim);
-  s->items_base = reinterpret_cast<uint64_t*>(m + o_it);
   s->diag = reinterpret_cast<unsigned long long*>(m + o_dg);
-  bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) == hipSuccess;
+  bool ok = true;
+  for (uint32_t li = 0; li < s->n_lanes; ++li) {
+    Lane& L = s->lane[li];
+    L.run_dev = reinterpret_cast<JobDev*>(m + o_run[li]);
+    L.prep_dev = reinterpret_cast<JobDev*>(m + o_prep[li]);
+    L.lim_base = reinterpret_cast<uint64_t*>(m + o_lim[li]);
+    L.items_base = reinterpret_cast<uint64_t*>(m + o_it[li]);
+    ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&L.aux, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&L.ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&L.ev_join, hipEventDisableTiming) == hipSuccess;
+  }
   // the resident prime table (the paper's one-time cost, Section 5)
-  ok = ok && launch_primes(cfg->max_limit, s->pw, s->stream) == hipSuccess;
-  ok = ok && launch_fill_u32(reinterpret_cast<uint32_t*>(s->diag), 2ull * D_COUNT, 0u, s->stream) == hipSuccess;
-  ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+  hipStream_t st0 = s->lane[0].stream;
+  ok = ok && launch_primes(cfg->max_limit, s->pw, st0) == hipSuccess;
+  ok = ok && launch_fill_u32(reinterpret_cast<uint32_t*>(s->diag), 2ull * D_COUNT, 0u, st0) == hipSuccess;
+  ok = ok && hipStreamSynchronize(st0) == hipSuccess;
   if (!ok) {
-    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
-    if (s->aux) (void)hipStreamDestroy(s->aux);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (uint32_t li = 0; li < s->n_lanes; ++li) {
+      Lane& L = s->lane[li];
+      if (L.ev_fork) (void)hipEventDestroy(L.ev_fork);
+      if (L.ev_join) (void)hipEventDestroy(L.ev_join);
+      if (L.aux) (void)hipStreamDestroy(L.aux);
+      if (L.stream) (void)hipStreamDestroy(L.stream);
+    }
     (void)hipFree(s->arena_mem);
     (void)hipFree(s->fixed_mem);
     delete s;
     return CS_EDEVICE;
   }
-  s->th = std::thread(server_loop, s);
+  for (uint32_t li = 0; li < s->n_lanes; ++li) s->lane[li].th = std::thread(server_loop, s, li);
   *out = s;
   return CS_OK;
 }
@@ -515,9 +558,10 @@ extern "C" cs_status cs_server_submit(cs_server* s, const cs_job* job, uint64_t*
   J.job = *job;
   J.plan = pl;
   J.t_submit = now_s();
-  s->pending.push_back(t);
+  J.lane = (s->n_lanes > 1 && est_ms(pl) > s->cfg.long_ms) ? 1u : 0u;
+  s->lane[J.lane].pending.push_back(t);
   s->st.submitted++;
-  s->cv_work.notify_one();
+  s->cv_work.notify_all();
   *ticket = t;
   return CS_OK;
 }
@@ -580,8 +624,12 @@ extern "C" cs_status cs_server_stats(cs_server* s, cs_server_counters* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->st;
   out->bytes_in_use = s->arena.used();
-  out->active = s->active.size();
-  out->queued = s->pending.size();
+  out->active = 0;
+  out->queued = 0;
+  for (uint32_t li = 0; li < s->n_lanes; ++li) {
+    out->active += s->lane[li].active.size();
+    out->queued += s->lane[li].pending.size();
+  }
   return s->failed ? CS_EDEVICE : CS_OK;
 }
 
@@ -592,13 +640,16 @@ extern "C" cs_status cs_server_destroy(cs_server* s) {
     s->stop = true;
     s->cv_work.notify_all();
   }
-  if (s->th.joinable()) s->th.join();
-  (void)hipStreamSynchronize(s->stream);
-  (void)hipStreamSynchronize(s->aux);
-  (void)hipEventDestroy(s->ev_fork);
-  (void)hipEventDestroy(s->ev_join);
-  (void)hipStreamDestroy(s->aux);
-  (void)hipStreamDestroy(s->stream);
+  for (uint32_t li = 0; li < s->n_lanes; ++li) {
+    Lane& L = s->lane[li];
+    if (L.th.joinable()) L.th.join();
+    (void)hipStreamSynchronize(L.stream);
+    (void)hipStreamSynchronize(L.aux);
+    (void)hipEventDestroy(L.ev_fork);
+    (void)hipEventDestroy(L.ev_join);
+    (void)hipStreamDestroy(L.aux);
+    (void)hipStreamDestroy(L.stream);
+  }
   (void)hipFree(s->arena_mem);
   (void)hipFree(s->fixed_mem);
   delete s;

@@ -67,6 +67,26 @@ def test_served_equals_alone(mode, kmod):
     srv.close()
 
 
+def test_two_lanes_equal_alone():
+    """long_ms small enough that the larger jobs run in the second lane, beside the others."""
+    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
+    srv = cs.Server(budget_bytes=2 << 30, max_limit=10**8, max_active=4, chunks=1, tune=tune, long_ms=0.5)
+    tickets = [srv.submit(job) for job in JOBS]
+    for t in tickets:
+        assert srv.wait(t, 120.0).state == 2
+    for job, t in zip(JOBS, tickets):
+        b, c = srv.fetch(t)
+        torch.cuda.synchronize()
+        a_b, a_c = _alone(job, tune)
+        assert np.array_equal(_np(b), a_b) and np.array_equal(_np(c), a_c), job
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == len(JOBS) and st["failed"] == 0 and st["active"] == 0 and st["queued"] == 0
+    srv.close()
+    with pytest.raises(cs.CsError):
+        cs.Server(budget_bytes=1 << 20, max_limit=10**6, long_ms=-1.0)
+
+
 def test_budget_forces_queueing_and_results_hold():
     """A budget that fits about one job at a time: jobs wait for memory, results are unchanged."""
     jobs = [W.Job(307, 2, 12345 + 1000 * i, 4000, 2500, 10**7) for i in range(4)]
