@@ -474,7 +474,8 @@ __device__ bool q_sprp2(const uint32_t (&n)[L], uint32_t r, uint32_t* own, const
 // -7, 9, -11, ... with Jacobi symbol (D/n) = -1, P = 1, Q = (1 - D)/4; with n + 1 = 2^s d, d odd,
 // n passes iff U_d = 0 or V_(2^r d) = 0 (mod n) for some 0 <= r < s.  U, V and Q^k run in
 // Montgomery form through the doubling formulas U_2k = U_k V_k, V_2k = V_k^2 - 2Q^k and the step
-// U_(k+1) = (U_k + V_k)/2, V_(k+1) = (D U_k + V_k)/2.
+// U_(k+1) = (U_k + V_k)/2, V_(k+1) = (D U_k + V_k)/2, whose products by D and Q (small integers)
+// are chains of doublings and additions.
 // ---------------------------------------------------------------------------------------------
 // Searched values of |D|: a non-square n has (D/n) = -1 for some |D| below 2 (ln n)^2 under the
 // generalised Riemann hypothesis (4.1e6 for n < 2^2048); a search that reaches the bound reports
@@ -616,6 +617,32 @@ __device__ __forceinline__ void q_mont_small(uint32_t (&t)[L], int32_t c, const 
   }
 }
 
+// t = c x mod n for a small signed c != 0 and x < n (any form: the product of a residue in
+// Montgomery form by an integer stays in that form), by doubling and adding; t may alias x.
+template <int L>
+__device__ __forceinline__ void q_mul_small(uint32_t (&t)[L], const uint32_t (&x)[L], int32_t c,
+                                            const uint32_t (&n)[L], uint32_t r) {
+  const uint32_t a = (uint32_t)(c < 0 ? -c : c);
+  uint32_t y[L], acc[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    y[j] = x[j];
+    acc[j] = x[j];                                             // the top bit of a
+  }
+  for (int bit = 30 - __clz(a); bit >= 0; --bit) {
+    q_mod_dbl<L>(acc, n, r);
+    if ((a >> bit) & 1u) q_mod_add<L>(acc, acc, y, n, r);
+  }
+  if (c < 0) {
+    uint32_t z[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) z[j] = 0;
+    q_mod_sub<L>(acc, z, acc, n, r);
+  }
+#pragma unroll
+  for (int j = 0; j < L; ++j) t[j] = acc[j];
+}
+
 // Strong Lucas probable-prime test of n (NL = 4L limbs spread over the quad); own/col as in
 // q_sprp2 (the second L words of each lane's column receive n + 1).
 template <int L>
@@ -696,8 +723,7 @@ __device__ bool q_strong_lucas(const uint32_t (&n)[L], uint32_t r, uint32_t* own
 #pragma unroll
   for (int j = 0; j < L; ++j) one[j] = ((int)(r * L + j) == ((nbits - 1) >> 5)) ? (1u << ((nbits - 1) & 31)) : 0u;
   for (int k = 0; k < 32 * 4 * L - nbits + 1; ++k) q_mod_dbl<L>(one, n, r);
-  uint32_t Dm[L], Qm[L];
-  q_mont_small<L>(Dm, D, one, n, r);
+  uint32_t Qm[L];
   q_mont_small<L>(Qm, Q, one, n, r);
   // U_1 = 1, V_1 = P = 1, Q^1; then the bits of d = (n + 1) / 2^s below its top bit
   uint32_t U[L], V[L], Qk[L], t[L], w[L];
@@ -714,9 +740,7 @@ __device__ bool q_strong_lucas(const uint32_t (&n)[L], uint32_t r, uint32_t* own
     q_mod_sub<L>(V, V, t, n, r);                                      // V_2k = V_k^2 - 2 Q^k
     q_mont_sqr<L>(Qk, n, ninv, r, own, col);                          // Q^2k
     if (np1_bit(bit)) {
-#pragma unroll
-      for (int j = 0; j < L; ++j) w[j] = U[j];
-      q_mont_mul<L>(w, Dm, n, ninv, r, own, col);                     // D U_k
+      q_mul_small<L>(w, U, D, n, r);                                  // D U_k (|D| small)
       q_mod_add<L>(t, U, V, n, r);
       q_half<L>(t, n, r);                                             // U_(k+1) = (U_k + V_k) / 2
       q_mod_add<L>(w, w, V, n, r);
@@ -726,7 +750,7 @@ __device__ bool q_strong_lucas(const uint32_t (&n)[L], uint32_t r, uint32_t* own
         U[j] = t[j];
         V[j] = w[j];
       }
-      q_mont_mul<L>(Qk, Qm, n, ninv, r, own, col);                    // Q^(k+1)
+      q_mul_small<L>(Qk, Qk, Q, n, r);                                // Q^(k+1) (|Q| small)
     }
   }
   if (q_is_zero<L>(U) || q_is_zero<L>(V)) return true;
