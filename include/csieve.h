@@ -122,7 +122,10 @@ typedef struct cs_tune {
  * beyond it fall back to the atomic path, so results stay exact.  LIST needs n_m * 2^s <= 2^32 and
  * at most 8192 row buckets (CS_EINVAL when requested otherwise).  AUTO, for cs_sieve / cs_prepare
  * / cs_sieve_range: BYTES where exact, else ATOMIC.  Batches use BYTES when every job can, else
- * ATOMIC (they ignore LIST); the server uses ATOMIC.  With BYTES, a whole-range call runs the
+ * ATOMIC (they ignore LIST); the server gives each job byte counters where they are exact and
+ * its tables with them take at most a quarter of the budget, and an iteration uses BYTES when
+ * every job in it has them, else ATOMIC (LIST and an explicit BYTES act as AUTO there; ATOMIC
+ * keeps ATOMIC).  With BYTES, a whole-range call runs the
  * small-prime branch on a second stream beside the large one (the large branch writes only its
  * counters until the fold), joined back into `stream` before the call's last kernel.  Outputs are
  * identical in every mode. */
@@ -459,7 +462,10 @@ typedef struct cs_server_config {
   uint32_t max_active;     /* jobs in flight at once (slots) */
   uint32_t chunks;         /* large-prime chunks per job, one per iteration (0 = 1: every job in one
                               iteration, measured best for latency on mixed jobs) */
-  cs_tune tune;            /* applied to every job */
+  cs_tune tune;            /* applied to every job; with thr = 0 and CS_LARGE_THREE_GAP each job's
+                              threshold is 44 n_x (the small and large branches of many jobs share
+                              the device at once, so their costs add: n_m 1.25 ps per small prime
+                              against n_m n_x / p hit atomics of 55 ps per large one) */
   double long_ms;          /* > 0: jobs whose estimated device time alone exceeds this many ms run
                               in a second lane (its own loop, streams and iterations) beside the
                               others, so that their iterations do not wait for the long jobs;
@@ -482,6 +488,7 @@ typedef struct cs_server_stats {
   uint64_t submitted, admitted, completed, failed, iterations;
   uint64_t kmod_builds, kmod_hits, kmod_evictions;
   uint64_t bytes_in_use, active, queued;
+  uint64_t bytes_iterations;   /* iterations whose large branch used the byte counters */
 } cs_server_counters;
 
 /* Allocates budget_bytes plus the prime table on the current device, builds the prime table

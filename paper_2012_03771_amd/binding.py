@@ -77,7 +77,7 @@ class cs_ticket_info(C.Structure):
 class cs_server_counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "iterations",
                                           "kmod_builds", "kmod_hits", "kmod_evictions", "bytes_in_use",
-                                          "active", "queued")]
+                                          "active", "queued", "bytes_iterations")]
 
 
 @dataclass

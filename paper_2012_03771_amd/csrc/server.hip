@@ -165,24 +165,47 @@ struct cs_server {
 
 namespace {
 
-// A job whose large branch forms K mod p itself keeps a table for its small primes in its own
-// tables; any other job shares one K mod p table per (P, d) across jobs.
-cs_status plan_for_server(const cs_server* s, const cs_job* job, Plan* pl) {
-  cs_status st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, true, false);
-  if (st) return st;
-  if (!pl->kmod_fused) {
-    st = make_plan(job, &s->cfg.tune, s->n_cu, pl, false, false, false);
-    if (st) return st;
-  }
-  if (pl->Lp > s->cfg.max_limit) return CS_ERANGE;
-  return CS_OK;
-}
-
 uint64_t job_bytes(const Plan& pl) {
   return a256(pl.ws.total) + a256(pl.n_m * (uint64_t)pl.row_words * 4ull) + a256(pl.n_m * 4ull);
 }
 
 uint64_t kmod_bytes(uint64_t limit) { return a256(pi_upper(limit) * 8ull); }
+
+// Small/large threshold of a served three-gap job, per column of the interval.  A prime p in the
+// small branch costs about n_m residue steps of c_pair = 1.25 ps; in the large branch it costs
+// about n_m n_x / p hit atomics of c_hit = 55 ps (plus a setup that is small beside n_m c_pair).
+// A lone job hides its small branch beside the large one, but the server's iterations run many
+// jobs' small and large branches at once, where the two add up: their sum is least at
+// p = n_x c_hit / c_pair, about 44 n_x (measured on the mixed jobs alone: 15% less device time
+// than the lone job's 30 S).
+constexpr uint64_t kServerThrPerColumn = 44;
+
+// A job whose large branch forms K mod p itself keeps a table for its small primes in its own
+// tables; any other job shares one K mod p table per (P, d) across jobs.  The job's tables hold
+// byte counters for its large hits (one atomic per hit instead of two) where they are exact and
+// the job then takes at most a quarter of the budget; the scatter ATOMIC keeps them out.
+cs_status plan_for_server(const cs_server* s, const cs_job* job, Plan* pl) {
+  cs_tune t = s->cfg.tune;
+  if (t.scatter != CS_SCATTER_ATOMIC) t.scatter = CS_SCATTER_AUTO;
+  if (t.thr == 0 && t.large_mode == CS_LARGE_THREE_GAP) {
+    const cs_status st = make_plan(job, &t, s->n_cu, pl, false, true, false);
+    if (st) return st;
+    t.thr = std::max<uint64_t>(1, kServerThrPerColumn * pl->n_x);
+  }
+  for (int bytes = t.scatter == CS_SCATTER_AUTO ? 1 : 0; bytes >= 0; --bytes) {
+    cs_status st = make_plan(job, &t, s->n_cu, pl, false, true, bytes != 0);
+    if (st) return st;
+    if (!pl->kmod_fused) {
+      st = make_plan(job, &t, s->n_cu, pl, false, false, bytes != 0);
+      if (st) return st;
+    }
+    if (!pl->scatter_bytes ||
+        job_bytes(*pl) + (pl->kmod_fused ? 0 : kmod_bytes(job->limit)) <= s->cfg.budget_bytes / 4)
+      break;
+  }
+  if (pl->Lp > s->cfg.max_limit) return CS_ERANGE;
+  return CS_OK;
+}
 
 // Frees unreferenced K mod p tables, least recently used first, until `need` bytes fit.
 bool make_room(cs_server* s, uint64_t need) {
@@ -320,7 +343,7 @@ void retire(cs_server* s, SJob& J, int state) {
 }
 
 // One iteration: prepare the newly admitted jobs and advance every active job by one chunk.
-bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act) {
+bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act, bool* used_bytes) {
   hipStream_t st = L.stream;
   const uint32_t n = (uint32_t)act.size();
   std::vector<SJob*> fresh;
@@ -354,7 +377,16 @@ bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act) {
     if (launch_kmod(L.prep_dev, nf, L.lim_base, kcap, s->n_cu, st) != hipSuccess) return false;
     if (launch_rows_cols(L.prep_dev, nf, max_m, max_sl, s->n_cu, st) != hipSuccess) return false;
     if (launch_dpattern(L.prep_dev, nf, max_phi, max_rw, st) != hipSuccess) return false;
+    // the byte counters start cleared; every fold clears them again
+    if (launch_zero_bytes(L.prep_dev, nf, max_words, s->n_cu, st) != hipSuccess) return false;
     for (SJob* J : fresh) J->prepped = true;
+  }
+  // the byte counters when every job has them (a job without rows has no large items)
+  bool bytes = true;
+  uint64_t max_rows = 0;
+  for (SJob* J : act) {
+    if (J->plan.n_m && !J->plan.scatter_bytes) bytes = false;
+    max_rows = std::max<uint64_t>(max_rows, J->plan.n_m);
   }
   // the sieve: every active job's current chunk, fused
   uint64_t units = 0;
@@ -373,7 +405,7 @@ bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act) {
     jd.p_hi = J.bounds[J.chunk + 1];
     fill_tiers(J.plan, jd.p_lo, jd.p_hi, &jd);
     jd.small_unit_base = units;
-    jd.small_atomic = 1;
+    jd.small_atomic = bytes ? 0u : 1u;   // with the counters the large branch leaves the bitmap alone
     if (J.chunk == 0) {
       units += (uint64_t)J.plan.n_windows * J.plan.n_slices;
       lds = std::max(lds, J.plan.lds_bytes);
@@ -382,21 +414,23 @@ bool iterate(cs_server* s, Lane& L, std::vector<SJob*>& act) {
   }
   if (launch_prep_bounds(L.run_dev, n, st) != hipSuccess) return false;
   if (launch_items_scan(L.run_dev, n, L.items_base, st) != hipSuccess) return false;
-  // the small branch on the second stream beside the large one: both merge into the bitmap and
-  // counts with atomics (small_atomic), so the order of their updates does not matter
+  // the small branch on the second stream beside the large one: either the large branch writes
+  // only its byte counters, folded in after both, or both merge into the bitmap and counts with
+  // atomics (small_atomic); the order of their updates does not matter
   if (units) {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(units, 1ull << 31);   // one workgroup per unit
     if (hipEventRecord(L.ev_fork, st) != hipSuccess || hipStreamWaitEvent(L.aux, L.ev_fork, 0) != hipSuccess)
       return false;
     if (launch_small(L.run_dev, n, units, lds, lds_ct, blocks, L.aux) != hipSuccess) return false;
   }
-  if (launch_large(L.run_dev, n, L.items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0, 0u,
-                   s->cfg.tune.large_mode, st) !=
-      hipSuccess)
+  if (launch_large(L.run_dev, n, L.items_base, s->diag, nullptr, (uint32_t)s->n_cu * kLargeBlocksPerCu, 0, 0, 0,
+                   bytes ? 1u : 0u, s->cfg.tune.large_mode, st) != hipSuccess)
     return false;
   if (units && (hipEventRecord(L.ev_join, L.aux) != hipSuccess || hipStreamWaitEvent(st, L.ev_join, 0) != hipSuccess))
     return false;
+  if (bytes && launch_fold_bytes(L.run_dev, n, max_rows, s->n_cu, st) != hipSuccess) return false;
   if (hipStreamSynchronize(st) != hipSuccess) return false;
+  *used_bytes = bytes;
   return true;
 }
 
@@ -419,9 +453,11 @@ void server_loop(cs_server* s, uint32_t li) {
     std::vector<SJob*> act;
     for (uint64_t t : L.active) act.push_back(&s->jobs[t]);
     lk.unlock();
-    const bool ok = iterate(s, L, act);
+    bool used_bytes = false;
+    const bool ok = iterate(s, L, act, &used_bytes);
     lk.lock();
     s->st.iterations++;
+    if (used_bytes) s->st.bytes_iterations++;
     std::vector<uint64_t> keep;
     for (uint64_t t : L.active) {
       SJob& J = s->jobs[t];

@@ -34,11 +34,15 @@ JOBS = [W.Job(61, 6, 1000, 3000, 500, 10**6), W.Job(131, 1, 7, 5000, 900, 2 * 10
         W.Job(503, 210, 10**6, 4000, 7000, 3 * 10**7), W.Job(97, 30, 10**6, 20000, 1200, 5 * 10**6)]
 
 
-@pytest.mark.parametrize("mode,kmod", [(cs.LARGE_G, cs.KMOD_AUTO), (cs.LARGE_THREE_GAP, cs.KMOD_AUTO),
-                                       (cs.LARGE_THREE_GAP, cs.KMOD_TABLE)], ids=["g", "three_gap", "three_gap_table"])
-def test_served_equals_alone(mode, kmod):
-    """Jobs forming K mod p in their large branch (the default), or sharing one table per (P, d)."""
-    tune = cs.Tune(large_mode=mode, kmod=kmod)
+@pytest.mark.parametrize("mode,kmod,scatter", [(cs.LARGE_G, cs.KMOD_AUTO, cs.SCATTER_AUTO),
+                                               (cs.LARGE_THREE_GAP, cs.KMOD_AUTO, cs.SCATTER_AUTO),
+                                               (cs.LARGE_THREE_GAP, cs.KMOD_TABLE, cs.SCATTER_AUTO),
+                                               (cs.LARGE_THREE_GAP, cs.KMOD_AUTO, cs.SCATTER_ATOMIC)],
+                         ids=["g", "three_gap", "three_gap_table", "three_gap_atomic"])
+def test_served_equals_alone(mode, kmod, scatter):
+    """Jobs forming K mod p in their large branch (the default), or sharing one table per (P, d);
+    large hits through byte counters (the default) or per-hit atomics."""
+    tune = cs.Tune(large_mode=mode, kmod=kmod, scatter=scatter)
     srv = cs.Server(budget_bytes=2 << 30, max_limit=10**8, max_active=4, chunks=3, tune=tune)
     tickets = []
     for i, job in enumerate(JOBS):
@@ -64,6 +68,10 @@ def test_served_equals_alone(mode, kmod):
     else:
         assert st["kmod_builds"] == 0 and st["kmod_hits"] == 0
     assert st["iterations"] >= 4
+    if scatter == cs.SCATTER_ATOMIC:
+        assert st["bytes_iterations"] == 0
+    else:
+        assert st["bytes_iterations"] == st["iterations"]     # every job here admits the counters
     srv.close()
 
 
