@@ -9,7 +9,8 @@ affects speed.
 
 tune_batch then tunes the whole batch: the batch path (one persistent launch over a device task
 queue, or per-job launches over lane streams) and the rows per small-branch LDS tile (the
-m-window of a tile), timing each combination on the batch itself replayed from its hipGraph.
+m-window of a tile), timing each combination on the batch itself replayed from its hipGraph, and
+then the per-job thresholds against one rule for jobs that share the device (44 n_x).
 """
 from __future__ import annotations
 
@@ -90,21 +91,28 @@ class Autotuner:
                          for ipt, rows in ((256, 16), (1024, 8), (1024, 16), (4096, 16))]
                         + [{"path": B.BATCH_LANES, "items_per_task": 0, "tile_rows": rows} for rows in (8, 16)])
 
+    # threshold per column of the interval for jobs that share the device (the small and large
+    # branches of many jobs then add up rather than overlap: n_m 1.25 ps per small prime against
+    # n_m n_x / p hit atomics of 55 ps per large one, least at thr = 44 n_x)
+    THR_PER_COLUMN = 44
+
     def tune_batch(self, jobs, reps: int = 2):
         """Per-job tunings (tune_all), then the batch path, items per task and small-branch tile
-        rows that run the whole batch fastest.  Returns (tunes, batch options, timings)."""
+        rows that run the whole batch fastest; for that combination, the per-job thresholds are
+        then set against thr = 44 n_x for every job, and the faster kept.  Returns (tunes, batch
+        options, timings)."""
         import dataclasses
         import time
         import torch
         base = self.tune_all(jobs)
         timings = []
         best = None
-        for cand in self.BATCH_CANDIDATES:
-            tunes = [dataclasses.replace(t, tile_rows=cand["tile_rows"]) for t in base]
+
+        def timed(tunes, cand):
             try:
                 batch = B.Batch(jobs, tunes, path=cand["path"], items_per_task=cand["items_per_task"])
             except B.CsError:
-                continue                                  # this path does not admit the jobs
+                return None                               # this path does not admit the jobs
             bm, ct = batch.alloc_outputs()
             batch.run(bm, ct, use_graph=True)
             torch.cuda.synchronize()
@@ -115,8 +123,24 @@ class Autotuner:
             t = (time.perf_counter() - t0) / reps
             batch.close()
             del bm, ct
-            timings.append({**cand, "ms": t * 1e3})
+            return t
+
+        for cand in self.BATCH_CANDIDATES:
+            tunes = [dataclasses.replace(t, tile_rows=cand["tile_rows"]) for t in base]
+            t = timed(tunes, cand)
+            if t is None:
+                continue
+            timings.append({**cand, "thr": "per job", "ms": t * 1e3})
             if best is None or t < best[0]:
+                best = (t, cand, tunes)
+        cand = best[1]
+        tunes = [dataclasses.replace(t, tile_rows=cand["tile_rows"], large_mode=B.LARGE_THREE_GAP,
+                                     thr=self.THR_PER_COLUMN * max(1, B.plan(j).n_x))
+                 for t, j in zip(base, jobs)]
+        t = timed(tunes, cand)
+        if t is not None:
+            timings.append({**cand, "thr": "%d n_x" % self.THR_PER_COLUMN, "ms": t * 1e3})
+            if t < best[0]:
                 best = (t, cand, tunes)
         torch.cuda.empty_cache()
         return best[2], {"path": best[1]["path"], "items_per_task": best[1]["items_per_task"]}, timings

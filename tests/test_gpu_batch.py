@@ -120,6 +120,16 @@ def test_autotuned_batch_equals_alone():
         a_b, a_c = _alone(job)                    # default tuning: outputs do not depend on it
         assert np.array_equal(_np(bm[i]), a_b) and np.array_equal(_np(ct[i]), a_c), job
     batch.close()
+    # the whole-batch tuning: path, tile rows, then the per-column threshold rule
+    tunes2, opts, timings = tuner.tune_batch(jobs, reps=1)
+    assert any(t["thr"] == "44 n_x" for t in timings) and any(t["thr"] == "per job" for t in timings)
+    b2 = cs.Batch(jobs, tunes2, **opts)
+    bm2, ct2 = b2.alloc_outputs()
+    b2.run(bm2, ct2, use_graph=True)
+    torch.cuda.synchronize()
+    for i, job in enumerate(jobs):
+        assert torch.equal(bm[i], bm2[i]) and torch.equal(ct[i], ct2[i]), job
+    b2.close()
 
 
 @pytest.mark.parametrize("mode", [cs.LARGE_G, cs.LARGE_THREE_GAP], ids=["g", "three_gap"])
