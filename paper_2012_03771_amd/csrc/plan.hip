@@ -145,9 +145,11 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 2.5 M / M_c (a quarter of the paper's 10 M / M_c: at 953#/210 the step is flat from 120,000
   // to 437,507 = 2.5 M / M_c S, 216-218 ms, against 223 ms at 5 M / M_c S); with three-gap stepping
-  // a hit costs a few operations and the small branch runs beside the large one, so twice the
-  // paper's naive 10 S is used (measured at 953#/210: step 101 ms at 20 S, 99 ms at 25 S,
-  // 104 ms at 30 S, 114 ms at 40 S).  Clamped so that a large prime divides at most one number of an interval
+  // a hit costs a few operations and the small branch runs beside the large one, so three times
+  // the paper's naive 10 S is used.  Measured at 953#/210, m_inc 1e6: one call takes 86.4 ms at
+  // 24 S, 85.0 at 30 S, 84.1 at 44 S, 86.2 at 60 S; on jobs with fewer rows the small branch
+  // hides less and lower multiples win (the sum of 96 mixed jobs alone: 309 ms at 8 S, 361 ms at
+  // 30 S, 390 ms at 40 S), so 30 S is kept.  Clamped so that a large prime divides at most one number of an interval
   // (p > 2 sl), or (three-gap) p > 4 sl.
   uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
