@@ -255,7 +255,7 @@ cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bit
   }
   hipStream_t s_small = aux ? aux->s : s;
   if (branches != CS_BRANCH_LARGE && !aux)
-    CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s_small));
+    CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, s_small, pl.small_hit_rows));
   JobCtrl* ctrl = reinterpret_cast<JobCtrl*>(ws + L.ctrl);
   if (branches != CS_BRANCH_SMALL) {
     if (pl.scatter_list) {
@@ -276,7 +276,7 @@ cs_status range_core(const Plan& pl, uint64_t p_lo, uint64_t p_hi, uint32_t* bit
       ev->recorded = true;
     }
     if (aux) {   // small branch queued after the large kernel so the large one starts first
-      CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, aux->s));
+      CS_TRY(launch_small(jdp, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, aux->s, pl.small_hit_rows));
       CS_TRY(hipEventRecord(aux->join, aux->s));
       CS_TRY(hipStreamWaitEvent(s, aux->join, 0));
     }

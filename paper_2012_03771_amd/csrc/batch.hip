@@ -241,7 +241,7 @@ cs_status multi_enqueue(MultiJob& b, hipStream_t s) {
     uint64_t* ib = reinterpret_cast<uint64_t*>(b.mem + b.job_off[i] + pl.ws.items_base);
     CS_TRY(launch_items_scan(jd, 1, ib, ls));
     const uint64_t units = (uint64_t)pl.n_windows * pl.n_slices;
-    CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, ls));
+    CS_TRY(launch_small(jd, 1, units, pl.lds_bytes, pl.lds_ct_words, pl.small_blocks, ls, pl.small_hit_rows));
     CS_TRY(launch_large(jd, 1, ib, b.jds[i].ctrl->diag, &b.jds[i].ctrl->dec[0][0], pl.large_blocks, pl.large_lds_bytes, pl.large_lds_ct_words,
                         (uint32_t)pl.dpre.size(), pl.scatter_bytes ? 1u : 0u, pl.large_mode, ls));
     if (pl.scatter_bytes) CS_TRY(launch_fold_bytes(jd, 1, pl.n_m, b.n_cu, ls));

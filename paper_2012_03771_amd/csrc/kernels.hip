@@ -864,10 +864,15 @@ struct SmallArgs {
 // [i_lo, i_hi), one lane per prime.  Between rows the offset s (the X + sl with p | m K + X)
 // steps by -dm k (mod p) for the row gap dm, which is the same for every lane: the multiples
 // g k mod p for g < 16 sit in registers and the gap indexes them (a scalar index), and a gap of
-// 16 or more takes one modular product.  The column lookup runs for every lane without a branch,
-// two rows at a time so that their LDS reads overlap, and row r's marks by the wave accumulate
-// in lane r of one register (rows <= 64), added to the tile's row counts once at the end.
-template <class CT>
+// 16 or more takes one modular product.
+// Where a wave's primes hit few of the tile's rows (p >= R (w + 1) / 2: at most about two hits
+// per lane), a first pass only steps the offsets and keeps the rows with s <= w as bits; a second
+// pass visits each lane's own hit rows (the offset again from the first row's by one modular
+// product), looks the column up and marks it, with the row count added by an LDS atomic.  Below
+// that bound the column lookup runs for every lane and row without a branch, two rows at a time
+// so that their LDS reads overlap, and row r's marks by the wave accumulate in lane r of one
+// register (rows <= 64), added to the tile's row counts once at the end.
+template <bool kHit, class CT>
 __device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, uint64_t i_lo, uint64_t i_hi,
                                                    unsigned long long& n_pairs, unsigned long long& n_marks) {
   const JobDev& j = a.j;
@@ -880,7 +885,14 @@ __device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, ui
   const gptr<const uint64_t> kmod = gbl(j.kmod);
   const gptr<const uint64_t> mkp = gbl(j.mk);
   const uint32_t moffv = lane < R ? a.moff[lane] : 0u;         // lane r: m offset of row r
+  // the hit-row pass steps a fixed kHitRows rows, those past R repeating the last row (gap 0),
+  // when every row gap of the tile indexes the register table
+  constexpr uint32_t kHitRows = 16;
+  const uint32_t moffc = R ? a.moff[lane < R ? lane : R - 1] : 0u;
+  const uint32_t gapv = lane + 1 < R ? a.moff[lane + 1] - a.moff[lane] : 0u;
+  const bool hit_rows_ok = R >= 1 && R <= kHitRows && __ballot(gapv >= 16u) == 0;
   uint32_t cntv = 0;                                           // lane r: this wave's marks in row r
+  uint32_t nmv = 0;                                            // this lane's marks by hit rows
   for (uint64_t ib = i_lo; ib < i_hi; ib += blockDim.x) {
     const uint64_t i = ib + threadIdx.x;
     bool act = i < i_hi;
@@ -909,6 +921,40 @@ __device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, ui
       return s >= kd ? t : t + p32;
     };
     const uint32_t na = (uint32_t)__popcll(__ballot(act));
+    if (lane == 0) n_pairs += (unsigned long long)na * R;
+    // the wave's smallest prime sits in its first lane (an idle first lane: an idle wave)
+    const uint32_t p_first = __builtin_amdgcn_readfirstlane(p32);
+    if (kHit && hit_rows_ok && (uint64_t)R * (w + 1ull) <= 2ull * p_first) {
+      const uint32_t o0 = __builtin_amdgcn_readfirstlane(moffc);
+      uint32_t hitm = s0 <= w ? 1u : 0u;                       // bit r: row r has s <= w
+      uint32_t sr = s0, o_prev = o0;
+#pragma unroll
+      for (uint32_t r = 1; r < kHitRows; ++r) {
+        const uint32_t o = __builtin_amdgcn_readlane(moffc, r);
+        const uint32_t kd = km[o - o_prev];                    // a scalar index below 16
+        o_prev = o;
+        const uint32_t t = sr - kd;
+        sr = min(t, t + p32);                                  // t wrapped above 2^31 when sr < kd
+        hitm |= sr <= w ? 1u << r : 0u;
+      }
+      hitm &= (1u << R) - 1u;                                  // R <= 16
+      if (!act) hitm = 0;
+      while (hitm) {
+        const uint32_t r = (uint32_t)__builtin_ctz(hitm);
+        hitm &= hitm - 1;
+        const uint32_t kd = (uint32_t)mulmod(a.moff[r] - o0, k, p, pinv);
+        const uint32_t sh = s0 >= kd ? s0 - kd : s0 + p32 - kd;
+        const uint64_t e = ct_entry(ct, sh >> 5);
+        const uint32_t b = sh & 31u;
+        if (((uint32_t)e >> b) & 1u) {
+          const uint32_t col = (uint32_t)(e >> 32) + __popc((uint32_t)e & ((1u << b) - 1u));
+          atomicOr(&tile[r * rw + (col >> 5)], 1u << (col & 31));
+          atomicAdd(&a.cnt[r], 1u);
+          ++nmv;
+        }
+      }
+      continue;
+    }
     for (uint32_t r = 0; r < R; r += 2) {
       const bool two = r + 1 < R;                              // the same for every lane
       const uint32_t o_r = __builtin_amdgcn_readlane(moffv, r);
@@ -938,13 +984,13 @@ __device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, ui
         s0 = advance(s1, o_r2 - o_r1);
       }
     }
-    if (lane == 0) n_pairs += (unsigned long long)na * R;
   }
   if (lane < R && cntv) atomicAdd(&a.cnt[lane], cntv);
-  const uint32_t tot = wave_sum_u32(cntv);
+  const uint32_t tot = wave_sum_u32(cntv + nmv);
   if (lane == 0) n_marks += tot;
 }
 
+template <bool kHit>
 __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __restrict__ ct,
                                             unsigned long long& n_pairs, unsigned long long& n_marks) {
   const JobDev& j = a.j;
@@ -994,7 +1040,7 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
   if (j.thr < (1ull << 31)) {
     // primes above w: at most one mark per row
     const uint64_t sg_lo = max(sp_lo, min(a.small_single, s_hi));
-    if (R <= kWave && sg_lo < s_hi) small_single_marks(a, ct, sg_lo, s_hi, n_pairs, n_marks);
+    if (R <= kWave && sg_lo < s_hi) small_single_marks<kHit>(a, ct, sg_lo, s_hi, n_pairs, n_marks);
     const uint64_t sp_hi = R <= kWave ? sg_lo : s_hi;
     // the others: every small prime (<= thr) is below 2^31, so residues sit in 32-bit registers
     // (s + p - k < 2^32, jj + p < 2^32), and the marks of a row are counted by ballots (a lane
@@ -1099,6 +1145,7 @@ __device__ __forceinline__ void small_marks(const SmallArgs& a, const uint2* __r
 // One small-branch unit (a window of tile_rows rows and a slice of the small primes) of job j,
 // by the whole workgroup: unit `local` of the job.  lds: [column table, lds_ct_words uint2][tile
 // rows x row_words][counts][m offsets]; ct_ready: the job's column table is already in place.
+template <bool kHit>
 __device__ __forceinline__ void small_unit(const JobDev& j, uint64_t local, uint32_t* lds, uint32_t lds_ct_words,
                                            bool ct_ready, unsigned long long& n_pairs, unsigned long long& n_marks) {
   const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -1152,8 +1199,8 @@ __device__ __forceinline__ void small_unit(const JobDev& j, uint64_t local, uint
 
   {
     SmallArgs a{j, c.small_dense, c.small_single, tile, cnt, moff, R, rw, w, s_lo, s_hi, dpat, lane, wid, nwaves};
-    if (ct_in_lds) small_marks(a, ct_l, n_pairs, n_marks);   // LDS column table
-    else small_marks(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
+    if (ct_in_lds) small_marks<kHit>(a, ct_l, n_pairs, n_marks);   // LDS column table
+    else small_marks<kHit>(a, (const uint2*)gbl(j.coltab), n_pairs, n_marks);   // global column table
   }
   __syncthreads();
   // write the tile: rows of this unit belong to it alone unless the primes are sliced
@@ -1175,6 +1222,9 @@ __device__ __forceinline__ void small_unit(const JobDev& j, uint64_t local, uint
   __syncthreads();
 }
 
+// kHit: the hit-row pass for the primes far above w (its own instance, so that the other keeps
+// its register budget: jobs of few rows per prime range ran slower with the pass compiled in)
+template <bool kHit>
 __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, uint32_t n_jobs,
                                                uint64_t total_units, uint32_t lds_ct_words) {
   extern __shared__ uint32_t lds[];
@@ -1184,7 +1234,7 @@ __global__ __launch_bounds__(256) void k_small(const JobDev* __restrict__ jobs, 
   uint32_t ji = 0;                                   // units only grow: resume the job search
   for (uint64_t unit = blockIdx.x; unit < total_units; unit += gridDim.x) {
     while (ji + 1 < n_jobs && jobs[ji + 1].small_unit_base <= unit) ++ji;
-    small_unit(jobs[ji], unit - jobs[ji].small_unit_base, lds, lds_ct_words, false, n_pairs, n_marks);
+    small_unit<kHit>(jobs[ji], unit - jobs[ji].small_unit_base, lds, lds_ct_words, false, n_pairs, n_marks);
   }
   // counters: one atomic per workgroup and counter (lane 0 of each wavefront holds its sums)
   __shared__ unsigned long long s_cnt[2][256 / kWave];
@@ -1719,6 +1769,10 @@ __global__ __launch_bounds__(256) void k_large(const JobDev* __restrict__ jobs, 
   __shared__ uint32_t s_sup[kListSupers];                    // list scatter: cells per group of buckets
   const uint64_t total = job_item_base[n_jobs];
   if ((uint64_t)blockIdx.x * blockDim.x >= total) return;   // workgroups past the last item (uniform)
+  // Issue priority over the small branch's waves that share the CUs: this kernel's rate is its
+  // hit atomics in flight, and a busy small branch beside it otherwise takes the issue cycles
+  // that keep them in flight (the small branch fills the cycles this kernel leaves).
+  __builtin_amdgcn_s_setprio(1);
   unsigned long long* lkey = s_list + threadIdx.x / kWave;
   if (threadIdx.x < 256 / kWave) s_list[threadIdx.x] = 0ull;
   for (uint32_t i = threadIdx.x; i < DC_COUNT * kDecades; i += blockDim.x) (&s_dec[0][0])[i] = 0ull;
@@ -1908,8 +1962,9 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
     const JobDev& j = jobs[ji];
     const uint64_t local = task - tbase[lo];
     if (!large) {
+      __builtin_amdgcn_s_setprio(0);                 // small tasks fill the cycles large ones leave
       unsigned long long n_pairs = 0, n_marks = 0;
-      small_unit(j, local, lds, lds_ct_words, ct_job == ji, n_pairs, n_marks);
+      small_unit<false>(j, local, lds, lds_ct_words, ct_job == ji, n_pairs, n_marks);
       ct_job = ji;
       dp_job = kg_job = 0xffffffffu;                 // the tile overwrote the residue table and K's groups
       if (lane == 0) {
@@ -1918,7 +1973,9 @@ __global__ __launch_bounds__(256) void k_batch(const JobDev* __restrict__ jobs, 
       }
       continue;
     }
-    // a large task: the job's tables in LDS (the plan guarantees they fit), then its items
+    // a large task: the job's tables in LDS (the plan guarantees they fit), then its items, at
+    // the issue priority k_large takes over small-branch waves
+    __builtin_amdgcn_s_setprio(1);
     uint2* ctl = reinterpret_cast<uint2*>(lds);
     uint16_t* dpl = reinterpret_cast<uint16_t*>(lds + 2 * lds_ct_words);
     if (ct_job != ji) {
@@ -2494,9 +2551,13 @@ hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base
 }
 
 hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
-                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s) {
+                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s, bool hit_rows) {
   if (total_units == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_small, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, total_units, lds_ct_words); { hipError_t e_ = note("k_small"); if (e_ != hipSuccess) return e_; }
+  if (hit_rows)
+    hipLaunchKernelGGL(k_small<true>, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, total_units, lds_ct_words);
+  else
+    hipLaunchKernelGGL(k_small<false>, dim3(blocks), dim3(256), lds_bytes, s, jobs, n_jobs, total_units, lds_ct_words);
+  { hipError_t e_ = note("k_small"); if (e_ != hipSuccess) return e_; }
   return hipGetLastError();
 }
 

@@ -64,8 +64,9 @@ hipError_t launch_zero_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_w
 hipError_t launch_fold_bytes(const JobDev* jobs, uint32_t n_jobs, uint64_t max_rows, int n_cu, hipStream_t s);
 hipError_t launch_prep_bounds(JobDev* jobs, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_items_scan(const JobDev* jobs, uint32_t n_jobs, uint64_t* base, hipStream_t s);
+// hit_rows: the instance with the hit-row pass for small primes far above w (see k_small)
 hipError_t launch_small(const JobDev* jobs, uint32_t n_jobs, uint64_t total_units, uint32_t lds_bytes,
-                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s);
+                        uint32_t lds_ct_words, uint32_t blocks, hipStream_t s, bool hit_rows = false);
 // lds_bytes = 0: tables read from global memory (any number of jobs); otherwise n_jobs must be 1
 // and the column table (lds_ct_words uint2, 0 = global) and residue table (dpre_n entries) of
 // that job are staged in LDS.  scatter_kind: 0 = atomic OR/add into the bitmaps and counts,

@@ -50,6 +50,7 @@ struct Plan {
   uint32_t tile_rows, n_windows, n_slices;
   uint32_t hits_per_item;
   uint32_t large_blocks, small_blocks;
+  bool small_hit_rows = false;      // k_small with the hit-row pass (thr >= 24 w)
   uint32_t lds_bytes, lds_ct_words;
   uint32_t large_lds_bytes, large_lds_ct_words;   // LDS tables of the large branch (0: global)
   uint64_t dense_max;

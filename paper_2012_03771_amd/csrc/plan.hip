@@ -23,6 +23,36 @@ uint64_t pi_upper(uint64_t x) {
   return (uint64_t)b + 64;
 }
 
+// Default small/large threshold of the three-gap walk, from the two branches' costs: a small
+// prime costs about n_m residue steps of c_pair = 0.83 ps, a large prime about n_m n_x / p hit
+// atomics of c_hit = 55 ps.  Where the hits take long (over 40 ms), the small branch runs hidden
+// beside them on its own stream while it takes at most about two fifths of their time: the
+// largest C_mult of 30, 36, 44, 52 and 64 that keeps it there (at 953#/210, m_inc 1e6, limit 1e10
+// that is 52: one call 79.6 ms, against 84.4 ms at 30 S, 80.9 at 44 S and 83.4 at 64 S; with
+// limit 1e9 it is 36, within 2% of the best multiple measured there).  Otherwise the
+// two branches' times add, and the sum n_m pi(thr) c_pair' + n_m n_x (log log limit - log log thr)
+// c_hit is least at thr = n_x c_hit / c_pair' = 44 n_x, with c_pair' = 1.25 ps measured for jobs
+// of fewer rows (96 mixed jobs alone: 307 ms in all, against 361 ms at 30 S).
+static uint64_t three_gap_threshold(const cs_job& j, const Plan& pl) {
+  constexpr double kPair = 0.83e-12, kHit = 55e-12;
+  const double L = std::max<double>((double)j.limit, 16.0);
+  auto pi_est = [](double x) { return x / (log(x) - 1.0); };
+  auto hit_s = [&](double t) {
+    return (double)pl.n_m * pl.n_x * std::max(0.0, log(log(L)) - log(log(std::max(t, 3.0)))) * kHit;
+  };
+  uint64_t thr = 44ull * std::max<uint32_t>(pl.n_x, 1u);
+  const double t30 = 30.0 * (double)pl.S;
+  if (t30 < L && hit_s(t30) > 40e-3) {
+    thr = (uint64_t)t30;
+    for (double cm : {36.0, 44.0, 52.0, 64.0}) {
+      const double t = cm * (double)pl.S;
+      if (t >= L || (double)pl.n_m * pi_est(t) * kPair > 0.4 * hit_s(t)) break;
+      thr = (uint64_t)t;
+    }
+  }
+  return thr;
+}
+
 static std::vector<uint32_t> host_primes_upto(uint32_t n) {
   std::vector<uint8_t> comp(n + 1, 0);
   std::vector<uint32_t> out;
@@ -144,25 +174,28 @@ cs_status make_plan(const cs_job* job, const cs_tune* tune, int n_cu, Plan* out,
 
   // small/large threshold C_mult * S (Section 5).  With one Eq. 5 solve per hit, C_mult =
   // 2.5 M / M_c (a quarter of the paper's 10 M / M_c: at 953#/210 the step is flat from 120,000
-  // to 437,507 = 2.5 M / M_c S, 216-218 ms, against 223 ms at 5 M / M_c S); with three-gap stepping
-  // a hit costs a few operations and the small branch runs beside the large one, so three times
-  // the paper's naive 10 S is used.  Measured at 953#/210, m_inc 1e6: one call takes 86.4 ms at
-  // 24 S, 85.0 at 30 S, 84.1 at 44 S, 86.2 at 60 S; on jobs with fewer rows the small branch
-  // hides less and lower multiples win (the sum of 96 mixed jobs alone: 309 ms at 8 S, 361 ms at
-  // 30 S, 390 ms at 40 S), so 30 S is kept.  Clamped so that a large prime divides at most one number of an interval
-  // (p > 2 sl), or (three-gap) p > 4 sl.
+  // to 437,507 = 2.5 M / M_c S, 216-218 ms, against 223 ms at 5 M / M_c S).  With three-gap
+  // stepping the threshold comes from the two branches' costs (three_gap_threshold).  Clamped so
+  // that a large prime divides at most one number of an interval (p > 2 sl), or (three-gap) p > 4 sl.
   uint64_t thr_min = std::max<uint64_t>(j.P, pl.w);
   if (mode == CS_LARGE_THREE_GAP) thr_min = std::max<uint64_t>(thr_min, 2ull * pl.w);
   uint64_t thr = tune && tune->thr ? tune->thr : 0;
   if (!thr) {
-    double cm = mode == CS_LARGE_THREE_GAP ? 30.0
-                                           : (pl.n_m ? 2.5 * (double)j.m_inc / (double)pl.n_m : 2.5);
-    thr = (uint64_t)(cm * (double)pl.S);
+    if (mode == CS_LARGE_THREE_GAP) {
+      thr = three_gap_threshold(j, pl);
+    } else {
+      const double cm = pl.n_m ? 2.5 * (double)j.m_inc / (double)pl.n_m : 2.5;
+      thr = (uint64_t)(cm * (double)pl.S);
+    }
   }
   pl.thr = std::max(thr, thr_min);
   // the small branch and the fp64 large branch stop below wide_lo
   if (thr_min >= pl.wide_lo) return CS_EINVAL;
   pl.thr = std::min<uint64_t>(pl.thr, pl.wide_lo - 1);
+  // the small branch's hit-row pass where most small primes lie far above w (it pays at the paper
+  // scale, 52 S = 52 w; on the mixed jobs, whose thresholds sit at 4-18 w, the instance without it
+  // ran faster)
+  pl.small_hit_rows = pl.thr >= 24ull * std::max<uint64_t>(pl.w, 1);
 
   // small branch tiles
   const bool ct_lds = pl.ct_words * 8u <= kLdsCtMax;

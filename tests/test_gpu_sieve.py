@@ -158,6 +158,27 @@ def test_range_calls_compose():
     assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref_c)
 
 
+@pytest.mark.parametrize("job,mult", [
+    (W.Job(61, 6, 1000, 4003, 300, 10**6), 24),          # ragged last tile, gaps 2 and 4
+    (W.Job(61, 6, 1000, 4003, 300, 10**6), 100),
+    (W.Job(97, 1, 7, 1501, 250, 3 * 10**6), 40),         # d = 1: every m, gap 1
+    (W.Job(131, 210, 10**6, 20011, 700, 5 * 10**6), 52),  # gaps up to 10
+    (W.Job(97, 30030, 1, 90000, 400, 2 * 10**6), 30),     # gaps up to 22: tiles without the pass
+    (W.Job(503, 210, 10**6, 3000, 7000, 10**7), 30),
+], ids=["d6_24w", "d6_100w", "d1_40w", "d210_52w", "d30030_30w", "p503_30w"])
+def test_small_branch_hit_rows(job, mult):
+    """Thresholds of 24 w and more run the small branch's hit-row pass (offsets stepped over the
+    tile's rows, then each lane's hit rows marked): every row equals the oracle's."""
+    w = 2 * job.sl
+    tune = cs.Tune(thr=mult * w, large_mode=cs.LARGE_THREE_GAP)
+    assert cs.plan(job, tune).thr == mult * w
+    _say("hit rows", job, mult)
+    got_b, got_c, diag, _ = _run(job, tune)
+    want_b, want_c = _oracle(job)
+    _assert_same(job, got_b, got_c, want_b, want_c)
+    assert diag.error_flags == 0 and diag.small_marks > 0
+
+
 @pytest.mark.parametrize("thr", [2**31 - 1, 2**32], ids=["thr_below_2^31", "thr_2^32"])
 def test_small_branch_primes_above_2_31(thr):
     """Small-branch primes just above 2^31 (a threshold set at or beyond 2^31 sends them through
