@@ -913,7 +913,7 @@ __device__ __forceinline__ void small_single_marks(const SmallArgs& a, CT ct, ui
       const uint32_t o0 = __builtin_amdgcn_readfirstlane(moffv);
       uint64_t rn = mk + mulmod(o0, k, p, pinv);
       rn = rn >= p ? rn - p : rn;
-      s0 = (uint32_t)sub_mod(mod64(sl, p, pinv), rn, p);
+      s0 = (uint32_t)sub_mod(sl, rn, p);                        // sl < w < p
     }
     auto advance = [&](uint32_t s, uint32_t dm) -> uint32_t {
       const uint32_t kd = dm < 16u ? km[dm] : (uint32_t)mulmod(dm, k, p, pinv);

@@ -95,6 +95,32 @@ def test_two_lanes_equal_alone():
         cs.Server(budget_bytes=1 << 20, max_limit=10**6, long_ms=-1.0)
 
 
+def test_iterations_fall_back_to_atomics_for_a_job_without_byte_counters():
+    """A job whose numbers may have 256 or more prime factors above its threshold (2003#, sl = 5:
+    threshold 2003) gets no byte counters; the iterations it is in use per-hit atomics for every
+    job, and every result still equals the job alone (and the oracle)."""
+    odd = W.Job(2003, 1, 1, 50, 5, 10**5)
+    assert cs.plan(odd, cs.Tune(large_mode=cs.LARGE_THREE_GAP)).scatter == cs.SCATTER_ATOMIC
+    jobs = [JOBS[0], odd, JOBS[3], JOBS[5]]
+    tune = cs.Tune(large_mode=cs.LARGE_THREE_GAP)
+    srv = cs.Server(budget_bytes=2 << 30, max_limit=10**7, max_active=4, chunks=1, tune=tune)
+    tickets = [srv.submit(j) for j in jobs]
+    for t in tickets:
+        assert srv.wait(t, 120.0).state == 2
+    for job, t in zip(jobs, tickets):
+        b, c = srv.fetch(t)
+        torch.cuda.synchronize()
+        a_b, a_c = _alone(job, tune)
+        assert np.array_equal(_np(b), a_b) and np.array_equal(_np(c), a_c), job
+        srv.release(t)
+    w_b, w_c = coracle.sieve_job(odd)
+    a_b, a_c = _alone(odd, tune)
+    assert np.array_equal(a_b, w_b) and np.array_equal(a_c, w_c)
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["bytes_iterations"] < st["iterations"]
+    srv.close()
+
+
 def test_budget_forces_queueing_and_results_hold():
     """A budget that fits about one job at a time: jobs wait for memory, results are unchanged."""
     jobs = [W.Job(307, 2, 12345 + 1000 * i, 4000, 2500, 10**7) for i in range(4)]
