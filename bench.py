@@ -313,8 +313,8 @@ def _scatter_probe(cs, torch, n_words, n_ops, slices=1, op=0, seed=7):
 def _scatter_table(cs, torch):
     """The probe over the buffer sizes and modes that bound the hit scatters."""
     rows = []
-    for mib, slices, op in [(3 * 1024, 1, 0), (1024, 1, 0), (256, 1, 0), (64, 1, 0), (16, 8, 0), (3 * 1024, 1, 1),
-                            (256, 1, 1), (16, 8, 1), (1, 1, 2)]:
+    for mib, slices, op in [(3 * 1024, 1, 0), (3 * 1024, 8, 0), (1024, 1, 0), (256, 1, 0), (256, 8, 0), (64, 1, 0),
+                            (16, 8, 0), (3 * 1024, 1, 1), (3 * 1024, 8, 1), (256, 1, 1), (16, 8, 1), (1, 1, 2)]:
         n_words = mib * 2**20 // 4
         n_ops = 1 << 28
         r = _scatter_probe(cs, torch, n_words, n_ops, slices, op)
